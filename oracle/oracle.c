@@ -1,0 +1,893 @@
+/* oracle.c -- plain FP64 CPU reference for one lattice update of the
+ * multiphase-multicomponent lattice Boltzmann model for self-diffusiophoretic
+ * Janus colloids at liquid-liquid interfaces (Palacios, Scagliarini,
+ * Pagonabarraga, arXiv:2202.01631).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the solver.  It is written to be
+ * read against the paper: one plain loop per step of the update, FP64
+ * throughout, no blocking, fusion or reordering.  Build with
+ * -O2 -fno-fast-math -ffp-contract=off so that no multiply-add is fused; the
+ * colloid geometry decisions (inside test, cap test) depend on exact FP64
+ * rounding.
+ *
+ * The paper gives the model (Eqs. 1-10) but not its discretisation.  The
+ * readings taken here, each marked "reading" below, are:
+ *   - solvent: D3Q19, BGK with relaxation time tau (nu = (tau-1/2)/3; tau = 1
+ *     gives the paper's nu = 1/6, Sec. II.C), second-order equilibrium, forcing
+ *     term of Guo, Zheng and Shi (2002); body force F = -psi grad(mu_psi), the
+ *     usual potential form of the free-energy force ("thermohydrodynamic"
+ *     model, Sec. I);
+ *   - psi and c: explicit Euler finite volumes on the lattice, 7-point
+ *     Laplacian, central face fluxes for advection (Eq. 3);
+ *   - particles: bounce-back on links with the moving-wall term, momentum
+ *     exchange (Sec. II.B), implicit velocity update in the manner of
+ *     Nguyen and Ladd, cover/uncover repair;
+ *   - slip (Eq. 4) added to the wall velocity of every link, with the
+ *     concentration gradient taken at the link's fluid node; Janus activity
+ *     (Eq. 5) emitted once per active link into its fluid node; Janus mobility
+ *     (Eq. 6); tie m.n = 0 on the active cap as Eqs. 5-6 write it;
+ *   - wetting (Eqs. 8-9) as a ghost value of psi in the Laplacian at solid
+ *     face neighbours, signed so that kappa n.grad(psi) = H with n pointing out
+ *     of the particle; contact angle from Eq. 10.
+ *
+ * Order of one step t -> t+1:
+ *   1. mu_psi(t) at fluid nodes                                    (Eq. 2, 9)
+ *   2. body force, moments, BGK-Guo collision; pull streaming;
+ *      bounce-back on the links of R(t) with wall velocity V + W x r + slip,
+ *      momentum exchange accumulated per colloid                 (Sec. II.B, Eq. 4, 6)
+ *   3. psi and c updates with u(t), mu(t), chi(t) and emission      (Eq. 3, 5)
+ *   4. colloid update (implicit in V, W), position and orientation
+ *   5. geometry at R(t+1): cover/uncover repair, owner map, link table
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+/* ---------------------------------------------------------------- lattice */
+/* D3Q19 velocity set, numbered as documented in oracle.h */
+static const int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+static double wt(int i)
+{
+    if (i == 0) return 1.0 / 3.0;
+    if (i <= 6) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+static int opp(int i)
+{
+    if (i == 0) return 0;
+    return (i % 2 == 1) ? i + 1 : i - 1;
+}
+
+/* ---------------------------------------------------------------- context */
+struct or_ctx {
+    or_params p;
+    int nx, ny, nz;
+    long N;
+    double *f, *fs, *fn;          /* pre-collision state f(t), post-collision, f(t+1) */
+    double *psi, *cc, *psin, *ccn;
+    double *mu, *force, *uf, *src;
+    int *owner, *owner_new;
+    or_colloid *col;
+    int ncol;
+    double *F0, *T0, *zeta, *trF, *trT, *Flast, *Tlast;
+    int *lk, *ln, *ld, *lcap;
+    long nl, lcapacity;
+    long step;
+    int stage;
+    int err;
+    double diag[OR_DIAG_N];
+    char msg[256];
+};
+
+static int fail(or_ctx *c, int code, const char *m)
+{
+    if (c) snprintf(c->msg, sizeof c->msg, "%s", m);
+    return code;
+}
+
+static long node(const or_ctx *c, int x, int y, int z)
+{
+    x = ((x % c->nx) + c->nx) % c->nx;
+    y = ((y % c->ny) + c->ny) % c->ny;
+    z = ((z % c->nz) + c->nz) % c->nz;
+    return x + (long)c->nx * (y + (long)c->ny * z);
+}
+
+static void coords(const or_ctx *c, long n, int *x, int *y, int *z)
+{
+    *x = (int)(n % c->nx);
+    *y = (int)((n / c->nx) % c->ny);
+    *z = (int)(n / ((long)c->nx * c->ny));
+}
+
+/* neighbour of node n along lattice vector i */
+static long nbr(const or_ctx *c, long n, int i)
+{
+    int x, y, z;
+    coords(c, n, &x, &y, &z);
+    return node(c, x + CX[i], y + CY[i], z + CZ[i]);
+}
+
+/* neighbour of node n along -c_i */
+static long nbr_back(const or_ctx *c, long n, int i)
+{
+    int x, y, z;
+    coords(c, n, &x, &y, &z);
+    return node(c, x - CX[i], y - CY[i], z - CZ[i]);
+}
+
+/* ------------------------------------------------------- colloid geometry */
+/* minimum-image displacement along one periodic axis of length L */
+static double min_image(double d, int L)
+{
+    double h = 0.5 * (double)L;
+    if (d > h) d -= (double)L;
+    else if (d < -h) d += (double)L;
+    return d;
+}
+
+/* displacement from the colloid centre to the point x + s*c_i (s = 0 or 1/2) */
+static void disp(const or_ctx *c, const or_colloid *k, int x, int y, int z,
+                 int i, double s, double r[3])
+{
+    r[0] = min_image(((double)x + s * (double)CX[i]) - k->pos[0], c->nx);
+    r[1] = min_image(((double)y + s * (double)CY[i]) - k->pos[1], c->ny);
+    r[2] = min_image(((double)z + s * (double)CZ[i]) - k->pos[2], c->nz);
+}
+
+/* a node is solid when it lies strictly inside the sphere (Sec. II.B) */
+static int inside(const or_ctx *c, const or_colloid *k, int x, int y, int z)
+{
+    double r[3], d2;
+    disp(c, k, x, y, z, 0, 0.0, r);
+    d2 = r[0] * r[0] + r[1] * r[1];
+    d2 = d2 + r[2] * r[2];
+    return d2 < k->radius * k->radius;
+}
+
+/* active hemisphere of Eqs. 5-6: m.n <= 0, n taken at the link midpoint */
+static int on_active_cap(const or_colloid *k, const double r[3])
+{
+    double md = k->m[0] * r[0] + k->m[1] * r[1];
+    md = md + k->m[2] * r[2];
+    return md <= 0.0;
+}
+
+/* ------------------------------------------------------------ equilibrium */
+static double feq(int i, double rho, const double u[3])
+{
+    double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return wt(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+/* forcing term of Guo, Zheng and Shi, Phys. Rev. E 65, 046308 (2002) */
+static double guo(int i, const double u[3], const double F[3], double tau)
+{
+    double ci[3] = {(double)CX[i], (double)CY[i], (double)CZ[i]};
+    double cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+    double s = 0.0;
+    for (int a = 0; a < 3; a++) s += (3.0 * (ci[a] - u[a]) + 9.0 * cu * ci[a]) * F[a];
+    return (1.0 - 0.5 / tau) * wt(i) * s;
+}
+
+/* ----------------------------------------------------------- allocation */
+static void *zalloc(size_t n)
+{
+    void *p = calloc(n ? n : 1, 1);
+    return p;
+}
+
+int or_create(const or_params *p, or_ctx **out)
+{
+    if (!p || !out) return OR_E_INVALID;
+    *out = NULL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return OR_E_INVALID;
+    if (!(p->tau > 0.5) || !(p->rho0 > 0.0)) return OR_E_INVALID;
+    if (p->kappa < 0.0 || p->M_psi < 0.0 || p->D_c < 0.0 || p->k_d < 0.0 || p->C < 0.0)
+        return OR_E_INVALID;
+    /* explicit-Euler stability of the 7-point schemes for psi and c */
+    if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
+        return OR_E_INVALID;
+    if (12.0 * p->D_c + p->k_d >= 2.0) return OR_E_INVALID;
+
+    or_ctx *c = (or_ctx *)zalloc(sizeof *c);
+    if (!c) return OR_E_INVALID;
+    c->p = *p;
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->nz = p->nz;
+    c->N = (long)p->nx * p->ny * p->nz;
+    long N = c->N;
+    c->f = zalloc(sizeof(double) * 19 * N);
+    c->fs = zalloc(sizeof(double) * 19 * N);
+    c->fn = zalloc(sizeof(double) * 19 * N);
+    c->psi = zalloc(sizeof(double) * N);
+    c->cc = zalloc(sizeof(double) * N);
+    c->psin = zalloc(sizeof(double) * N);
+    c->ccn = zalloc(sizeof(double) * N);
+    c->mu = zalloc(sizeof(double) * N);
+    c->force = zalloc(sizeof(double) * 3 * N);
+    c->uf = zalloc(sizeof(double) * 3 * N);
+    c->src = zalloc(sizeof(double) * N);
+    c->owner = zalloc(sizeof(int) * N);
+    c->owner_new = zalloc(sizeof(int) * N);
+    if (!c->f || !c->fs || !c->fn || !c->psi || !c->cc || !c->psin || !c->ccn || !c->mu ||
+        !c->force || !c->uf || !c->src || !c->owner || !c->owner_new) {
+        or_destroy(c);
+        return OR_E_INVALID;
+    }
+    for (long n = 0; n < N; n++) c->owner[n] = -1;
+    *out = c;
+    return OR_OK;
+}
+
+static void free_colloids(or_ctx *c)
+{
+    free(c->col); free(c->F0); free(c->T0); free(c->zeta); free(c->trF); free(c->trT);
+    free(c->Flast); free(c->Tlast);
+    free(c->lk); free(c->ln); free(c->ld); free(c->lcap);
+    c->col = NULL; c->F0 = c->T0 = c->zeta = c->trF = c->trT = c->Flast = c->Tlast = NULL;
+    c->lk = c->ln = c->ld = c->lcap = NULL;
+    c->ncol = 0; c->nl = 0; c->lcapacity = 0;
+}
+
+int or_destroy(or_ctx *c)
+{
+    if (!c) return OR_OK;
+    free(c->f); free(c->fs); free(c->fn); free(c->psi); free(c->cc); free(c->psin);
+    free(c->ccn); free(c->mu); free(c->force); free(c->uf); free(c->src);
+    free(c->owner); free(c->owner_new);
+    free_colloids(c);
+    free(c);
+    return OR_OK;
+}
+
+const char *or_last_error(const or_ctx *c) { return c ? c->msg : "null context"; }
+
+/* ------------------------------------------------------------- init */
+int or_init_fields(or_ctx *c, const double *psi, const double *cc, const double *rho,
+                   const double *u)
+{
+    if (!c || !psi || !cc) return fail(c, OR_E_INVALID, "psi and c are required");
+    long N = c->N;
+    for (long n = 0; n < N; n++) {
+        double r = rho ? rho[n] : c->p.rho0;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (u) { v[0] = u[n]; v[1] = u[N + n]; v[2] = u[2 * N + n]; }
+        if (!isfinite(psi[n]) || !isfinite(cc[n]) || !isfinite(r) || !(r > 0.0) ||
+            !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]))
+            return fail(c, OR_E_INVALID, "non-finite or non-positive initial field");
+        for (int i = 0; i < 19; i++) c->f[i * N + n] = feq(i, r, v);
+        c->psi[n] = psi[n];
+        c->cc[n] = cc[n];
+        c->owner[n] = -1;
+    }
+    free_colloids(c);
+    c->step = 0;
+    c->err = 0;
+    c->stage = 1;
+    memset(c->diag, 0, sizeof c->diag);
+    return OR_OK;
+}
+
+/* ----------------------------------------------------- geometry and links */
+/* owner map at the current colloid positions; -1 fluid.  Returns nonzero if
+ * two colloids claim one node. */
+static int owner_map(or_ctx *c, int *own)
+{
+    int bad = 0;
+    for (long n = 0; n < c->N; n++) {
+        int x, y, z;
+        coords(c, n, &x, &y, &z);
+        own[n] = -1;
+        for (int k = 0; k < c->ncol; k++) {
+            if (inside(c, &c->col[k], x, y, z)) {
+                if (own[n] != -1) bad = 1;
+                own[n] = k;
+            }
+        }
+    }
+    return bad;
+}
+
+/* link table in canonical order (k, n, d): fluid node n, n + c_d solid in k */
+static void build_links(or_ctx *c)
+{
+    long *count = zalloc(sizeof(long) * (c->ncol + 1));
+    long total = 0;
+    for (long n = 0; n < c->N; n++) {
+        if (c->owner[n] >= 0) continue;
+        for (int d = 1; d < 19; d++) {
+            int k = c->owner[nbr(c, n, d)];
+            if (k >= 0) { count[k]++; total++; }
+        }
+    }
+    if (total > c->lcapacity) {
+        free(c->lk); free(c->ln); free(c->ld); free(c->lcap);
+        c->lcapacity = total;
+        c->lk = zalloc(sizeof(int) * total);
+        c->ln = zalloc(sizeof(int) * total);
+        c->ld = zalloc(sizeof(int) * total);
+        c->lcap = zalloc(sizeof(int) * total);
+    }
+    long *off = zalloc(sizeof(long) * (c->ncol + 1));
+    for (int k = 1; k <= c->ncol; k++) off[k] = off[k - 1] + count[k - 1];
+    for (long n = 0; n < c->N; n++) {
+        if (c->owner[n] >= 0) continue;
+        int x, y, z;
+        coords(c, n, &x, &y, &z);
+        for (int d = 1; d < 19; d++) {
+            int k = c->owner[nbr(c, n, d)];
+            if (k < 0) continue;
+            double r[3];
+            disp(c, &c->col[k], x, y, z, d, 0.5, r);
+            long l = off[k]++;
+            c->lk[l] = k;
+            c->ln[l] = (int)n;
+            c->ld[l] = d;
+            c->lcap[l] = on_active_cap(&c->col[k], r);
+        }
+    }
+    c->nl = total;
+    free(count);
+    free(off);
+}
+
+int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
+{
+    if (!c) return OR_E_INVALID;
+    if (c->stage < 1) return fail(c, OR_E_STATE, "init_fields first");
+    if (n < 0 || (n > 0 && !cols)) return fail(c, OR_E_INVALID, "bad colloid array");
+    free_colloids(c);
+    c->ncol = n;
+    c->col = zalloc(sizeof(or_colloid) * (n + 1));
+    c->F0 = zalloc(sizeof(double) * 3 * (n + 1));
+    c->T0 = zalloc(sizeof(double) * 3 * (n + 1));
+    c->zeta = zalloc(sizeof(double) * 36 * (n + 1));
+    c->trF = zalloc(sizeof(double) * 3 * (n + 1));
+    c->trT = zalloc(sizeof(double) * 3 * (n + 1));
+    c->Flast = zalloc(sizeof(double) * 3 * (n + 1));
+    c->Tlast = zalloc(sizeof(double) * 3 * (n + 1));
+    int L[3] = {c->nx, c->ny, c->nz};
+    for (int k = 0; k < n; k++) {
+        or_colloid q = cols[k];
+        double mm = sqrt(q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2]);
+        if (!(q.radius > 0.0) || !(q.rho_p > 0.0) || !(mm > 0.0))
+            return fail(c, OR_E_INVALID, "colloid radius, density and axis must be positive");
+        if (q.H != 0.0 && !(c->p.kappa > 0.0))
+            return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
+        for (int a = 0; a < 3; a++) {
+            if (2.0 * q.radius + 4.0 > (double)L[a])
+                return fail(c, OR_E_INVALID, "colloid does not fit in the box");
+            q.m[a] /= mm;
+            /* positions are kept in [0, L) */
+            q.pos[a] = fmod(q.pos[a], (double)L[a]);
+            if (q.pos[a] < 0.0) q.pos[a] += (double)L[a];
+        }
+        c->col[k] = q;
+    }
+    if (owner_map(c, c->owner)) {
+        for (long m = 0; m < c->N; m++) c->owner[m] = -1;
+        free_colloids(c);
+        return fail(c, OR_E_STATE, "colloids overlap");
+    }
+    /* solid nodes hold the rest populations; they are never read */
+    for (long m = 0; m < c->N; m++)
+        if (c->owner[m] >= 0)
+            for (int i = 0; i < 19; i++) c->f[i * c->N + m] = wt(i) * c->p.rho0;
+    build_links(c);
+    c->stage = 2;
+    return OR_OK;
+}
+
+/* --------------------------------------------------------------- one step */
+/* wall velocity of colloid k at displacement r: V + Omega x r */
+static void rigid_velocity(const or_colloid *k, const double r[3], double u[3])
+{
+    u[0] = k->vel[0] + (k->omega[1] * r[2] - k->omega[2] * r[1]);
+    u[1] = k->vel[1] + (k->omega[2] * r[0] - k->omega[0] * r[2]);
+    u[2] = k->vel[2] + (k->omega[0] * r[1] - k->omega[1] * r[0]);
+}
+
+static void cross(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* step 1: chemical potential mu_psi of Eq. 2 at fluid nodes.  At a solid face
+ * neighbour the Laplacian uses the wetting ghost psi(x) - (H/kappa)|e.n|, the
+ * one-sided form of kappa n.grad(psi) = H (Eq. 9, reading: signed, n out of
+ * the particle, n taken at the face midpoint). */
+static void chemical_potential(or_ctx *c)
+{
+    const or_params *p = &c->p;
+    for (long n = 0; n < c->N; n++) {
+        if (c->owner[n] >= 0) { c->mu[n] = 0.0; continue; }
+        int x, y, z;
+        coords(c, n, &x, &y, &z);
+        double lap = -6.0 * c->psi[n];
+        for (int e = 1; e <= 6; e++) {
+            long m = nbr(c, n, e);
+            int k = c->owner[m];
+            if (k < 0) {
+                lap += c->psi[m];
+            } else {
+                double r[3];
+                disp(c, &c->col[k], x, y, z, e, 0.5, r);
+                double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double en = fabs(r[(e - 1) / 2]) / rn;
+                double ghost = c->psi[n];
+                if (p->kappa > 0.0) ghost = c->psi[n] - (c->col[k].H / p->kappa) * en;
+                lap += ghost;
+            }
+        }
+        double ps = c->psi[n];
+        double chi = c->cc[n] - p->c_b0 - p->E * tanh(ps);
+        double ch = cosh(ps);
+        c->mu[n] = p->a * ps + p->b * ps * ps * ps - p->kappa * lap - p->C * p->E * chi / (ch * ch);
+    }
+}
+
+/* value of a scalar field at neighbour m of fluid node n, with the node's own
+ * value substituted when m is solid (no flux through the particle surface) */
+static double hat(const or_ctx *c, const double *fld, long n, long m)
+{
+    return c->owner[m] < 0 ? fld[m] : fld[n];
+}
+
+/* step 2: force, moments, collision, streaming and bounce-back on links */
+static void collide_stream(or_ctx *c)
+{
+    const or_params *p = &c->p;
+    long N = c->N;
+    double sumF[3] = {0.0, 0.0, 0.0};
+    for (long n = 0; n < N; n++) {
+        if (c->owner[n] >= 0) {
+            for (int i = 0; i < 19; i++) c->fs[i * N + n] = c->f[i * N + n];
+            for (int a = 0; a < 3; a++) { c->force[a * N + n] = 0.0; c->uf[a * N + n] = 0.0; }
+            continue;
+        }
+        /* body force -psi grad(mu) with central differences */
+        double F[3];
+        for (int a = 0; a < 3; a++) {
+            long mp = nbr(c, n, 1 + 2 * a), mm = nbr(c, n, 2 + 2 * a);
+            F[a] = -c->psi[n] * (hat(c, c->mu, n, mp) - hat(c, c->mu, n, mm)) / 2.0 + p->ext_force[a];
+            sumF[a] += F[a];
+        }
+        double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < 19; i++) {
+            double fi = c->f[i * N + n];
+            rho += fi;
+            mom[0] += fi * CX[i];
+            mom[1] += fi * CY[i];
+            mom[2] += fi * CZ[i];
+        }
+        double u[3];
+        for (int a = 0; a < 3; a++) u[a] = (mom[a] + F[a] / 2.0) / rho;
+        for (int i = 0; i < 19; i++) {
+            double fi = c->f[i * N + n];
+            c->fs[i * N + n] = fi - (fi - feq(i, rho, u)) / p->tau + guo(i, u, F, p->tau);
+        }
+        for (int a = 0; a < 3; a++) { c->force[a * N + n] = F[a]; c->uf[a * N + n] = u[a]; }
+    }
+    /* pull streaming from fluid upstream neighbours */
+    for (long n = 0; n < N; n++) {
+        if (c->owner[n] >= 0) {
+            for (int i = 0; i < 19; i++) c->fn[i * N + n] = c->f[i * N + n];
+            continue;
+        }
+        for (int i = 0; i < 19; i++) {
+            long m = nbr_back(c, n, i);
+            if (c->owner[m] < 0) c->fn[i * N + n] = c->fs[i * N + m];
+        }
+    }
+    /* bounce-back on links, canonical order; momentum exchange per colloid */
+    double sumdp[3] = {0.0, 0.0, 0.0}, dmass = 0.0;
+    for (int k = 0; k < c->ncol; k++) {
+        for (int a = 0; a < 3; a++) { c->F0[3 * k + a] = 0.0; c->T0[3 * k + a] = 0.0; }
+        for (int j = 0; j < 36; j++) c->zeta[36 * k + j] = 0.0;
+    }
+    for (long n = 0; n < N; n++) c->src[n] = 0.0;
+    for (long l = 0; l < c->nl; l++) {
+        int k = c->lk[l], d = c->ld[l];
+        long n = c->ln[l];
+        const or_colloid *q = &c->col[k];
+        int x, y, z;
+        coords(c, n, &x, &y, &z);
+        double r[3], nh[3], g[3], slip[3], ur[3], ub[3];
+        disp(c, q, x, y, z, d, 0.5, r);
+        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        for (int a = 0; a < 3; a++) nh[a] = r[a] / rn;
+        /* phoretic slip (Eq. 4) with the Janus mobility of Eq. 6 */
+        double mob = c->lcap[l] ? q->mu_minus : q->mu_plus;
+        for (int a = 0; a < 3; a++) {
+            long mp = nbr(c, n, 1 + 2 * a), mm = nbr(c, n, 2 + 2 * a);
+            g[a] = (hat(c, c->cc, n, mp) - hat(c, c->cc, n, mm)) / 2.0;
+        }
+        double ng = nh[0] * g[0] + nh[1] * g[1] + nh[2] * g[2];
+        for (int a = 0; a < 3; a++) slip[a] = mob * (g[a] - nh[a] * ng);
+        rigid_velocity(q, r, ur);
+        for (int a = 0; a < 3; a++) ub[a] = ur[a] + slip[a];
+        double cd[3] = {(double)CX[d], (double)CY[d], (double)CZ[d]};
+        double w = wt(d), fsd = c->fs[d * N + n];
+        double cub = cd[0] * ub[0] + cd[1] * ub[1] + cd[2] * ub[2];
+        double cus = cd[0] * slip[0] + cd[1] * slip[1] + cd[2] * slip[2];
+        c->fn[opp(d) * N + n] = fsd - 6.0 * w * c->p.rho0 * cub;
+        /* momentum handed to the colloid: c_d (2 f*_d - 6 w rho0 c_d.u_b) */
+        for (int a = 0; a < 3; a++) sumdp[a] += cd[a] * (2.0 * fsd - 6.0 * w * c->p.rho0 * cub);
+        dmass += -6.0 * w * c->p.rho0 * cub;
+        /* the part of it that does not depend on V and Omega */
+        double dp0[3], t0[3], rc[3];
+        for (int a = 0; a < 3; a++) dp0[a] = cd[a] * (2.0 * fsd - 6.0 * w * c->p.rho0 * cus);
+        cross(r, dp0, t0);
+        for (int a = 0; a < 3; a++) { c->F0[3 * k + a] += dp0[a]; c->T0[3 * k + a] += t0[a]; }
+        /* drag tensor zeta = sum 6 w rho0 g g^T, g = (c_d, r x c_d) */
+        cross(r, cd, rc);
+        double gg[6] = {cd[0], cd[1], cd[2], rc[0], rc[1], rc[2]};
+        for (int i = 0; i < 6; i++)
+            for (int j = 0; j < 6; j++) c->zeta[36 * k + 6 * i + j] += 6.0 * w * c->p.rho0 * gg[i] * gg[j];
+        /* Janus activity of Eq. 5, one emission per link into its fluid node */
+        c->src[n] += c->lcap[l] ? q->alpha_minus : q->alpha_plus;
+    }
+    for (int a = 0; a < 3; a++) {
+        c->diag[OR_DIAG_SUM_FORCE + a] = sumF[a];
+        c->diag[OR_DIAG_SUM_DP + a] = sumdp[a];
+    }
+    c->diag[OR_DIAG_SUM_DMASS] = dmass;
+}
+
+/* step 3: Cahn-Hilliard update of psi and advection-diffusion-reaction update
+ * of c (Eq. 3), explicit Euler, fluxes through the 6 faces of each node;
+ * no flux through faces shared with solid nodes. */
+static void scalar_update(or_ctx *c)
+{
+    const or_params *p = &c->p;
+    long N = c->N;
+    double sumsrc = 0.0, sumchi = 0.0;
+    for (long n = 0; n < N; n++) {
+        if (c->owner[n] >= 0) { c->psin[n] = c->psi[n]; c->ccn[n] = c->cc[n]; continue; }
+        double ps = c->psi[n], cn = c->cc[n];
+        double chi = cn - p->c_b0 - p->E * tanh(ps);
+        double adv_psi = 0.0, adv_c = 0.0, dmu = 0.0, dchi = 0.0;
+        for (int e = 1; e <= 6; e++) {
+            long m = nbr(c, n, e);
+            if (c->owner[m] >= 0) continue;
+            int a = (e - 1) / 2;
+            double sgn = (e % 2 == 1) ? 1.0 : -1.0;
+            double ue = 0.5 * (sgn * c->uf[a * N + n] + sgn * c->uf[a * N + m]);
+            adv_psi += ue * 0.5 * (ps + c->psi[m]);
+            adv_c += ue * 0.5 * (cn + c->cc[m]);
+            dmu += c->mu[m] - c->mu[n];
+            double chim = c->cc[m] - p->c_b0 - p->E * tanh(c->psi[m]);
+            dchi += chim - chi;
+        }
+        c->psin[n] = ps - adv_psi + p->M_psi * dmu;
+        c->ccn[n] = cn - adv_c + p->D_c * dchi + c->src[n] - p->k_d * chi;
+        sumsrc += c->src[n];
+        sumchi += chi;
+    }
+    c->diag[OR_DIAG_SUM_SRC] = sumsrc;
+    c->diag[OR_DIAG_SUM_CHI] = sumchi;
+}
+
+/* solve A x = b for a symmetric positive definite 6x6 A by Gaussian
+ * elimination without pivoting (A = M + zeta is SPD) */
+static void solve6(double A[36], double b[6], double x[6])
+{
+    for (int k = 0; k < 6; k++) {
+        for (int i = k + 1; i < 6; i++) {
+            double l = A[6 * i + k] / A[6 * k + k];
+            for (int j = k; j < 6; j++) A[6 * i + j] -= l * A[6 * k + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = 5; i >= 0; i--) {
+        double s = b[i];
+        for (int j = i + 1; j < 6; j++) s -= A[6 * i + j] * x[j];
+        x[i] = s / A[6 * i + i];
+    }
+}
+
+/* step 4: rigid-body update, implicit in the link drag (Nguyen and Ladd):
+ * (M + zeta) X' = M X + (F0, T0), X = (V, Omega); R' = R + V';
+ * m' = m rotated by the angle |Omega'| about Omega' (Rodrigues). */
+static void colloid_update(or_ctx *c)
+{
+    int L[3] = {c->nx, c->ny, c->nz};
+    for (int k = 0; k < c->ncol; k++) {
+        or_colloid *q = &c->col[k];
+        double *Z = &c->zeta[36 * k];
+        double Fk[6], X[6] = {q->vel[0], q->vel[1], q->vel[2], q->omega[0], q->omega[1], q->omega[2]};
+        for (int a = 0; a < 3; a++) {
+            Fk[a] = c->F0[3 * k + a] + c->trF[3 * k + a];
+            Fk[3 + a] = c->T0[3 * k + a] + c->trT[3 * k + a];
+        }
+        double Xn[6];
+        if (q->fixed) {
+            for (int i = 0; i < 6; i++) Xn[i] = X[i];
+        } else {
+            double mass = q->rho_p * (4.0 * M_PI / 3.0) * q->radius * q->radius * q->radius;
+            double inertia = 0.4 * mass * q->radius * q->radius;
+            double Mv[6] = {mass, mass, mass, inertia, inertia, inertia};
+            double A[36], b[6];
+            for (int i = 0; i < 36; i++) A[i] = Z[i];
+            for (int i = 0; i < 6; i++) { A[6 * i + i] += Mv[i]; b[i] = Mv[i] * X[i] + Fk[i]; }
+            solve6(A, b, Xn);
+        }
+        /* force and torque actually acting: F0 - zeta X' */
+        for (int i = 0; i < 6; i++) {
+            double s = Fk[i];
+            for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * Xn[j];
+            if (i < 3) c->Flast[3 * k + i] = s; else c->Tlast[3 * k + i - 3] = s;
+        }
+        if (!q->fixed) {
+            for (int a = 0; a < 3; a++) {
+                q->vel[a] = Xn[a];
+                q->omega[a] = Xn[3 + a];
+                double r = q->pos[a] + q->vel[a];
+                if (r >= (double)L[a]) r -= (double)L[a];
+                else if (r < 0.0) r += (double)L[a];
+                q->pos[a] = r;
+            }
+            if (fabs(q->vel[0]) >= 0.5 || fabs(q->vel[1]) >= 0.5 || fabs(q->vel[2]) >= 0.5)
+                c->err |= 2;
+            double th = sqrt(q->omega[0] * q->omega[0] + q->omega[1] * q->omega[1] + q->omega[2] * q->omega[2]);
+            if (th > 0.0) {
+                double ax[3] = {q->omega[0] / th, q->omega[1] / th, q->omega[2] / th}, kxm[3];
+                cross(ax, q->m, kxm);
+                double km = ax[0] * q->m[0] + ax[1] * q->m[1] + ax[2] * q->m[2];
+                double cs = cos(th), sn = sin(th), mn[3];
+                for (int a = 0; a < 3; a++) mn[a] = q->m[a] * cs + kxm[a] * sn + ax[a] * km * (1.0 - cs);
+                double nn = sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+                for (int a = 0; a < 3; a++) q->m[a] = mn[a] / nn;
+            }
+        }
+        for (int a = 0; a < 3; a++) { c->trF[3 * k + a] = 0.0; c->trT[3 * k + a] = 0.0; }
+    }
+}
+
+/* step 5: geometry at the new positions.  A node that turns solid hands its
+ * fluid momentum to the colloid; a node that turns fluid is refilled with the
+ * equilibrium at rho0 and the local rigid-body velocity, the colloid being
+ * debited that momentum, and takes psi and c as the mean of its face
+ * neighbours that are fluid before and after. */
+static void regeometry(or_ctx *c)
+{
+    long N = c->N;
+    double tr[3] = {0.0, 0.0, 0.0}, dmass = 0.0;
+    if (owner_map(c, c->owner_new)) c->err |= 4;
+    for (long n = 0; n < N; n++) {
+        int o = c->owner[n], w = c->owner_new[n];
+        if (o == w) continue;
+        int x, y, z;
+        coords(c, n, &x, &y, &z);
+        if (o >= 0 && w >= 0) { c->err |= 4; continue; }
+        if (o < 0) {
+            const or_colloid *q = &c->col[w];
+            double pm[3] = {0.0, 0.0, 0.0}, r[3], t[3], mass = 0.0;
+            for (int i = 0; i < 19; i++) {
+                double fi = c->fn[i * N + n];
+                pm[0] += fi * CX[i];
+                pm[1] += fi * CY[i];
+                pm[2] += fi * CZ[i];
+                mass += fi;
+            }
+            disp(c, q, x, y, z, 0, 0.0, r);
+            cross(r, pm, t);
+            for (int a = 0; a < 3; a++) { c->trF[3 * w + a] += pm[a]; c->trT[3 * w + a] += t[a]; tr[a] += pm[a]; }
+            dmass -= mass;
+        } else {
+            const or_colloid *q = &c->col[o];
+            double r[3], uw[3], pm[3], t[3];
+            disp(c, q, x, y, z, 0, 0.0, r);
+            rigid_velocity(q, r, uw);
+            for (int i = 0; i < 19; i++) c->fn[i * N + n] = feq(i, c->p.rho0, uw);
+            for (int a = 0; a < 3; a++) pm[a] = c->p.rho0 * uw[a];
+            cross(r, pm, t);
+            for (int a = 0; a < 3; a++) { c->trF[3 * o + a] -= pm[a]; c->trT[3 * o + a] -= t[a]; tr[a] -= pm[a]; }
+            dmass += c->p.rho0;
+            double sp = 0.0, sc = 0.0;
+            int cnt = 0;
+            for (int e = 1; e <= 6; e++) {
+                long m = nbr(c, n, e);
+                if (c->owner[m] < 0 && c->owner_new[m] < 0) { sp += c->psin[m]; sc += c->ccn[m]; cnt++; }
+            }
+            if (cnt > 0) { c->psin[n] = sp / cnt; c->ccn[n] = sc / cnt; }
+        }
+    }
+    for (long n = 0; n < N; n++) c->owner[n] = c->owner_new[n];
+    for (int a = 0; a < 3; a++) c->diag[OR_DIAG_SUM_TR + a] = tr[a];
+    c->diag[OR_DIAG_SUM_DMASS] += dmass;
+    build_links(c);
+}
+
+int or_step(or_ctx *c, int64_t nsteps)
+{
+    if (!c) return OR_E_INVALID;
+    if (c->stage < 1) return fail(c, OR_E_STATE, "init_fields first");
+    if (nsteps < 0) return fail(c, OR_E_INVALID, "negative step count");
+    for (int64_t s = 0; s < nsteps; s++) {
+        chemical_potential(c);
+        collide_stream(c);
+        scalar_update(c);
+        if (c->ncol > 0) {
+            colloid_update(c);
+            regeometry(c);
+        } else {
+            for (int a = 0; a < 3; a++) c->diag[OR_DIAG_SUM_TR + a] = 0.0;
+        }
+        double *t;
+        t = c->f; c->f = c->fn; c->fn = t;
+        t = c->psi; c->psi = c->psin; c->psin = t;
+        t = c->cc; c->cc = c->ccn; c->ccn = t;
+        c->step++;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------- readback */
+int or_get_fields(or_ctx *c, double *rho, double *u, double *psi, double *cc)
+{
+    if (!c) return OR_E_INVALID;
+    long N = c->N;
+    for (long n = 0; n < N; n++) {
+        double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+        if (c->owner[n] < 0) {
+            for (int i = 0; i < 19; i++) {
+                double fi = c->f[i * N + n];
+                r += fi;
+                m[0] += fi * CX[i];
+                m[1] += fi * CY[i];
+                m[2] += fi * CZ[i];
+            }
+        }
+        if (rho) rho[n] = r;
+        if (u)
+            for (int a = 0; a < 3; a++) u[a * N + n] = (c->owner[n] < 0) ? m[a] / r : 0.0;
+        if (psi) psi[n] = c->psi[n];
+        if (cc) cc[n] = c->cc[n];
+    }
+    return OR_OK;
+}
+
+int or_get_populations(or_ctx *c, double *f)
+{
+    if (!c || !f) return OR_E_INVALID;
+    memcpy(f, c->f, sizeof(double) * 19 * c->N);
+    return OR_OK;
+}
+
+int or_set_populations(or_ctx *c, const double *f)
+{
+    if (!c || !f) return OR_E_INVALID;
+    memcpy(c->f, f, sizeof(double) * 19 * c->N);
+    return OR_OK;
+}
+
+int or_get_aux(or_ctx *c, double *mu, double *force, double *uforced)
+{
+    if (!c) return OR_E_INVALID;
+    if (mu) memcpy(mu, c->mu, sizeof(double) * c->N);
+    if (force) memcpy(force, c->force, sizeof(double) * 3 * c->N);
+    if (uforced) memcpy(uforced, c->uf, sizeof(double) * 3 * c->N);
+    return OR_OK;
+}
+
+int or_get_owner(or_ctx *c, int32_t *owner)
+{
+    if (!c || !owner) return OR_E_INVALID;
+    for (long n = 0; n < c->N; n++) owner[n] = c->owner[n];
+    return OR_OK;
+}
+
+int or_get_links(or_ctx *c, int32_t *rec4, int64_t cap, int64_t *n)
+{
+    if (!c || !n) return OR_E_INVALID;
+    *n = c->nl;
+    if (!rec4) return OR_OK;
+    if (cap < c->nl) return fail(c, OR_E_INVALID, "link buffer too small");
+    for (long l = 0; l < c->nl; l++) {
+        rec4[4 * l + 0] = c->lk[l];
+        rec4[4 * l + 1] = c->ln[l];
+        rec4[4 * l + 2] = c->ld[l];
+        rec4[4 * l + 3] = c->lcap[l];
+    }
+    return OR_OK;
+}
+
+int or_observables(or_ctx *c, or_totals *t, or_colloid *out, int32_t n)
+{
+    if (!c) return OR_E_INVALID;
+    if (t) {
+        memset(t, 0, sizeof *t);
+        long N = c->N;
+        for (long m = 0; m < N; m++) {
+            if (c->owner[m] >= 0) continue;
+            for (int i = 0; i < 19; i++) {
+                double fi = c->f[i * N + m];
+                t->mass += fi;
+                t->mom[0] += fi * CX[i];
+                t->mom[1] += fi * CY[i];
+                t->mom[2] += fi * CZ[i];
+            }
+            t->sum_psi += c->psi[m];
+            t->sum_c += c->cc[m];
+            t->n_fluid++;
+        }
+        t->n_links = c->nl;
+        for (long l = 0; l < c->nl; l++) t->n_active += c->lcap[l];
+        t->step = c->step;
+        int e = c->err;
+        if (!isfinite(t->mass) || !isfinite(t->sum_psi) || !isfinite(t->sum_c)) e |= 1;
+        t->error_bits = e;
+    }
+    if (out) {
+        if (n > c->ncol) n = c->ncol;
+        for (int k = 0; k < n; k++) out[k] = c->col[k];
+    }
+    return OR_OK;
+}
+
+/* F0[3] T0[3] zeta[36] trF[3] trT[3] Flast[3] Tlast[3]: 54 doubles */
+int or_colloid_diag(or_ctx *c, int32_t k, double *out)
+{
+    if (!c || !out || k < 0 || k >= c->ncol) return OR_E_INVALID;
+    int o = 0;
+    for (int a = 0; a < 3; a++) out[o++] = c->F0[3 * k + a];
+    for (int a = 0; a < 3; a++) out[o++] = c->T0[3 * k + a];
+    for (int j = 0; j < 36; j++) out[o++] = c->zeta[36 * k + j];
+    for (int a = 0; a < 3; a++) out[o++] = c->trF[3 * k + a];
+    for (int a = 0; a < 3; a++) out[o++] = c->trT[3 * k + a];
+    for (int a = 0; a < 3; a++) out[o++] = c->Flast[3 * k + a];
+    for (int a = 0; a < 3; a++) out[o++] = c->Tlast[3 * k + a];
+    return OR_OK;
+}
+
+int or_step_diag(or_ctx *c, double *out)
+{
+    if (!c || !out) return OR_E_INVALID;
+    memcpy(out, c->diag, sizeof c->diag);
+    return OR_OK;
+}
+
+int or_lattice(int32_t *cvec57, double *w19)
+{
+    for (int i = 0; i < 19; i++) {
+        if (cvec57) { cvec57[3 * i] = CX[i]; cvec57[3 * i + 1] = CY[i]; cvec57[3 * i + 2] = CZ[i]; }
+        if (w19) w19[i] = wt(i);
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------ parameter maps */
+/* Eq. 10: cos(theta) = ((1+h)^(3/2) - (1-h)^(3/2)) / 2 with h = H / sqrt(kappa b),
+ * inverted for h in [-1, 1] by bisection (the right side is increasing in h). */
+double or_wetting_H(double theta_deg, double kappa, double b)
+{
+    double target = cos(theta_deg * M_PI / 180.0);
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; it++) {
+        double h = 0.5 * (lo + hi);
+        double v = 0.5 * (pow(1.0 + h, 1.5) - pow(1.0 - h, 1.5));
+        if (v < target) lo = h; else hi = h;
+    }
+    return 0.5 * (lo + hi) * sqrt(kappa * b);
+}
+
+/* solubility ratio r = <c>_oil / <c>_water of the equilibrium c0(psi) =
+ * c_b0 + E tanh(psi) (Eq. 1) at psi = -1 (oil) and +1 (water):
+ * r = (c_b0 - E tanh 1) / (c_b0 + E tanh 1). */
+double or_solubility_E(double ratio, double c_b0)
+{
+    return -c_b0 * (ratio - 1.0) / ((ratio + 1.0) * tanh(1.0));
+}

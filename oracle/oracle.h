@@ -1,0 +1,95 @@
+/* oracle.h -- plain FP64 CPU reference for one lattice update of the
+ * multiphase-multicomponent lattice Boltzmann model for self-diffusiophoretic
+ * Janus colloids at liquid-liquid interfaces (Palacios, Scagliarini,
+ * Pagonabarraga, arXiv:2202.01631).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no source,
+ * header, table or helper with the GPU solver; the two agree only on the
+ * public data formats documented below (node numbering, D3Q19 direction
+ * numbering, the link record), which are interfaces, not arithmetic.
+ *
+ * Conventions
+ *   node index      n = x + nx*(y + ny*z), periodic box, unit spacing, dt = 1
+ *   host arrays     FP64, x-fastest; vector fields are structure-of-arrays
+ *                   (component a of node n at a*N + n)
+ *   D3Q19 numbering 0:(0,0,0)
+ *                   1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1) 6:(0,0,-1)
+ *                   7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0)
+ *                   11:(+1,0,+1) 12:(-1,0,-1) 13:(+1,0,-1) 14:(-1,0,+1)
+ *                   15:(0,+1,+1) 16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1)
+ *                   (odd i >= 1 and i+1 are opposite)
+ *   link record     (colloid k, fluid node n, direction d, cap) with node
+ *                   n + c_d inside colloid k; cap = 1 on the active hemisphere
+ *                   (m.n <= 0).  Canonical order: (k, n, d) ascending.
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double rho0, tau;            /* tau = 1 gives nu = 1/6 (Sec. II.C) */
+    double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2 (Eq. 1) */
+    double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); Eq. 3a */
+    double ext_force[3];         /* uniform body force on the fluid (tests) */
+} or_params;
+
+typedef struct {
+    double pos[3], m[3], vel[3], omega[3];
+    double radius, alpha_minus, alpha_plus, mu_minus, mu_plus, H, rho_p;
+    int32_t fixed;               /* 1: position, orientation and velocities held */
+} or_colloid;
+
+typedef struct {
+    double mass, mom[3], sum_psi, sum_c;
+    int64_t n_fluid, n_links, n_active, step;
+    int32_t error_bits;
+} or_totals;
+
+/* per-step diagnostics of the last completed step (see or_step_diag) */
+enum {
+    OR_DIAG_SUM_FORCE = 0,  /* 3: sum over fluid nodes of the body force F(x) */
+    OR_DIAG_SUM_SRC = 3,    /* 1: total solute emitted this step */
+    OR_DIAG_SUM_CHI = 4,    /* 1: sum over fluid nodes of chi(t) */
+    OR_DIAG_SUM_DP = 5,     /* 3: momentum handed to all colloids through links (full u_b) */
+    OR_DIAG_SUM_TR = 8,     /* 3: momentum handed to all colloids by cover/uncover */
+    OR_DIAG_SUM_DMASS = 11, /* 1: mass change from moving-wall terms and uncovering */
+    OR_DIAG_N = 12
+};
+
+#define OR_OK 0
+#define OR_E_INVALID (-1)
+#define OR_E_UNSTABLE (-4)
+#define OR_E_STATE (-5)
+
+typedef struct or_ctx or_ctx;
+
+int or_create(const or_params *p, or_ctx **out);
+int or_destroy(or_ctx *c);
+int or_init_fields(or_ctx *c, const double *psi, const double *cc,
+                   const double *rho, const double *u);
+int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n);
+int or_step(or_ctx *c, int64_t nsteps);
+int or_get_fields(or_ctx *c, double *rho, double *u, double *psi, double *cc);
+int or_get_populations(or_ctx *c, double *f);          /* 19*N, plane-major */
+int or_set_populations(or_ctx *c, const double *f);
+int or_get_aux(or_ctx *c, double *mu, double *force, double *uforced);
+int or_get_owner(or_ctx *c, int32_t *owner);           /* -1 fluid, k solid */
+int or_get_links(or_ctx *c, int32_t *rec4, int64_t cap, int64_t *n);
+int or_observables(or_ctx *c, or_totals *t, or_colloid *out, int32_t n);
+int or_colloid_diag(or_ctx *c, int32_t k, double *out40); /* F0[3] T0[3] zeta[36] -> see .c */
+int or_step_diag(or_ctx *c, double *out);              /* OR_DIAG_N doubles */
+int or_lattice(int32_t *cvec57, double *w19);
+double or_wetting_H(double theta_deg, double kappa, double b);
+double or_solubility_E(double ratio, double c_b0);
+const char *or_last_error(const or_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

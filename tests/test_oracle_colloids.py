@@ -1,0 +1,250 @@
+"""Pins of the oracle's particle model (Sec. II.B, Eqs. 4-10): link tables
+against brute force and lattice-point counts, momentum bookkeeping of
+bounce-back on links and of the implicit rigid-body update, the rotation of
+the particle axis, Eq. 10, and the direction and linearity of
+self-diffusiophoretic swimming (Sec. III.A, Fig. 3B)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2202_01631_amd import inputs as I
+
+EPS = np.finfo(np.float64).eps
+CVEC = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                 [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+                 [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+
+
+def _min_image(d, L):
+    h = 0.5 * L
+    return np.where(d > h, d - L, np.where(d < -h, d + L, d))
+
+
+def brute_links(shape, cols):
+    """Link table by direct enumeration: every fluid node, every direction,
+    inside test |x - R|^2 < R^2 (strict) with minimum image, cap m.r <= 0 at
+    the link midpoint.  Same FP64 operation order as the published rule
+    ((dx*dx + dy*dy) + dz*dz), evaluated by numpy (no fused multiply-add)."""
+    nx, ny, nz = shape
+    X = np.stack(I.coords(shape))
+    N = X.shape[1]
+    owner = -np.ones(N, dtype=np.int64)
+    Ls = np.array(shape, dtype=np.float64)
+    for k, q in enumerate(cols):
+        d = [_min_image(X[a] - q["pos"][a], Ls[a]) for a in range(3)]
+        d2 = d[0] * d[0] + d[1] * d[1]
+        d2 = d2 + d[2] * d[2]
+        owner[d2 < q["radius"] * q["radius"]] = k
+    recs = []
+    for k, q in enumerate(cols):
+        for n in range(N):
+            if owner[n] >= 0:
+                continue
+            for dd in range(1, 19):
+                y = (X[:, n] + CVEC[dd]) % Ls
+                m = int(y[0] + nx * (y[1] + ny * y[2]))
+                if owner[m] != k:
+                    continue
+                r = [_min_image((X[a, n] + 0.5 * CVEC[dd][a]) - q["pos"][a], Ls[a]) for a in range(3)]
+                md = q["m"][0] * r[0] + q["m"][1] * r[1]
+                md = md + q["m"][2] * r[2]
+                recs.append((k, n, dd, int(md <= 0.0)))
+    return np.array(recs, dtype=np.int64).reshape(-1, 4), owner
+
+
+def test_sphere_solid_count_is_lattice_point_count():
+    # integer centre and radius R: solid nodes are the lattice points with
+    # i^2 + j^2 + k^2 < R^2, i.e. sum_{n < R^2} r3(n) (r3 = number of
+    # representations as a sum of three squares, enumerated directly)
+    def r3(n):
+        m = int(math.isqrt(n)) + 1
+        return sum(1 for i in range(-m, m + 1) for j in range(-m, m + 1) for k in range(-m, m + 1)
+                   if i * i + j * j + k * k == n)
+
+    for R, box in ((2, 12), (3, 14), (4, 16)):
+        o = oracle.Oracle((box, box, box))
+        o.init_fields(np.zeros(box ** 3), np.zeros(box ** 3))
+        o.add_colloids([dict(pos=(box / 2, box / 2, box / 2), radius=float(R))])
+        assert int((o.owner() >= 0).sum()) == sum(r3(n) for n in range(R * R))
+    assert sum(r3(n) for n in range(16)) == 251
+
+
+def test_link_table_32_box_counts():
+    # the 32^3 workload's sphere (radius 4 at (16,16,12), axis +z): 251 solid
+    # nodes, 1050 links, 561 of them on the active cap (72 exactly on the
+    # equator, m.n = 0, counted active as Eqs. 5-6 write it)
+    w = I.workload_small()
+    o = oracle.from_spec(w)
+    links = o.links()
+    assert int((o.owner() >= 0).sum()) == 251
+    assert len(links) == 1050
+    assert int(links[:, 3].sum()) == 561
+    brute, owner = brute_links(w["shape"], o.observables()[1])
+    assert np.array_equal(links, brute)
+    assert np.array_equal(o.owner(), owner)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_link_table_brute_force_random(seed):
+    # random non-integer spheres, some across the periodic boundary
+    shape = (14, 12, 13)
+    u = I.uniform(seed, 40)
+    cols = []
+    centres = [(1.3 + u[0], 2.0 + u[1], 11.5 + u[2]), (8.0 + u[3], 7.5 + u[4], 5.0 + u[5])]
+    for k, c in enumerate(centres):
+        m = I.unit_vectors(seed + 10 + k, 1)[0]
+        cols.append(dict(pos=c, m=m, radius=2.2 + u[6 + k]))
+    o = oracle.Oracle(shape)
+    o.init_fields(np.zeros(int(np.prod(shape))), np.zeros(int(np.prod(shape))))
+    o.add_colloids(cols)
+    brute, owner = brute_links(shape, o.observables()[1])
+    assert np.array_equal(o.links(), brute)
+    assert np.array_equal(o.owner(), owner)
+
+
+def _fluid_momentum(o):
+    f = o.populations()
+    fl = o.owner() < 0
+    ff = f[:, fl]
+    return np.array([math.fsum((ff * CVEC[:, a][:, None]).ravel()) for a in range(3)]), \
+        math.fsum(ff.ravel())
+
+
+def test_bounce_back_momentum_exchange_fixed_sphere():
+    # fixed sphere, uniform body force, phoretic slip on: per step the fluid
+    # momentum changes by the summed body force minus what the links hand to
+    # the particle, and the mass by the moving-wall terms -- exactly
+    shape = (14, 12, 12)
+    N = int(np.prod(shape))
+    p = dict(a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0625, E=0.0, c_b0=0.0, D_c=0.1,
+             k_d=0.01, tau=0.8, ext_force=(2e-6, -1e-6, 5e-7))
+    o = oracle.Oracle(shape, **p)
+    c0 = 0.01 * (1 + np.sin(2 * np.pi * I.coords(shape)[0] / 14))
+    o.init_fields(np.zeros(N), c0)
+    o.add_colloids([dict(pos=(6.3, 6.1, 5.7), m=(0.6, 0.0, 0.8), radius=3.1, alpha_minus=1e-3,
+                         mu_minus=0.3, mu_plus=-0.2, fixed=1)])
+    for _ in range(10):
+        pb, mb = _fluid_momentum(o)
+        o.step(1)
+        pa, ma = _fluid_momentum(o)
+        dg = o.step_diag()
+        tol = 64 * N * EPS
+        assert np.allclose(pa - pb, dg["sum_force"] - dg["sum_dp"], rtol=0, atol=tol)
+        assert abs((ma - mb) - dg["sum_dmass"]) <= tol
+    # the slip term makes the wall move: the link momentum is not just 2 f c
+    assert abs(dg["sum_dmass"]) > 0
+
+
+def test_moving_colloid_momentum_balance():
+    # free colloid launched through a quiescent fluid with cover/uncover:
+    # fluid momentum + particle momentum + pending cover/uncover transfer
+    # changes per step by the body force plus the implicit-update defect
+    # zeta (X - X'), where X = (V, Omega) before and X' after the update
+    shape = (16, 14, 14)
+    N = int(np.prod(shape))
+    p = dict(a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0625, E=0.0, c_b0=0.0, D_c=0.1,
+             k_d=0.01, tau=1.0)
+    o = oracle.Oracle(shape, **p)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    o.add_colloids([dict(pos=(5.2, 7.1, 6.9), m=(0, 0, 1), radius=3.2, vel=(0.05, 0.01, -0.02),
+                         omega=(0.0, 0.0, 0.02), rho_p=1.5, alpha_minus=1e-3, mu_minus=0.2,
+                         mu_plus=0.2)])
+    mass = 1.5 * 4.0 / 3.0 * math.pi * 3.2 ** 3
+    n_changed = 0
+    for _ in range(25):
+        ob = o.owner()
+        pb, _ = _fluid_momentum(o)
+        _, cb = o.observables()
+        trb = o.colloid_diag(0)["trF"] if o.observables()[0]["step"] > 0 else np.zeros(3)
+        Xb = np.concatenate([cb[0]["vel"], cb[0]["omega"]])
+        o.step(1)
+        pa, _ = _fluid_momentum(o)
+        _, ca = o.observables()
+        dgc = o.colloid_diag(0)
+        Xa = np.concatenate([ca[0]["vel"], ca[0]["omega"]])
+        n_changed += int((o.owner() != ob).sum())
+        lhs = (pa + mass * ca[0]["vel"] + dgc["trF"]) - (pb + mass * cb[0]["vel"] + trb)
+        rhs = o.step_diag()["sum_force"] + (dgc["zeta"] @ (Xb - Xa))[:3]
+        assert np.allclose(lhs, rhs, rtol=0, atol=256 * N * EPS)
+    assert n_changed > 0  # cover/uncover exercised
+
+
+def test_axis_rotation_and_translation():
+    # after one step the axis is the old one rotated by |Omega'| about Omega'
+    # (rotation vector Omega' dt, dt = 1), and the centre moved by V'
+    shape = (14, 14, 14)
+    N = 14 ** 3
+    o = oracle.Oracle(shape, C=0.0625, D_c=0.1, k_d=0.01)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    m0 = np.array([0.3, -0.5, 0.8])
+    m0 /= np.linalg.norm(m0)
+    o.add_colloids([dict(pos=(6.0, 7.0, 7.5), m=m0, radius=3.0, omega=(0.03, -0.02, 0.05),
+                         vel=(0.01, 0.0, 0.0))])
+    _, c0 = o.observables()
+    o.step(1)
+    _, c1 = o.observables()
+    want = Rotation.from_rotvec(c1[0]["omega"]).apply(c0[0]["m"])
+    assert np.allclose(c1[0]["m"], want, rtol=0, atol=8 * EPS)
+    assert np.allclose(c1[0]["pos"], c0[0]["pos"] + c1[0]["vel"], rtol=0, atol=32 * EPS)
+
+
+def test_contact_angle_map_eq10():
+    # Eq. 10: cos(theta) = ((1+h)^1.5 - (1-h)^1.5)/2, h = H/sqrt(kappa A);
+    # neutral wetting at H = 0; the map is odd about 90 degrees; round trip
+    kappa, b = 0.04, 0.0625
+    assert oracle.wetting_H(90.0, kappa, b) == pytest.approx(0.0, abs=1e-15)
+    for th in (30.0, 45.0, 60.0, 75.0, 100.0, 120.0, 135.0, 150.0):
+        H = oracle.wetting_H(th, kappa, b)
+        h = H / math.sqrt(kappa * b)
+        assert 0.5 * ((1 + h) ** 1.5 - (1 - h) ** 1.5) == pytest.approx(math.cos(math.radians(th)), abs=1e-13)
+        assert oracle.wetting_H(180.0 - th, kappa, b) == pytest.approx(-H, abs=1e-14)
+        assert (H > 0) == (th < 90.0)  # theta < 90: oil (psi = -1) wets, H > 0
+    # h = 1 is the end of the range: cos(theta) = 2^1.5/2 = sqrt 2 > 1 is
+    # never reached; theta = 0 sits inside it
+    assert 0.5 < oracle.wetting_H(0.0, kappa, b) / math.sqrt(kappa * b) < 1.0
+
+
+def test_solubility_map():
+    # oil/water ratio of c0(psi) = c_b0 + E tanh(psi) at psi = -1 / +1
+    for r in (1.0, 2.0, 5.0):
+        E = oracle.solubility_E(r, 0.5)
+        th = math.tanh(1.0)
+        assert (0.5 - E * th) / (0.5 + E * th) == pytest.approx(r, rel=1e-14)
+    assert oracle.solubility_E(1.0, 0.5) == 0.0
+
+
+def test_self_propulsion_direction_and_linearity():
+    # single-phase fluid, Janus sphere emitting on the m.n <= 0 cap: the
+    # solute piles up behind, and a repulsive (mu > 0) particle swims along
+    # +m (Sec. II.B).  Held in place, the propulsive force it exerts is
+    # linear in the mobility (low Peclet number: the slip is linear in mu and
+    # the flow linear in the slip; Eq. 7, Fig. 3B).  The prefactor of Eq. 7 is
+    # not pinned: the lattice activity is per link, the paper's a surface flux.
+    shape = (20, 20, 20)
+    N = 8000
+    m = np.array([1.0, 0.5, 0.3])
+    m /= np.linalg.norm(m)
+    force = {}
+    for mu in (0.1, 0.2, -0.1):
+        o = oracle.Oracle(shape, C=0.0625, D_c=0.1, k_d=0.01)
+        o.init_fields(np.zeros(N), np.zeros(N))
+        o.add_colloids([dict(pos=(10.3, 9.8, 10.1), m=m, radius=3.0, alpha_minus=1e-3,
+                             mu_minus=mu, mu_plus=mu, fixed=1)])
+        o.step(60)
+        force[mu] = o.colloid_diag(0)["F"]
+    f1 = force[0.1]
+    assert f1 @ m > 0.9 * np.linalg.norm(f1)  # along +m
+    # the O(Pe) advective nonlinearity is below 1% here
+    assert np.linalg.norm(force[0.2] - 2.0 * f1) < 0.01 * np.linalg.norm(f1)
+    assert np.linalg.norm(force[-0.1] + f1) < 0.01 * np.linalg.norm(f1)
+    # and free, it swims along +m
+    o = oracle.Oracle(shape, C=0.0625, D_c=0.1, k_d=0.01)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    o.add_colloids([dict(pos=(10.3, 9.8, 10.1), m=m, radius=3.0, alpha_minus=1e-3,
+                         mu_minus=0.1, mu_plus=0.1)])
+    o.step(60)
+    v = o.observables()[1][0]["vel"]
+    assert v @ m > 0.9 * np.linalg.norm(v)

@@ -1,0 +1,151 @@
+"""Pins of the oracle's solvent: D3Q19 lattice, BGK collision with Guo forcing,
+streaming.  Each check compares against something the lattice-Boltzmann
+theory or plain mechanics fixes, not against the oracle's own formulas."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_01631_amd import inputs as I
+
+EPS = np.finfo(np.float64).eps
+
+
+def test_d3q19_isotropy():
+    # moments of the discrete velocity set up to fourth order equal those of
+    # the Maxwellian with c_s^2 = 1/3 (textbook D3Q19 property)
+    c, w = oracle.lattice()
+    c = c.astype(np.float64)
+    assert np.isclose(w.sum(), 1.0, atol=1e-15)
+    assert np.allclose(w @ c, 0.0, atol=1e-15)
+    M2 = np.einsum("i,ia,ib->ab", w, c, c)
+    assert np.allclose(M2, np.eye(3) / 3.0, atol=1e-15)
+    M3 = np.einsum("i,ia,ib,ic->abc", w, c, c, c)
+    assert np.allclose(M3, 0.0, atol=1e-15)
+    M4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9.0
+    assert np.allclose(M4, iso, atol=1e-15)
+    # numbering: 0 at rest, (odd i, i+1) opposite pairs, 6 faces then 12 edges
+    assert np.all(c[0] == 0)
+    for i in range(1, 19, 2):
+        assert np.all(c[i] == -c[i + 1])
+    assert np.all(np.abs(c[1:7]).sum(axis=1) == 1)
+    assert np.all(np.abs(c[7:]).sum(axis=1) == 2)
+
+
+def _single_phase(shape, **kw):
+    return oracle.Oracle(shape, **kw)
+
+
+def test_rest_state_is_fixed_point():
+    shape = (6, 5, 4)
+    N = 120
+    o = _single_phase(shape)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    f0 = o.populations().copy()
+    o.step(20)
+    assert np.abs(o.populations() - f0).max() <= 4 * EPS
+
+
+def test_uniform_flow_is_fixed_point():
+    # Galilean-invariant uniform state of BGK with the equilibrium as initial
+    # condition and no force: it must stay put
+    shape = (5, 4, 6)
+    N = 120
+    u0 = np.array([0.03, -0.02, 0.01])
+    u = np.repeat(u0[:, None], N, axis=1)
+    o = _single_phase(shape, tau=0.8)
+    o.init_fields(np.zeros(N), np.zeros(N), None, u)
+    f0 = o.populations().copy()
+    o.step(25)
+    assert np.abs(o.populations() - f0).max() <= 16 * EPS
+    assert np.allclose(o.fields()["u"], u, atol=1e-15)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.7])
+def test_uniform_force_closed_form(tau):
+    # uniform body force on a uniform periodic fluid: the momentum grows by F
+    # per node per step exactly, and the forcing-corrected velocity after t
+    # steps is (t + 1/2) F / rho
+    shape = (4, 3, 5)
+    N = 60
+    F = np.array([1e-5, -2e-5, 3e-6])
+    o = _single_phase(shape, tau=tau, ext_force=F)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    for t in range(1, 11):
+        o.step(1)
+        tot, _ = o.observables()
+        # rounding bound: a sum of 19 N populations of size <= 1/3, t steps
+        assert np.allclose(tot["mom"], N * t * F, rtol=0, atol=19 * N * t * EPS)
+        uf = o.aux()["u"]  # velocity used in step t (state at t-1)
+        assert np.allclose(uf, ((t - 1) + 0.5) * F[:, None], rtol=0, atol=19 * t * EPS)
+        assert abs(tot["mass"] - N) < 1e-12
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+@pytest.mark.parametrize("axes", [(0, 2), (1, 0), (2, 1)])
+def test_shear_wave_decay(tau, axes):
+    # u_a = U0 sin(2 pi s / L) along axis s decays as exp(-nu k^2 t) with
+    # nu = (tau - 1/2)/3 (BGK viscosity; tau = 1 gives the paper's nu = 1/6)
+    a, s = axes
+    L = 32
+    shape = [2, 2, 2]
+    shape[s] = L
+    shape = tuple(shape)
+    N = int(np.prod(shape))
+    xs = I.coords(shape)[s]
+    U0 = 1e-6
+    u = np.zeros((3, N))
+    u[a] = U0 * np.sin(2 * np.pi * xs / L)
+    o = _single_phase(shape, tau=tau)
+    o.init_fields(np.zeros(N), np.zeros(N), None, u)
+    nst = 300
+    o.step(nst)
+    ua = o.fields()["u"][a]
+    amp = 2.0 * np.mean(ua * np.sin(2 * np.pi * xs / L))
+    nu = (tau - 0.5) / 3.0
+    k = 2 * np.pi / L
+    assert abs(amp / U0 / math.exp(-nu * k * k * nst) - 1.0) < 0.01
+
+
+def _exact_totals(o):
+    """Exactly rounded sums (math.fsum) of the state over fluid nodes, so that
+    the balance checks below see the update's rounding and not the
+    summation's."""
+    f = o.populations()
+    flds = o.fields()
+    c, _ = oracle.lattice()
+    fluid = o.owner() < 0
+    ff = f[:, fluid]
+    mass = math.fsum(ff.ravel())
+    mom = np.array([math.fsum((ff * c[:, a][:, None]).ravel()) for a in range(3)])
+    return mass, mom, math.fsum(flds["psi"][fluid]), math.fsum(flds["c"][fluid])
+
+
+def test_mass_and_momentum_balance_with_free_energy_force():
+    # no particles: mass exact; momentum changes by the summed body force each
+    # step (Guo forcing injects exactly F per node); sum of psi exact; the sum
+    # of c changes by the sink only (Eq. 3a with no source)
+    shape = (12, 10, 8)
+    N = int(np.prod(shape))
+    psi = I.slab(shape, I.WIDTH, amp=0.05, seed=11)
+    c = 0.2 + I.noise(12, N, 0.05)
+    p = dict(I.FREE_ENERGY)
+    p["E"] = -0.2
+    o = oracle.Oracle(shape, **p)
+    o.init_fields(psi, c)
+    m0, _, s0, _ = _exact_totals(o)
+    # per-node rounding of one update is a few ulps of O(1) quantities
+    tol = 32 * N * EPS
+    for _ in range(15):
+        mb, pb, sb, cb = _exact_totals(o)
+        o.step(1)
+        ma, pa, sa, ca = _exact_totals(o)
+        dg = o.step_diag()
+        assert abs(ma - m0) <= tol
+        assert np.allclose(pa - pb, dg["sum_force"], rtol=0, atol=tol)
+        assert abs(sa - s0) <= tol
+        assert abs((ca - cb) - (dg["sum_src"] - p["k_d"] * dg["sum_chi"])) <= tol
