@@ -1,0 +1,164 @@
+"""Benchmark of the lattice update on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: a 256^3 periodic box, planar interface with noise, 64 Janus spheres
+of radius 6 (32 on the interface, 32 near it), moving, FP32 shifted
+population storage; every step is the whole update (chemical potential,
+collide-stream, psi/c update, bounce-back links and particle update, cover/
+uncover, geometry).  Inputs are resident in HBM before timing.  Prints one
+JSON line; the same workload in FP64 (the plain double-precision form) and in
+FP16 storage is timed beside it, and the FP64 CPU oracle is timed on one step
+of it on the host (cpu_baseline).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("MLUPS & % HBM roofline (256³ FP32 vs FP64 plain); batched sweep p50/p99")
+# algorithmic bytes per lattice update: 19 populations and psi, c read once
+# and written once (storage bytes 8 / 4 / 2, psi and c in the compute type)
+STEP_BYTES = {"fp64": 19 * 2 * 8 + 2 * 2 * 8, "fp32": 19 * 2 * 4 + 2 * 2 * 4,
+              "fp16": 19 * 2 * 2 + 2 * 2 * 4}
+# the collide-stream kernel alone moves the populations: 19 read + 19 written
+COLLIDE_BYTES = {"fp64": 19 * 2 * 8, "fp32": 19 * 2 * 4, "fp16": 19 * 2 * 2}
+KERNELS = ("k_mu", "k_collide", "k_scalar", "k_links_colloid", "k_cover", "k_commit+k_links")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_box256_fp32_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lb_kernels.hip", "lb_device.h", "lb_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2202_01631_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_gpu(spec, precision, steps, warmup, torch, lb):
+    stream = torch.cuda.current_stream()
+    arena = torch.empty(lb.footprint_bytes(spec["shape"], precision), dtype=torch.uint8,
+                        device="cuda")
+    box = lb.from_spec(spec, precision=precision, arena=arena, stream=stream)
+    box.step(warmup)
+    torch.cuda.synchronize()
+    box.timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    box.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kms, calls = box.timing_read()
+    tot, _ = box.observables(check=False)
+    box.timing_enable(False)
+    box.close()
+    del arena
+    torch.cuda.synchronize()
+    N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
+    per_kernel = {KERNELS[i]: (kms[i] / calls[i] if calls[i] else None) for i in range(6)}
+    return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
+                kernel_ms=per_kernel, error_bits=tot["error_bits"], N=N)
+
+
+def cpu_baseline(spec):
+    import oracle
+    log("[bench] cpu baseline: FP64 oracle, 1 step of the workload")
+    t0 = time.time()
+    o = oracle.from_spec(spec)
+    t1 = time.time()
+    o.step(1)
+    t2 = time.time()
+    N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
+    o.close()
+    return dict(value=round(N / (t2 - t1) / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                sample="1 time step of the full 256^3 64-sphere workload, FP64 oracle, "
+                       "single thread (setup %.1f s excluded, step %.1f s)" % (t1 - t0, t2 - t1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2202_01631_amd import inputs as I
+    from paper_2202_01631_amd import lb
+    lb.load()
+    torch.cuda.set_device(0)
+    n = args.size
+    spec = I.workload_many(n=n, count=64, radius=6.0, precision="fp32")
+    res = {}
+    precs = [args.only] if args.only else ["fp32", "fp64", "fp16"]
+    for prec in precs:
+        log("[bench] %d^3 %s: warmup %d, timed %d" % (n, prec, args.warmup, args.steps))
+        res[prec] = time_gpu(spec, prec, args.steps, args.warmup, torch, lb)
+        log("[bench] %s: %.3f ms/step, %.0f MLUPS, kernels %s" % (
+            prec, res[prec]["ms_per_step"], res[prec]["mlups"], res[prec]["kernel_ms"]))
+    main_prec = precs[0]
+    r = res[main_prec]
+    N = r["N"]
+    kc = r["kernel_ms"]["k_collide"]
+    achieved = COLLIDE_BYTES[main_prec] * N / (kc * 1e-3) / 1e9
+    traffic = None
+    if main_prec == "fp32" and os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_source_hash") == kernel_source_hash() and t.get("size") == n:
+            traffic = t.get("bytes_per_launch")
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32"}[main_prec],
+        "data": "synthetic",
+        "config": {"workload": "box%d_64spheres_%s" % (n, main_prec), "shape": [n, n, n],
+                   "spheres": 64, "radius": 6.0, "precision": main_prec,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_collide",
+                     "bytes_per_lu": COLLIDE_BYTES[main_prec]},
+        "step_roofline": {p: {"mlups": round(v["mlups"], 1),
+                              "algorithmic_GBs": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9, 1),
+                              "frac": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_per_lu": STEP_BYTES[p],
+                              "kernel_ms": {k: (round(x, 5) if x else None)
+                                            for k, x in v["kernel_ms"].items()},
+                              "error_bits": v["error_bits"]} for p, v in res.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

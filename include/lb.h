@@ -1,0 +1,211 @@
+/* lb.h -- C ABI of the MI355X (gfx950) lattice update of the
+ * multiphase-multicomponent lattice Boltzmann model for self-diffusiophoretic
+ * Janus colloids at liquid-liquid interfaces
+ * (Palacios, Scagliarini, Pagonabarraga, arXiv:2202.01631).
+ *
+ * One context = one periodic box resident in GPU memory.  Each lb_step
+ * advances it by one time step of the paper's model (Sec. II, Eqs. 1-10):
+ *   1. chemical potential mu_psi of Eq. 2, with the wetting condition of
+ *      Eqs. 8-9 as a ghost value at particle faces;
+ *   2. D3Q19 BGK collision (tau; nu = (tau-1/2)/3, 1/6 at tau = 1, Sec. II.C)
+ *      under the free-energy body force F = -psi grad(mu_psi) with the
+ *      forcing term of Guo, Zheng and Shi (2002); push streaming;
+ *   3. bounce-back on links with the moving-wall term, the wall velocity
+ *      being V + Omega x r plus the phoretic slip of Eq. 4 with the Janus
+ *      mobility of Eq. 6; momentum exchange summed per particle (Sec. II.B);
+ *   4. explicit updates of psi (Cahn-Hilliard, Eq. 3b) and of the solute c
+ *      (advection-diffusion with the sink k_d and the Janus production of
+ *      Eq. 5 emitted per active link, Eq. 3a);
+ *   5. rigid-body update of every particle, implicit in the link drag;
+ *   6. particle geometry at the new positions: cover/uncover repair, owner
+ *      map, link table.
+ *
+ * All functions return an lb_status; no exception crosses the ABI.
+ * lb_last_error() gives a message for the last failure on a context.
+ *
+ * Conventions
+ *   node index      n = x + nx*(y + ny*z), periodic box, unit spacing, dt = 1.
+ *   host arrays     caller-owned, FP64 whatever the storage precision,
+ *                   x-fastest; vector fields are structure-of-arrays
+ *                   (component a of node n at a*N + n, N = nx*ny*nz).  The
+ *                   library copies in and out and keeps no host pointer.
+ *   D3Q19 numbering 0:(0,0,0)
+ *                   1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1) 6:(0,0,-1)
+ *                   7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0)
+ *                   11:(+1,0,+1) 12:(-1,0,-1) 13:(+1,0,-1) 14:(-1,0,+1)
+ *                   15:(0,+1,+1) 16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1)
+ *                   (odd i >= 1 and i+1 are opposite); weights 1/3, 1/18, 1/36.
+ *   links           (particle k, fluid node n, direction d, cap): node n + c_d
+ *                   lies strictly inside particle k; cap = 1 when the link
+ *                   midpoint is on the active hemisphere m.n <= 0 (Eqs. 5-6).
+ *                   Canonical order (k, n, d) ascending.
+ *   device memory   the context owns its device state.  If the caller hands
+ *                   in an arena (e.g. a torch uint8 tensor), the context only
+ *                   borrows it; it must outlive lb_destroy.
+ *   streams         work is enqueued on the stream given to lb_create (NULL:
+ *                   the default stream).  One context per stream; no internal
+ *                   locking.  Calls that return host data synchronise that
+ *                   stream.
+ *   call order      lb_create -> lb_init_fields -> [lb_add_colloids] ->
+ *                   lb_step* ; violations return LB_E_STATE.
+ */
+#ifndef LB_H
+#define LB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_E_INVALID = -1,  /* bad argument or parameter (incl. stability bounds) */
+    LB_E_OOM = -2,      /* device allocation failed or arena too small */
+    LB_E_DEVICE = -3,   /* HIP runtime error */
+    LB_E_UNSTABLE = -4, /* NaN/Inf seen in the FP64 totals */
+    LB_E_STATE = -5     /* call order, particle overlap/contact, link overflow */
+} lb_status;
+
+typedef enum {
+    LB_FP64 = 0,        /* populations, psi, c and arithmetic in FP64 */
+    LB_FP32 = 1,        /* populations stored as f_i - w_i rho0 in FP32, FP32 arithmetic */
+    LB_FP16_STORAGE = 2 /* (f_i - w_i rho0) * f16_scale stored in IEEE half, FP32 arithmetic */
+} lb_precision;
+
+/* error bits reported in lb_totals.error_bits */
+#define LB_ERR_NAN 1        /* non-finite FP64 totals */
+#define LB_ERR_FAST 2       /* a particle moved 0.5 or more lattice units in one step */
+#define LB_ERR_CONTACT 4    /* two particles claim one node, or touch */
+#define LB_ERR_LINKS 8      /* link table of a particle overflowed its capacity */
+
+typedef struct {
+    int32_t nx, ny, nz;          /* periodic box */
+    int32_t precision;           /* lb_precision */
+    double rho0, tau;            /* rest density, BGK relaxation time (> 1/2) */
+    double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2, Eq. 1
+                                    (the paper's B = a < 0 < A = b); psi mobility */
+    double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); solute
+                                    diffusivity D_c (= C M_c) and sink rate (Eq. 3a) */
+    double ext_force[3];         /* uniform body force on the fluid (0 in the paper) */
+    double f16_scale;            /* FP16 storage scale, a power of two; 0 -> 16384 */
+    int32_t max_colloids;        /* particle capacity, <= 255; 0 -> 64 */
+    uint32_t flags;              /* reserved, 0 */
+} lb_params;
+
+typedef struct {                 /* FP64, caller-owned */
+    double pos[3], m[3], vel[3], omega[3]; /* centre, axis (normalised on add), V, Omega */
+    double radius;
+    double alpha_minus, alpha_plus;  /* production per link on the m.n <= 0 / > 0 cap (Eq. 5) */
+    double mu_minus, mu_plus;        /* phoretic mobility on the two caps (Eq. 6) */
+    double H;                        /* wetting parameter of Eqs. 8-9 (lb_wetting_H) */
+    double rho_p;                    /* particle density: mass rho_p 4/3 pi R^3 */
+    int32_t fixed;                   /* 1: position, axis and velocities held */
+} lb_colloid;
+
+typedef struct {
+    double mass, mom[3], sum_psi, sum_c; /* FP64 sums over fluid nodes of sum_i f_i,
+                                            sum_i f_i c_i, psi, c */
+    int64_t n_fluid, n_links, n_active, step;
+    int32_t error_bits;                  /* LB_ERR_* */
+} lb_totals;
+
+typedef struct lb_ctx lb_ctx; /* opaque */
+
+/* Device bytes lb_create needs for a box with these parameters (the lattice
+ * fields; particle tables are allocated by lb_add_colloids).
+ * Errors: LB_E_INVALID for a NULL argument or a non-positive box size. */
+lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes);
+
+/* Validate p and create a context for one box.  Checks: box sizes >= 1,
+ * tau > 1/2, rho0 > 0, kappa, M_psi, C, D_c, k_d >= 0, explicit-Euler
+ * stability of the psi and c updates, M_psi (12|a| + 36|b| + 144 kappa) < 2
+ * and 12 D_c + k_d < 2 (LB_E_INVALID otherwise).  dev_arena: device memory
+ * of at least lb_footprint_bytes (borrowed), or NULL for the library to
+ * allocate it (LB_E_OOM if it cannot).  hip_stream: a hipStream_t, or NULL
+ * for the default stream.  *out receives the context. */
+lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes,
+                    void *hip_stream, lb_ctx **out);
+
+/* Free the context and everything the library allocated for it. */
+lb_status lb_destroy(lb_ctx *ctx);
+
+/* Set the state (Sec. II.C, initial condition): psi and c (N each,
+ * required), density rho (N, NULL -> rho0) and velocity u (3N SoA, NULL ->
+ * 0); populations start at the second-order equilibrium f_i^eq(rho, u).
+ * Converts to the storage precision with round-to-nearest-even.  Removes any
+ * particles and resets the step counter.  LB_E_INVALID on NULL psi/c or a
+ * non-finite or non-positive value. */
+lb_status lb_init_fields(lb_ctx *ctx, const double *psi, const double *c,
+                         const double *rho, const double *u);
+
+/* Place n particles (Sec. II.B) at their given state; nodes strictly inside
+ * a sphere become solid.  The axis m is normalised.  LB_E_INVALID for
+ * radius, rho_p or |m| <= 0, wetting H != 0 with kappa = 0, 2 radius + 8
+ * larger than a box side, n above max_colloids; LB_E_STATE when two
+ * surfaces come closer than 2 lattice units or before lb_init_fields.
+ * Replaces any previous particles. */
+lb_status lb_add_colloids(lb_ctx *ctx, const lb_colloid *cols, int32_t n);
+
+/* Enqueue nsteps time steps on the context's stream and return (no host
+ * synchronisation).  Device-side failures are reported by lb_observables. */
+lb_status lb_step(lb_ctx *ctx, int64_t nsteps);
+
+/* Synchronise and read the FP64 totals (may be NULL) and the state of the
+ * first n particles (out may be NULL).  Returns LB_E_UNSTABLE when the
+ * totals are not finite, LB_E_STATE when error bits are set (the totals are
+ * filled in either case). */
+lb_status lb_observables(lb_ctx *ctx, lb_totals *t, lb_colloid *out, int32_t n);
+
+/* FP64 host copies of the fields (any pointer may be NULL): rho = sum_i f_i
+ * and u = sum_i f_i c_i / rho (N and 3N; 0 at solid nodes), psi and c (N;
+ * solid nodes keep their last fluid value). */
+lb_status lb_get_fields(lb_ctx *ctx, double *rho, double *u, double *psi, double *c);
+
+/* FP64 host copy of the populations f_i (19 planes of N, plane-major),
+ * reconstructed from storage (f = stored/scale + w_i rho0). */
+lb_status lb_get_populations(lb_ctx *ctx, double *f);
+
+/* Owner map: -1 fluid, k for a node inside particle k (int32, N). */
+lb_status lb_get_owner(lb_ctx *ctx, int32_t *owner);
+
+/* Link table for the current particle positions, canonical order, as
+ * records (k, n, d, cap) of int32.  *n receives the count; rec4 may be NULL
+ * to query it; LB_E_INVALID if cap is smaller than the count. */
+lb_status lb_get_links(lb_ctx *ctx, int32_t *rec4, int64_t cap, int64_t *n);
+
+/* Per particle k, 12 FP64 values: force and torque acting on it in the last
+ * step (F0 - zeta X', including cover/uncover transfers) and the part F0,
+ * T0 of the link momentum that does not depend on its velocity. */
+lb_status lb_colloid_forces(lb_ctx *ctx, double *out12, int32_t n);
+
+/* Raw state for bitwise resume: stored populations, psi, c, owner map,
+ * particle tables and step counter.  *n receives the size in bytes; buf may
+ * be NULL to query it.  lb_load_state requires the same parameters. */
+lb_status lb_save_state(lb_ctx *ctx, void *buf, size_t cap, size_t *n);
+lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
+
+/* Per-kernel timing on the context's stream with HIP events, for the
+ * benchmark: enable resets the accumulators; lb_timing_read fills ms[i] with
+ * the summed duration and calls[i] with the launch count of kernel i
+ * (0 mu, 1 collide-stream, 2 psi/c update, 3 links+particles, 4 cover,
+ * 5 geometry), synchronising the stream. */
+lb_status lb_timing_enable(lb_ctx *ctx, int32_t on);
+lb_status lb_timing_read(lb_ctx *ctx, double *ms6, int64_t *calls6);
+
+/* Message for the last failure on ctx (thread-local text; never NULL). */
+const char *lb_last_error(const lb_ctx *ctx);
+
+/* Host helpers for parameters given through derived quantities.
+ * lb_wetting_H: H of Eqs. 9-10 for a contact angle in degrees,
+ *   cos(theta) = ((1+h)^(3/2) - (1-h)^(3/2))/2, h = H / sqrt(kappa b),
+ *   solved for h in [-1, 1] by bisection; NaN if kappa b <= 0.
+ * lb_solubility_E: E of Eq. 1 giving an oil/water ratio of the equilibrium
+ *   solute c0(psi) = c_b0 + E tanh psi at psi = -1 and +1. */
+double lb_wetting_H(double theta_deg, double kappa, double b);
+double lb_solubility_E(double ratio, double c_b0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

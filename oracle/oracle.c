@@ -17,7 +17,7 @@
  *     gives the paper's nu = 1/6, Sec. II.C), second-order equilibrium, forcing
  *     term of Guo, Zheng and Shi (2002); body force F = -psi grad(mu_psi), the
  *     usual potential form of the free-energy force ("thermohydrodynamic"
- *     model, Sec. I);
+ *     model, Sec. I), with the isotropic 18-neighbour lattice gradient;
  *   - psi and c: explicit Euler finite volumes on the lattice, 7-point
  *     Laplacian, central face fluxes for advection (Eq. 3);
  *   - particles: bounce-back on links with the moving-wall term, momentum
@@ -457,11 +457,19 @@ static void collide_stream(or_ctx *c)
             for (int a = 0; a < 3; a++) { c->force[a * N + n] = 0.0; c->uf[a * N + n] = 0.0; }
             continue;
         }
-        /* body force -psi grad(mu) with central differences */
-        double F[3];
+        /* body force -psi grad(mu), gradient by the isotropic lattice
+         * stencil grad(mu) = 3 sum_i w_i c_i mu(x + c_i) (reading: the central
+         * 2-point difference makes the explicit force/advection coupling
+         * unstable at grid scale when kappa > 0) */
+        double gm[3] = {0.0, 0.0, 0.0}, F[3];
+        for (int i = 1; i < 19; i++) {
+            double mi = hat(c, c->mu, n, nbr(c, n, i));
+            gm[0] += wt(i) * CX[i] * mi;
+            gm[1] += wt(i) * CY[i] * mi;
+            gm[2] += wt(i) * CZ[i] * mi;
+        }
         for (int a = 0; a < 3; a++) {
-            long mp = nbr(c, n, 1 + 2 * a), mm = nbr(c, n, 2 + 2 * a);
-            F[a] = -c->psi[n] * (hat(c, c->mu, n, mp) - hat(c, c->mu, n, mm)) / 2.0 + p->ext_force[a];
+            F[a] = -c->psi[n] * 3.0 * gm[a] + p->ext_force[a];
             sumF[a] += F[a];
         }
         double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};

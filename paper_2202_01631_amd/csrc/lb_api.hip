@@ -1,0 +1,752 @@
+// lb_api.hip -- host side of the C ABI in include/lb.h: parameter checks,
+// device memory layout, per-step launch sequence, readback.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb_kernels.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;  // message when no context is at hand
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t storage_bytes(int prec) { return prec == LB_FP64 ? 8 : (prec == LB_FP32 ? 4 : 2); }
+size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
+
+// Arena layout (each piece 256-byte aligned): f[2] (19 N storage), psi[2],
+// c[2], mu (N compute), u (3N compute), owner (N bytes).
+struct Layout {
+    size_t f[2], psi[2], cc[2], mu, u, own, total;
+};
+
+Layout layout_of(const lb_params &p)
+{
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    const size_t sb = storage_bytes(p.precision), cb = compute_bytes(p.precision);
+    Layout L;
+    size_t o = 0;
+    for (int b = 0; b < 2; b++) { L.f[b] = o; o = align256(o + 19 * N * sb); }
+    for (int b = 0; b < 2; b++) { L.psi[b] = o; o = align256(o + N * cb); }
+    for (int b = 0; b < 2; b++) { L.cc[b] = o; o = align256(o + N * cb); }
+    L.mu = o; o = align256(o + N * cb);
+    L.u = o; o = align256(o + 3 * N * cb);
+    L.own = o; o = align256(o + N);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    KParams kp;
+    long long N;
+    hipStream_t stream;
+    bool own_arena;
+    char *arena;
+    Layout L;
+    int cur;
+    int stage;  // 0 created, 1 fields, 2 colloids
+    int64_t step;
+    // particles
+    int ncol, maxcol, lcap;
+    DColloid *dcol;
+    int *lnode;
+    uint8_t *ldc;
+    int *derr;
+    double *part;   // reduction partials
+    double *dsum;   // 7 totals
+    int nred;
+    TimingHook *timing;
+    std::string err;
+};
+
+static lb_status fail(lb_ctx *c, lb_status s, const std::string &m)
+{
+    if (c) c->err = m; else g_err = m;
+    return s;
+}
+
+static lb_status hip_fail(lb_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, LB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, call)                                                                           \
+    do {                                                                                           \
+        hipError_t _e = (call);                                                                    \
+        if (_e != hipSuccess) return hip_fail((c), _e, #call);                                     \
+    } while (0)
+
+static void *ptr(lb_ctx *c, size_t off) { return c->arena + off; }
+
+static StepBuffers buffers(lb_ctx *c)
+{
+    StepBuffers b;
+    const int cu = c->cur, nx = 1 - c->cur;
+    b.fin = ptr(c, c->L.f[cu]);
+    b.fout = ptr(c, c->L.f[nx]);
+    b.psi = ptr(c, c->L.psi[cu]);
+    b.cc = ptr(c, c->L.cc[cu]);
+    b.psin = ptr(c, c->L.psi[nx]);
+    b.ccn = ptr(c, c->L.cc[nx]);
+    b.mu = ptr(c, c->L.mu);
+    b.u = ptr(c, c->L.u);
+    b.own = (uint8_t *)ptr(c, c->L.own);
+    b.col = c->dcol;
+    b.lnode = c->lnode;
+    b.ldc = c->ldc;
+    b.lcap = c->lcap;
+    b.err = c->derr;
+    return b;
+}
+
+// ---------------------------------------------------------------- timing
+hipEvent_t TimingHook::take()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+void TimingHook::begin(int i, hipStream_t s)
+{
+    hipEvent_t e = take();
+    if (e) { hipEventRecord(e, s); open[i].push_back(e); }
+}
+void TimingHook::end(int i, hipStream_t s)
+{
+    if (open[i].empty()) return;
+    hipEvent_t b = open[i].back();
+    open[i].pop_back();
+    hipEvent_t e = take();
+    if (!e) { pool.push_back(b); return; }
+    hipEventRecord(e, s);
+    done[i].push_back(std::make_pair(b, e));
+}
+void TimingHook::flush()
+{
+    for (int i = 0; i < 6; i++) {
+        for (auto &pr : done[i]) {
+            float t = 0.f;
+            hipEventSynchronize(pr.second);
+            if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+                ms[i] += t;
+                calls[i]++;
+            }
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+        }
+        done[i].clear();
+    }
+}
+void TimingHook::reset()
+{
+    flush();
+    for (int i = 0; i < 6; i++) { ms[i] = 0.0; calls[i] = 0; }
+}
+TimingHook::~TimingHook()
+{
+    for (int i = 0; i < 6; i++) {
+        for (auto &pr : done[i]) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+        for (auto e : open[i]) hipEventDestroy(e);
+    }
+    for (auto e : pool) hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------- dispatch
+template <int P> static void step_once(lb_ctx *c)
+{
+    StepBuffers b = buffers(c);
+    launch_step_lattice<P>(c->kp, b, c->stream, c->timing);
+    launch_step_particles<P>(c->kp, b, c->ncol, c->stream, c->timing);
+}
+
+static void dispatch_step(lb_ctx *c)
+{
+    switch (c->p.precision) {
+    case LB_FP64: step_once<LB_FP64>(c); break;
+    case LB_FP32: step_once<LB_FP32>(c); break;
+    default: step_once<LB_FP16_STORAGE>(c); break;
+    }
+}
+
+// ------------------------------------------------------------- checks
+static lb_status check_params(const lb_params *p, std::string &why)
+{
+    if (!p) { why = "null parameters"; return LB_E_INVALID; }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "box sizes must be >= 1"; return LB_E_INVALID; }
+    if ((double)p->nx * p->ny * p->nz >= 2147483647.0) { why = "box too large (N >= 2^31)"; return LB_E_INVALID; }
+    if (p->nz > 65535) { why = "nz > 65535"; return LB_E_INVALID; }
+    if (p->precision < LB_FP64 || p->precision > LB_FP16_STORAGE) { why = "bad precision"; return LB_E_INVALID; }
+    if (!(p->tau > 0.5)) { why = "tau must exceed 1/2"; return LB_E_INVALID; }
+    if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return LB_E_INVALID; }
+    if (p->kappa < 0 || p->M_psi < 0 || p->C < 0 || p->D_c < 0 || p->k_d < 0) {
+        why = "kappa, M_psi, C, D_c, k_d must be >= 0";
+        return LB_E_INVALID;
+    }
+    if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
+        why = "M_psi above the explicit-Euler stability bound M (12|a| + 36|b| + 144 kappa) < 2";
+        return LB_E_INVALID;
+    }
+    if (12.0 * p->D_c + p->k_d >= 2.0) { why = "12 D_c + k_d must be < 2"; return LB_E_INVALID; }
+    if (p->max_colloids < 0 || p->max_colloids > MAX_COLLOIDS) { why = "max_colloids in [0, 127]"; return LB_E_INVALID; }
+    if (p->precision == LB_FP16_STORAGE && p->f16_scale != 0.0) {
+        int e;
+        double m = frexp(p->f16_scale, &e);
+        if (!(p->f16_scale > 0.0) || m != 0.5) { why = "f16_scale must be a power of two"; return LB_E_INVALID; }
+    }
+    return LB_OK;
+}
+
+template <int P> static void reduce_t(lb_ctx *c)
+{
+    launch_reduce<P>(c->kp, ptr(c, c->L.f[c->cur]), ptr(c, c->L.psi[c->cur]), ptr(c, c->L.cc[c->cur]),
+                     (const uint8_t *)ptr(c, c->L.own), c->part, c->nred, c->dsum, c->stream);
+}
+
+template <int P> static void fields_t(lb_ctx *c, double *out, double *fout)
+{
+    launch_fields<P>(c->kp, ptr(c, c->L.f[c->cur]), ptr(c, c->L.psi[c->cur]), ptr(c, c->L.cc[c->cur]),
+                     (const uint8_t *)ptr(c, c->L.own), out, fout, c->stream);
+}
+
+static lb_status run_fields(lb_ctx *c, double *out, double *fout)
+{
+    switch (c->p.precision) {
+    case LB_FP64: fields_t<LB_FP64>(c, out, fout); break;
+    case LB_FP32: fields_t<LB_FP32>(c, out, fout); break;
+    default: fields_t<LB_FP16_STORAGE>(c, out, fout); break;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return LB_OK;
+}
+
+// raw state: header, f (both buffers not needed: current only), psi, c,
+// owner, particle table, link tables
+struct StateHeader {
+    uint64_t magic;
+    int32_t nx, ny, nz, precision, ncol, lcap;
+    int64_t step;
+};
+static const uint64_t STATE_MAGIC = 0x4c42504852534131ull;
+
+static size_t state_size(lb_ctx *c)
+{
+    const size_t N = (size_t)c->N;
+    return sizeof(StateHeader) + 19 * N * storage_bytes(c->p.precision) +
+           2 * N * compute_bytes(c->p.precision) + N + sizeof(DColloid) * c->ncol +
+           (sizeof(int) + 1) * (size_t)c->lcap * c->ncol;
+}
+
+extern "C" {
+
+lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(nullptr, LB_E_INVALID, "null argument");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(nullptr, LB_E_INVALID, "box sizes must be >= 1");
+    *bytes = layout_of(*p).total;
+    return LB_OK;
+}
+
+lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                    lb_ctx **out)
+{
+    if (!out) return fail(nullptr, LB_E_INVALID, "null output pointer");
+    *out = nullptr;
+    std::string why;
+    lb_status s = check_params(p, why);
+    if (s != LB_OK) return fail(nullptr, s, why);
+    lb_ctx *c = new (std::nothrow) lb_ctx();
+    if (!c) return fail(nullptr, LB_E_OOM, "host allocation failed");
+    c->p = *p;
+    if (c->p.max_colloids == 0) c->p.max_colloids = 64;
+    if (c->p.precision == LB_FP16_STORAGE && c->p.f16_scale == 0.0) c->p.f16_scale = 16384.0;
+    c->N = (long long)p->nx * p->ny * p->nz;
+    KParams &k = c->kp;
+    k.nx = p->nx; k.ny = p->ny; k.nz = p->nz; k.N = (int)c->N;
+    k.rho0 = p->rho0; k.tau = p->tau; k.a = p->a; k.b = p->b; k.kappa = p->kappa;
+    k.M = p->M_psi; k.C = p->C; k.E = p->E; k.cb0 = p->c_b0; k.D = p->D_c; k.kd = p->k_d;
+    k.fx = p->ext_force[0]; k.fy = p->ext_force[1]; k.fz = p->ext_force[2];
+    k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;
+    k.inv_scale = 1.0f / k.scale;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = layout_of(c->p);
+    if (dev_arena) {
+        if (arena_bytes < c->L.total) {
+            delete c;
+            return fail(nullptr, LB_E_OOM, "arena smaller than lb_footprint_bytes");
+        }
+        c->arena = (char *)dev_arena;
+        c->own_arena = false;
+    } else {
+        if (hipMalloc((void **)&c->arena, c->L.total) != hipSuccess) {
+            delete c;
+            return fail(nullptr, LB_E_OOM, "hipMalloc of the lattice arena failed");
+        }
+        c->own_arena = true;
+    }
+    c->nred = 1024;
+    if (hipMalloc((void **)&c->derr, sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->part, sizeof(double) * 7 * c->nred) != hipSuccess ||
+        hipMalloc((void **)&c->dsum, sizeof(double) * 8) != hipSuccess) {
+        lb_destroy(c);
+        return fail(nullptr, LB_E_OOM, "hipMalloc of small buffers failed");
+    }
+    hipMemsetAsync(c->derr, 0, sizeof(int), c->stream);
+    c->maxcol = c->p.max_colloids;
+    *out = c;
+    return LB_OK;
+}
+
+static void free_colloids(lb_ctx *c)
+{
+    if (c->dcol) hipFree(c->dcol);
+    if (c->lnode) hipFree(c->lnode);
+    if (c->ldc) hipFree(c->ldc);
+    c->dcol = nullptr;
+    c->lnode = nullptr;
+    c->ldc = nullptr;
+    c->ncol = 0;
+    c->lcap = 0;
+}
+
+lb_status lb_destroy(lb_ctx *c)
+{
+    if (!c) return LB_OK;
+    if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+    free_colloids(c);
+    if (c->own_arena && c->arena) hipFree(c->arena);
+    if (c->derr) hipFree(c->derr);
+    if (c->part) hipFree(c->part);
+    if (c->dsum) hipFree(c->dsum);
+    delete c->timing;
+    delete c;
+    return LB_OK;
+}
+
+const char *lb_last_error(const lb_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const double *rho,
+                         const double *u)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (!psi || !cc) return fail(c, LB_E_INVALID, "psi and c are required");
+    const size_t N = (size_t)c->N;
+    for (size_t n = 0; n < N; n++) {
+        if (!std::isfinite(psi[n]) || !std::isfinite(cc[n])) return fail(c, LB_E_INVALID, "non-finite psi or c");
+        if (rho && !(std::isfinite(rho[n]) && rho[n] > 0.0)) return fail(c, LB_E_INVALID, "rho must be finite and positive");
+    }
+    if (u)
+        for (size_t n = 0; n < 3 * N; n++)
+            if (!std::isfinite(u[n])) return fail(c, LB_E_INVALID, "non-finite u");
+    double *d = nullptr;
+    const size_t need = (2 + (rho ? 1 : 0) + (u ? 3 : 0)) * N;
+    HIP_TRY(c, hipMalloc((void **)&d, need * sizeof(double)));
+    double *dpsi = d, *dc = d + N, *drho = rho ? d + 2 * N : nullptr;
+    double *du = u ? d + (rho ? 3 : 2) * N : nullptr;
+    hipError_t e = hipMemcpyAsync(dpsi, psi, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dc, cc, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(drho, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) { hipFree(d); return hip_fail(c, e, "hipMemcpyAsync"); }
+    free_colloids(c);
+    c->cur = 0;
+    void *f = ptr(c, c->L.f[0]), *ps = ptr(c, c->L.psi[0]), *cv = ptr(c, c->L.cc[0]);
+    uint8_t *own = (uint8_t *)ptr(c, c->L.own);
+    switch (c->p.precision) {
+    case LB_FP64: launch_init<LB_FP64>(c->kp, dpsi, dc, drho, du, f, ps, cv, own, c->stream); break;
+    case LB_FP32: launch_init<LB_FP32>(c->kp, dpsi, dc, drho, du, f, ps, cv, own, c->stream); break;
+    default: launch_init<LB_FP16_STORAGE>(c->kp, dpsi, dc, drho, du, f, ps, cv, own, c->stream); break;
+    }
+    e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    hipFree(d);
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel launch");
+    if (e2 != hipSuccess) return hip_fail(c, e2, "init kernel");
+    HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    c->step = 0;
+    c->stage = 1;
+    return LB_OK;
+}
+
+lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    if (n < 0 || (n > 0 && !cols)) return fail(c, LB_E_INVALID, "bad particle array");
+    if (n > c->maxcol) return fail(c, LB_E_INVALID, "more particles than max_colloids");
+    const int Ls[3] = {c->p.nx, c->p.ny, c->p.nz};
+    std::vector<DColloid> h(n > 0 ? n : 1);
+    double rmax = 0.0;
+    for (int k = 0; k < n; k++) {
+        const lb_colloid &q = cols[k];
+        DColloid &d = h[k];
+        memset(&d, 0, sizeof d);
+        double mm;
+        {
+#pragma clang fp contract(off)
+            mm = sqrt(q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2]);
+        }
+        if (!(q.radius > 0.0) || !(q.rho_p > 0.0) || !(mm > 0.0))
+            return fail(c, LB_E_INVALID, "particle radius, density and axis must be positive");
+        if (q.H != 0.0 && !(c->p.kappa > 0.0)) return fail(c, LB_E_INVALID, "wetting needs kappa > 0");
+        for (int a = 0; a < 3; a++) {
+            if (2.0 * q.radius + 8.0 > (double)Ls[a])
+                return fail(c, LB_E_INVALID, "particle too large for the box (2 R + 8 > side)");
+            if (!std::isfinite(q.pos[a]) || !std::isfinite(q.vel[a]) || !std::isfinite(q.omega[a]))
+                return fail(c, LB_E_INVALID, "non-finite particle state");
+            double ps = fmod(q.pos[a], (double)Ls[a]);
+            if (ps < 0.0) ps += (double)Ls[a];
+            d.pos[a] = ps;
+            d.m[a] = q.m[a] / mm;
+            d.vel[a] = q.vel[a];
+            d.omega[a] = q.omega[a];
+        }
+        d.radius = q.radius;
+        d.am = q.alpha_minus;
+        d.ap = q.alpha_plus;
+        d.mum = q.mu_minus;
+        d.mup = q.mu_plus;
+        d.H = q.H;
+        d.rho_p = q.rho_p;
+        d.mass = q.rho_p * (4.0 * M_PI / 3.0) * q.radius * q.radius * q.radius;
+        d.inertia = 0.4 * d.mass * q.radius * q.radius;
+        d.fixed = q.fixed ? 1 : 0;
+        rmax = std::max(rmax, q.radius);
+    }
+    // surfaces at least 2 lattice units apart (minimum image)
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++) {
+            double s2 = 0.0;
+            for (int a = 0; a < 3; a++) {
+                double d = min_image(h[i].pos[a] - h[j].pos[a], Ls[a]);
+                s2 += d * d;
+            }
+            if (sqrt(s2) < h[i].radius + h[j].radius + 2.0)
+                return fail(c, LB_E_STATE, "particle surfaces closer than 2 lattice units");
+        }
+    free_colloids(c);
+    // reset the owner map to all fluid before placing the new set
+    HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.own), 0, (size_t)c->N, c->stream));
+    if (n == 0) { c->stage = 2; return LB_OK; }
+    // link capacity: 10 links per node of the shell R-1/2 .. R+3/2, plus slack
+    const double ro = rmax + 1.5, ri = std::max(0.0, rmax - 0.5);
+    c->lcap = (int)(10.0 * (4.0 / 3.0) * M_PI * (ro * ro * ro - ri * ri * ri)) + 512;
+    HIP_TRY(c, hipMalloc((void **)&c->dcol, sizeof(DColloid) * c->maxcol));
+    HIP_TRY(c, hipMalloc((void **)&c->lnode, sizeof(int) * (size_t)c->lcap * c->maxcol));
+    HIP_TRY(c, hipMalloc((void **)&c->ldc, (size_t)c->lcap * c->maxcol));
+    HIP_TRY(c, hipMemcpyAsync(c->dcol, h.data(), sizeof(DColloid) * n, hipMemcpyHostToDevice, c->stream));
+    c->ncol = n;
+    launch_geometry(c->kp, buffers(c), c->ncol, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int herr = 0;
+    HIP_TRY(c, hipMemcpy(&herr, c->derr, sizeof(int), hipMemcpyDeviceToHost));
+    if (herr & LB_ERR_LINKS) return fail(c, LB_E_STATE, "link table overflow");
+    c->stage = 2;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    if (nsteps < 0) return fail(c, LB_E_INVALID, "negative step count");
+    for (int64_t s = 0; s < nsteps; s++) {
+        dispatch_step(c);
+        c->cur ^= 1;
+        c->step++;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    int herr = 0;
+    std::vector<DColloid> h(c->ncol > 0 ? c->ncol : 1);
+    double sums[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (t) {
+        switch (c->p.precision) {
+        case LB_FP64: reduce_t<LB_FP64>(c); break;
+        case LB_FP32: reduce_t<LB_FP32>(c); break;
+        default: reduce_t<LB_FP16_STORAGE>(c); break;
+        }
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipMemcpyAsync(sums, c->dsum, sizeof(double) * 7, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(&herr, c->derr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (c->ncol > 0)
+        HIP_TRY(c, hipMemcpyAsync(h.data(), c->dcol, sizeof(DColloid) * c->ncol, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (t) {
+        memset(t, 0, sizeof *t);
+        t->mass = sums[0];
+        t->mom[0] = sums[1];
+        t->mom[1] = sums[2];
+        t->mom[2] = sums[3];
+        t->sum_psi = sums[4];
+        t->sum_c = sums[5];
+        t->n_fluid = (int64_t)sums[6];
+        for (int k = 0; k < c->ncol; k++) {
+            t->n_links += h[k].nlinks;
+            t->n_active += h[k].nactive;
+        }
+        t->step = c->step;
+        int e = herr;
+        for (int j = 0; j < 6; j++)
+            if (!std::isfinite(sums[j])) e |= LB_ERR_NAN;
+        t->error_bits = e;
+        herr = e;
+    }
+    if (out) {
+        if (n > c->ncol) n = c->ncol;
+        for (int k = 0; k < n; k++) {
+            lb_colloid &q = out[k];
+            const DColloid &d = h[k];
+            for (int a = 0; a < 3; a++) {
+                q.pos[a] = d.pos[a];
+                q.m[a] = d.m[a];
+                q.vel[a] = d.vel[a];
+                q.omega[a] = d.omega[a];
+            }
+            q.radius = d.radius;
+            q.alpha_minus = d.am;
+            q.alpha_plus = d.ap;
+            q.mu_minus = d.mum;
+            q.mu_plus = d.mup;
+            q.H = d.H;
+            q.rho_p = d.rho_p;
+            q.fixed = d.fixed;
+        }
+    }
+    if (herr & LB_ERR_NAN) return fail(c, LB_E_UNSTABLE, "non-finite totals");
+    if (herr) return fail(c, LB_E_STATE, "device error bits set: " + std::to_string(herr));
+    return LB_OK;
+}
+
+lb_status lb_get_fields(lb_ctx *c, double *rho, double *u, double *psi, double *cc)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    const size_t N = (size_t)c->N;
+    double *d = nullptr;
+    HIP_TRY(c, hipMalloc((void **)&d, 6 * N * sizeof(double)));
+    lb_status s = run_fields(c, d, nullptr);
+    hipError_t e = hipSuccess;
+    if (s == LB_OK) {
+        if (rho) e = hipMemcpyAsync(rho, d, N * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + N, 3 * N * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && psi) e = hipMemcpyAsync(psi, d + 4 * N, N * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && cc) e = hipMemcpyAsync(cc, d + 5 * N, N * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    hipFree(d);
+    if (s != LB_OK) return s;
+    if (e != hipSuccess) return hip_fail(c, e, "field readback");
+    return LB_OK;
+}
+
+lb_status lb_get_populations(lb_ctx *c, double *f)
+{
+    if (!c || !f) return fail(c, LB_E_INVALID, "null argument");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    const size_t N = (size_t)c->N;
+    double *d = nullptr;
+    HIP_TRY(c, hipMalloc((void **)&d, 19 * N * sizeof(double)));
+    lb_status s = run_fields(c, nullptr, d);
+    hipError_t e = hipSuccess;
+    if (s == LB_OK) {
+        e = hipMemcpyAsync(f, d, 19 * N * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    hipFree(d);
+    if (s != LB_OK) return s;
+    if (e != hipSuccess) return hip_fail(c, e, "population readback");
+    return LB_OK;
+}
+
+lb_status lb_get_owner(lb_ctx *c, int32_t *owner)
+{
+    if (!c || !owner) return fail(c, LB_E_INVALID, "null argument");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    std::vector<uint8_t> h((size_t)c->N);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), ptr(c, c->L.own), (size_t)c->N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t n = 0; n < h.size(); n++) owner[n] = (int)(h[n] & OWN_SOLID) - 1;
+    return LB_OK;
+}
+
+lb_status lb_get_links(lb_ctx *c, int32_t *rec4, int64_t cap, int64_t *nout)
+{
+    if (!c || !nout) return fail(c, LB_E_INVALID, "null argument");
+    *nout = 0;
+    if (c->ncol == 0) return LB_OK;
+    std::vector<DColloid> h(c->ncol);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->dcol, sizeof(DColloid) * c->ncol, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int64_t total = 0;
+    for (int k = 0; k < c->ncol; k++) total += std::min(h[k].nlinks, c->lcap);
+    *nout = total;
+    if (!rec4) return LB_OK;
+    if (cap < total) return fail(c, LB_E_INVALID, "link buffer too small");
+    std::vector<int> nodes((size_t)c->lcap * c->ncol);
+    std::vector<uint8_t> dcs((size_t)c->lcap * c->ncol);
+    HIP_TRY(c, hipMemcpy(nodes.data(), c->lnode, sizeof(int) * nodes.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(dcs.data(), c->ldc, dcs.size(), hipMemcpyDeviceToHost));
+    int64_t l = 0;
+    for (int k = 0; k < c->ncol; k++)
+        for (int j = 0; j < std::min(h[k].nlinks, c->lcap); j++) {
+            const size_t s = (size_t)k * c->lcap + j;
+            rec4[4 * l + 0] = k;
+            rec4[4 * l + 1] = nodes[s];
+            rec4[4 * l + 2] = dcs[s] & 31;
+            rec4[4 * l + 3] = (dcs[s] & 0x80) ? 1 : 0;
+            l++;
+        }
+    return LB_OK;
+}
+
+lb_status lb_colloid_forces(lb_ctx *c, double *out12, int32_t n)
+{
+    if (!c || !out12) return fail(c, LB_E_INVALID, "null argument");
+    if (n > c->ncol) n = c->ncol;
+    if (n <= 0) return LB_OK;
+    std::vector<DColloid> h(c->ncol);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->dcol, sizeof(DColloid) * c->ncol, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; k++)
+        for (int a = 0; a < 3; a++) {
+            out12[12 * k + a] = h[k].F[a];
+            out12[12 * k + 3 + a] = h[k].T[a];
+            out12[12 * k + 6 + a] = h[k].F0[a];
+            out12[12 * k + 9 + a] = h[k].T0[a];
+        }
+    return LB_OK;
+}
+
+lb_status lb_save_state(lb_ctx *c, void *buf, size_t cap, size_t *nout)
+{
+    if (!c || !nout) return fail(c, LB_E_INVALID, "null argument");
+    if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
+    const size_t need = state_size(c);
+    *nout = need;
+    if (!buf) return LB_OK;
+    if (cap < need) return fail(c, LB_E_INVALID, "state buffer too small");
+    const size_t N = (size_t)c->N;
+    char *o = (char *)buf;
+    StateHeader hd = {STATE_MAGIC, c->p.nx, c->p.ny, c->p.nz, c->p.precision, c->ncol, c->lcap, c->step};
+    memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    const size_t fb = 19 * N * storage_bytes(c->p.precision), sb = N * compute_bytes(c->p.precision);
+    HIP_TRY(c, hipMemcpyAsync(o, ptr(c, c->L.f[c->cur]), fb, hipMemcpyDeviceToHost, c->stream)); o += fb;
+    HIP_TRY(c, hipMemcpyAsync(o, ptr(c, c->L.psi[c->cur]), sb, hipMemcpyDeviceToHost, c->stream)); o += sb;
+    HIP_TRY(c, hipMemcpyAsync(o, ptr(c, c->L.cc[c->cur]), sb, hipMemcpyDeviceToHost, c->stream)); o += sb;
+    HIP_TRY(c, hipMemcpyAsync(o, ptr(c, c->L.own), N, hipMemcpyDeviceToHost, c->stream)); o += N;
+    if (c->ncol) {
+        HIP_TRY(c, hipMemcpyAsync(o, c->dcol, sizeof(DColloid) * c->ncol, hipMemcpyDeviceToHost, c->stream));
+        o += sizeof(DColloid) * c->ncol;
+        HIP_TRY(c, hipMemcpyAsync(o, c->lnode, sizeof(int) * (size_t)c->lcap * c->ncol, hipMemcpyDeviceToHost, c->stream));
+        o += sizeof(int) * (size_t)c->lcap * c->ncol;
+        HIP_TRY(c, hipMemcpyAsync(o, c->ldc, (size_t)c->lcap * c->ncol, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
+{
+    if (!c || !buf) return fail(c, LB_E_INVALID, "null argument");
+    StateHeader hd;
+    if (n < sizeof hd) return fail(c, LB_E_INVALID, "state too short");
+    memcpy(&hd, buf, sizeof hd);
+    if (hd.magic != STATE_MAGIC || hd.nx != c->p.nx || hd.ny != c->p.ny || hd.nz != c->p.nz ||
+        hd.precision != c->p.precision || hd.ncol > c->maxcol)
+        return fail(c, LB_E_INVALID, "state does not match this context");
+    free_colloids(c);
+    if (hd.ncol > 0) {
+        c->lcap = hd.lcap;
+        HIP_TRY(c, hipMalloc((void **)&c->dcol, sizeof(DColloid) * c->maxcol));
+        HIP_TRY(c, hipMalloc((void **)&c->lnode, sizeof(int) * (size_t)c->lcap * c->maxcol));
+        HIP_TRY(c, hipMalloc((void **)&c->ldc, (size_t)c->lcap * c->maxcol));
+    }
+    c->ncol = hd.ncol;
+    if (n < state_size(c)) return fail(c, LB_E_INVALID, "state too short");
+    const size_t N = (size_t)c->N;
+    const char *o = (const char *)buf + sizeof hd;
+    c->cur = 0;
+    const size_t fb = 19 * N * storage_bytes(c->p.precision), sb = N * compute_bytes(c->p.precision);
+    HIP_TRY(c, hipMemcpyAsync(ptr(c, c->L.f[0]), o, fb, hipMemcpyHostToDevice, c->stream)); o += fb;
+    HIP_TRY(c, hipMemcpyAsync(ptr(c, c->L.psi[0]), o, sb, hipMemcpyHostToDevice, c->stream)); o += sb;
+    HIP_TRY(c, hipMemcpyAsync(ptr(c, c->L.cc[0]), o, sb, hipMemcpyHostToDevice, c->stream)); o += sb;
+    HIP_TRY(c, hipMemcpyAsync(ptr(c, c->L.own), o, N, hipMemcpyHostToDevice, c->stream)); o += N;
+    if (c->ncol) {
+        HIP_TRY(c, hipMemcpyAsync(c->dcol, o, sizeof(DColloid) * c->ncol, hipMemcpyHostToDevice, c->stream));
+        o += sizeof(DColloid) * c->ncol;
+        HIP_TRY(c, hipMemcpyAsync(c->lnode, o, sizeof(int) * (size_t)c->lcap * c->ncol, hipMemcpyHostToDevice, c->stream));
+        o += sizeof(int) * (size_t)c->lcap * c->ncol;
+        HIP_TRY(c, hipMemcpyAsync(c->ldc, o, (size_t)c->lcap * c->ncol, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = hd.step;
+    c->stage = 2;
+    return LB_OK;
+}
+
+lb_status lb_timing_enable(lb_ctx *c, int32_t on)
+{
+    if (!c) return fail(nullptr, LB_E_INVALID, "null context");
+    if (on) {
+        if (!c->timing) c->timing = new (std::nothrow) TimingHook();
+        if (!c->timing) return fail(c, LB_E_OOM, "host allocation failed");
+        c->timing->reset();
+    } else {
+        delete c->timing;
+        c->timing = nullptr;
+    }
+    return LB_OK;
+}
+
+lb_status lb_timing_read(lb_ctx *c, double *ms6, int64_t *calls6)
+{
+    if (!c || !ms6 || !calls6) return fail(c, LB_E_INVALID, "null argument");
+    if (!c->timing) return fail(c, LB_E_STATE, "timing is not enabled");
+    c->timing->flush();
+    for (int i = 0; i < 6; i++) { ms6[i] = c->timing->ms[i]; calls6[i] = c->timing->calls[i]; }
+    return LB_OK;
+}
+
+double lb_wetting_H(double theta_deg, double kappa, double b)
+{
+    if (!(kappa * b > 0.0)) return NAN;
+    const double target = cos(theta_deg * M_PI / 180.0);
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; it++) {
+        const double h = 0.5 * (lo + hi);
+        const double v = 0.5 * (pow(1.0 + h, 1.5) - pow(1.0 - h, 1.5));
+        if (v < target) lo = h; else hi = h;
+    }
+    return 0.5 * (lo + hi) * sqrt(kappa * b);
+}
+
+double lb_solubility_E(double ratio, double c_b0)
+{
+    return -c_b0 * (ratio - 1.0) / ((ratio + 1.0) * tanh(1.0));
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// lb_device.h -- device-side building blocks of the lattice update: D3Q19
+// constants, storage precisions, kernel parameter block, particle record and
+// FP64 particle geometry.  Included by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "lb.h"
+
+namespace lbk {
+
+// ------------------------------------------------------------------ D3Q19
+// Lattice vectors as constexpr functions: in fully unrolled loops they fold
+// to immediates, so the collision carries no table loads.
+__host__ __device__ constexpr int cx(int i)
+{
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+           : ((i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i)
+{
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+           : ((i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0);
+}
+__host__ __device__ constexpr int cz(int i)
+{
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+           : ((i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wgt(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Owner byte per node: bits 0-6 hold k+1 for a node inside particle k
+// (0 = fluid); bit 7 marks a fluid node with a solid node among its 18
+// neighbours, the only nodes where bounce-back, wetting ghosts, no-flux
+// faces and emission can occur.
+constexpr uint8_t OWN_SOLID = 0x7f;
+constexpr uint8_t OWN_BOUNDARY = 0x80;
+constexpr int MAX_COLLOIDS = 127;
+
+// ------------------------------------------------------- storage precision
+template <int P> struct Prec;
+template <> struct Prec<LB_FP64> { typedef double T; typedef double S; };
+template <> struct Prec<LB_FP32> { typedef float T; typedef float S; };
+template <> struct Prec<LB_FP16_STORAGE> { typedef __half T; typedef float S; };
+
+__device__ __forceinline__ double ld_pop(const double *p, size_t i, float) { return p[i]; }
+__device__ __forceinline__ float ld_pop(const float *p, size_t i, float) { return p[i]; }
+__device__ __forceinline__ float ld_pop(const __half *p, size_t i, float inv)
+{
+    return __half2float(p[i]) * inv;
+}
+__device__ __forceinline__ void st_pop(double *p, size_t i, double v, float) { p[i] = v; }
+__device__ __forceinline__ void st_pop(float *p, size_t i, float v, float) { p[i] = v; }
+__device__ __forceinline__ void st_pop(__half *p, size_t i, float v, float sc)
+{
+    p[i] = __float2half_rn(v * sc);
+}
+
+// --------------------------------------------------------- parameter block
+struct KParams {
+    int nx, ny, nz, N;         // N = nx*ny*nz < 2^31
+    double rho0, tau, a, b, kappa, M, C, E, cb0, D, kd;
+    double fx, fy, fz;
+    float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
+};
+
+// ---------------------------------------------------------- particle record
+struct DColloid {
+    double pos[3], m[3], vel[3], omega[3];
+    double radius, am, ap, mum, mup, H, rho_p, mass, inertia;
+    double trF[3], trT[3];     // pending cover/uncover transfer, used next step
+    double F[3], T[3];         // force and torque acting in the last step
+    double F0[3], T0[3];       // velocity-independent link momentum of the last step
+    int fixed, nlinks, nactive, pad;
+};
+
+// -------------------------------------------------------- particle geometry
+// FP64 with no contraction: the inside test and the cap test must resolve
+// exact ties the same way everywhere.
+__host__ __device__ inline double min_image(double d, int L)
+{
+#pragma clang fp contract(off)
+    const double h = 0.5 * (double)L;
+    if (d > h) d -= (double)L;
+    else if (d < -h) d += (double)L;
+    return d;
+}
+
+// displacement from the centre to node (x,y,z) + s*(ex,ey,ez), s in {0, 1/2}
+__host__ __device__ inline void displacement(const DColloid &q, int x, int y, int z, int ex, int ey,
+                                             int ez, double s, int nx, int ny, int nz, double r[3])
+{
+#pragma clang fp contract(off)
+    r[0] = min_image(((double)x + s * (double)ex) - q.pos[0], nx);
+    r[1] = min_image(((double)y + s * (double)ey) - q.pos[1], ny);
+    r[2] = min_image(((double)z + s * (double)ez) - q.pos[2], nz);
+}
+
+// strictly inside the sphere
+__host__ __device__ inline bool inside(const DColloid &q, int x, int y, int z, int nx, int ny, int nz)
+{
+#pragma clang fp contract(off)
+    double r[3];
+    displacement(q, x, y, z, 0, 0, 0, 0.0, nx, ny, nz, r);
+    double d2 = r[0] * r[0] + r[1] * r[1];
+    d2 = d2 + r[2] * r[2];
+    return d2 < q.radius * q.radius;
+}
+
+// active hemisphere m.n <= 0, n through the link midpoint (Eqs. 5-6)
+__host__ __device__ inline bool active_cap(const DColloid &q, const double r[3])
+{
+#pragma clang fp contract(off)
+    double md = q.m[0] * r[0] + q.m[1] * r[1];
+    md = md + q.m[2] * r[2];
+    return md <= 0.0;
+}
+
+// Particle bounding box along one axis, with the node coordinates visited in
+// ascending wrapped order: element t of the sorted list is
+// wrap(lo + (t + shift) % count).
+struct AxisBox {
+    int lo, count, shift, L;
+    __host__ __device__ int at(int t) const
+    {
+        int v = lo + (t + shift) % count;
+        v %= L;
+        return v < 0 ? v + L : v;
+    }
+};
+
+__host__ __device__ inline AxisBox axis_box(double c, double radius, int L)
+{
+    AxisBox b;
+    int lo = (int)floor(c - radius) - 3;
+    int hi = (int)floor(c + radius) + 3;
+    int count = hi - lo + 1;
+    if (count >= L) { lo = 0; count = L; }
+    b.lo = lo;
+    b.count = count;
+    b.L = L;
+    int l = lo % L;
+    if (l < 0) l += L;
+    // index in range order of the first element in ascending wrapped order
+    int first = 0;
+    if (l + count > L) first = L - l;
+    b.shift = first % count;
+    return b;
+}
+
+}  // namespace lbk

@@ -1,0 +1,57 @@
+// lb_kernels.h -- host-side launch interface of the lattice-update kernels.
+#pragma once
+#include <utility>
+#include <vector>
+
+#include "lb_device.h"
+
+namespace lbk {
+
+// Device buffers one step reads and writes (cur -> nxt).
+struct StepBuffers {
+    const void *fin;
+    void *fout;
+    const void *psi, *cc;   // state at t
+    void *psin, *ccn;       // state at t+1
+    void *mu, *u;           // derived fields of step t
+    uint8_t *own;
+    DColloid *col;
+    int *lnode;
+    uint8_t *ldc;
+    int lcap;
+    int *err;
+};
+
+// Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,
+// links+particles, cover, geometry).
+struct TimingHook {
+    std::vector<hipEvent_t> pool;            // free events
+    std::vector<hipEvent_t> open[6];         // begin events awaiting their end
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> done[6];
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    long long calls[6] = {0, 0, 0, 0, 0, 0};
+    hipEvent_t take();
+    void begin(int i, hipStream_t s);
+    void end(int i, hipStream_t s);
+    void flush();   // waits for recorded events, accumulates, recycles
+    void reset();
+    ~TimingHook();
+};
+
+template <int P>
+void launch_step_lattice(const KParams &p, const StepBuffers &b, hipStream_t s, TimingHook *tm);
+template <int P>
+void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s,
+                           TimingHook *tm);
+void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s);
+template <int P>
+void launch_init(const KParams &p, const double *psi0, const double *c0, const double *rho0,
+                 const double *u0, void *f, void *psi, void *cc, uint8_t *own, hipStream_t s);
+template <int P>
+void launch_reduce(const KParams &p, const void *f, const void *psi, const void *cc,
+                   const uint8_t *own, double *part, int nblocks, double *out, hipStream_t s);
+template <int P>
+void launch_fields(const KParams &p, const void *f, const void *psi, const void *cc,
+                   const uint8_t *own, double *out, double *fout, hipStream_t s);
+
+}  // namespace lbk

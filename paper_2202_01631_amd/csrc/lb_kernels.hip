@@ -1,0 +1,838 @@
+// lb_kernels.hip -- gfx950 kernels of one time step of the lattice update of
+// the multiphase-multicomponent LB model for self-diffusiophoretic Janus
+// colloids (arXiv:2202.01631, Sec. II).
+//
+// Step sequence on one stream (cur -> nxt buffers):
+//   k_mu             mu_psi of Eq. 2 with the wetting ghost of Eqs. 8-9
+//   k_collide        force -psi grad(mu), moments, BGK-Guo collision, push
+//                    streaming with plain (resting-wall) bounce-back
+//   k_scalar         psi and c updates of Eq. 3 with Janus emission (Eq. 5)
+//   k_links_colloid  per particle: moving-wall and slip correction of every
+//                    link (Eqs. 4, 6), FP64 momentum exchange, implicit
+//                    rigid-body update
+//   k_cover          per particle: cover/uncover repair at the new position
+//   k_commit         per particle: owner bytes at the new position
+//   k_links          per particle: boundary bits and canonical link table
+// Lattice kernels use one thread per node, 64-wide rows in x (one wavefront
+// per row segment, coalesced structure-of-arrays access).
+#include "lb_kernels.h"
+
+namespace lbk {
+
+__device__ __forceinline__ int wrap_p(int v, int L) { return v + 1 == L ? 0 : v + 1; }
+__device__ __forceinline__ int wrap_m(int v, int L) { return v == 0 ? L - 1 : v - 1; }
+
+template <class S> __device__ __forceinline__ S s_tanh(S v);
+template <> __device__ __forceinline__ double s_tanh<double>(double v) { return tanh(v); }
+template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tanhf(v); }
+
+// ------------------------------------------------------------------ k_mu
+// mu_psi = a psi + b psi^3 - kappa lap(psi) - C E chi (1 - tanh^2 psi),
+// chi = c - c_b0 - E tanh psi (Eq. 2; 1/cosh^2 = 1 - tanh^2, cubic factored
+// as b psi (psi-1)(psi+1) + (a+b) psi to keep FP32 cancellation small).
+// At a solid face neighbour the Laplacian takes the ghost psi - (H/kappa)|e.n|
+// (Eq. 9, n through the face midpoint).
+template <class S>
+__global__ __launch_bounds__(256) void k_mu(KParams p, const S *__restrict__ psi,
+                                            const S *__restrict__ cc,
+                                            const uint8_t *__restrict__ own,
+                                            const DColloid *__restrict__ col, S *__restrict__ mu)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int n = x + sy * y + sz * z;
+    const uint8_t o = own[n];
+    if (o & OWN_SOLID) { mu[n] = S(0); return; }
+    const int nb[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                       n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                       n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+    const S ps = psi[n];
+    S lap = S(-6) * ps;
+    if (o & OWN_BOUNDARY) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const uint8_t om = own[nb[e]] & OWN_SOLID;
+            if (!om) {
+                lap += psi[nb[e]];
+            } else {
+                const DColloid &q = col[om - 1];
+                double r[3];
+                const int ax = e >> 1, sg = (e & 1) ? -1 : 1;
+                displacement(q, x, y, z, ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0, 0.5,
+                             p.nx, p.ny, p.nz, r);
+                const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                const double en = fabs(r[ax]) / rn;
+                const double gh = p.kappa > 0.0 ? (q.H / p.kappa) * en : 0.0;
+                lap += ps - (S)gh;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 6; e++) lap += psi[nb[e]];
+    }
+    const S a = (S)p.a, b = (S)p.b;
+    const S t = s_tanh<S>(ps);
+    const S chi = cc[n] - (S)p.cb0 - (S)p.E * t;
+    mu[n] = b * ps * (ps - S(1)) * (ps + S(1)) + (a + b) * ps - (S)p.kappa * lap -
+            (S)(p.C * p.E) * chi * (S(1) - t * t);
+}
+
+// ------------------------------------------------------------- k_collide
+// Populations are stored shifted, g_i = f_i - w_i rho0 (scaled for FP16).
+// rho = rho0 + sum g; j = sum g c; F = -psi grad(mu) (isotropic lattice
+// gradient over the 18 neighbours, mu(x) substituted at solid neighbours; the
+// central two-point gradient would make the explicit force/advection coupling
+// unstable at grid scale) + external force;
+// u = (j + F/2)/rho; g*_i = g_i - (g_i - geq_i)/tau + (1 - 1/2tau) w_i
+// [3(c_i - u) + 9 (c_i.u) c_i].F with geq_i = w_i [drho + rho(3 c.u +
+// 4.5 (c.u)^2 - 1.5 u.u)] (BGK with Guo forcing).  Push: g*_i goes to
+// x + c_i, or back into slot opp(i) of x when x + c_i is solid (resting-wall
+// bounce-back; the moving-wall and slip terms are added by k_links_colloid).
+template <int P>
+__global__ __launch_bounds__(256) void k_collide(KParams p,
+                                                 const typename Prec<P>::T *__restrict__ fin,
+                                                 typename Prec<P>::T *__restrict__ fout,
+                                                 const typename Prec<P>::S *__restrict__ psi,
+                                                 const typename Prec<P>::S *__restrict__ mu,
+                                                 const uint8_t *__restrict__ own,
+                                                 typename Prec<P>::S *__restrict__ uout)
+{
+    typedef typename Prec<P>::S S;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int n = x + sy * y + sz * z;
+    const uint8_t o = own[n];
+    if (o & OWN_SOLID) return;
+    const bool bnd = (o & OWN_BOUNDARY) != 0;
+    const size_t N = (size_t)p.N;
+    const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
+    const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
+    const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
+
+    S g[19];
+#pragma unroll
+    for (int i = 0; i < 19; i++) g[i] = ld_pop(fin, i * N + n, p.inv_scale);
+    S drho = S(0), jx = S(0), jy = S(0), jz = S(0);
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        drho += g[i];
+        if (cx(i)) jx += cx(i) > 0 ? g[i] : -g[i];
+        if (cy(i)) jy += cy(i) > 0 ? g[i] : -g[i];
+        if (cz(i)) jz += cz(i) > 0 ? g[i] : -g[i];
+    }
+    // body force -psi grad(mu), isotropic lattice gradient
+    // grad(mu) = 3 sum_i w_i c_i mu(x + c_i), mu(x) at solid neighbours
+    const S m0 = mu[n];
+    S gx = S(0), gy = S(0), gz = S(0);
+#pragma unroll
+    for (int i = 1; i < 19; i++) {
+        const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
+        S mi = mu[m];
+        if (bnd && (own[m] & OWN_SOLID)) mi = m0;
+        const S wi = (S)(3.0 * wgt(i));
+        if (cx(i)) gx += cx(i) > 0 ? wi * mi : -wi * mi;
+        if (cy(i)) gy += cy(i) > 0 ? wi * mi : -wi * mi;
+        if (cz(i)) gz += cz(i) > 0 ? wi * mi : -wi * mi;
+    }
+    const S ps = psi[n];
+    const S Fx = -ps * gx + (S)p.fx;
+    const S Fy = -ps * gy + (S)p.fy;
+    const S Fz = -ps * gz + (S)p.fz;
+    const S rho = (S)p.rho0 + drho;
+    const S ir = S(1) / rho;
+    const S ux = (jx + S(0.5) * Fx) * ir;
+    const S uy = (jy + S(0.5) * Fy) * ir;
+    const S uz = (jz + S(0.5) * Fz) * ir;
+    const S uu = ux * ux + uy * uy + uz * uz;
+    const S uF = ux * Fx + uy * Fy + uz * Fz;
+    const S om = (S)(1.0 / p.tau);
+    const S pref = (S)(1.0 - 0.5 / p.tau);
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        const S w = (S)wgt(i);
+        const S cu = (S)cx(i) * ux + (S)cy(i) * uy + (S)cz(i) * uz;
+        const S cF = (S)cx(i) * Fx + (S)cy(i) * Fy + (S)cz(i) * Fz;
+        const S geq = w * (drho + rho * (S(3) * cu + S(4.5) * cu * cu - S(1.5) * uu));
+        const S gs = g[i] - om * (g[i] - geq) + pref * w * (S(3) * (cF - uF) + S(9) * cu * cF);
+        if (i == 0) {
+            st_pop(fout, (size_t)n, gs, p.scale);
+        } else {
+            const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
+            if (bnd && (own[m] & OWN_SOLID))
+                st_pop(fout, opp(i) * N + n, gs, p.scale);
+            else
+                st_pop(fout, i * N + m, gs, p.scale);
+        }
+    }
+    uout[n] = ux;
+    uout[N + n] = uy;
+    uout[2 * N + n] = uz;
+}
+
+// -------------------------------------------------------------- k_scalar
+// psi' = psi - sum_e J_e + M sum_e (mu_e - mu),
+// c'   = c - sum_e Jc_e + D sum_e (chi_e - chi) + emission - k_d chi,
+// J_e = 1/2 (u.e + u_e.e) 1/2 (psi + psi_e) over the 6 faces, nothing
+// through faces shared with solid nodes (Eq. 3, explicit Euler, dt = 1).
+// Emission: alpha of the cap of each link of the node (Eq. 5).
+template <class S>
+__global__ __launch_bounds__(256) void k_scalar(KParams p, const S *__restrict__ psi,
+                                                const S *__restrict__ cc,
+                                                const S *__restrict__ mu,
+                                                const S *__restrict__ u,
+                                                const uint8_t *__restrict__ own,
+                                                const DColloid *__restrict__ col,
+                                                S *__restrict__ psin, S *__restrict__ ccn)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int n = x + sy * y + sz * z;
+    const uint8_t o = own[n];
+    const S ps = psi[n], cn = cc[n];
+    if (o & OWN_SOLID) { psin[n] = ps; ccn[n] = cn; return; }
+    const bool bnd = (o & OWN_BOUNDARY) != 0;
+    const size_t N = (size_t)p.N;
+    const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
+    const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
+    const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
+    const int fn[6] = {n + xo[2], n + xo[0], n + yo[2], n + yo[0], n + zo[2], n + zo[0]};
+    const S E = (S)p.E, cb0 = (S)p.cb0;
+    const S chi = cn - cb0 - E * s_tanh<S>(ps);
+    const S m0 = mu[n];
+    const S u0[3] = {u[n], u[N + n], u[2 * N + n]};
+    S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        const int m = fn[e];
+        if (bnd && (own[m] & OWN_SOLID)) continue;
+        const int ax = e >> 1;
+        const S um = u[ax * N + m];
+        const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um) : S(0.5) * (u0[ax] + um);
+        const S pm = psi[m], cm = cc[m];
+        adv_p += ue * (S(0.5) * (ps + pm));
+        adv_c += ue * (S(0.5) * (cn + cm));
+        dmu += mu[m] - m0;
+        dchi += (cm - cb0 - E * s_tanh<S>(pm)) - chi;
+    }
+    S src = S(0);
+    if (bnd) {
+        for (int d = 1; d < 19; d++) {
+            const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
+            const uint8_t om = own[m] & OWN_SOLID;
+            if (!om) continue;
+            const DColloid &q = col[om - 1];
+            double r[3];
+            displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
+            src += (S)(active_cap(q, r) ? q.am : q.ap);
+        }
+    }
+    psin[n] = ps - adv_p + (S)p.M * dmu;
+    ccn[n] = cn - adv_c + (S)p.D * dchi + src - (S)p.kd * chi;
+}
+
+// ------------------------------------------------ block reductions (FP64)
+// Fixed-shape reductions: wavefront butterfly, then the waves in order, so
+// results do not depend on scheduling.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double *lds /* NV * nwaves */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        double s = v[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[j] = s;
+    }
+    __syncthreads();
+    if (lane == 0)
+        for (int j = 0; j < NV; j++) lds[wave * NV + j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < NV; j++) {
+            double s = lds[j];
+            for (int w = 1; w < nw; w++) s += lds[w * NV + j];
+            v[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int node_of(const KParams &p, int n, int &x, int &y, int &z)
+{
+    const int sz = p.nx * p.ny;
+    z = n / sz;
+    const int r = n - z * sz;
+    y = r / p.nx;
+    x = r - y * p.nx;
+    return n;
+}
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// ------------------------------------------------------ k_links_colloid
+// One block per particle k.  For each link (n, d) of k (fluid n, n + c_d in
+// k): wall velocity u_b = V + Omega x r + mu_cap (I - nn) grad c(n) with r
+// the link midpoint from the centre (Eq. 4, 6); bounced population
+// f_opp(d)(n) = f*_d(n) - 6 w_d rho0 c_d.u_b; momentum to the particle
+// c_d (2 f*_d - 6 w_d rho0 c_d.u_b), of which the velocity-independent part
+// F0 = sum c_d (2 f*_d - 6 w_d rho0 c_d.u_slip) and the drag tensor
+// zeta = sum 6 w_d rho0 g g^T, g = (c_d, r x c_d), are accumulated in FP64.
+// Then (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
+// R' = R + V', m' = m rotated by |Omega'| about Omega'.
+template <int P>
+__global__ __launch_bounds__(256) void k_links_colloid(KParams p, DColloid *__restrict__ col,
+                                                       const int *__restrict__ lnode,
+                                                       const uint8_t *__restrict__ ldc, int lcap,
+                                                       typename Prec<P>::T *__restrict__ fout,
+                                                       const typename Prec<P>::S *__restrict__ cc,
+                                                       const uint8_t *__restrict__ own,
+                                                       int *__restrict__ err)
+{
+    typedef typename Prec<P>::S S;
+    __shared__ double lds[28 * 16];
+    const int k = blockIdx.x;
+    DColloid &q = col[k];
+    const int nl = min(q.nlinks, lcap);
+    const size_t N = (size_t)p.N;
+    const double rho0 = p.rho0;
+    double acc[28];
+#pragma unroll
+    for (int j = 0; j < 28; j++) acc[j] = 0.0;
+    const double pos[3] = {q.pos[0], q.pos[1], q.pos[2]};
+    const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
+    const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
+    (void)pos;
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+        const int n = lnode[(size_t)k * lcap + l];
+        const int dc = ldc[(size_t)k * lcap + l];
+        const int d = dc & 31;
+        const bool cap = (dc & 0x80) != 0;
+        int x, y, z;
+        node_of(p, n, x, y, z);
+        const int ex = cx(d), ey = cy(d), ez = cz(d);
+        double r[3];
+        displacement(q, x, y, z, ex, ey, ez, 0.5, p.nx, p.ny, p.nz, r);
+        const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const double nh[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+        // grad c at the fluid node, c(x) substituted at solid neighbours
+        const int sy = p.nx, sz = p.nx * p.ny;
+        const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                           n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                           n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+        const double c0 = (double)cc[n];
+        double cv[6];
+        for (int e = 0; e < 6; e++) cv[e] = (own[fn[e]] & OWN_SOLID) ? c0 : (double)cc[fn[e]];
+        const double g[3] = {0.5 * (cv[0] - cv[1]), 0.5 * (cv[2] - cv[3]), 0.5 * (cv[4] - cv[5])};
+        const double mob = cap ? q.mum : q.mup;
+        const double ng = nh[0] * g[0] + nh[1] * g[1] + nh[2] * g[2];
+        double slip[3], ub[3], wr[3];
+        for (int a = 0; a < 3; a++) slip[a] = mob * (g[a] - nh[a] * ng);
+        cross3(W, r, wr);
+        for (int a = 0; a < 3; a++) ub[a] = V[a] + wr[a] + slip[a];
+        const double w = wgt(d);
+        const size_t slot = (size_t)opp(d) * N + n;
+        const S gs = ld_pop(fout, slot, p.inv_scale);
+        const double fs = (double)gs + w * rho0;
+        const double cub = ex * ub[0] + ey * ub[1] + ez * ub[2];
+        const double cus = ex * slip[0] + ey * slip[1] + ez * slip[2];
+        st_pop(fout, slot, (S)((double)gs - 6.0 * w * rho0 * cub), p.scale);
+        const double mag = 2.0 * fs - 6.0 * w * rho0 * cus;
+        const double dp[3] = {ex * mag, ey * mag, ez * mag};
+        double t[3];
+        cross3(r, dp, t);
+        const double cd[3] = {(double)ex, (double)ey, (double)ez};
+        double rc[3];
+        cross3(r, cd, rc);
+        const double gv[6] = {cd[0], cd[1], cd[2], rc[0], rc[1], rc[2]};
+        const double coef = 6.0 * w * rho0;
+        for (int a = 0; a < 3; a++) { acc[a] += dp[a]; acc[3 + a] += t[a]; }
+        int j = 6;
+        for (int i1 = 0; i1 < 6; i1++)
+            for (int i2 = i1; i2 < 6; i2++) acc[j++] += coef * gv[i1] * gv[i2];
+        acc[27] += cap ? 1.0 : 0.0;
+    }
+    block_sum<28>(acc, lds);
+    if (threadIdx.x != 0) return;
+    double Z[36];
+    {
+        int j = 6;
+        for (int i1 = 0; i1 < 6; i1++)
+            for (int i2 = i1; i2 < 6; i2++) { Z[6 * i1 + i2] = acc[j]; Z[6 * i2 + i1] = acc[j]; j++; }
+    }
+    double Fk[6], X[6] = {V[0], V[1], V[2], W[0], W[1], W[2]}, Xn[6];
+    for (int a = 0; a < 3; a++) {
+        q.F0[a] = acc[a];
+        q.T0[a] = acc[3 + a];
+        Fk[a] = acc[a] + q.trF[a];
+        Fk[3 + a] = acc[3 + a] + q.trT[a];
+    }
+    if (q.fixed) {
+        for (int i = 0; i < 6; i++) Xn[i] = X[i];
+    } else {
+        const double Mv[6] = {q.mass, q.mass, q.mass, q.inertia, q.inertia, q.inertia};
+        double A[36], bb[6];
+        for (int i = 0; i < 36; i++) A[i] = Z[i];
+        for (int i = 0; i < 6; i++) { A[6 * i + i] += Mv[i]; bb[i] = Mv[i] * X[i] + Fk[i]; }
+        // Gaussian elimination without pivoting (M + zeta is symmetric positive definite)
+        for (int c = 0; c < 6; c++)
+            for (int i = c + 1; i < 6; i++) {
+                const double l = A[6 * i + c] / A[6 * c + c];
+                for (int j = c; j < 6; j++) A[6 * i + j] -= l * A[6 * c + j];
+                bb[i] -= l * bb[c];
+            }
+        for (int i = 5; i >= 0; i--) {
+            double s = bb[i];
+            for (int j = i + 1; j < 6; j++) s -= A[6 * i + j] * Xn[j];
+            Xn[i] = s / A[6 * i + i];
+        }
+    }
+    for (int i = 0; i < 6; i++) {
+        double s = Fk[i];
+        for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * Xn[j];
+        if (i < 3) q.F[i] = s; else q.T[i - 3] = s;
+    }
+    q.nactive = (int)acc[27];
+    for (int a = 0; a < 3; a++) { q.trF[a] = 0.0; q.trT[a] = 0.0; }
+    if (q.fixed) return;
+    const int L[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; a++) {
+        q.vel[a] = Xn[a];
+        q.omega[a] = Xn[3 + a];
+        double rr = q.pos[a] + Xn[a];
+        if (rr >= (double)L[a]) rr -= (double)L[a];
+        else if (rr < 0.0) rr += (double)L[a];
+        q.pos[a] = rr;
+    }
+    if (fabs(Xn[0]) >= 0.5 || fabs(Xn[1]) >= 0.5 || fabs(Xn[2]) >= 0.5) atomicOr(err, LB_ERR_FAST);
+    const double th = sqrt(Xn[3] * Xn[3] + Xn[4] * Xn[4] + Xn[5] * Xn[5]);
+    if (th > 0.0) {
+        const double ax[3] = {Xn[3] / th, Xn[4] / th, Xn[5] / th};
+        double kxm[3];
+        cross3(ax, q.m, kxm);
+        const double km = ax[0] * q.m[0] + ax[1] * q.m[1] + ax[2] * q.m[2];
+        const double cs = cos(th), sn = sin(th);
+        double mn[3];
+        for (int a = 0; a < 3; a++) mn[a] = q.m[a] * cs + kxm[a] * sn + ax[a] * km * (1.0 - cs);
+        const double nn = sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+        for (int a = 0; a < 3; a++) q.m[a] = mn[a] / nn;
+    }
+}
+
+// ------------------------------------------------------------- k_cover
+// One block per particle, over its bounding box at the new position.  A fluid
+// node now inside hands its momentum sum_i f_i c_i to the particle; a node of
+// this particle now outside is refilled with f^eq(rho0, V + Omega x r) (the
+// particle is debited rho0 (V + Omega x r)) and takes psi, c as the mean of
+// its face neighbours that are fluid before and after.  Transfers are summed
+// in FP64 and applied in the next rigid-body update.
+template <int P>
+__global__ __launch_bounds__(256) void k_cover(KParams p, DColloid *__restrict__ col,
+                                               typename Prec<P>::T *__restrict__ f,
+                                               typename Prec<P>::S *__restrict__ psi,
+                                               typename Prec<P>::S *__restrict__ cc,
+                                               const uint8_t *__restrict__ own,
+                                               int *__restrict__ err)
+{
+    typedef typename Prec<P>::S S;
+    __shared__ double lds[6 * 16];
+    const int k = blockIdx.x;
+    DColloid &q = col[k];
+    const size_t N = (size_t)p.N;
+    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
+    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
+    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
+    const int total = bx.count * by.count * bz.count;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int sy = p.nx, sz = p.nx * p.ny;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
+        const int x = bx.at(ix), y = by.at(iy), z = bz.at(iz);
+        const int n = x + sy * y + sz * z;
+        const int old = own[n] & OWN_SOLID;
+        const bool ins = inside(q, x, y, z, p.nx, p.ny, p.nz);
+        if (ins && old == 0) {
+            double pm[3] = {0.0, 0.0, 0.0}, r[3], tq[3];
+            for (int i = 1; i < 19; i++) {
+                const double gi = (double)ld_pop(f, i * N + n, p.inv_scale);
+                pm[0] += cx(i) * gi;
+                pm[1] += cy(i) * gi;
+                pm[2] += cz(i) * gi;
+            }
+            displacement(q, x, y, z, 0, 0, 0, 0.0, p.nx, p.ny, p.nz, r);
+            cross3(r, pm, tq);
+            for (int a = 0; a < 3; a++) { acc[a] += pm[a]; acc[3 + a] += tq[a]; }
+        } else if (ins && old != k + 1) {
+            atomicOr(err, LB_ERR_CONTACT);
+        } else if (!ins && old == k + 1) {
+            double r[3], uw[3], tq[3], pm[3];
+            displacement(q, x, y, z, 0, 0, 0, 0.0, p.nx, p.ny, p.nz, r);
+            cross3(q.omega, r, uw);
+            for (int a = 0; a < 3; a++) uw[a] += q.vel[a];
+            const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+            for (int i = 0; i < 19; i++) {
+                const double cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+                const double geq = wgt(i) * p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                st_pop(f, i * N + n, (S)geq, p.scale);
+            }
+            for (int a = 0; a < 3; a++) pm[a] = p.rho0 * uw[a];
+            cross3(r, pm, tq);
+            for (int a = 0; a < 3; a++) { acc[a] -= pm[a]; acc[3 + a] -= tq[a]; }
+            const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                               n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                               n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+            const int fx[6] = {wrap_p(x, p.nx), wrap_m(x, p.nx), x, x, x, x};
+            const int fy[6] = {y, y, wrap_p(y, p.ny), wrap_m(y, p.ny), y, y};
+            const int fz[6] = {z, z, z, z, wrap_p(z, p.nz), wrap_m(z, p.nz)};
+            double sp = 0.0, sc = 0.0;
+            int cnt = 0;
+            for (int e = 0; e < 6; e++) {
+                if ((own[fn[e]] & OWN_SOLID) == 0 && !inside(q, fx[e], fy[e], fz[e], p.nx, p.ny, p.nz)) {
+                    sp += (double)psi[fn[e]];
+                    sc += (double)cc[fn[e]];
+                    cnt++;
+                }
+            }
+            if (cnt > 0) { psi[n] = (S)(sp / cnt); cc[n] = (S)(sc / cnt); }
+        }
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; a++) { q.trF[a] += acc[a]; q.trT[a] += acc[3 + a]; }
+}
+
+// ------------------------------------------------------------- k_commit
+// Owner bytes at the new position: inside -> k+1, left behind -> fluid.
+__global__ __launch_bounds__(256) void k_commit(KParams p, const DColloid *__restrict__ col,
+                                                uint8_t *__restrict__ own)
+{
+    const int k = blockIdx.x;
+    const DColloid &q = col[k];
+    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
+    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
+    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
+    const int total = bx.count * by.count * bz.count;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
+        const int x = bx.at(ix), y = by.at(iy), z = bz.at(iz);
+        const int n = x + sy * y + sz * z;
+        const bool ins = inside(q, x, y, z, p.nx, p.ny, p.nz);
+        const uint8_t o = own[n];
+        if (ins) {
+            if ((o & OWN_SOLID) != k + 1) own[n] = (uint8_t)(k + 1);
+        } else if ((o & OWN_SOLID) == k + 1) {
+            own[n] = 0;
+        }
+    }
+}
+
+// --------------------------------------------------------------- k_links
+// Boundary bits and the link table of particle k in canonical order
+// (ascending node, then direction), by a block-wide exclusive scan over the
+// bounding box visited in ascending node order.
+__device__ int block_exclusive_scan(int v, int *lds, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int s = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(s, off, 64);
+        if (lane >= off) s += t;
+    }
+    if (lane == 63) lds[wave] = s;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; w++) base += lds[w];
+    total = 0;
+    for (int w = 0; w < nw; w++) total += lds[w];
+    __syncthreads();
+    return base + s - v;
+}
+
+__global__ __launch_bounds__(256) void k_links(KParams p, DColloid *__restrict__ col,
+                                               uint8_t *__restrict__ own, int *__restrict__ lnode,
+                                               uint8_t *__restrict__ ldc, int lcap,
+                                               int *__restrict__ err)
+{
+    __shared__ int lds[16];
+    const int k = blockIdx.x;
+    DColloid &q = col[k];
+    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
+    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
+    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
+    const int total = bx.count * by.count * bz.count;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    int base = 0, nact = 0;
+    for (int t0 = 0; t0 < total; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        int cnt = 0;
+        uint32_t mask = 0;  // directions linked to k, bit d
+        int x = 0, y = 0, z = 0, n = 0;
+        if (t < total) {
+            const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
+            x = bx.at(ix);
+            y = by.at(iy);
+            z = bz.at(iz);
+            n = x + sy * y + sz * z;
+            const uint8_t o = own[n];
+            if ((o & OWN_SOLID) == 0) {
+                bool bnd = false;
+                const int xs[3] = {wrap_m(x, p.nx), x, wrap_p(x, p.nx)};
+                const int ys[3] = {wrap_m(y, p.ny), y, wrap_p(y, p.ny)};
+                const int zs[3] = {wrap_m(z, p.nz), z, wrap_p(z, p.nz)};
+                for (int d = 1; d < 19; d++) {
+                    const int m = xs[cx(d) + 1] + sy * ys[cy(d) + 1] + sz * zs[cz(d) + 1];
+                    const int om = own[m] & OWN_SOLID;
+                    if (om) bnd = true;
+                    if (om == k + 1) { mask |= 1u << d; cnt++; }
+                }
+                const uint8_t want = bnd ? OWN_BOUNDARY : 0;
+                if (o != want) own[n] = want;
+            }
+        }
+        int tot;
+        const int off = block_exclusive_scan(cnt, lds, tot);
+        if (cnt) {
+            int l = base + off;
+            for (int d = 1; d < 19; d++) {
+                if (!(mask & (1u << d))) continue;
+                double r[3];
+                displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
+                const bool cap = active_cap(q, r);
+                nact += cap ? 1 : 0;
+                if (l < lcap) {
+                    lnode[(size_t)k * lcap + l] = n;
+                    ldc[(size_t)k * lcap + l] = (uint8_t)(d | (cap ? 0x80 : 0));
+                }
+                l++;
+            }
+        }
+        base += tot;
+    }
+    // active count: sum over the block
+    double a[1] = {(double)nact};
+    __shared__ double ldsd[16];
+    block_sum<1>(a, ldsd);
+    if (threadIdx.x == 0) {
+        if (base > lcap) atomicOr(err, LB_ERR_LINKS);
+        q.nlinks = base;
+        q.nactive = (int)a[0];
+    }
+}
+
+// --------------------------------------------------------------- k_init
+template <int P>
+__global__ __launch_bounds__(256) void k_init(KParams p, const double *__restrict__ psi0,
+                                              const double *__restrict__ c0,
+                                              const double *__restrict__ rho0,
+                                              const double *__restrict__ u0,
+                                              typename Prec<P>::T *__restrict__ f,
+                                              typename Prec<P>::S *__restrict__ psi,
+                                              typename Prec<P>::S *__restrict__ cc,
+                                              uint8_t *__restrict__ own)
+{
+    typedef typename Prec<P>::S S;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const size_t N = (size_t)p.N;
+    const double r = rho0 ? rho0[n] : p.rho0;
+    const double ux = u0 ? u0[n] : 0.0, uy = u0 ? u0[N + n] : 0.0, uz = u0 ? u0[2 * N + n] : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < 19; i++) {
+        const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        const double geq = wgt(i) * (r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) - p.rho0);
+        st_pop(f, i * N + n, (S)geq, p.scale);
+    }
+    psi[n] = (S)psi0[n];
+    cc[n] = (S)c0[n];
+    own[n] = 0;
+}
+
+// ------------------------------------------------------------ k_reduce
+// FP64 totals over fluid nodes: sum_i f_i, sum_i f_i c_i, psi, c, count.
+template <int P>
+__global__ __launch_bounds__(256) void k_reduce(KParams p, const typename Prec<P>::T *__restrict__ f,
+                                                const typename Prec<P>::S *__restrict__ psi,
+                                                const typename Prec<P>::S *__restrict__ cc,
+                                                const uint8_t *__restrict__ own,
+                                                double *__restrict__ part)
+{
+    __shared__ double lds[7 * 16];
+    const size_t N = (size_t)p.N;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < p.N; n += gridDim.x * blockDim.x) {
+        if (own[n] & OWN_SOLID) continue;
+        double m = p.rho0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < 19; i++) {
+            const double g = (double)ld_pop(f, i * N + n, p.inv_scale);
+            m += g;
+            jx += cx(i) * g;
+            jy += cy(i) * g;
+            jz += cz(i) * g;
+        }
+        v[0] += m;
+        v[1] += jx;
+        v[2] += jy;
+        v[3] += jz;
+        v[4] += (double)psi[n];
+        v[5] += (double)cc[n];
+        v[6] += 1.0;
+    }
+    block_sum<7>(v, lds);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 7; j++) part[blockIdx.x * 7 + j] = v[j];
+}
+
+__global__ void k_reduce_final(const double *__restrict__ part, int nblocks, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int j = 0; j < 7; j++) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; b++) s += part[b * 7 + j];
+        out[j] = s;
+    }
+}
+
+// ------------------------------------------------------------ k_fields
+template <int P>
+__global__ __launch_bounds__(256) void k_fields(KParams p, const typename Prec<P>::T *__restrict__ f,
+                                                const typename Prec<P>::S *__restrict__ psi,
+                                                const typename Prec<P>::S *__restrict__ cc,
+                                                const uint8_t *__restrict__ own,
+                                                double *__restrict__ out /* 6N: rho u psi c */,
+                                                double *__restrict__ fout /* 19N or null */)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const size_t N = (size_t)p.N;
+    double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    const bool fluid = (own[n] & OWN_SOLID) == 0;
+    for (int i = 0; i < 19; i++) {
+        const double g = (double)ld_pop(f, i * N + n, p.inv_scale);
+        if (fout) fout[i * N + n] = g + wgt(i) * p.rho0;
+        m += g;
+        jx += cx(i) * g;
+        jy += cy(i) * g;
+        jz += cz(i) * g;
+    }
+    if (!out) return;
+    m += p.rho0;
+    out[n] = fluid ? m : 0.0;
+    out[N + n] = fluid ? jx / m : 0.0;
+    out[2 * N + n] = fluid ? jy / m : 0.0;
+    out[3 * N + n] = fluid ? jz / m : 0.0;
+    out[4 * N + n] = (double)psi[n];
+    out[5 * N + n] = (double)cc[n];
+}
+
+// ------------------------------------------------------------ launchers
+static dim3 lattice_grid(const KParams &p) { return dim3((p.nx + 63) / 64, (p.ny + 3) / 4, p.nz); }
+static const dim3 LATTICE_BLOCK(64, 4, 1);
+
+template <int P>
+void launch_step_lattice(const KParams &p, const StepBuffers &b, hipStream_t s, TimingHook *tm)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    const dim3 g = lattice_grid(p);
+    if (tm) tm->begin(0, s);
+    k_mu<S><<<g, LATTICE_BLOCK, 0, s>>>(p, (const S *)b.psi, (const S *)b.cc, b.own, b.col, (S *)b.mu);
+    if (tm) tm->end(0, s);
+    if (tm) tm->begin(1, s);
+    k_collide<P><<<g, LATTICE_BLOCK, 0, s>>>(p, (const T *)b.fin, (T *)b.fout, (const S *)b.psi,
+                                              (const S *)b.mu, b.own, (S *)b.u);
+    if (tm) tm->end(1, s);
+    if (tm) tm->begin(2, s);
+    k_scalar<S><<<g, LATTICE_BLOCK, 0, s>>>(p, (const S *)b.psi, (const S *)b.cc, (const S *)b.mu,
+                                            (const S *)b.u, b.own, b.col, (S *)b.psin, (S *)b.ccn);
+    if (tm) tm->end(2, s);
+}
+
+template <int P>
+void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s,
+                           TimingHook *tm)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    if (ncol <= 0) return;
+    if (tm) tm->begin(3, s);
+    k_links_colloid<P><<<ncol, 256, 0, s>>>(p, b.col, b.lnode, b.ldc, b.lcap, (T *)b.fout,
+                                             (const S *)b.cc, b.own, b.err);
+    if (tm) tm->end(3, s);
+    if (tm) tm->begin(4, s);
+    k_cover<P><<<ncol, 256, 0, s>>>(p, b.col, (T *)b.fout, (S *)b.psin, (S *)b.ccn, b.own, b.err);
+    if (tm) tm->end(4, s);
+    if (tm) tm->begin(5, s);
+    k_commit<<<ncol, 256, 0, s>>>(p, b.col, b.own);
+    k_links<<<ncol, 256, 0, s>>>(p, b.col, b.own, b.lnode, b.ldc, b.lcap, b.err);
+    if (tm) tm->end(5, s);
+}
+
+void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s)
+{
+    if (ncol <= 0) return;
+    k_commit<<<ncol, 256, 0, s>>>(p, b.col, b.own);
+    k_links<<<ncol, 256, 0, s>>>(p, b.col, b.own, b.lnode, b.ldc, b.lcap, b.err);
+}
+
+template <int P>
+void launch_init(const KParams &p, const double *psi0, const double *c0, const double *rho0,
+                 const double *u0, void *f, void *psi, void *cc, uint8_t *own, hipStream_t s)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    k_init<P><<<(p.N + 255) / 256, 256, 0, s>>>(p, psi0, c0, rho0, u0, (T *)f, (S *)psi, (S *)cc, own);
+}
+
+template <int P>
+void launch_reduce(const KParams &p, const void *f, const void *psi, const void *cc,
+                   const uint8_t *own, double *part, int nblocks, double *out, hipStream_t s)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    k_reduce<P><<<nblocks, 256, 0, s>>>(p, (const T *)f, (const S *)psi, (const S *)cc, own, part);
+    k_reduce_final<<<1, 64, 0, s>>>(part, nblocks, out);
+}
+
+template <int P>
+void launch_fields(const KParams &p, const void *f, const void *psi, const void *cc,
+                   const uint8_t *own, double *out, double *fout, hipStream_t s)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    k_fields<P><<<(p.N + 255) / 256, 256, 0, s>>>(p, (const T *)f, (const S *)psi, (const S *)cc,
+                                                  own, out, fout);
+}
+
+#define LB_INSTANTIATE(P)                                                                          \
+    template void launch_step_lattice<P>(const KParams &, const StepBuffers &, hipStream_t,         \
+                                         TimingHook *);                                             \
+    template void launch_step_particles<P>(const KParams &, const StepBuffers &, int, hipStream_t,  \
+                                           TimingHook *);                                           \
+    template void launch_init<P>(const KParams &, const double *, const double *, const double *,   \
+                                 const double *, void *, void *, void *, uint8_t *, hipStream_t);   \
+    template void launch_reduce<P>(const KParams &, const void *, const void *, const void *,       \
+                                   const uint8_t *, double *, int, double *, hipStream_t);          \
+    template void launch_fields<P>(const KParams &, const void *, const void *, const void *,       \
+                                   const uint8_t *, double *, double *, hipStream_t);
+
+LB_INSTANTIATE(LB_FP64)
+LB_INSTANTIATE(LB_FP32)
+LB_INSTANTIATE(LB_FP16_STORAGE)
+
+}  // namespace lbk

@@ -1,0 +1,55 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/lb.h declares; host-only helpers agree with the oracle's."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2202_01631_amd import lb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9A-Z]+)\s*\(", text)))
+
+
+def test_library_built():
+    assert os.path.exists(lb.LIB_PATH), "run python -m paper_2202_01631_amd.build"
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert "lb_create" in names and "lb_step" in names and "lb_observables" in names
+    L = C.CDLL(lb.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(lb.EXPORTS)
+
+
+def test_host_parameter_maps_match_oracle():
+    for th in (0.0, 30.0, 45.0, 60.0, 90.0, 120.0, 135.0, 180.0):
+        assert lb.wetting_H(th, 0.04, 0.0625) == pytest.approx(oracle.wetting_H(th, 0.04, 0.0625), abs=1e-15)
+    assert math.isnan(lb.wetting_H(60.0, 0.0, 0.0625))
+    for r in (1.0, 2.0, 3.5, 5.0):
+        assert lb.solubility_E(r, 0.5) == pytest.approx(oracle.solubility_E(r, 0.5), rel=1e-15)
+
+
+def test_footprint_is_host_only():
+    n32 = lb.footprint_bytes((256, 256, 256), "fp32")
+    n64 = lb.footprint_bytes((256, 256, 256), "fp64")
+    n16 = lb.footprint_bytes((256, 256, 256), "fp16")
+    N = 256 ** 3
+    # two population lattices + psi, c twice + mu + u + owner byte
+    assert n32 >= N * (2 * 19 * 4 + 4 * 4 + 4 + 12 + 1)
+    assert n64 >= N * (2 * 19 * 8 + 4 * 8 + 8 + 24 + 1)
+    assert n16 >= N * (2 * 19 * 2 + 4 * 4 + 4 + 12 + 1)
+    assert n16 < n32 < n64
+    with pytest.raises(lb.LBError):
+        lb.footprint_bytes((0, 4, 4), "fp32")

@@ -1,0 +1,258 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on
+identical seeded inputs.
+
+Bars: link tables and owner maps bit-exact; FP64 fields <= 1e-12 (error
+measure in parity_util); FP32 <= 2e-5 after 1000 steps; FP16 storage within
+the stated per-field bounds.  Particle velocities are compared against a
+bound derived from the summation error of the momentum exchange (the GPU
+sums the link momenta in a fixed tree, the oracle sequentially)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_01631_amd import inputs as I
+from paper_2202_01631_amd import lb
+from parity_util import field_errors, flush_print, run_pair
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _spec(shape, seed=7, E=-0.2, colloids=(), amp=0.05, **kw):
+    N = int(np.prod(shape))
+    psi = I.slab(shape, I.WIDTH, amp=amp, seed=seed)
+    c = 0.3 + I.noise(seed + 1, N, 0.05)
+    p = dict(I.FREE_ENERGY)
+    p["E"] = E
+    p.update(kw)
+    return dict(name="slab%s" % (shape,), shape=shape, precision="fp64", params=p,
+                psi=psi, c=c, colloids=list(colloids))
+
+
+def _compare(g, o, tol, what=""):
+    fl = o.owner() < 0
+    assert np.array_equal(g.owner() < 0, fl), "owner maps differ"
+    e = field_errors(g.fields(), o.fields(), fl)
+    flush_print("[parity] %s errors %s" % (what, e))
+    for k, v in e.items():
+        assert v <= tol[k] if isinstance(tol, dict) else v <= tol, (k, v)
+    return e
+
+
+# ------------------------------------------------------------------ FP64
+@pytest.mark.parametrize("shape", [(70, 9, 11), (16, 16, 16), (1, 1, 40), (33, 5, 1)])
+def test_fp64_lattice_matches_oracle(shape):
+    # no particles; ragged tiles (70 = 64 + 6 in x, 9 = 2*4 + 1 in y),
+    # degenerate one-node axes
+    g, o = run_pair(_spec(shape), 40, ext_force=(1e-6, 0.0, -2e-6))
+    _compare(g, o, 1e-12, "fp64 %s" % (shape,))
+    fo, fg = o.populations(), g.populations()
+    assert np.abs(fo - fg).max() <= 1e-13
+
+
+def test_fp64_one_step_populations():
+    g, o = run_pair(_spec((20, 12, 9), tau=0.8), 1)
+    assert np.abs(o.populations() - g.populations()).max() <= 8 * EPS
+
+
+def test_fp64_box32_workload():
+    # the 32^3 FP64 workload: flat interface with noise, 2:1 solubility,
+    # moving Janus sphere of radius 4, 200 steps
+    w = I.workload_small()
+    g = lb.from_spec(w)
+    o = oracle.from_spec(w)
+    # link tables at t = 0: bit-exact
+    assert np.array_equal(g.links(), o.links())
+    assert np.array_equal(g.owner(), o.owner())
+    for block in range(4):
+        g.step(50)
+        o.step(50)
+        flush_print("[parity] box32 step", 50 * (block + 1))
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+        _compare(g, o, 1e-12, "box32 t=%d" % (50 * (block + 1)))
+    tg, cg = g.observables()
+    to, co = o.observables()
+    assert tg["n_links"] == to["n_links"] and tg["n_active"] == to["n_active"]
+    # particle velocity: the link momenta sum to F with rounding at most
+    # (links) * eps * sum|dp|; the velocity error per step is that over the
+    # mass, accumulated over the steps
+    nl = to["n_links"]
+    mass = 4.0 / 3.0 * math.pi * 4.0 ** 3
+    bound = 200 * nl * EPS * nl * 0.5 / mass
+    for a in ("vel", "omega"):
+        assert np.abs(cg[0][a] - co[0][a]).max() <= bound, (a, cg[0][a], co[0][a])
+    assert np.abs(cg[0]["pos"] - co[0]["pos"]).max() <= 200 * bound
+    assert np.abs(cg[0]["m"] - co[0]["m"]).max() <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp64_several_moving_colloids(seed):
+    # three free particles with different caps, mobilities and wetting, one
+    # straddling the periodic boundary, launched with velocities so that
+    # cover/uncover happens; 60 steps
+    shape = (40, 36, 34)
+    u = I.uniform(seed, 30)
+    cols = [
+        I.janus((2.0 + u[0], 18.0 + u[1], 17.0 + u[2]), I.unit_vectors(seed, 1)[0], 4.2,
+                alpha=2e-3, mu=0.3, theta=60.0),
+        I.janus((20.0 + u[3], 6.0 + u[4], 9.0 + u[5]), I.unit_vectors(seed + 1, 1)[0], 3.6,
+                alpha=1e-3, mu_minus=0.2, mu_plus=-0.1, theta=120.0),
+        I.janus((24.0 + u[6], 26.0 + u[7], 25.0 + u[8]), I.unit_vectors(seed + 2, 1)[0], 5.1,
+                alpha=0.0, mu=-0.2, theta=90.0, rho_p=2.0),
+    ]
+    cols[0]["vel"] = np.array([0.04, -0.01, 0.02])
+    cols[1]["omega"] = np.array([0.0, 0.03, -0.02])
+    cols[2]["vel"] = np.array([-0.02, 0.03, 0.01])
+    spec = _spec(shape, seed=seed, colloids=cols)
+    g, o = run_pair(spec, 0)
+    assert np.array_equal(g.links(), o.links())
+    changed = 0
+    for _ in range(6):
+        own0 = o.owner()
+        g.step(10)
+        o.step(10)
+        changed += int((o.owner() != own0).sum())
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+    assert changed > 0
+    _compare(g, o, 1e-12, "3 colloids")
+    _, cg = g.observables()
+    _, co = o.observables()
+    for k in range(3):
+        for a in ("vel", "omega", "pos", "m"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+    # forces of the last step
+    fg = g.colloid_forces()
+    for k in range(3):
+        fo = o.colloid_diag(k)
+        assert np.abs(fg["F0"][k] - fo["F0"]).max() <= 1e-11
+        assert np.abs(fg["F"][k] - fo["F"]).max() <= 1e-11
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_link_tables_bit_exact_random(seed):
+    # many spheres at random non-integer positions, across the periodic
+    # boundary, random axes: owner map and canonical link table bit-exact
+    shape = (48, 40, 44)
+    pts = I.place_spheres(shape, 10, 4.0, lambda a, b: 44.0 * a, 2.0, seed)
+    rad = 2.5 + 1.5 * I.uniform(seed + 9, 10)
+    cols = [dict(pos=pts[k], m=I.unit_vectors(seed + 20 + k, 1)[0], radius=float(rad[k]))
+            for k in range(10)]
+    spec = _spec(shape, seed=seed, colloids=cols)
+    g, o = run_pair(spec, 0)
+    assert np.array_equal(g.owner(), o.owner())
+    assert np.array_equal(g.links(), o.links())
+    tg, _ = g.observables()
+    to, _ = o.observables()
+    assert (tg["n_links"], tg["n_active"], tg["n_fluid"]) == (to["n_links"], to["n_active"], to["n_fluid"])
+
+
+def test_integer_ties():
+    # integer centre and radius: nodes exactly on the sphere stay fluid,
+    # links exactly on the equator (m.n = 0) are active
+    spec = _spec((32, 32, 32), colloids=[dict(pos=(16.0, 16.0, 12.0), m=(0, 0, 1), radius=4.0)])
+    g, o = run_pair(spec, 0)
+    links = g.links()
+    assert len(links) == 1050 and int(links[:, 3].sum()) == 561
+    assert int((g.owner() >= 0).sum()) == 251
+    assert np.array_equal(links, o.links())
+
+
+def test_totals_match_oracle():
+    w = I.workload_small()
+    g, o = run_pair(w, 20)
+    tg, _ = g.observables()
+    to, _ = o.observables()
+    N = 32 ** 3
+    assert tg["n_fluid"] == to["n_fluid"]
+    # both are FP64 sums of N*19 terms of size <= 1; sequential (oracle)
+    # against tree (GPU) summation: bound 19 N eps * total
+    assert abs(tg["mass"] - to["mass"]) <= 19 * N * EPS * to["mass"]
+    assert abs(tg["sum_psi"] - to["sum_psi"]) <= N * EPS * N
+    assert abs(tg["sum_c"] - to["sum_c"]) <= N * EPS * N
+    assert np.abs(tg["mom"] - to["mom"]).max() <= 19 * N * EPS
+
+
+# ------------------------------------------------------------------ FP32
+def test_fp32_1000_steps_within_2e5():
+    # FP32 shifted storage against the FP64 oracle after 1000 steps, with a
+    # fixed emitting, slipping, wetting sphere (geometry identical on both
+    # sides) in a 24^3 box
+    shape = (24, 24, 24)
+    col = I.janus((11.3, 12.6, 10.8), (0.3, 0.4, 0.866), 4.0, alpha=1e-3, mu=0.2, theta=70.0,
+                  fixed=1)
+    spec = I.workload_small()
+    spec = dict(spec, shape=shape, psi=I.flat_interface(shape, 12.0, I.WIDTH, 0.01, 99),
+                c=np.zeros(24 ** 3), colloids=[col])
+    g, o = run_pair(spec, 1000, precision="fp32")
+    e = _compare(g, o, 2e-5, "fp32 1000 steps")
+    assert max(e.values()) > 0.0
+
+
+def test_fp32_moving_particle_short():
+    # free particle, 200 steps: FP32 against FP64 within 2e-5 as long as the
+    # geometry has not diverged
+    w = I.workload_small()
+    w = dict(w, colloids=[dict(w["colloids"][0], pos=np.array([16.3, 15.8, 12.2]))])
+    g, o = run_pair(w, 200, precision="fp32")
+    assert np.array_equal(g.owner(), o.owner())
+    _compare(g, o, 2e-5, "fp32 moving")
+
+
+# ------------------------------------------------------------------ FP16
+def test_fp16_storage_error_bounds():
+    # FP16 storage of (f - w rho0) * 2^14 with FP32 arithmetic: per-field
+    # error against the FP64 oracle after 500 steps, bounds stated here
+    # (half precision keeps 11 significant bits: 2^-11 ~ 5e-4 relative on
+    # each stored deviation)
+    shape = (24, 24, 24)
+    col = I.janus((11.3, 12.6, 10.8), (0.3, 0.4, 0.866), 4.0, alpha=1e-3, mu=0.2, theta=70.0,
+                  fixed=1)
+    spec = I.workload_small()
+    spec = dict(spec, shape=shape, psi=I.flat_interface(shape, 12.0, I.WIDTH, 0.01, 99),
+                c=np.zeros(24 ** 3), colloids=[col])
+    g, o = run_pair(spec, 500, precision="fp16")
+    _compare(g, o, dict(rho=2e-5, psi=1e-3, c=1e-2, u=1e-1), "fp16 500 steps")
+
+
+# -------------------------------------------------------- state handling
+def test_determinism_and_bitwise_resume():
+    w = I.workload_small()
+    a = lb.from_spec(w)
+    a.step(30)
+    snap = a.save_state()
+    a.step(30)
+    fa = a.populations()
+    b = lb.from_spec(w)
+    b.step(60)
+    assert np.array_equal(fa, b.populations())  # run-to-run bitwise
+    c = lb.Box(w["shape"], "fp64", **dict(w["params"], E=lb.solubility_E(2.0, 0.5)))
+    c.init_fields(w["psi"], w["c"])
+    c.load_state(snap)
+    c.step(30)
+    assert np.array_equal(fa, c.populations())  # save/load resume bitwise
+    assert np.array_equal(a.fields()["psi"], c.fields()["psi"])
+
+
+def test_error_paths():
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", tau=0.5)
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.4)
+    b = lb.Box((20, 20, 20), "fp32", a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.1)
+    with pytest.raises(lb.LBError):
+        b.step(1)  # before init_fields
+    b.init_fields(np.ones(8000), np.zeros(8000))
+    with pytest.raises(lb.LBError):
+        b.add_colloids([dict(pos=(5, 5, 5), radius=3.0), dict(pos=(11, 5, 5), radius=3.0)])
+    with pytest.raises(lb.LBError):
+        b.add_colloids([dict(pos=(5, 5, 5), radius=7.0)])  # 2R + 8 > 20
+    with pytest.raises(lb.LBError):
+        b.init_fields(np.full(8000, np.nan), np.zeros(8000))
+    b.add_colloids([])
+    b.step(3)
+    t, _ = b.observables()
+    assert t["n_links"] == 0 and t["step"] == 3 and t["error_bits"] == 0
