@@ -2,6 +2,7 @@
 // device memory layout, per-step launch sequence, readback.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -21,9 +22,9 @@ size_t storage_bytes(int prec) { return prec == LB_FP64 ? 8 : (prec == LB_FP32 ?
 size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 
 // Arena layout (each piece 256-byte aligned): f[2] (19 N storage), psi[2],
-// c[2], mu (N compute), u (3N compute), owner (N bytes).
+// c[2], mu and chi (N compute each), u (3N compute), owner (N bytes).
 struct Layout {
-    size_t f[2], psi[2], cc[2], mu, u, own, total;
+    size_t f[2], psi[2], cc[2], mu, chi, u, own, total;
 };
 
 Layout layout_of(const lb_params &p)
@@ -36,6 +37,7 @@ Layout layout_of(const lb_params &p)
     for (int b = 0; b < 2; b++) { L.psi[b] = o; o = align256(o + N * cb); }
     for (int b = 0; b < 2; b++) { L.cc[b] = o; o = align256(o + N * cb); }
     L.mu = o; o = align256(o + N * cb);
+    L.chi = o; o = align256(o + N * cb);
     L.u = o; o = align256(o + 3 * N * cb);
     L.own = o; o = align256(o + N);
     L.total = o;
@@ -60,11 +62,16 @@ struct lb_ctx {
     DColloid *dcol;
     int *lnode;
     uint8_t *ldc;
+    double *cpart;
+    uint32_t *lmask;
+    int *ccount;
+    int bbmax, nchunk_max;
     int *derr;
     double *part;   // reduction partials
     double *dsum;   // 7 totals
     int nred;
     TimingHook *timing;
+    LatticeShapes shapes;
     std::string err;
 };
 
@@ -98,6 +105,7 @@ static StepBuffers buffers(lb_ctx *c)
     b.psin = ptr(c, c->L.psi[nx]);
     b.ccn = ptr(c, c->L.cc[nx]);
     b.mu = ptr(c, c->L.mu);
+    b.chi = ptr(c, c->L.chi);
     b.u = ptr(c, c->L.u);
     b.own = (uint8_t *)ptr(c, c->L.own);
     b.col = c->dcol;
@@ -105,6 +113,11 @@ static StepBuffers buffers(lb_ctx *c)
     b.ldc = c->ldc;
     b.lcap = c->lcap;
     b.err = c->derr;
+    b.cpart = c->cpart;
+    b.lmask = c->lmask;
+    b.ccount = c->ccount;
+    b.bbmax = c->bbmax;
+    b.nchunk_max = c->nchunk_max;
     return b;
 }
 
@@ -169,7 +182,7 @@ TimingHook::~TimingHook()
 template <int P> static void step_once(lb_ctx *c)
 {
     StepBuffers b = buffers(c);
-    launch_step_lattice<P>(c->kp, b, c->stream, c->timing);
+    launch_step_lattice<P>(c->kp, c->shapes, b, c->stream, c->timing);
     launch_step_particles<P>(c->kp, b, c->ncol, c->stream, c->timing);
 }
 
@@ -208,6 +221,33 @@ static lb_status check_params(const lb_params *p, std::string &why)
         if (!(p->f16_scale > 0.0) || m != 0.5) { why = "f16_scale must be a power of two"; return LB_E_INVALID; }
     }
     return LB_OK;
+}
+
+// Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block,
+// blocks in natural order (measured faster than the XCD-aware renumbering); LB_LATTICE_SHAPES="bx,by,remap;bx,by,remap;bx,by,remap"
+// (mu; collide; scalar, 0 = default) overrides them for tuning sweeps.
+static void set_shapes(lb_ctx *c)
+{
+    LaunchShape d = {0, 0, 0, 0, 0};
+    LaunchShape v[3] = {d, d, d};
+    if (const char *e = getenv("LB_LATTICE_SHAPES")) {
+        for (int k = 0; k < 3 && *e; k++) {
+            int bx = 0, by = 0, rm = 1, used = 0;
+            if (sscanf(e, "%d,%d,%d%n", &bx, &by, &rm, &used) == 3) {
+                v[k].bx = bx;
+                v[k].by = by;
+                v[k].remap = rm;
+                e += used;
+                if (*e == ';') e++;
+            } else {
+                break;
+            }
+        }
+    }
+    for (int k = 0; k < 3; k++) finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz);
+    c->shapes.mu = v[0];
+    c->shapes.collide = v[1];
+    c->shapes.scalar = v[2];
 }
 
 template <int P> static void reduce_t(lb_ctx *c)
@@ -250,6 +290,27 @@ static size_t state_size(lb_ctx *c)
            (sizeof(int) + 1) * (size_t)c->lcap * c->ncol;
 }
 
+// particle tables sized for particles up to radius rmax
+static lb_status alloc_colloid_tables(lb_ctx *c, double rmax, int lcap)
+{
+    const int side = 2 * (int)ceil(rmax) + 8;
+    const int Ls[3] = {c->p.nx, c->p.ny, c->p.nz};
+    long long bb = 1;
+    for (int a = 0; a < 3; a++) bb *= std::min(side, Ls[a]);
+    c->bbmax = (int)bb;
+    c->nchunk_max = (c->bbmax + GCHUNK - 1) / GCHUNK;
+    c->lcap = lcap;
+    const size_t m = (size_t)c->maxcol;
+    HIP_TRY(c, hipMalloc((void **)&c->dcol, sizeof(DColloid) * m));
+    HIP_TRY(c, hipMalloc((void **)&c->lnode, sizeof(int) * (size_t)c->lcap * m));
+    HIP_TRY(c, hipMalloc((void **)&c->ldc, (size_t)c->lcap * m));
+    HIP_TRY(c, hipMalloc((void **)&c->cpart, sizeof(double) * 8 * (size_t)c->nchunk_max * m));
+    HIP_TRY(c, hipMalloc((void **)&c->lmask, sizeof(uint32_t) * (size_t)c->bbmax * m));
+    HIP_TRY(c, hipMalloc((void **)&c->ccount, sizeof(int) * (size_t)c->nchunk_max * m));
+    HIP_TRY(c, hipMemsetAsync(c->cpart, 0, sizeof(double) * 8 * (size_t)c->nchunk_max * m, c->stream));
+    return LB_OK;
+}
+
 extern "C" {
 
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes)
@@ -281,6 +342,7 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     k.fx = p->ext_force[0]; k.fy = p->ext_force[1]; k.fz = p->ext_force[2];
     k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;
     k.inv_scale = 1.0f / k.scale;
+    set_shapes(c);
     c->stream = (hipStream_t)hip_stream;
     c->L = layout_of(c->p);
     if (dev_arena) {
@@ -315,9 +377,15 @@ static void free_colloids(lb_ctx *c)
     if (c->dcol) hipFree(c->dcol);
     if (c->lnode) hipFree(c->lnode);
     if (c->ldc) hipFree(c->ldc);
+    if (c->cpart) hipFree(c->cpart);
+    if (c->lmask) hipFree(c->lmask);
+    if (c->ccount) hipFree(c->ccount);
     c->dcol = nullptr;
     c->lnode = nullptr;
     c->ldc = nullptr;
+    c->cpart = nullptr;
+    c->lmask = nullptr;
+    c->ccount = nullptr;
     c->ncol = 0;
     c->lcap = 0;
 }
@@ -424,6 +492,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
         d.mass = q.rho_p * (4.0 * M_PI / 3.0) * q.radius * q.radius * q.radius;
         d.inertia = 0.4 * d.mass * q.radius * q.radius;
         d.fixed = q.fixed ? 1 : 0;
+        d.changed = 1;  // build the owner map and link table on placement
         rmax = std::max(rmax, q.radius);
     }
     // surfaces at least 2 lattice units apart (minimum image)
@@ -443,10 +512,11 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
     if (n == 0) { c->stage = 2; return LB_OK; }
     // link capacity: 10 links per node of the shell R-1/2 .. R+3/2, plus slack
     const double ro = rmax + 1.5, ri = std::max(0.0, rmax - 0.5);
-    c->lcap = (int)(10.0 * (4.0 / 3.0) * M_PI * (ro * ro * ro - ri * ri * ri)) + 512;
-    HIP_TRY(c, hipMalloc((void **)&c->dcol, sizeof(DColloid) * c->maxcol));
-    HIP_TRY(c, hipMalloc((void **)&c->lnode, sizeof(int) * (size_t)c->lcap * c->maxcol));
-    HIP_TRY(c, hipMalloc((void **)&c->ldc, (size_t)c->lcap * c->maxcol));
+    const int lcap = (int)(10.0 * (4.0 / 3.0) * M_PI * (ro * ro * ro - ri * ri * ri)) + 512;
+    {
+        lb_status st = alloc_colloid_tables(c, rmax, lcap);
+        if (st != LB_OK) { free_colloids(c); return st; }
+    }
     HIP_TRY(c, hipMemcpyAsync(c->dcol, h.data(), sizeof(DColloid) * n, hipMemcpyHostToDevice, c->stream));
     c->ncol = n;
     launch_geometry(c->kp, buffers(c), c->ncol, c->stream);
@@ -502,9 +572,15 @@ lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
         t->sum_psi = sums[4];
         t->sum_c = sums[5];
         t->n_fluid = (int64_t)sums[6];
-        for (int k = 0; k < c->ncol; k++) {
-            t->n_links += h[k].nlinks;
-            t->n_active += h[k].nactive;
+        if (c->ncol > 0) {
+            int64_t nl = 0;
+            lb_status st = lb_get_links(c, nullptr, 0, &nl);
+            if (st != LB_OK) return st;
+            std::vector<int32_t> rec(4 * (size_t)std::max<int64_t>(nl, 1));
+            st = lb_get_links(c, rec.data(), nl, &nl);
+            if (st != LB_OK) return st;
+            t->n_links = nl;
+            for (int64_t l = 0; l < nl; l++) t->n_active += rec[4 * l + 3];
         }
         t->step = c->step;
         int e = herr;
@@ -614,8 +690,12 @@ lb_status lb_get_links(lb_ctx *c, int32_t *rec4, int64_t cap, int64_t *nout)
             const size_t s = (size_t)k * c->lcap + j;
             rec4[4 * l + 0] = k;
             rec4[4 * l + 1] = nodes[s];
-            rec4[4 * l + 2] = dcs[s] & 31;
-            rec4[4 * l + 3] = (dcs[s] & 0x80) ? 1 : 0;
+            const int d = dcs[s] & 31, n = nodes[s];
+            const int z = n / (c->p.nx * c->p.ny), y = (n / c->p.nx) % c->p.ny, x = n % c->p.nx;
+            double r[3];
+            displacement(h[k], x, y, z, cx(d), cy(d), cz(d), 0.5, c->p.nx, c->p.ny, c->p.nz, r);
+            rec4[4 * l + 2] = d;
+            rec4[4 * l + 3] = active_cap(h[k], r) ? 1 : 0;  // cap from the current axis
             l++;
         }
     return LB_OK;
@@ -678,13 +758,21 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
         hd.precision != c->p.precision || hd.ncol > c->maxcol)
         return fail(c, LB_E_INVALID, "state does not match this context");
     free_colloids(c);
-    if (hd.ncol > 0) {
-        c->lcap = hd.lcap;
-        HIP_TRY(c, hipMalloc((void **)&c->dcol, sizeof(DColloid) * c->maxcol));
-        HIP_TRY(c, hipMalloc((void **)&c->lnode, sizeof(int) * (size_t)c->lcap * c->maxcol));
-        HIP_TRY(c, hipMalloc((void **)&c->ldc, (size_t)c->lcap * c->maxcol));
-    }
     c->ncol = hd.ncol;
+    if (hd.ncol > 0) {
+        const DColloid *hc = (const DColloid *)((const char *)buf + sizeof hd +
+                                                19 * (size_t)c->N * storage_bytes(c->p.precision) +
+                                                2 * (size_t)c->N * compute_bytes(c->p.precision) +
+                                                (size_t)c->N);
+        if (n < sizeof hd + 19 * (size_t)c->N * storage_bytes(c->p.precision) +
+                    2 * (size_t)c->N * compute_bytes(c->p.precision) + (size_t)c->N +
+                    sizeof(DColloid) * hd.ncol)
+            return fail(c, LB_E_INVALID, "state too short");
+        double rmax = 0.0;
+        for (int k = 0; k < hd.ncol; k++) rmax = std::max(rmax, hc[k].radius);
+        lb_status st = alloc_colloid_tables(c, rmax, hd.lcap);
+        if (st != LB_OK) { free_colloids(c); c->ncol = 0; return st; }
+    }
     if (n < state_size(c)) return fail(c, LB_E_INVALID, "state too short");
     const size_t N = (size_t)c->N;
     const char *o = (const char *)buf + sizeof hd;

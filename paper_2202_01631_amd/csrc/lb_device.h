@@ -39,6 +39,8 @@ __host__ __device__ constexpr double wgt(int i)
 // neighbours, the only nodes where bounce-back, wetting ghosts, no-flux
 // faces and emission can occur.
 constexpr uint8_t OWN_SOLID = 0x7f;
+constexpr int GCHUNK = 256;        // bounding-box nodes per geometry block
+constexpr int LINK_THREADS = 512;  // threads per particle in the link kernel
 constexpr uint8_t OWN_BOUNDARY = 0x80;
 constexpr int MAX_COLLOIDS = 127;
 
@@ -62,8 +64,16 @@ __device__ __forceinline__ void st_pop(__half *p, size_t i, float v, float sc)
 }
 
 // --------------------------------------------------------- parameter block
+// Shape of a lattice launch: blocks of (bx, by) threads cover an x segment
+// of bx nodes in by consecutive rows (rows = (y, z) flattened).
+struct LaunchShape {
+    int bx, by, remap;         // remap: XCD-aware block renumbering on/off
+    int xseg, nblocks;         // derived: segments per row, number of blocks
+};
+
 struct KParams {
     int nx, ny, nz, N;         // N = nx*ny*nz < 2^31
+    LaunchShape ls;            // shape of the current lattice launch
     double rho0, tau, a, b, kappa, M, C, E, cb0, D, kd;
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
@@ -76,7 +86,7 @@ struct DColloid {
     double trF[3], trT[3];     // pending cover/uncover transfer, used next step
     double F[3], T[3];         // force and torque acting in the last step
     double F0[3], T0[3];       // velocity-independent link momentum of the last step
-    int fixed, nlinks, nactive, pad;
+    int fixed, nlinks, nactive, changed;  // changed: owner map moved this step
 };
 
 // -------------------------------------------------------- particle geometry
@@ -151,6 +161,30 @@ __host__ __device__ inline AxisBox axis_box(double c, double radius, int L)
     if (l + count > L) first = L - l;
     b.shift = first % count;
     return b;
+}
+
+// Lattice launch geometry.  With bx = nx (rows up to 256 nodes) a block owns
+// whole rows, so every shifted store of the push streaming completes the
+// cache lines of its row inside one block.  With remap on, blocks are
+// renumbered XCD-aware: the hardware sends workgroup i to XCD i % 8, and each
+// XCD receives a contiguous range of blocks, so the halo rows a block reads
+// were mostly loaded by blocks of the same XCD (same L2).
+__device__ __forceinline__ bool lattice_node(const KParams &p, int &x, int &y, int &z)
+{
+    const int i = blockIdx.x;
+    int b = i;
+    if (p.ls.remap) {
+        const int q = p.ls.nblocks >> 3, r = p.ls.nblocks & 7;
+        const int xcd = i & 7, slot = i >> 3;
+        b = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    }
+    const int seg = b % p.ls.xseg, grp = b / p.ls.xseg;
+    x = seg * (int)blockDim.x + (int)threadIdx.x;
+    const int row = grp * (int)blockDim.y + (int)threadIdx.y;
+    if (x >= p.nx || row >= p.ny * p.nz) return false;
+    z = row / p.ny;
+    y = row - z * p.ny;
+    return true;
 }
 
 }  // namespace lbk

@@ -13,13 +13,17 @@ struct StepBuffers {
     void *fout;
     const void *psi, *cc;   // state at t
     void *psin, *ccn;       // state at t+1
-    void *mu, *u;           // derived fields of step t
+    void *mu, *chi, *u;     // derived fields of step t
     uint8_t *own;
     DColloid *col;
     int *lnode;
     uint8_t *ldc;
     int lcap;
     int *err;
+    double *cpart;      // per (particle, chunk): 6 transfer partials + change flag
+    uint32_t *lmask;    // per (particle, box node): directions linked to the particle
+    int *ccount;        // per (particle, chunk): links in the chunk
+    int bbmax, nchunk_max;
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,
@@ -38,12 +42,20 @@ struct TimingHook {
     ~TimingHook();
 };
 
+// per-kernel launch shapes of the three lattice kernels
+struct LatticeShapes {
+    LaunchShape mu, collide, scalar;
+};
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz);
+
 template <int P>
-void launch_step_lattice(const KParams &p, const StepBuffers &b, hipStream_t s, TimingHook *tm);
+void launch_step_lattice(const KParams &p, const LatticeShapes &sh, const StepBuffers &b,
+                         hipStream_t s, TimingHook *tm);
 template <int P>
 void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s,
                            TimingHook *tm);
 void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s);
+
 template <int P>
 void launch_init(const KParams &p, const double *psi0, const double *c0, const double *rho0,
                  const double *u0, void *f, void *psi, void *cc, uint8_t *own, hipStream_t s);

@@ -27,6 +27,7 @@ template <> __device__ __forceinline__ double s_tanh<double>(double v) { return 
 template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tanhf(v); }
 
 // ------------------------------------------------------------------ k_mu
+// Also stores chi = c - c_b0 - E tanh psi for the solute update.
 // mu_psi = a psi + b psi^3 - kappa lap(psi) - C E chi (1 - tanh^2 psi),
 // chi = c - c_b0 - E tanh psi (Eq. 2; 1/cosh^2 = 1 - tanh^2, cubic factored
 // as b psi (psi-1)(psi+1) + (a+b) psi to keep FP32 cancellation small).
@@ -36,16 +37,15 @@ template <class S>
 __global__ __launch_bounds__(256) void k_mu(KParams p, const S *__restrict__ psi,
                                             const S *__restrict__ cc,
                                             const uint8_t *__restrict__ own,
-                                            const DColloid *__restrict__ col, S *__restrict__ mu)
+                                            const DColloid *__restrict__ col, S *__restrict__ mu,
+                                            S *__restrict__ chi_out)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
+    int x, y, z;
+    if (!lattice_node(p, x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
-    if (o & OWN_SOLID) { mu[n] = S(0); return; }
+    if (o & OWN_SOLID) { mu[n] = S(0); chi_out[n] = S(0); return; }
     const int nb[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
                        n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
                        n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_mu(KParams p, const S *__restrict__ psi
     const S chi = cc[n] - (S)p.cb0 - (S)p.E * t;
     mu[n] = b * ps * (ps - S(1)) * (ps + S(1)) + (a + b) * ps - (S)p.kappa * lap -
             (S)(p.C * p.E) * chi * (S(1) - t * t);
+    chi_out[n] = chi;
 }
 
 // ------------------------------------------------------------- k_collide
@@ -101,10 +102,8 @@ __global__ __launch_bounds__(256) void k_collide(KParams p,
                                                  typename Prec<P>::S *__restrict__ uout)
 {
     typedef typename Prec<P>::S S;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
+    int x, y, z;
+    if (!lattice_node(p, x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
@@ -185,15 +184,14 @@ template <class S>
 __global__ __launch_bounds__(256) void k_scalar(KParams p, const S *__restrict__ psi,
                                                 const S *__restrict__ cc,
                                                 const S *__restrict__ mu,
+                                                const S *__restrict__ chiv,
                                                 const S *__restrict__ u,
                                                 const uint8_t *__restrict__ own,
                                                 const DColloid *__restrict__ col,
                                                 S *__restrict__ psin, S *__restrict__ ccn)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
+    int x, y, z;
+    if (!lattice_node(p, x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
@@ -205,8 +203,7 @@ __global__ __launch_bounds__(256) void k_scalar(KParams p, const S *__restrict__
     const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
     const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
     const int fn[6] = {n + xo[2], n + xo[0], n + yo[2], n + yo[0], n + zo[2], n + zo[0]};
-    const S E = (S)p.E, cb0 = (S)p.cb0;
-    const S chi = cn - cb0 - E * s_tanh<S>(ps);
+    const S chi = chiv[n];
     const S m0 = mu[n];
     const S u0[3] = {u[n], u[N + n], u[2 * N + n]};
     S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
@@ -221,7 +218,7 @@ __global__ __launch_bounds__(256) void k_scalar(KParams p, const S *__restrict__
         adv_p += ue * (S(0.5) * (ps + pm));
         adv_c += ue * (S(0.5) * (cn + cm));
         dmu += mu[m] - m0;
-        dchi += (cm - cb0 - E * s_tanh<S>(pm)) - chi;
+        dchi += chiv[m] - chi;
     }
     S src = S(0);
     if (bnd) {
@@ -295,7 +292,7 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 // Then (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
 // R' = R + V', m' = m rotated by |Omega'| about Omega'.
 template <int P>
-__global__ __launch_bounds__(256) void k_links_colloid(KParams p, DColloid *__restrict__ col,
+__global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(KParams p, DColloid *__restrict__ col,
                                                        const int *__restrict__ lnode,
                                                        const uint8_t *__restrict__ ldc, int lcap,
                                                        typename Prec<P>::T *__restrict__ fout,
@@ -321,12 +318,13 @@ __global__ __launch_bounds__(256) void k_links_colloid(KParams p, DColloid *__re
         const int n = lnode[(size_t)k * lcap + l];
         const int dc = ldc[(size_t)k * lcap + l];
         const int d = dc & 31;
-        const bool cap = (dc & 0x80) != 0;
         int x, y, z;
         node_of(p, n, x, y, z);
         const int ex = cx(d), ey = cy(d), ez = cz(d);
         double r[3];
         displacement(q, x, y, z, ex, ey, ez, 0.5, p.nx, p.ny, p.nz, r);
+        // cap from the current axis (the table is rebuilt only on owner changes)
+        const bool cap = active_cap(q, r);
         const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         const double nh[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
         // grad c at the fluid node, c(x) substituted at solid neighbours
@@ -406,7 +404,6 @@ __global__ __launch_bounds__(256) void k_links_colloid(KParams p, DColloid *__re
         for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * Xn[j];
         if (i < 3) q.F[i] = s; else q.T[i - 3] = s;
     }
-    q.nactive = (int)acc[27];
     for (int a = 0; a < 3; a++) { q.trF[a] = 0.0; q.trT[a] = 0.0; }
     if (q.fixed) return;
     const int L[3] = {p.nx, p.ny, p.nz};
@@ -433,38 +430,71 @@ __global__ __launch_bounds__(256) void k_links_colloid(KParams p, DColloid *__re
     }
 }
 
+// ---------------------------------------------------- particle geometry
+// The geometry kernels run on a grid (chunk, particle): block (c, k) handles
+// bounding-box nodes [c*GCHUNK, (c+1)*GCHUNK) of particle k, visited in
+// ascending node order, so that per-particle results are assembled in a fixed
+// order whatever the block scheduling.
+struct BoxIter {
+    AxisBox bx, by, bz;
+    int total, nchunk;
+};
+
+__device__ __forceinline__ BoxIter box_of(const DColloid &q, const KParams &p)
+{
+    BoxIter b;
+    b.bx = axis_box(q.pos[0], q.radius, p.nx);
+    b.by = axis_box(q.pos[1], q.radius, p.ny);
+    b.bz = axis_box(q.pos[2], q.radius, p.nz);
+    b.total = b.bx.count * b.by.count * b.bz.count;
+    b.nchunk = (b.total + GCHUNK - 1) / GCHUNK;
+    return b;
+}
+
+__device__ __forceinline__ int box_node(const BoxIter &b, int t, const KParams &p, int &x, int &y,
+                                        int &z)
+{
+    const int ix = t % b.bx.count, iy = (t / b.bx.count) % b.by.count,
+              iz = t / (b.bx.count * b.by.count);
+    x = b.bx.at(ix);
+    y = b.by.at(iy);
+    z = b.bz.at(iz);
+    return x + p.nx * (y + p.ny * z);
+}
+
 // ------------------------------------------------------------- k_cover
-// One block per particle, over its bounding box at the new position.  A fluid
-// node now inside hands its momentum sum_i f_i c_i to the particle; a node of
-// this particle now outside is refilled with f^eq(rho0, V + Omega x r) (the
-// particle is debited rho0 (V + Omega x r)) and takes psi, c as the mean of
-// its face neighbours that are fluid before and after.  Transfers are summed
-// in FP64 and applied in the next rigid-body update.
+// At the new position: a fluid node now inside hands its momentum
+// sum_i f_i c_i to the particle; a node of this particle now outside is
+// refilled with f^eq(rho0, V + Omega x r) (the particle is debited
+// rho0 (V + Omega x r)) and takes psi, c as the mean of its face neighbours
+// that are fluid before and after.  Per-block FP64 partial transfers and an
+// owner-change flag go to cpart[k][c]; k_commit sums them in chunk order.
 template <int P>
-__global__ __launch_bounds__(256) void k_cover(KParams p, DColloid *__restrict__ col,
-                                               typename Prec<P>::T *__restrict__ f,
-                                               typename Prec<P>::S *__restrict__ psi,
-                                               typename Prec<P>::S *__restrict__ cc,
-                                               const uint8_t *__restrict__ own,
-                                               int *__restrict__ err)
+__global__ __launch_bounds__(GCHUNK) void k_cover(KParams p, const DColloid *__restrict__ col,
+                                                  typename Prec<P>::T *__restrict__ f,
+                                                  typename Prec<P>::S *__restrict__ psi,
+                                                  typename Prec<P>::S *__restrict__ cc,
+                                                  const uint8_t *__restrict__ own,
+                                                  double *__restrict__ cpart, int nchunk_max,
+                                                  int *__restrict__ err)
 {
     typedef typename Prec<P>::S S;
     __shared__ double lds[6 * 16];
-    const int k = blockIdx.x;
-    DColloid &q = col[k];
+    const int k = blockIdx.y, c = blockIdx.x;
+    const DColloid &q = col[k];
+    const BoxIter B = box_of(q, p);
+    if (c >= B.nchunk) return;
     const size_t N = (size_t)p.N;
-    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
-    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
-    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
-    const int total = bx.count * by.count * bz.count;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int changed = 0;
     const int sy = p.nx, sz = p.nx * p.ny;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
-        const int x = bx.at(ix), y = by.at(iy), z = bz.at(iz);
-        const int n = x + sy * y + sz * z;
+    const int t = c * GCHUNK + threadIdx.x;
+    if (t < B.total) {
+        int x, y, z;
+        const int n = box_node(B, t, p, x, y, z);
         const int old = own[n] & OWN_SOLID;
         const bool ins = inside(q, x, y, z, p.nx, p.ny, p.nz);
+        if (ins != (old == k + 1)) changed = 1;
         if (ins && old == 0) {
             double pm[3] = {0.0, 0.0, 0.0}, r[3], tq[3];
             for (int i = 1; i < 19; i++) {
@@ -510,41 +540,65 @@ __global__ __launch_bounds__(256) void k_cover(KParams p, DColloid *__restrict__
             if (cnt > 0) { psi[n] = (S)(sp / cnt); cc[n] = (S)(sc / cnt); }
         }
     }
+    const int any = __syncthreads_or(changed);
     block_sum<6>(acc, lds);
-    if (threadIdx.x == 0)
-        for (int a = 0; a < 3; a++) { q.trF[a] += acc[a]; q.trT[a] += acc[3 + a]; }
-}
-
-// ------------------------------------------------------------- k_commit
-// Owner bytes at the new position: inside -> k+1, left behind -> fluid.
-__global__ __launch_bounds__(256) void k_commit(KParams p, const DColloid *__restrict__ col,
-                                                uint8_t *__restrict__ own)
-{
-    const int k = blockIdx.x;
-    const DColloid &q = col[k];
-    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
-    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
-    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
-    const int total = bx.count * by.count * bz.count;
-    const int sy = p.nx, sz = p.nx * p.ny;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
-        const int x = bx.at(ix), y = by.at(iy), z = bz.at(iz);
-        const int n = x + sy * y + sz * z;
-        const bool ins = inside(q, x, y, z, p.nx, p.ny, p.nz);
-        const uint8_t o = own[n];
-        if (ins) {
-            if ((o & OWN_SOLID) != k + 1) own[n] = (uint8_t)(k + 1);
-        } else if ((o & OWN_SOLID) == k + 1) {
-            own[n] = 0;
-        }
+    if (threadIdx.x == 0) {
+        double *o = cpart + ((size_t)k * nchunk_max + c) * 8;
+        for (int a = 0; a < 6; a++) o[a] = acc[a];
+        o[6] = any ? 1.0 : 0.0;
     }
 }
 
-// --------------------------------------------------------------- k_links
+// ------------------------------------------------------------- k_commit
+// Owner bytes at the new position (inside -> k+1, left behind -> fluid), only
+// for particles whose owner map changed.  Block (0, k) also adds the chunk
+// partial transfers to the particle in chunk order and records the flag.
+__global__ __launch_bounds__(GCHUNK) void k_commit(KParams p, DColloid *__restrict__ col,
+                                                   uint8_t *__restrict__ own,
+                                                   const double *__restrict__ cpart, int nchunk_max)
+{
+    __shared__ int sh_changed;
+    const int k = blockIdx.y, c = blockIdx.x;
+    DColloid &q = col[k];
+    const BoxIter B = box_of(q, p);
+    if (c >= B.nchunk) return;
+    if (threadIdx.x == 0) {
+        const double *o = cpart + (size_t)k * nchunk_max * 8;
+        int any = 0;
+        for (int j = 0; j < B.nchunk; j++) any |= o[8 * j + 6] != 0.0;
+        sh_changed = any;
+        if (c == 0) {
+            for (int a = 0; a < 6; a++) {
+                double s = 0.0;
+                for (int j = 0; j < B.nchunk; j++) s += o[8 * j + a];
+                if (a < 3) q.trF[a] += s; else q.trT[a - 3] += s;
+            }
+            q.changed = any;
+        }
+    }
+    __syncthreads();
+    if (!sh_changed) return;
+    const int t = c * GCHUNK + threadIdx.x;
+    if (t >= B.total) return;
+    int x, y, z;
+    const int n = box_node(B, t, p, x, y, z);
+    const bool ins = inside(q, x, y, z, p.nx, p.ny, p.nz);
+    const uint8_t o = own[n];
+    if (ins) {
+        if ((o & OWN_SOLID) != k + 1) own[n] = (uint8_t)(k + 1);
+    } else if ((o & OWN_SOLID) == k + 1) {
+        own[n] = 0;
+    }
+}
+
+// ----------------------------------------------------- k_link_count/write
 // Boundary bits and the link table of particle k in canonical order
-// (ascending node, then direction), by a block-wide exclusive scan over the
-// bounding box visited in ascending node order.
+// (ascending node, then direction): k_link_count stores the 18-bit mask of
+// directions linked to k for every box node and the link count per chunk;
+// k_link_write places each chunk after the counts of the chunks before it.
+// Without an owner change the node set, the directions and the boundary bits
+// are unchanged and both kernels return; the cap bit is recomputed where it
+// is used.
 __device__ int block_exclusive_scan(int v, int *lds, int &total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -564,74 +618,91 @@ __device__ int block_exclusive_scan(int v, int *lds, int &total)
     return base + s - v;
 }
 
-__global__ __launch_bounds__(256) void k_links(KParams p, DColloid *__restrict__ col,
-                                               uint8_t *__restrict__ own, int *__restrict__ lnode,
-                                               uint8_t *__restrict__ ldc, int lcap,
-                                               int *__restrict__ err)
+__global__ __launch_bounds__(GCHUNK) void k_link_count(KParams p, const DColloid *__restrict__ col,
+                                                       uint8_t *__restrict__ own,
+                                                       uint32_t *__restrict__ lmask, int bbmax,
+                                                       int *__restrict__ ccount, int nchunk_max)
 {
     __shared__ int lds[16];
-    const int k = blockIdx.x;
-    DColloid &q = col[k];
-    const AxisBox bx = axis_box(q.pos[0], q.radius, p.nx);
-    const AxisBox by = axis_box(q.pos[1], q.radius, p.ny);
-    const AxisBox bz = axis_box(q.pos[2], q.radius, p.nz);
-    const int total = bx.count * by.count * bz.count;
-    const int sy = p.nx, sz = p.nx * p.ny;
-    int base = 0, nact = 0;
-    for (int t0 = 0; t0 < total; t0 += blockDim.x) {
-        const int t = t0 + threadIdx.x;
-        int cnt = 0;
-        uint32_t mask = 0;  // directions linked to k, bit d
-        int x = 0, y = 0, z = 0, n = 0;
-        if (t < total) {
-            const int ix = t % bx.count, iy = (t / bx.count) % by.count, iz = t / (bx.count * by.count);
-            x = bx.at(ix);
-            y = by.at(iy);
-            z = bz.at(iz);
-            n = x + sy * y + sz * z;
-            const uint8_t o = own[n];
-            if ((o & OWN_SOLID) == 0) {
-                bool bnd = false;
-                const int xs[3] = {wrap_m(x, p.nx), x, wrap_p(x, p.nx)};
-                const int ys[3] = {wrap_m(y, p.ny), y, wrap_p(y, p.ny)};
-                const int zs[3] = {wrap_m(z, p.nz), z, wrap_p(z, p.nz)};
-                for (int d = 1; d < 19; d++) {
-                    const int m = xs[cx(d) + 1] + sy * ys[cy(d) + 1] + sz * zs[cz(d) + 1];
-                    const int om = own[m] & OWN_SOLID;
-                    if (om) bnd = true;
-                    if (om == k + 1) { mask |= 1u << d; cnt++; }
-                }
-                const uint8_t want = bnd ? OWN_BOUNDARY : 0;
-                if (o != want) own[n] = want;
-            }
-        }
-        int tot;
-        const int off = block_exclusive_scan(cnt, lds, tot);
-        if (cnt) {
-            int l = base + off;
+    const int k = blockIdx.y, c = blockIdx.x;
+    const DColloid &q = col[k];
+    if (!q.changed) return;
+    const BoxIter B = box_of(q, p);
+    if (c >= B.nchunk) return;
+    const int t = c * GCHUNK + threadIdx.x;
+    int cnt = 0;
+    if (t < B.total) {
+        int x, y, z;
+        const int n = box_node(B, t, p, x, y, z);
+        uint32_t mask = 0;
+        const uint8_t o = own[n];
+        if ((o & OWN_SOLID) == 0) {
+            bool bnd = false;
+            const int sy = p.nx, sz = p.nx * p.ny;
+            const int xs[3] = {wrap_m(x, p.nx), x, wrap_p(x, p.nx)};
+            const int ys[3] = {wrap_m(y, p.ny), y, wrap_p(y, p.ny)};
+            const int zs[3] = {wrap_m(z, p.nz), z, wrap_p(z, p.nz)};
             for (int d = 1; d < 19; d++) {
-                if (!(mask & (1u << d))) continue;
-                double r[3];
-                displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-                const bool cap = active_cap(q, r);
-                nact += cap ? 1 : 0;
-                if (l < lcap) {
-                    lnode[(size_t)k * lcap + l] = n;
-                    ldc[(size_t)k * lcap + l] = (uint8_t)(d | (cap ? 0x80 : 0));
-                }
-                l++;
+                const int m = xs[cx(d) + 1] + sy * ys[cy(d) + 1] + sz * zs[cz(d) + 1];
+                const int om = own[m] & OWN_SOLID;
+                if (om) bnd = true;
+                if (om == k + 1) { mask |= 1u << d; cnt++; }
             }
+            const uint8_t want = bnd ? OWN_BOUNDARY : 0;
+            if (o != want) own[n] = want;
         }
-        base += tot;
+        lmask[(size_t)k * bbmax + t] = mask;
     }
-    // active count: sum over the block
-    double a[1] = {(double)nact};
-    __shared__ double ldsd[16];
-    block_sum<1>(a, ldsd);
+    int tot;
+    block_exclusive_scan(cnt, lds, tot);
+    if (threadIdx.x == 0) ccount[(size_t)k * nchunk_max + c] = tot;
+}
+
+__global__ __launch_bounds__(GCHUNK) void k_link_write(KParams p, DColloid *__restrict__ col,
+                                                       const uint32_t *__restrict__ lmask, int bbmax,
+                                                       const int *__restrict__ ccount, int nchunk_max,
+                                                       int *__restrict__ lnode,
+                                                       uint8_t *__restrict__ ldc, int lcap,
+                                                       int *__restrict__ err)
+{
+    __shared__ int lds[16];
+    __shared__ int sbase;
+    const int k = blockIdx.y, c = blockIdx.x;
+    DColloid &q = col[k];
+    if (!q.changed) return;
+    const BoxIter B = box_of(q, p);
+    if (c >= B.nchunk) return;
     if (threadIdx.x == 0) {
-        if (base > lcap) atomicOr(err, LB_ERR_LINKS);
-        q.nlinks = base;
-        q.nactive = (int)a[0];
+        const int *cnts = ccount + (size_t)k * nchunk_max;
+        int s = 0;
+        for (int j = 0; j < c; j++) s += cnts[j];
+        sbase = s;
+        if (c == 0) {
+            int total = 0;
+            for (int j = 0; j < B.nchunk; j++) total += cnts[j];
+            q.nlinks = total;
+            if (total > lcap) atomicOr(err, LB_ERR_LINKS);
+        }
+    }
+    __syncthreads();
+    const int t = c * GCHUNK + threadIdx.x;
+    const uint32_t mask = t < B.total ? lmask[(size_t)k * bbmax + t] : 0u;
+    int tot;
+    const int off = block_exclusive_scan(__popc(mask), lds, tot);
+    if (!mask) return;
+    int x, y, z;
+    const int n = box_node(B, t, p, x, y, z);
+    int l = sbase + off;
+    for (int d = 1; d < 19; d++) {
+        if (!(mask & (1u << d))) continue;
+        double r[3];
+        displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
+        const bool cap = active_cap(q, r);
+        if (l < lcap) {
+            lnode[(size_t)k * lcap + l] = n;
+            ldc[(size_t)k * lcap + l] = (uint8_t)(d | (cap ? 0x80 : 0));
+        }
+        l++;
     }
 }
 
@@ -698,14 +769,16 @@ __global__ __launch_bounds__(256) void k_reduce(KParams p, const typename Prec<P
         for (int j = 0; j < 7; j++) part[blockIdx.x * 7 + j] = v[j];
 }
 
-__global__ void k_reduce_final(const double *__restrict__ part, int nblocks, double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__ part, int nblocks,
+                                                      double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int j = 0; j < 7; j++) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; b++) s += part[b * 7 + j];
-        out[j] = s;
-    }
+    __shared__ double lds[7 * 16];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int j = 0; j < 7; j++) v[j] += part[b * 7 + j];
+    block_sum<7>(v, lds);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 7; j++) out[j] = v[j];
 }
 
 // ------------------------------------------------------------ k_fields
@@ -741,26 +814,55 @@ __global__ __launch_bounds__(256) void k_fields(KParams p, const typename Prec<P
 }
 
 // ------------------------------------------------------------ launchers
-static dim3 lattice_grid(const KParams &p) { return dim3((p.nx + 63) / 64, (p.ny + 3) / 4, p.nz); }
-static const dim3 LATTICE_BLOCK(64, 4, 1);
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz)
+{
+    if (ls.bx <= 0 || ls.bx > 256) ls.bx = nx < 256 ? nx : 256;
+    if (ls.bx > nx) ls.bx = nx;
+    if (ls.by <= 0) ls.by = ls.bx >= 256 ? 1 : 256 / ls.bx;
+    if (ls.bx * ls.by > 256) ls.by = 256 / ls.bx;  // the kernels' launch bound
+    if (ls.by < 1) ls.by = 1;
+    ls.xseg = (nx + ls.bx - 1) / ls.bx;
+    const long long rows = (long long)ny * nz;
+    ls.nblocks = (int)(ls.xseg * ((rows + ls.by - 1) / ls.by));
+}
+
+static KParams with_shape(const KParams &p, const LaunchShape &ls)
+{
+    KParams q = p;
+    q.ls = ls;
+    return q;
+}
 
 template <int P>
-void launch_step_lattice(const KParams &p, const StepBuffers &b, hipStream_t s, TimingHook *tm)
+void launch_step_lattice(const KParams &p, const LatticeShapes &sh, const StepBuffers &b,
+                         hipStream_t s, TimingHook *tm)
 {
     typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
-    const dim3 g = lattice_grid(p);
+    const KParams pm = with_shape(p, sh.mu), pc = with_shape(p, sh.collide), ps = with_shape(p, sh.scalar);
     if (tm) tm->begin(0, s);
-    k_mu<S><<<g, LATTICE_BLOCK, 0, s>>>(p, (const S *)b.psi, (const S *)b.cc, b.own, b.col, (S *)b.mu);
+    k_mu<S><<<pm.ls.nblocks, dim3(pm.ls.bx, pm.ls.by), 0, s>>>(pm, (const S *)b.psi, (const S *)b.cc,
+                                                            b.own, b.col, (S *)b.mu, (S *)b.chi);
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
-    k_collide<P><<<g, LATTICE_BLOCK, 0, s>>>(p, (const T *)b.fin, (T *)b.fout, (const S *)b.psi,
-                                              (const S *)b.mu, b.own, (S *)b.u);
+    k_collide<P><<<pc.ls.nblocks, dim3(pc.ls.bx, pc.ls.by), 0, s>>>(pc, (const T *)b.fin, (T *)b.fout,
+                                                                 (const S *)b.psi, (const S *)b.mu,
+                                                                 b.own, (S *)b.u);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
-    k_scalar<S><<<g, LATTICE_BLOCK, 0, s>>>(p, (const S *)b.psi, (const S *)b.cc, (const S *)b.mu,
-                                            (const S *)b.u, b.own, b.col, (S *)b.psin, (S *)b.ccn);
+    k_scalar<S><<<ps.ls.nblocks, dim3(ps.ls.bx, ps.ls.by), 0, s>>>(
+        ps, (const S *)b.psi, (const S *)b.cc, (const S *)b.mu, (const S *)b.chi, (const S *)b.u, b.own,
+        b.col, (S *)b.psin, (S *)b.ccn);
     if (tm) tm->end(2, s);
+}
+
+static void launch_geometry_tail(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s)
+{
+    const dim3 g(b.nchunk_max, ncol);
+    k_commit<<<g, GCHUNK, 0, s>>>(p, b.col, b.own, b.cpart, b.nchunk_max);
+    k_link_count<<<g, GCHUNK, 0, s>>>(p, b.col, b.own, b.lmask, b.bbmax, b.ccount, b.nchunk_max);
+    k_link_write<<<g, GCHUNK, 0, s>>>(p, b.col, b.lmask, b.bbmax, b.ccount, b.nchunk_max, b.lnode,
+                                      b.ldc, b.lcap, b.err);
 }
 
 template <int P>
@@ -771,23 +873,36 @@ void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hip
     typedef typename Prec<P>::S S;
     if (ncol <= 0) return;
     if (tm) tm->begin(3, s);
-    k_links_colloid<P><<<ncol, 256, 0, s>>>(p, b.col, b.lnode, b.ldc, b.lcap, (T *)b.fout,
-                                             (const S *)b.cc, b.own, b.err);
+    k_links_colloid<P><<<ncol, LINK_THREADS, 0, s>>>(p, b.col, b.lnode, b.ldc, b.lcap, (T *)b.fout,
+                                                      (const S *)b.cc, b.own, b.err);
     if (tm) tm->end(3, s);
     if (tm) tm->begin(4, s);
-    k_cover<P><<<ncol, 256, 0, s>>>(p, b.col, (T *)b.fout, (S *)b.psin, (S *)b.ccn, b.own, b.err);
+    k_cover<P><<<dim3(b.nchunk_max, ncol), GCHUNK, 0, s>>>(p, b.col, (T *)b.fout, (S *)b.psin,
+                                                          (S *)b.ccn, b.own, b.cpart, b.nchunk_max,
+                                                          b.err);
     if (tm) tm->end(4, s);
     if (tm) tm->begin(5, s);
-    k_commit<<<ncol, 256, 0, s>>>(p, b.col, b.own);
-    k_links<<<ncol, 256, 0, s>>>(p, b.col, b.own, b.lnode, b.ldc, b.lcap, b.err);
+    launch_geometry_tail(p, b, ncol, s);
     if (tm) tm->end(5, s);
+}
+
+// geometry at placement: no transfer, every particle marked changed
+__global__ void k_mark_placed(DColloid *__restrict__ col, double *__restrict__ cpart, int nchunk_max,
+                              int ncol)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ncol * nchunk_max;
+         j += gridDim.x * blockDim.x) {
+        double *o = cpart + (size_t)j * 8;
+        for (int a = 0; a < 8; a++) o[a] = 0.0;
+        o[6] = 1.0;
+    }
 }
 
 void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s)
 {
     if (ncol <= 0) return;
-    k_commit<<<ncol, 256, 0, s>>>(p, b.col, b.own);
-    k_links<<<ncol, 256, 0, s>>>(p, b.col, b.own, b.lnode, b.ldc, b.lcap, b.err);
+    k_mark_placed<<<64, 256, 0, s>>>(b.col, b.cpart, b.nchunk_max, ncol);
+    launch_geometry_tail(p, b, ncol, s);
 }
 
 template <int P>
@@ -806,7 +921,7 @@ void launch_reduce(const KParams &p, const void *f, const void *psi, const void 
     typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
     k_reduce<P><<<nblocks, 256, 0, s>>>(p, (const T *)f, (const S *)psi, (const S *)cc, own, part);
-    k_reduce_final<<<1, 64, 0, s>>>(part, nblocks, out);
+    k_reduce_final<<<1, 256, 0, s>>>(part, nblocks, out);
 }
 
 template <int P>
@@ -820,8 +935,8 @@ void launch_fields(const KParams &p, const void *f, const void *psi, const void 
 }
 
 #define LB_INSTANTIATE(P)                                                                          \
-    template void launch_step_lattice<P>(const KParams &, const StepBuffers &, hipStream_t,         \
-                                         TimingHook *);                                             \
+    template void launch_step_lattice<P>(const KParams &, const LatticeShapes &, const StepBuffers &,\
+                                         hipStream_t, TimingHook *);                                \
     template void launch_step_particles<P>(const KParams &, const StepBuffers &, int, hipStream_t,  \
                                            TimingHook *);                                           \
     template void launch_init<P>(const KParams &, const double *, const double *, const double *,   \
