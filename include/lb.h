@@ -185,6 +185,24 @@ lb_status lb_colloid_forces(lb_ctx *ctx, double *out12, int32_t n);
 lb_status lb_save_state(lb_ctx *ctx, void *buf, size_t cap, size_t *n);
 lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
 
+/* Advance n contexts by nsteps each with batched launches: every kernel of
+ * the step is one launch covering all boxes (boxes may differ in size and in
+ * particle count; all must share the precision), and on a non-default stream
+ * the launch sequence of two steps is captured once as a HIP graph and
+ * replayed.  Work goes to the stream of ctxs[0]; the call synchronises that
+ * stream before returning.  LB_E_INVALID for an empty list, a repeated
+ * context or mixed precisions; LB_E_STATE if a context lacks its fields. */
+lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
+
+/* Launch shapes of the three lattice kernels (chemical potential,
+ * collide-stream, psi/c update): for each, (bx, by, remap) = nodes per row
+ * segment, rows per block (bx*by <= 256; 0 = default) and block renumbering
+ * (0 natural order, 1 contiguous ranges per XCD, 2 one eighth of every z
+ * plane per XCD).  Used by the autotuner; results are identical for every
+ * shape.  lb_get_launch_shapes returns the shapes in effect. */
+lb_status lb_set_launch_shapes(lb_ctx *ctx, const int32_t *shapes9);
+lb_status lb_get_launch_shapes(lb_ctx *ctx, int32_t *shapes9);
+
 /* Per-kernel timing on the context's stream with HIP events, for the
  * benchmark: enable resets the accumulators; lb_timing_read fills ms[i] with
  * the summed duration and calls[i] with the launch count of kernel i

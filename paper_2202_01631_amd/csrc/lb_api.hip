@@ -71,7 +71,13 @@ struct lb_ctx {
     double *dsum;   // 7 totals
     int nred;
     TimingHook *timing;
-    LatticeShapes shapes;
+    LaunchShape shapes[3];  // mu, collide, scalar
+    // single-box batches for the two buffer parities, their device tables,
+    // and the replay graphs of a (cur, 1-cur) step pair
+    Batch self[2];
+    char *selfdev;
+    bool dirty;
+    hipGraphExec_t graph[2];
     std::string err;
 };
 
@@ -94,10 +100,10 @@ static lb_status hip_fail(lb_ctx *c, hipError_t e, const char *what)
 
 static void *ptr(lb_ctx *c, size_t off) { return c->arena + off; }
 
-static StepBuffers buffers(lb_ctx *c)
+static StepBuffers buffers(lb_ctx *c, int cu)
 {
     StepBuffers b;
-    const int cu = c->cur, nx = 1 - c->cur;
+    const int nx = 1 - cu;
     b.fin = ptr(c, c->L.f[cu]);
     b.fout = ptr(c, c->L.f[nx]);
     b.psi = ptr(c, c->L.psi[cu]);
@@ -119,6 +125,71 @@ static StepBuffers buffers(lb_ctx *c)
     b.bbmax = c->bbmax;
     b.nchunk_max = c->nchunk_max;
     return b;
+}
+
+static BoxDesc box_desc(lb_ctx *c, int parity)
+{
+    BoxDesc d;
+    d.p = c->kp;
+    for (int w = 0; w < 3; w++) d.ls[w] = c->shapes[w];
+    d.b = buffers(c, parity);
+    return d;
+}
+
+// Host side of a batch: descriptors and block/particle start tables, laid
+// out in one device buffer: [BoxDesc x n][bstart 3(n+1)][cstart n+1].
+static size_t batch_bytes(int n)
+{
+    return align256(sizeof(BoxDesc) * n) + sizeof(int) * (4 * (size_t)n + 4);
+}
+
+static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vector<char> &host,
+                       char *dev, Batch &B)
+{
+    host.assign(batch_bytes(n), 0);
+    BoxDesc *d = (BoxDesc *)host.data();
+    int *bst = (int *)(host.data() + align256(sizeof(BoxDesc) * n));
+    int *cst = bst + 3 * (n + 1);
+    for (int w = 0; w < 3; w++) bst[w * (n + 1)] = 0;
+    cst[0] = 0;
+    B.nchunk_max = 0;
+    for (int j = 0; j < n; j++) {
+        d[j] = box_desc(ctxs[j], parity[j]);
+        for (int w = 0; w < 3; w++) bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
+        cst[j + 1] = cst[j] + ctxs[j]->ncol;
+        if (ctxs[j]->ncol > 0) B.nchunk_max = std::max(B.nchunk_max, ctxs[j]->nchunk_max);
+    }
+    for (int w = 0; w < 3; w++) B.nblocks[w] = bst[w * (n + 1) + n];
+    B.ncol = cst[n];
+    B.precision = ctxs[0]->p.precision;
+    B.args.d = (const BoxDesc *)dev;
+    B.args.bstart = (const int *)(dev + align256(sizeof(BoxDesc) * n));
+    B.args.cstart = B.args.bstart + 3 * (n + 1);
+    B.args.nbox = n;
+}
+
+static void drop_graphs(lb_ctx *c)
+{
+    for (int g = 0; g < 2; g++)
+        if (c->graph[g]) { hipGraphExecDestroy(c->graph[g]); c->graph[g] = nullptr; }
+}
+
+// rebuild the two single-box batches after buffers or shapes changed
+static lb_status refresh_self(lb_ctx *c)
+{
+    if (!c->dirty) return LB_OK;
+    drop_graphs(c);
+    if (!c->selfdev) HIP_TRY(c, hipMalloc((void **)&c->selfdev, 2 * align256(batch_bytes(1))));
+    std::vector<char> host[2];
+    for (int par = 0; par < 2; par++) {
+        char *dev = c->selfdev + par * align256(batch_bytes(1));
+        lb_ctx *one[1] = {c};
+        batch_fill(one, 1, &par, host[par], dev, c->self[par]);
+        HIP_TRY(c, hipMemcpyAsync(dev, host[par].data(), host[par].size(), hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->dirty = false;
+    return LB_OK;
 }
 
 // ---------------------------------------------------------------- timing
@@ -179,20 +250,28 @@ TimingHook::~TimingHook()
 }
 
 // ------------------------------------------------------------- dispatch
-template <int P> static void step_once(lb_ctx *c)
+static void launch_one_step(const Batch &B, hipStream_t s, TimingHook *tm)
 {
-    StepBuffers b = buffers(c);
-    launch_step_lattice<P>(c->kp, c->shapes, b, c->stream, c->timing);
-    launch_step_particles<P>(c->kp, b, c->ncol, c->stream, c->timing);
+    switch (B.precision) {
+    case LB_FP64: launch_step<LB_FP64>(B, s, tm); break;
+    case LB_FP32: launch_step<LB_FP32>(B, s, tm); break;
+    default: launch_step<LB_FP16_STORAGE>(B, s, tm); break;
+    }
 }
 
-static void dispatch_step(lb_ctx *c)
+// capture the step pair (B0 then B1) on stream s into an executable graph
+static hipError_t capture_pair(const Batch &B0, const Batch &B1, hipStream_t s, hipGraphExec_t *out)
 {
-    switch (c->p.precision) {
-    case LB_FP64: step_once<LB_FP64>(c); break;
-    case LB_FP32: step_once<LB_FP32>(c); break;
-    default: step_once<LB_FP16_STORAGE>(c); break;
-    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    launch_one_step(B0, s, nullptr);
+    launch_one_step(B1, s, nullptr);
+    e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    return e;
 }
 
 // ------------------------------------------------------------- checks
@@ -223,13 +302,15 @@ static lb_status check_params(const lb_params *p, std::string &why)
     return LB_OK;
 }
 
-// Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block,
-// blocks in natural order (measured faster than the XCD-aware renumbering); LB_LATTICE_SHAPES="bx,by,remap;bx,by,remap;bx,by,remap"
+// Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block;
+// blocks in natural order for mu and collide, plane-wise XCD renumbering for
+// the psi/c update (the fastest of the shapes swept on 256^3); LB_LATTICE_SHAPES="bx,by,remap;bx,by,remap;bx,by,remap"
 // (mu; collide; scalar, 0 = default) overrides them for tuning sweeps.
 static void set_shapes(lb_ctx *c)
 {
-    LaunchShape d = {0, 0, 0, 0, 0};
+    LaunchShape d = {0, 0, 0, 0, 0, 0};
     LaunchShape v[3] = {d, d, d};
+    v[2].remap = 2;  // the psi/c update gains from plane-wise XCD renumbering
     if (const char *e = getenv("LB_LATTICE_SHAPES")) {
         for (int k = 0; k < 3 && *e; k++) {
             int bx = 0, by = 0, rm = 1, used = 0;
@@ -244,10 +325,11 @@ static void set_shapes(lb_ctx *c)
             }
         }
     }
-    for (int k = 0; k < 3; k++) finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz);
-    c->shapes.mu = v[0];
-    c->shapes.collide = v[1];
-    c->shapes.scalar = v[2];
+    for (int k = 0; k < 3; k++) {
+        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz);
+        c->shapes[k] = v[k];
+    }
+    c->dirty = true;
 }
 
 template <int P> static void reduce_t(lb_ctx *c)
@@ -388,6 +470,7 @@ static void free_colloids(lb_ctx *c)
     c->ccount = nullptr;
     c->ncol = 0;
     c->lcap = 0;
+    c->dirty = true;  // descriptors hold the particle-table pointers
 }
 
 lb_status lb_destroy(lb_ctx *c)
@@ -395,6 +478,8 @@ lb_status lb_destroy(lb_ctx *c)
     if (!c) return LB_OK;
     if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
     free_colloids(c);
+    drop_graphs(c);
+    if (c->selfdev) hipFree(c->selfdev);
     if (c->own_arena && c->arena) hipFree(c->arena);
     if (c->derr) hipFree(c->derr);
     if (c->part) hipFree(c->part);
@@ -430,6 +515,7 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) { hipFree(d); return hip_fail(c, e, "hipMemcpyAsync"); }
     free_colloids(c);
+    c->dirty = true;
     c->cur = 0;
     void *f = ptr(c, c->L.f[0]), *ps = ptr(c, c->L.psi[0]), *cv = ptr(c, c->L.cc[0]);
     uint8_t *own = (uint8_t *)ptr(c, c->L.own);
@@ -507,6 +593,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
                 return fail(c, LB_E_STATE, "particle surfaces closer than 2 lattice units");
         }
     free_colloids(c);
+    c->dirty = true;
     // reset the owner map to all fluid before placing the new set
     HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.own), 0, (size_t)c->N, c->stream));
     if (n == 0) { c->stage = 2; return LB_OK; }
@@ -519,7 +606,12 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
     }
     HIP_TRY(c, hipMemcpyAsync(c->dcol, h.data(), sizeof(DColloid) * n, hipMemcpyHostToDevice, c->stream));
     c->ncol = n;
-    launch_geometry(c->kp, buffers(c), c->ncol, c->stream);
+    c->dirty = true;
+    {
+        lb_status st = refresh_self(c);
+        if (st != LB_OK) return st;
+    }
+    launch_geometry(c->self[c->cur], c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int herr = 0;
@@ -534,12 +626,97 @@ lb_status lb_step(lb_ctx *c, int64_t nsteps)
     if (!c) return fail(nullptr, LB_E_INVALID, "null context");
     if (c->stage < 1) return fail(c, LB_E_STATE, "lb_init_fields must come first");
     if (nsteps < 0) return fail(c, LB_E_INVALID, "negative step count");
-    for (int64_t s = 0; s < nsteps; s++) {
-        dispatch_step(c);
-        c->cur ^= 1;
-        c->step++;
+    lb_status st = refresh_self(c);
+    if (st != LB_OK) return st;
+    int64_t s = 0;
+    // step pairs replayed from a captured graph (not while timing kernels,
+    // not on the legacy default stream, which cannot be captured)
+    if (!c->timing && c->stream && nsteps >= 2) {
+        const int par = c->cur;
+        if (!c->graph[par]) {
+            hipError_t e = capture_pair(c->self[par], c->self[1 - par], c->stream, &c->graph[par]);
+            if (e != hipSuccess) { c->graph[par] = nullptr; return hip_fail(c, e, "graph capture"); }
+        }
+        for (; s + 2 <= nsteps; s += 2) HIP_TRY(c, hipGraphLaunch(c->graph[par], c->stream));
     }
+    for (; s < nsteps; s++) {
+        launch_one_step(c->self[c->cur], c->stream, c->timing);
+        c->cur ^= 1;
+    }
+    c->step += nsteps;
     HIP_TRY(c, hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
+{
+    if (!ctxs || n < 1) return fail(nullptr, LB_E_INVALID, "empty batch");
+    if (nsteps < 0) return fail(nullptr, LB_E_INVALID, "negative step count");
+    for (int j = 0; j < n; j++) {
+        if (!ctxs[j]) return fail(nullptr, LB_E_INVALID, "null context in batch");
+        if (ctxs[j]->stage < 1) return fail(ctxs[j], LB_E_STATE, "lb_init_fields must come first");
+        if (ctxs[j]->p.precision != ctxs[0]->p.precision)
+            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share the precision");
+        for (int i = 0; i < j; i++)
+            if (ctxs[i] == ctxs[j]) return fail(ctxs[j], LB_E_INVALID, "context twice in a batch");
+    }
+    lb_ctx *c0 = ctxs[0];
+    hipStream_t s = c0->stream;
+    std::vector<int> par0(n), par1(n);
+    for (int j = 0; j < n; j++) { par0[j] = ctxs[j]->cur; par1[j] = 1 - ctxs[j]->cur; }
+    char *dev = nullptr;
+    const size_t bb = align256(batch_bytes(n));
+    HIP_TRY(c0, hipMalloc((void **)&dev, 2 * bb));
+    Batch B0, B1;
+    std::vector<char> h0, h1;
+    batch_fill(ctxs, n, par0.data(), h0, dev, B0);
+    batch_fill(ctxs, n, par1.data(), h1, dev + bb, B1);
+    hipError_t e = hipMemcpyAsync(dev, h0.data(), h0.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev + bb, h1.data(), h1.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int64_t k = 0;
+    hipGraphExec_t ge = nullptr;
+    if (e == hipSuccess && s && nsteps >= 2) {
+        e = capture_pair(B0, B1, s, &ge);
+        for (; e == hipSuccess && k + 2 <= nsteps; k += 2) e = hipGraphLaunch(ge, s);
+    }
+    for (; e == hipSuccess && k < nsteps; k++) {
+        launch_one_step((k & 1) ? B1 : B0, s, nullptr);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (ge) hipGraphExecDestroy(ge);
+    hipFree(dev);
+    if (e != hipSuccess) return hip_fail(c0, e, "batched step");
+    if (e2 != hipSuccess) return hip_fail(c0, e2, "batched step");
+    for (int j = 0; j < n; j++) {
+        if (nsteps & 1) ctxs[j]->cur ^= 1;
+        ctxs[j]->step += nsteps;
+    }
+    return LB_OK;
+}
+
+lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)
+{
+    if (!c || !shapes9) return fail(c, LB_E_INVALID, "null argument");
+    for (int k = 0; k < 3; k++) {
+        LaunchShape v = {shapes9[3 * k], shapes9[3 * k + 1], shapes9[3 * k + 2], 0, 0, 0};
+        if (v.bx < 0 || v.by < 0 || v.remap < 0 || v.remap > 2) return fail(c, LB_E_INVALID, "bad shape");
+        finish_shape(v, c->p.nx, c->p.ny, c->p.nz);
+        c->shapes[k] = v;
+    }
+    c->dirty = true;
+    return LB_OK;
+}
+
+lb_status lb_get_launch_shapes(lb_ctx *c, int32_t *shapes9)
+{
+    if (!c || !shapes9) return fail(c, LB_E_INVALID, "null argument");
+    for (int k = 0; k < 3; k++) {
+        shapes9[3 * k] = c->shapes[k].bx;
+        shapes9[3 * k + 1] = c->shapes[k].by;
+        shapes9[3 * k + 2] = c->shapes[k].remap;
+    }
     return LB_OK;
 }
 
@@ -793,6 +970,7 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = hd.step;
     c->stage = 2;
+    c->dirty = true;
     return LB_OK;
 }
 

@@ -67,8 +67,8 @@ __device__ __forceinline__ void st_pop(__half *p, size_t i, float v, float sc)
 // Shape of a lattice launch: blocks of (bx, by) threads cover an x segment
 // of bx nodes in by consecutive rows (rows = (y, z) flattened).
 struct LaunchShape {
-    int bx, by, remap;         // remap: XCD-aware block renumbering on/off
-    int xseg, nblocks;         // derived: segments per row, number of blocks
+    int bx, by, remap;         // remap: XCD-aware block renumbering (0 off, 1, 2)
+    int xseg, nblocks, bpp;    // derived: segments per row, blocks, blocks per z plane
 };
 
 struct KParams {
@@ -169,18 +169,29 @@ __host__ __device__ inline AxisBox axis_box(double c, double radius, int L)
 // renumbered XCD-aware: the hardware sends workgroup i to XCD i % 8, and each
 // XCD receives a contiguous range of blocks, so the halo rows a block reads
 // were mostly loaded by blocks of the same XCD (same L2).
-__device__ __forceinline__ bool lattice_node(const KParams &p, int &x, int &y, int &z)
+__device__ __forceinline__ bool lattice_node(const KParams &p, int i, int &x, int &y, int &z)
 {
-    const int i = blockIdx.x;
     int b = i;
-    if (p.ls.remap) {
+    if (p.ls.remap == 1) {
+        // contiguous block ranges per XCD
         const int q = p.ls.nblocks >> 3, r = p.ls.nblocks & 7;
         const int xcd = i & 7, slot = i >> 3;
         b = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    } else if (p.ls.remap == 2) {
+        // one eighth of every z plane per XCD, planes in order: the eight XCDs
+        // sweep a plane together (no address-range camping) and the z +- 1
+        // rows of a block belong to its own XCD
+        const int bpp = p.ls.bpp, G = bpp >> 3;
+        const int xcd = i & 7, slot = i >> 3;
+        b = (slot / G) * bpp + xcd * G + (slot % G);
     }
+    // 256 threads per block, read as (bx, by) for this box: boxes of a batch
+    // may use different shapes within one launch
+    const int tx = (int)threadIdx.x % p.ls.bx, ty = (int)threadIdx.x / p.ls.bx;
+    if (ty >= p.ls.by) return false;
     const int seg = b % p.ls.xseg, grp = b / p.ls.xseg;
-    x = seg * (int)blockDim.x + (int)threadIdx.x;
-    const int row = grp * (int)blockDim.y + (int)threadIdx.y;
+    x = seg * p.ls.bx + tx;
+    const int row = grp * p.ls.by + ty;
     if (x >= p.nx || row >= p.ny * p.nz) return false;
     z = row / p.ny;
     y = row - z * p.ny;

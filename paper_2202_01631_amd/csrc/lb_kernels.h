@@ -26,6 +26,33 @@ struct StepBuffers {
     int bbmax, nchunk_max;
 };
 
+// One box of a batched launch: parameters, per-kernel lattice launch shapes
+// (mu, collide, scalar) and the buffers of the step it takes.
+struct BoxDesc {
+    KParams p;
+    LaunchShape ls[3];
+    StepBuffers b;
+};
+
+// Device-side view of a batch: box descriptors, the first block of each box
+// in each of the three lattice launches (3 x (nbox+1)), and the first global
+// particle index of each box (nbox+1).
+struct BatchArgs {
+    const BoxDesc *d;
+    const int *bstart;
+    const int *cstart;
+    int nbox;
+};
+
+// Host-side batch: device tables plus launch extents.
+struct Batch {
+    BatchArgs args;
+    int nblocks[3];   // blocks of the mu, collide, scalar launches
+    int ncol;         // particles over all boxes
+    int nchunk_max;   // geometry chunks of the largest particle box
+    int precision;
+};
+
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,
 // links+particles, cover, geometry).
 struct TimingHook {
@@ -48,13 +75,10 @@ struct LatticeShapes {
 };
 void finish_shape(LaunchShape &ls, int nx, int ny, int nz);
 
-template <int P>
-void launch_step_lattice(const KParams &p, const LatticeShapes &sh, const StepBuffers &b,
-                         hipStream_t s, TimingHook *tm);
-template <int P>
-void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s,
-                           TimingHook *tm);
-void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s);
+// one time step of every box of the batch (all boxes share the precision P)
+template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm);
+// particle geometry at placement (owner map, boundary bits, link tables)
+void launch_geometry(const Batch &B, hipStream_t s);
 
 template <int P>
 void launch_init(const KParams &p, const double *psi0, const double *c0, const double *rho0,

@@ -22,6 +22,17 @@ namespace lbk {
 __device__ __forceinline__ int wrap_p(int v, int L) { return v + 1 == L ? 0 : v + 1; }
 __device__ __forceinline__ int wrap_m(int v, int L) { return v == 0 ? L - 1 : v - 1; }
 
+// box of global block (or particle) index g: largest j with start[j] <= g
+__device__ __forceinline__ int find_box(const int *__restrict__ start, int nbox, int g)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <class S> __device__ __forceinline__ S s_tanh(S v);
 template <> __device__ __forceinline__ double s_tanh<double>(double v) { return tanh(v); }
 template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tanhf(v); }
@@ -34,14 +45,20 @@ template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tan
 // At a solid face neighbour the Laplacian takes the ghost psi - (H/kappa)|e.n|
 // (Eq. 9, n through the face midpoint).
 template <class S>
-__global__ __launch_bounds__(256) void k_mu(KParams p, const S *__restrict__ psi,
-                                            const S *__restrict__ cc,
-                                            const uint8_t *__restrict__ own,
-                                            const DColloid *__restrict__ col, S *__restrict__ mu,
-                                            S *__restrict__ chi_out)
+__global__ __launch_bounds__(256) void k_mu(BatchArgs A)
 {
+    const int j = find_box(A.bstart, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    KParams p = D.p;
+    p.ls = D.ls[0];
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const uint8_t *__restrict__ own = D.b.own;
+    const DColloid *__restrict__ col = D.b.col;
+    S *__restrict__ mu = (S *)D.b.mu;
+    S *__restrict__ chi_out = (S *)D.b.chi;
     int x, y, z;
-    if (!lattice_node(p, x, y, z)) return;
+    if (!lattice_node(p, blockIdx.x - A.bstart[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
@@ -93,17 +110,23 @@ __global__ __launch_bounds__(256) void k_mu(KParams p, const S *__restrict__ psi
 // x + c_i, or back into slot opp(i) of x when x + c_i is solid (resting-wall
 // bounce-back; the moving-wall and slip terms are added by k_links_colloid).
 template <int P>
-__global__ __launch_bounds__(256) void k_collide(KParams p,
-                                                 const typename Prec<P>::T *__restrict__ fin,
-                                                 typename Prec<P>::T *__restrict__ fout,
-                                                 const typename Prec<P>::S *__restrict__ psi,
-                                                 const typename Prec<P>::S *__restrict__ mu,
-                                                 const uint8_t *__restrict__ own,
-                                                 typename Prec<P>::S *__restrict__ uout)
+__global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 {
+    typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
+    const int *bst = A.bstart + (A.nbox + 1);
+    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    KParams p = D.p;
+    p.ls = D.ls[1];
+    const T *__restrict__ fin = (const T *)D.b.fin;
+    T *__restrict__ fout = (T *)D.b.fout;
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const uint8_t *__restrict__ own = D.b.own;
+    S *__restrict__ uout = (S *)D.b.u;
     int x, y, z;
-    if (!lattice_node(p, x, y, z)) return;
+    if (!lattice_node(p, blockIdx.x - bst[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
@@ -181,17 +204,24 @@ __global__ __launch_bounds__(256) void k_collide(KParams p,
 // through faces shared with solid nodes (Eq. 3, explicit Euler, dt = 1).
 // Emission: alpha of the cap of each link of the node (Eq. 5).
 template <class S>
-__global__ __launch_bounds__(256) void k_scalar(KParams p, const S *__restrict__ psi,
-                                                const S *__restrict__ cc,
-                                                const S *__restrict__ mu,
-                                                const S *__restrict__ chiv,
-                                                const S *__restrict__ u,
-                                                const uint8_t *__restrict__ own,
-                                                const DColloid *__restrict__ col,
-                                                S *__restrict__ psin, S *__restrict__ ccn)
+__global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
 {
+    const int *bst = A.bstart + 2 * (A.nbox + 1);
+    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    KParams p = D.p;
+    p.ls = D.ls[2];
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const S *__restrict__ chiv = (const S *)D.b.chi;
+    const S *__restrict__ u = (const S *)D.b.u;
+    const uint8_t *__restrict__ own = D.b.own;
+    const DColloid *__restrict__ col = D.b.col;
+    S *__restrict__ psin = (S *)D.b.psin;
+    S *__restrict__ ccn = (S *)D.b.ccn;
     int x, y, z;
-    if (!lattice_node(p, x, y, z)) return;
+    if (!lattice_node(p, blockIdx.x - bst[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const uint8_t o = own[n];
@@ -292,17 +322,23 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 // Then (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
 // R' = R + V', m' = m rotated by |Omega'| about Omega'.
 template <int P>
-__global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(KParams p, DColloid *__restrict__ col,
-                                                       const int *__restrict__ lnode,
-                                                       const uint8_t *__restrict__ ldc, int lcap,
-                                                       typename Prec<P>::T *__restrict__ fout,
-                                                       const typename Prec<P>::S *__restrict__ cc,
-                                                       const uint8_t *__restrict__ own,
-                                                       int *__restrict__ err)
+__global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(BatchArgs A)
 {
+    typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
     __shared__ double lds[28 * 16];
-    const int k = blockIdx.x;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    DColloid *__restrict__ col = D.b.col;
+    const int *__restrict__ lnode = D.b.lnode;
+    const uint8_t *__restrict__ ldc = D.b.ldc;
+    const int lcap = D.b.lcap;
+    T *__restrict__ fout = (T *)D.b.fout;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const uint8_t *__restrict__ own = D.b.own;
+    int *__restrict__ err = D.b.err;
+    const int k = blockIdx.x - A.cstart[j];
     DColloid &q = col[k];
     const int nl = min(q.nlinks, lcap);
     const size_t N = (size_t)p.N;
@@ -470,17 +506,23 @@ __device__ __forceinline__ int box_node(const BoxIter &b, int t, const KParams &
 // that are fluid before and after.  Per-block FP64 partial transfers and an
 // owner-change flag go to cpart[k][c]; k_commit sums them in chunk order.
 template <int P>
-__global__ __launch_bounds__(GCHUNK) void k_cover(KParams p, const DColloid *__restrict__ col,
-                                                  typename Prec<P>::T *__restrict__ f,
-                                                  typename Prec<P>::S *__restrict__ psi,
-                                                  typename Prec<P>::S *__restrict__ cc,
-                                                  const uint8_t *__restrict__ own,
-                                                  double *__restrict__ cpart, int nchunk_max,
-                                                  int *__restrict__ err)
+__global__ __launch_bounds__(GCHUNK) void k_cover(BatchArgs A)
 {
+    typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
     __shared__ double lds[6 * 16];
-    const int k = blockIdx.y, c = blockIdx.x;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.y);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    const DColloid *__restrict__ col = D.b.col;
+    T *__restrict__ f = (T *)D.b.fout;
+    S *__restrict__ psi = (S *)D.b.psin;
+    S *__restrict__ cc = (S *)D.b.ccn;
+    const uint8_t *__restrict__ own = D.b.own;
+    double *__restrict__ cpart = D.b.cpart;
+    const int nchunk_max = D.b.nchunk_max;
+    int *__restrict__ err = D.b.err;
+    const int k = blockIdx.y - A.cstart[j], c = blockIdx.x;
     const DColloid &q = col[k];
     const BoxIter B = box_of(q, p);
     if (c >= B.nchunk) return;
@@ -553,24 +595,29 @@ __global__ __launch_bounds__(GCHUNK) void k_cover(KParams p, const DColloid *__r
 // Owner bytes at the new position (inside -> k+1, left behind -> fluid), only
 // for particles whose owner map changed.  Block (0, k) also adds the chunk
 // partial transfers to the particle in chunk order and records the flag.
-__global__ __launch_bounds__(GCHUNK) void k_commit(KParams p, DColloid *__restrict__ col,
-                                                   uint8_t *__restrict__ own,
-                                                   const double *__restrict__ cpart, int nchunk_max)
+__global__ __launch_bounds__(GCHUNK) void k_commit(BatchArgs A)
 {
     __shared__ int sh_changed;
-    const int k = blockIdx.y, c = blockIdx.x;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.y);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    DColloid *__restrict__ col = D.b.col;
+    uint8_t *__restrict__ own = D.b.own;
+    const double *__restrict__ cpart = D.b.cpart;
+    const int nchunk_max = D.b.nchunk_max;
+    const int k = blockIdx.y - A.cstart[j], c = blockIdx.x;
     DColloid &q = col[k];
     const BoxIter B = box_of(q, p);
     if (c >= B.nchunk) return;
     if (threadIdx.x == 0) {
         const double *o = cpart + (size_t)k * nchunk_max * 8;
         int any = 0;
-        for (int j = 0; j < B.nchunk; j++) any |= o[8 * j + 6] != 0.0;
+        for (int jj = 0; jj < B.nchunk; jj++) any |= o[8 * jj + 6] != 0.0;
         sh_changed = any;
         if (c == 0) {
             for (int a = 0; a < 6; a++) {
                 double s = 0.0;
-                for (int j = 0; j < B.nchunk; j++) s += o[8 * j + a];
+                for (int jj = 0; jj < B.nchunk; jj++) s += o[8 * jj + a];
                 if (a < 3) q.trF[a] += s; else q.trT[a - 3] += s;
             }
             q.changed = any;
@@ -618,13 +665,19 @@ __device__ int block_exclusive_scan(int v, int *lds, int &total)
     return base + s - v;
 }
 
-__global__ __launch_bounds__(GCHUNK) void k_link_count(KParams p, const DColloid *__restrict__ col,
-                                                       uint8_t *__restrict__ own,
-                                                       uint32_t *__restrict__ lmask, int bbmax,
-                                                       int *__restrict__ ccount, int nchunk_max)
+__global__ __launch_bounds__(GCHUNK) void k_link_count(BatchArgs A)
 {
     __shared__ int lds[16];
-    const int k = blockIdx.y, c = blockIdx.x;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.y);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    const DColloid *__restrict__ col = D.b.col;
+    uint8_t *__restrict__ own = D.b.own;
+    uint32_t *__restrict__ lmask = D.b.lmask;
+    const int bbmax = D.b.bbmax;
+    int *__restrict__ ccount = D.b.ccount;
+    const int nchunk_max = D.b.nchunk_max;
+    const int k = blockIdx.y - A.cstart[j], c = blockIdx.x;
     const DColloid &q = col[k];
     if (!q.changed) return;
     const BoxIter B = box_of(q, p);
@@ -658,16 +711,23 @@ __global__ __launch_bounds__(GCHUNK) void k_link_count(KParams p, const DColloid
     if (threadIdx.x == 0) ccount[(size_t)k * nchunk_max + c] = tot;
 }
 
-__global__ __launch_bounds__(GCHUNK) void k_link_write(KParams p, DColloid *__restrict__ col,
-                                                       const uint32_t *__restrict__ lmask, int bbmax,
-                                                       const int *__restrict__ ccount, int nchunk_max,
-                                                       int *__restrict__ lnode,
-                                                       uint8_t *__restrict__ ldc, int lcap,
-                                                       int *__restrict__ err)
+__global__ __launch_bounds__(GCHUNK) void k_link_write(BatchArgs A)
 {
     __shared__ int lds[16];
     __shared__ int sbase;
-    const int k = blockIdx.y, c = blockIdx.x;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.y);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    DColloid *__restrict__ col = D.b.col;
+    const uint32_t *__restrict__ lmask = D.b.lmask;
+    const int bbmax = D.b.bbmax;
+    const int *__restrict__ ccount = D.b.ccount;
+    const int nchunk_max = D.b.nchunk_max;
+    int *__restrict__ lnode = D.b.lnode;
+    uint8_t *__restrict__ ldc = D.b.ldc;
+    const int lcap = D.b.lcap;
+    int *__restrict__ err = D.b.err;
+    const int k = blockIdx.y - A.cstart[j], c = blockIdx.x;
     DColloid &q = col[k];
     if (!q.changed) return;
     const BoxIter B = box_of(q, p);
@@ -675,11 +735,11 @@ __global__ __launch_bounds__(GCHUNK) void k_link_write(KParams p, DColloid *__re
     if (threadIdx.x == 0) {
         const int *cnts = ccount + (size_t)k * nchunk_max;
         int s = 0;
-        for (int j = 0; j < c; j++) s += cnts[j];
+        for (int jj = 0; jj < c; jj++) s += cnts[jj];
         sbase = s;
         if (c == 0) {
             int total = 0;
-            for (int j = 0; j < B.nchunk; j++) total += cnts[j];
+            for (int jj = 0; jj < B.nchunk; jj++) total += cnts[jj];
             q.nlinks = total;
             if (total > lcap) atomicOr(err, LB_ERR_LINKS);
         }
@@ -824,85 +884,65 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz)
     ls.xseg = (nx + ls.bx - 1) / ls.bx;
     const long long rows = (long long)ny * nz;
     ls.nblocks = (int)(ls.xseg * ((rows + ls.by - 1) / ls.by));
+    ls.bpp = 0;
+    if (ls.remap == 2) {
+        // plane-wise renumbering needs whole planes per block row and
+        // blocks per plane divisible by 8
+        if (ny % ls.by == 0 && (ls.xseg * (ny / ls.by)) % 8 == 0) ls.bpp = ls.xseg * (ny / ls.by);
+        else ls.remap = 0;
+    }
 }
 
-static KParams with_shape(const KParams &p, const LaunchShape &ls)
+static void launch_geometry_tail(const Batch &B, hipStream_t s)
 {
-    KParams q = p;
-    q.ls = ls;
-    return q;
+    const dim3 g(B.nchunk_max, B.ncol);
+    k_commit<<<g, GCHUNK, 0, s>>>(B.args);
+    k_link_count<<<g, GCHUNK, 0, s>>>(B.args);
+    k_link_write<<<g, GCHUNK, 0, s>>>(B.args);
 }
 
-template <int P>
-void launch_step_lattice(const KParams &p, const LatticeShapes &sh, const StepBuffers &b,
-                         hipStream_t s, TimingHook *tm)
+template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm)
 {
-    typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
-    const KParams pm = with_shape(p, sh.mu), pc = with_shape(p, sh.collide), ps = with_shape(p, sh.scalar);
     if (tm) tm->begin(0, s);
-    k_mu<S><<<pm.ls.nblocks, dim3(pm.ls.bx, pm.ls.by), 0, s>>>(pm, (const S *)b.psi, (const S *)b.cc,
-                                                            b.own, b.col, (S *)b.mu, (S *)b.chi);
+    k_mu<S><<<B.nblocks[0], 256, 0, s>>>(B.args);
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
-    k_collide<P><<<pc.ls.nblocks, dim3(pc.ls.bx, pc.ls.by), 0, s>>>(pc, (const T *)b.fin, (T *)b.fout,
-                                                                 (const S *)b.psi, (const S *)b.mu,
-                                                                 b.own, (S *)b.u);
+    k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
-    k_scalar<S><<<ps.ls.nblocks, dim3(ps.ls.bx, ps.ls.by), 0, s>>>(
-        ps, (const S *)b.psi, (const S *)b.cc, (const S *)b.mu, (const S *)b.chi, (const S *)b.u, b.own,
-        b.col, (S *)b.psin, (S *)b.ccn);
+    k_scalar<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
     if (tm) tm->end(2, s);
-}
-
-static void launch_geometry_tail(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s)
-{
-    const dim3 g(b.nchunk_max, ncol);
-    k_commit<<<g, GCHUNK, 0, s>>>(p, b.col, b.own, b.cpart, b.nchunk_max);
-    k_link_count<<<g, GCHUNK, 0, s>>>(p, b.col, b.own, b.lmask, b.bbmax, b.ccount, b.nchunk_max);
-    k_link_write<<<g, GCHUNK, 0, s>>>(p, b.col, b.lmask, b.bbmax, b.ccount, b.nchunk_max, b.lnode,
-                                      b.ldc, b.lcap, b.err);
-}
-
-template <int P>
-void launch_step_particles(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s,
-                           TimingHook *tm)
-{
-    typedef typename Prec<P>::T T;
-    typedef typename Prec<P>::S S;
-    if (ncol <= 0) return;
+    if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
-    k_links_colloid<P><<<ncol, LINK_THREADS, 0, s>>>(p, b.col, b.lnode, b.ldc, b.lcap, (T *)b.fout,
-                                                      (const S *)b.cc, b.own, b.err);
+    k_links_colloid<P><<<B.ncol, LINK_THREADS, 0, s>>>(B.args);
     if (tm) tm->end(3, s);
     if (tm) tm->begin(4, s);
-    k_cover<P><<<dim3(b.nchunk_max, ncol), GCHUNK, 0, s>>>(p, b.col, (T *)b.fout, (S *)b.psin,
-                                                          (S *)b.ccn, b.own, b.cpart, b.nchunk_max,
-                                                          b.err);
+    k_cover<P><<<dim3(B.nchunk_max, B.ncol), GCHUNK, 0, s>>>(B.args);
     if (tm) tm->end(4, s);
     if (tm) tm->begin(5, s);
-    launch_geometry_tail(p, b, ncol, s);
+    launch_geometry_tail(B, s);
     if (tm) tm->end(5, s);
 }
 
 // geometry at placement: no transfer, every particle marked changed
-__global__ void k_mark_placed(DColloid *__restrict__ col, double *__restrict__ cpart, int nchunk_max,
-                              int ncol)
+__global__ void k_mark_placed(BatchArgs A)
 {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ncol * nchunk_max;
-         j += gridDim.x * blockDim.x) {
-        double *o = cpart + (size_t)j * 8;
+    const int j = find_box(A.cstart, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    const int k = blockIdx.x - A.cstart[j];
+    for (int c = threadIdx.x; c < D.b.nchunk_max; c += blockDim.x) {
+        double *o = D.b.cpart + ((size_t)k * D.b.nchunk_max + c) * 8;
         for (int a = 0; a < 8; a++) o[a] = 0.0;
         o[6] = 1.0;
     }
 }
 
-void launch_geometry(const KParams &p, const StepBuffers &b, int ncol, hipStream_t s)
+void launch_geometry(const Batch &B, hipStream_t s)
 {
-    if (ncol <= 0) return;
-    k_mark_placed<<<64, 256, 0, s>>>(b.col, b.cpart, b.nchunk_max, ncol);
-    launch_geometry_tail(p, b, ncol, s);
+    if (B.ncol <= 0) return;
+    k_mark_placed<<<B.ncol, 64, 0, s>>>(B.args);
+    launch_geometry_tail(B, s);
 }
 
 template <int P>
@@ -935,10 +975,7 @@ void launch_fields(const KParams &p, const void *f, const void *psi, const void 
 }
 
 #define LB_INSTANTIATE(P)                                                                          \
-    template void launch_step_lattice<P>(const KParams &, const LatticeShapes &, const StepBuffers &,\
-                                         hipStream_t, TimingHook *);                                \
-    template void launch_step_particles<P>(const KParams &, const StepBuffers &, int, hipStream_t,  \
-                                           TimingHook *);                                           \
+    template void launch_step<P>(const Batch &, hipStream_t, TimingHook *);                          \
     template void launch_init<P>(const KParams &, const double *, const double *, const double *,   \
                                  const double *, void *, void *, void *, uint8_t *, hipStream_t);   \
     template void launch_reduce<P>(const KParams &, const void *, const void *, const void *,       \

@@ -21,7 +21,8 @@ ERR_NAN, ERR_FAST, ERR_CONTACT, ERR_LINKS = 1, 2, 4, 8
 EXPORTS = ("lb_footprint_bytes", "lb_create", "lb_destroy", "lb_init_fields",
            "lb_add_colloids", "lb_step", "lb_observables", "lb_get_fields",
            "lb_get_populations", "lb_get_owner", "lb_get_links", "lb_colloid_forces",
-           "lb_save_state", "lb_load_state", "lb_timing_enable", "lb_timing_read",
+           "lb_save_state", "lb_load_state", "lb_batch_step", "lb_set_launch_shapes",
+           "lb_get_launch_shapes", "lb_timing_enable", "lb_timing_read",
            "lb_last_error", "lb_wetting_H", "lb_solubility_E")
 
 
@@ -87,6 +88,9 @@ def load():
     L.lb_colloid_forces.argtypes = [vp, dp, C.c_int32]
     L.lb_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lb_load_state.argtypes = [vp, vp, C.c_size_t]
+    L.lb_batch_step.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
+    L.lb_set_launch_shapes.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lb_get_launch_shapes.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lb_timing_enable.argtypes = [vp, C.c_int32]
     L.lb_timing_read.argtypes = [vp, dp, i64p]
     L.lb_last_error.argtypes = [vp]
@@ -273,6 +277,16 @@ class Box:
         self._check(load().lb_load_state(self._ctx, buf, len(data)))
         self.ncol = int(np.frombuffer(data[:40], dtype=np.int32)[6])
 
+    def set_launch_shapes(self, shapes):
+        """shapes: 3 x (bx, by, remap) for the mu, collide and scalar kernels."""
+        a = (C.c_int32 * 9)(*[int(v) for t in shapes for v in t])
+        self._check(load().lb_set_launch_shapes(self._ctx, a))
+
+    def launch_shapes(self):
+        a = (C.c_int32 * 9)()
+        self._check(load().lb_get_launch_shapes(self._ctx, a))
+        return [tuple(a[3 * k:3 * k + 3]) for k in range(3)]
+
     def timing_enable(self, on=True):
         self._check(load().lb_timing_enable(self._ctx, 1 if on else 0))
 
@@ -281,6 +295,17 @@ class Box:
         calls = (C.c_int64 * 6)()
         self._check(load().lb_timing_read(self._ctx, ms, calls))
         return np.array(ms[:]), np.array(calls[:])
+
+
+def batch_step(boxes, nsteps):
+    """Advance several boxes together with batched launches (one launch per
+    kernel over all boxes, graph-replayed step pairs)."""
+    if not boxes:
+        return
+    arr = (C.c_void_p * len(boxes))(*[b._ctx.value for b in boxes])
+    rc = load().lb_batch_step(arr, len(boxes), int(nsteps))
+    if rc != 0:
+        raise LBError(rc, load().lb_last_error(boxes[0]._ctx).decode())
 
 
 def from_spec(spec, precision=None, arena=None, stream=None, **override):
