@@ -29,7 +29,8 @@ STEP_BYTES = {"fp64": 19 * 2 * 8 + 2 * 2 * 8, "fp32": 19 * 2 * 4 + 2 * 2 * 4,
               "fp16": 19 * 2 * 2 + 2 * 2 * 4}
 # the collide-stream kernel alone moves the populations: 19 read + 19 written
 COLLIDE_BYTES = {"fp64": 19 * 2 * 8, "fp32": 19 * 2 * 4, "fp16": 19 * 2 * 2}
-KERNELS = ("k_mu", "k_collide", "k_scalar", "k_links_colloid", "k_cover", "k_commit+k_links")
+KERNELS = ("k_mu", "k_collide", "k_scalar", "k_link_partial+k_colloid_update", "k_cover",
+           "k_commit+k_link_count+k_link_write")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_box256_fp32_traffic.json")
 
 
@@ -95,12 +96,26 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (torch) five times, for "
+                         "scaling the HBM byte counters against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); "
               "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                                               "launches": 5}}), flush=True)
+        return
 
     from paper_2202_01631_amd import inputs as I
     from paper_2202_01631_amd import lb

@@ -66,6 +66,8 @@ struct lb_ctx {
     uint32_t *lmask;
     int *ccount;
     int bbmax, nchunk_max;
+    double *lpart;
+    int nlchunk_max;
     int *derr;
     double *part;   // reduction partials
     double *dsum;   // 7 totals
@@ -124,6 +126,8 @@ static StepBuffers buffers(lb_ctx *c, int cu)
     b.ccount = c->ccount;
     b.bbmax = c->bbmax;
     b.nchunk_max = c->nchunk_max;
+    b.lpart = c->lpart;
+    b.nlchunk_max = c->nlchunk_max;
     return b;
 }
 
@@ -153,11 +157,15 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     for (int w = 0; w < 3; w++) bst[w * (n + 1)] = 0;
     cst[0] = 0;
     B.nchunk_max = 0;
+    B.nlchunk_max = 0;
     for (int j = 0; j < n; j++) {
         d[j] = box_desc(ctxs[j], parity[j]);
         for (int w = 0; w < 3; w++) bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
         cst[j + 1] = cst[j] + ctxs[j]->ncol;
-        if (ctxs[j]->ncol > 0) B.nchunk_max = std::max(B.nchunk_max, ctxs[j]->nchunk_max);
+        if (ctxs[j]->ncol > 0) {
+            B.nchunk_max = std::max(B.nchunk_max, ctxs[j]->nchunk_max);
+            B.nlchunk_max = std::max(B.nlchunk_max, ctxs[j]->nlchunk_max);
+        }
     }
     for (int w = 0; w < 3; w++) B.nblocks[w] = bst[w * (n + 1) + n];
     B.ncol = cst[n];
@@ -389,6 +397,8 @@ static lb_status alloc_colloid_tables(lb_ctx *c, double rmax, int lcap)
     HIP_TRY(c, hipMalloc((void **)&c->cpart, sizeof(double) * 8 * (size_t)c->nchunk_max * m));
     HIP_TRY(c, hipMalloc((void **)&c->lmask, sizeof(uint32_t) * (size_t)c->bbmax * m));
     HIP_TRY(c, hipMalloc((void **)&c->ccount, sizeof(int) * (size_t)c->nchunk_max * m));
+    c->nlchunk_max = (c->lcap + LINK_THREADS - 1) / LINK_THREADS;
+    HIP_TRY(c, hipMalloc((void **)&c->lpart, sizeof(double) * 28 * (size_t)c->nlchunk_max * m));
     HIP_TRY(c, hipMemsetAsync(c->cpart, 0, sizeof(double) * 8 * (size_t)c->nchunk_max * m, c->stream));
     return LB_OK;
 }
@@ -462,6 +472,8 @@ static void free_colloids(lb_ctx *c)
     if (c->cpart) hipFree(c->cpart);
     if (c->lmask) hipFree(c->lmask);
     if (c->ccount) hipFree(c->ccount);
+    if (c->lpart) hipFree(c->lpart);
+    c->lpart = nullptr;
     c->dcol = nullptr;
     c->lnode = nullptr;
     c->ldc = nullptr;

@@ -24,6 +24,8 @@ struct StepBuffers {
     uint32_t *lmask;    // per (particle, box node): directions linked to the particle
     int *ccount;        // per (particle, chunk): links in the chunk
     int bbmax, nchunk_max;
+    double *lpart;      // per (particle, link chunk): 28 FP64 link-momentum partials
+    int nlchunk_max;
 };
 
 // One box of a batched launch: parameters, per-kernel lattice launch shapes
@@ -50,6 +52,7 @@ struct Batch {
     int nblocks[3];   // blocks of the mu, collide, scalar launches
     int ncol;         // particles over all boxes
     int nchunk_max;   // geometry chunks of the largest particle box
+    int nlchunk_max;  // link chunks of the largest link table
     int precision;
 };
 

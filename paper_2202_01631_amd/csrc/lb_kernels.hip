@@ -7,8 +7,10 @@
 //   k_collide        force -psi grad(mu), moments, BGK-Guo collision, push
 //                    streaming with plain (resting-wall) bounce-back
 //   k_scalar         psi and c updates of Eq. 3 with Janus emission (Eq. 5)
-//   k_links_colloid  per particle: moving-wall and slip correction of every
-//                    link (Eqs. 4, 6), FP64 momentum exchange, implicit
+//   k_link_partial   per (link chunk, particle): moving-wall and slip
+//                    correction of every link (Eqs. 4, 6), FP64 momentum
+//                    exchange partials
+//   k_colloid_update per particle: partials summed in chunk order, implicit
 //                    rigid-body update
 //   k_cover          per particle: cover/uncover repair at the new position
 //   k_commit         per particle: owner bytes at the new position
@@ -311,8 +313,9 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// ------------------------------------------------------ k_links_colloid
-// One block per particle k.  For each link (n, d) of k (fluid n, n + c_d in
+// ------------------------------------------------------- k_link_partial
+// Block (c, k) takes links [c*LINK_THREADS, (c+1)*LINK_THREADS) of particle k.
+// For each link (n, d) of k (fluid n, n + c_d in
 // k): wall velocity u_b = V + Omega x r + mu_cap (I - nn) grad c(n) with r
 // the link midpoint from the centre (Eq. 4, 6); bounced population
 // f_opp(d)(n) = f*_d(n) - 6 w_d rho0 c_d.u_b; momentum to the particle
@@ -322,12 +325,12 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 // Then (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
 // R' = R + V', m' = m rotated by |Omega'| about Omega'.
 template <int P>
-__global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(BatchArgs A)
+__global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
 {
     typedef typename Prec<P>::T T;
     typedef typename Prec<P>::S S;
     __shared__ double lds[28 * 16];
-    const int j = find_box(A.cstart, A.nbox, blockIdx.x);
+    const int j = find_box(A.cstart, A.nbox, blockIdx.y);
     const BoxDesc &D = A.d[j];
     const KParams p = D.p;
     DColloid *__restrict__ col = D.b.col;
@@ -337,20 +340,21 @@ __global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(BatchArgs A)
     T *__restrict__ fout = (T *)D.b.fout;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
-    int *__restrict__ err = D.b.err;
-    const int k = blockIdx.x - A.cstart[j];
-    DColloid &q = col[k];
+    const int k = blockIdx.y - A.cstart[j];
+    const DColloid &q = col[k];
     const int nl = min(q.nlinks, lcap);
+    const int l0 = blockIdx.x * LINK_THREADS;
+    if (l0 >= nl) return;
     const size_t N = (size_t)p.N;
     const double rho0 = p.rho0;
     double acc[28];
 #pragma unroll
-    for (int j = 0; j < 28; j++) acc[j] = 0.0;
-    const double pos[3] = {q.pos[0], q.pos[1], q.pos[2]};
+    for (int jj = 0; jj < 28; jj++) acc[jj] = 0.0;
     const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
     const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
-    (void)pos;
-    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+    {
+        const int l = l0 + threadIdx.x;
+        if (l < nl) {
         const int n = lnode[(size_t)k * lcap + l];
         const int dc = ldc[(size_t)k * lcap + l];
         const int d = dc & 31;
@@ -399,9 +403,43 @@ __global__ __launch_bounds__(LINK_THREADS) void k_links_colloid(BatchArgs A)
         for (int i1 = 0; i1 < 6; i1++)
             for (int i2 = i1; i2 < 6; i2++) acc[j++] += coef * gv[i1] * gv[i2];
         acc[27] += cap ? 1.0 : 0.0;
+        }
     }
     block_sum<28>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *o = D.b.lpart + ((size_t)k * D.b.nlchunk_max + blockIdx.x) * 28;
+        for (int a = 0; a < 28; a++) o[a] = acc[a];
+    }
+}
+
+// ------------------------------------------------------ k_colloid_update
+// One block per particle: link partials summed in chunk order (FP64), then
+// (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
+// R' = R + V', m' = m rotated by |Omega'| about Omega'.
+__global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
+{
+    __shared__ double sacc[28];
+    const int j = find_box(A.cstart, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    DColloid *__restrict__ col = D.b.col;
+    int *__restrict__ err = D.b.err;
+    const int k = blockIdx.x - A.cstart[j];
+    DColloid &q = col[k];
+    const int nl = min(q.nlinks, D.b.lcap);
+    const int nch = (nl + LINK_THREADS - 1) / LINK_THREADS;
+    if (threadIdx.x < 28) {
+        const double *o = D.b.lpart + (size_t)k * D.b.nlchunk_max * 28 + threadIdx.x;
+        double s = 0.0;
+        for (int c = 0; c < nch; c++) s += o[(size_t)c * 28];
+        sacc[threadIdx.x] = s;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double acc[28];
+    for (int a = 0; a < 28; a++) acc[a] = sacc[a];
+    const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
+    const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
     double Z[36];
     {
         int j = 6;
@@ -597,7 +635,6 @@ __global__ __launch_bounds__(GCHUNK) void k_cover(BatchArgs A)
 // partial transfers to the particle in chunk order and records the flag.
 __global__ __launch_bounds__(GCHUNK) void k_commit(BatchArgs A)
 {
-    __shared__ int sh_changed;
     const int j = find_box(A.cstart, A.nbox, blockIdx.y);
     const BoxDesc &D = A.d[j];
     const KParams p = D.p;
@@ -609,22 +646,22 @@ __global__ __launch_bounds__(GCHUNK) void k_commit(BatchArgs A)
     DColloid &q = col[k];
     const BoxIter B = box_of(q, p);
     if (c >= B.nchunk) return;
-    if (threadIdx.x == 0) {
-        const double *o = cpart + (size_t)k * nchunk_max * 8;
-        int any = 0;
-        for (int jj = 0; jj < B.nchunk; jj++) any |= o[8 * jj + 6] != 0.0;
-        sh_changed = any;
-        if (c == 0) {
-            for (int a = 0; a < 6; a++) {
-                double s = 0.0;
-                for (int jj = 0; jj < B.nchunk; jj++) s += o[8 * jj + a];
-                if (a < 3) q.trF[a] += s; else q.trT[a - 3] += s;
-            }
-            q.changed = any;
+    const double *cp = cpart + (size_t)k * nchunk_max * 8;
+    // change flags of all chunks, loaded in parallel
+    int flag = 0;
+    for (int jj = threadIdx.x; jj < B.nchunk; jj += blockDim.x) flag |= cp[8 * jj + 6] != 0.0;
+    const int any = __syncthreads_or(flag);
+    if (c == 0) {
+        // transfers summed in chunk order: thread a < 6 sums component a
+        if (threadIdx.x < 6) {
+            const int a = threadIdx.x;
+            double s = 0.0;
+            for (int jj = 0; jj < B.nchunk; jj++) s += cp[8 * jj + a];
+            if (a < 3) q.trF[a] += s; else q.trT[a - 3] += s;
         }
+        if (threadIdx.x == 0) q.changed = any;
     }
-    __syncthreads();
-    if (!sh_changed) return;
+    if (!any) return;
     const int t = c * GCHUNK + threadIdx.x;
     if (t >= B.total) return;
     int x, y, z;
@@ -732,19 +769,27 @@ __global__ __launch_bounds__(GCHUNK) void k_link_write(BatchArgs A)
     if (!q.changed) return;
     const BoxIter B = box_of(q, p);
     if (c >= B.nchunk) return;
-    if (threadIdx.x == 0) {
+    {
+        // links in the chunks before this one, and in all chunks (block sums)
         const int *cnts = ccount + (size_t)k * nchunk_max;
-        int s = 0;
-        for (int jj = 0; jj < c; jj++) s += cnts[jj];
-        sbase = s;
-        if (c == 0) {
-            int total = 0;
-            for (int jj = 0; jj < B.nchunk; jj++) total += cnts[jj];
-            q.nlinks = total;
-            if (total > lcap) atomicOr(err, LB_ERR_LINKS);
+        int before = 0, all = 0;
+        for (int jj = threadIdx.x; jj < B.nchunk; jj += blockDim.x) {
+            const int v = cnts[jj];
+            all += v;
+            if (jj < c) before += v;
         }
+        int tb, ta;
+        block_exclusive_scan(before, lds, tb);
+        block_exclusive_scan(all, lds, ta);
+        if (threadIdx.x == 0) {
+            sbase = tb;
+            if (c == 0) {
+                q.nlinks = ta;
+                if (ta > lcap) atomicOr(err, LB_ERR_LINKS);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int t = c * GCHUNK + threadIdx.x;
     const uint32_t mask = t < B.total ? lmask[(size_t)k * bbmax + t] : 0u;
     int tot;
@@ -915,7 +960,8 @@ template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm)
     if (tm) tm->end(2, s);
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
-    k_links_colloid<P><<<B.ncol, LINK_THREADS, 0, s>>>(B.args);
+    k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, s>>>(B.args);
+    k_colloid_update<<<B.ncol, 64, 0, s>>>(B.args);
     if (tm) tm->end(3, s);
     if (tm) tm->begin(4, s);
     k_cover<P><<<dim3(B.nchunk_max, B.ncol), GCHUNK, 0, s>>>(B.args);
