@@ -51,6 +51,8 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     arena = torch.empty(lb.footprint_bytes(spec["shape"], precision), dtype=torch.uint8,
                         device="cuda")
     box = lb.from_spec(spec, precision=precision, arena=arena, stream=stream)
+    from paper_2202_01631_amd import tune
+    tune.apply(box)  # cached autotuned launch shapes for this size, if any
     box.step(warmup)
     torch.cuda.synchronize()
     box.timing_enable(True)
@@ -71,6 +73,57 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     per_kernel = {KERNELS[i]: (kms[i] / calls[i] if calls[i] else None) for i in range(6)}
     return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
                 kernel_ms=per_kernel, error_bits=tot["error_bits"], N=N)
+
+
+def batched_sweep(torch, lb, I, nbox, steps):
+    """Boxes of the batched sweep (sides 32/48/64, one sphere each), FP32:
+    aggregate MLUPS of the batched graph-replayed step against the same boxes
+    advanced one after another with the plain single-box step."""
+    from paper_2202_01631_amd import tune
+    specs = I.batch_boxes(count=nbox, steps=steps)
+    stream = torch.cuda.Stream()
+    lu = sum(s["shape"][0] * s["shape"][1] * s["shape"][2] for s in specs) * steps
+    boxes = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+    for b in boxes:
+        tune.apply(b)
+    lb.batch_step(boxes, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.batch_step(boxes, steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    for b in boxes:
+        b.close()
+    boxes = [lb.from_spec(s, precision="fp32") for s in specs]
+    for b in boxes:
+        tune.apply(b)
+        b.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in boxes:
+        b.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for b in boxes:
+        b.close()
+    return dict(boxes=nbox, steps=steps, lattice_updates=lu,
+                batched_mlups=round(lu / tb / 1e6, 1), sequential_mlups=round(lu / ts / 1e6, 1),
+                speedup=round(ts / tb, 3))
+
+
+def serving_run(torch, I, nreq, rate, step_scale):
+    """Continuous-batching server on a Poisson trace (50/s, sides 32..96,
+    1-8 spheres, FP32 or FP16 storage), request lengths scaled by step_scale
+    to bound the run; p50/p99 time-to-result and sustained MLUPS."""
+    from paper_2202_01631_amd import serve
+    trace = I.serving_trace(n_requests=nreq, rate=rate)
+    free, _ = torch.cuda.mem_get_info()
+    stream = torch.cuda.Stream()
+    _, summ, _ = serve.replay(trace, budget_bytes=int(0.5 * free), chunk=100,
+                              step_scale=step_scale, stream=stream)
+    summ = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    summ.update(rate_per_s=rate, step_scale=step_scale)
+    return summ
 
 
 def cpu_baseline(spec):
@@ -96,6 +149,11 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
+    ap.add_argument("--batch", type=int, default=64, help="boxes in the batched sweep (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.02,
+                    help="request length scale of the serving run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (torch) five times, for "
                          "scaling the HBM byte counters against a kernel of known traffic")
@@ -168,6 +226,14 @@ def main():
                                             for k, x in v["kernel_ms"].items()},
                               "error_bits": v["error_bits"]} for p, v in res.items()},
     }
+    if args.batch and not args.only:
+        log("[bench] batched sweep: %d boxes x %d steps" % (args.batch, args.batch_steps))
+        out["batched_sweep"] = batched_sweep(torch, lb, I, args.batch, args.batch_steps)
+        log("[bench] batched sweep %s" % out["batched_sweep"])
+    if args.serve and not args.only:
+        log("[bench] serving: %d requests" % args.serve)
+        out["serving"] = serving_run(torch, I, args.serve, 50.0, args.serve_scale)
+        log("[bench] serving %s" % out["serving"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec)
     else:

@@ -1,0 +1,55 @@
+"""GPU tests of the continuous-batching server: every request's result is
+bitwise identical to the same request run alone, admission respects the HBM
+budget and the slot limit, and latecomers are admitted while earlier requests
+are still on the GPU."""
+import numpy as np
+import pytest
+
+from paper_2202_01631_amd import inputs as I
+from paper_2202_01631_amd import lb, serve
+from parity_util import flush_print
+
+pytestmark = pytest.mark.gpu
+
+
+def _collect(box):
+    f = box.fields()
+    return dict(pop=box.populations(), psi=f["psi"], c=f["c"], links=box.links())
+
+
+def test_served_equals_alone():
+    import torch
+    trace = I.serving_trace(n_requests=8, rate=50.0, sides=(32, 44), steps=(40, 120))
+    stream = torch.cuda.Stream()
+    budget = 6 * serve.request_bytes(I.serving_request(dict(trace[0], side=44, spheres=8)))
+    res, summ, specs = serve.replay(trace, budget, max_slots=3, chunk=16, stream=stream,
+                                    collect=_collect)
+    flush_print("[serve] summary", summ)
+    assert summ["completed"] == 8
+    assert summ["peak_live"] <= 3
+    assert summ["peak_bytes"] <= budget
+    # requests overlapped on the device: some were admitted before an earlier one finished
+    order = sorted(res, key=lambda i: res[i]["admitted"])
+    overlaps = sum(1 for a, b in zip(order, order[1:]) if res[b]["admitted"] < res[a]["finished"])
+    assert overlaps > 0
+    for i, spec in enumerate(specs):
+        alone = lb.from_spec(spec, max_colloids=max(1, len(spec["colloids"])))
+        alone.step(spec["steps"])
+        a = _collect(alone)
+        for key in ("pop", "psi", "c", "links"):
+            assert np.array_equal(res[i][key], a[key]), (i, key)
+        _, ca = alone.observables()
+        for k, q in enumerate(res[i]["colloids"]):
+            for key in ("pos", "vel", "omega", "m"):
+                assert np.array_equal(q[key], ca[k][key])
+        assert res[i]["totals"]["step"] == spec["steps"]
+        alone.close()
+
+
+def test_oversized_request_is_refused():
+    srv = serve.Server(budget_bytes=1 << 20)
+    spec = I.serving_request(dict(I.serving_trace(1)[0], side=40, spheres=1))
+    spec["steps"] = 4
+    srv.submit(0, spec, 0.0)
+    res = srv.run()
+    assert "error" in res[0]
