@@ -167,8 +167,25 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
             B.nlchunk_max = std::max(B.nlchunk_max, ctxs[j]->nlchunk_max);
         }
     }
+    // one psi/c kernel per launch: if the boxes disagree on z-marching, all
+    // of them take the one-node-per-thread form
+    bool all_zm = n > 0, any_zm = false;
+    for (int j = 0; j < n; j++) {
+        all_zm = all_zm && d[j].ls[2].zc > 0;
+        any_zm = any_zm || d[j].ls[2].zc > 0;
+    }
+    if (any_zm && !all_zm) {
+        for (int j = 0; j < n; j++) {
+            if (d[j].ls[2].zc > 0) {
+                d[j].ls[2].zc = 0;
+                finish_shape(d[j].ls[2], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz);
+            }
+            bst[2 * (n + 1) + j + 1] = bst[2 * (n + 1) + j] + d[j].ls[2].nblocks;
+        }
+    }
     for (int w = 0; w < 3; w++) B.nblocks[w] = bst[w * (n + 1) + n];
     B.ncol = cst[n];
+    B.scalar_zm = all_zm;
     B.precision = ctxs[0]->p.precision;
     B.args.d = (const BoxDesc *)dev;
     B.args.bstart = (const int *)(dev + align256(sizeof(BoxDesc) * n));
@@ -316,17 +333,18 @@ static lb_status check_params(const lb_params *p, std::string &why)
 // (mu; collide; scalar, 0 = default) overrides them for tuning sweeps.
 static void set_shapes(lb_ctx *c)
 {
-    LaunchShape d = {0, 0, 0, 0, 0, 0};
+    LaunchShape d = {0, 0, 0, 0, 0, 0, 0};
     LaunchShape v[3] = {d, d, d};
     v[2].remap = 2;  // the psi/c update gains from plane-wise XCD renumbering
     if (const char *e = getenv("LB_LATTICE_SHAPES")) {
         for (int k = 0; k < 3 && *e; k++) {
-            int bx = 0, by = 0, rm = 1, used = 0;
+            int bx = 0, by = 0, rm = 1, used = 0, zc = 0, used2 = 0;
             if (sscanf(e, "%d,%d,%d%n", &bx, &by, &rm, &used) == 3) {
                 v[k].bx = bx;
                 v[k].by = by;
                 v[k].remap = rm;
                 e += used;
+                if (sscanf(e, ",%d%n", &zc, &used2) == 1) { v[k].zc = zc; e += used2; }
                 if (*e == ';') e++;
             } else {
                 break;
@@ -712,7 +730,10 @@ lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)
 {
     if (!c || !shapes9) return fail(c, LB_E_INVALID, "null argument");
     for (int k = 0; k < 3; k++) {
-        LaunchShape v = {shapes9[3 * k], shapes9[3 * k + 1], shapes9[3 * k + 2], 0, 0, 0};
+        // remap values 8 + r: the same with z-marching of 8 planes (psi/c update only)
+        int rm = shapes9[3 * k + 2], zc = 0;
+        if (rm >= 8) { zc = 8 * (rm / 8); rm = rm % 8; }
+        LaunchShape v = {shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, k == 2 ? zc : 0};
         if (v.bx < 0 || v.by < 0 || v.remap < 0 || v.remap > 2) return fail(c, LB_E_INVALID, "bad shape");
         finish_shape(v, c->p.nx, c->p.ny, c->p.nz);
         c->shapes[k] = v;
@@ -727,7 +748,7 @@ lb_status lb_get_launch_shapes(lb_ctx *c, int32_t *shapes9)
     for (int k = 0; k < 3; k++) {
         shapes9[3 * k] = c->shapes[k].bx;
         shapes9[3 * k + 1] = c->shapes[k].by;
-        shapes9[3 * k + 2] = c->shapes[k].remap;
+        shapes9[3 * k + 2] = c->shapes[k].remap + c->shapes[k].zc;
     }
     return LB_OK;
 }

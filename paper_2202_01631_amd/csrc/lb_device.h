@@ -69,6 +69,7 @@ __device__ __forceinline__ void st_pop(__half *p, size_t i, float v, float sc)
 struct LaunchShape {
     int bx, by, remap;         // remap: XCD-aware block renumbering (0 off, 1, 2)
     int xseg, nblocks, bpp;    // derived: segments per row, blocks, blocks per z plane
+    int zc;                    // > 0: each thread marches zc consecutive planes (psi/c update)
 };
 
 struct KParams {

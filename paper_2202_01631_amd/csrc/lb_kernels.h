@@ -54,6 +54,7 @@ struct Batch {
     int nchunk_max;   // geometry chunks of the largest particle box
     int nlchunk_max;  // link chunks of the largest link table
     int precision;
+    int scalar_zm;    // psi/c update by z-marching columns (all boxes of the batch)
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,

@@ -69,13 +69,16 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
                        n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
                        n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
     const S ps = psi[n];
+    S pv[6];
+#pragma unroll
+    for (int e = 0; e < 6; e++) pv[e] = psi[nb[e]];
     S lap = S(-6) * ps;
     if (o & OWN_BOUNDARY) {
 #pragma unroll
         for (int e = 0; e < 6; e++) {
             const uint8_t om = own[nb[e]] & OWN_SOLID;
             if (!om) {
-                lap += psi[nb[e]];
+                lap += pv[e];
             } else {
                 const DColloid &q = col[om - 1];
                 double r[3];
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 6; e++) lap += psi[nb[e]];
+        for (int e = 0; e < 6; e++) lap += pv[e];
     }
     const S a = (S)p.a, b = (S)p.b;
     const S t = s_tanh<S>(ps);
@@ -150,6 +153,15 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
         if (cy(i)) jy += cy(i) > 0 ? g[i] : -g[i];
         if (cz(i)) jz += cz(i) > 0 ? g[i] : -g[i];
     }
+    // solid neighbours (only boundary nodes have any), as a mask over i
+    unsigned solid = 0;
+    if (bnd) {
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+            const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
+            solid |= (own[m] & OWN_SOLID) ? (1u << i) : 0u;
+        }
+    }
     // body force -psi grad(mu), isotropic lattice gradient
     // grad(mu) = 3 sum_i w_i c_i mu(x + c_i), mu(x) at solid neighbours
     const S m0 = mu[n];
@@ -158,7 +170,7 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
     for (int i = 1; i < 19; i++) {
         const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
         S mi = mu[m];
-        if (bnd && (own[m] & OWN_SOLID)) mi = m0;
+        if (solid & (1u << i)) mi = m0;
         const S wi = (S)(3.0 * wgt(i));
         if (cx(i)) gx += cx(i) > 0 ? wi * mi : -wi * mi;
         if (cy(i)) gy += cy(i) > 0 ? wi * mi : -wi * mi;
@@ -188,7 +200,7 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
             st_pop(fout, (size_t)n, gs, p.scale);
         } else {
             const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
-            if (bnd && (own[m] & OWN_SOLID))
+            if (solid & (1u << i))
                 st_pop(fout, opp(i) * N + n, gs, p.scale);
             else
                 st_pop(fout, i * N + m, gs, p.scale);
@@ -238,19 +250,32 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     const S chi = chiv[n];
     const S m0 = mu[n];
     const S u0[3] = {u[n], u[N + n], u[2 * N + n]};
-    S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
+    // all neighbour loads issued together; solid faces masked afterwards
+    S um[6], pm[6], cm[6], mm[6], xm[6];
 #pragma unroll
     for (int e = 0; e < 6; e++) {
         const int m = fn[e];
-        if (bnd && (own[m] & OWN_SOLID)) continue;
+        um[e] = u[(e >> 1) * N + m];
+        pm[e] = psi[m];
+        cm[e] = cc[m];
+        mm[e] = mu[m];
+        xm[e] = chiv[m];
+    }
+    unsigned solid = 0;
+    if (bnd) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) solid |= (own[fn[e]] & OWN_SOLID) ? (1u << e) : 0u;
+    }
+    S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        const bool fl = !(solid & (1u << e));  // no flux through a solid face
         const int ax = e >> 1;
-        const S um = u[ax * N + m];
-        const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um) : S(0.5) * (u0[ax] + um);
-        const S pm = psi[m], cm = cc[m];
-        adv_p += ue * (S(0.5) * (ps + pm));
-        adv_c += ue * (S(0.5) * (cn + cm));
-        dmu += mu[m] - m0;
-        dchi += chiv[m] - chi;
+        const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um[e]) : S(0.5) * (u0[ax] + um[e]);
+        adv_p += fl ? ue * (S(0.5) * (ps + pm[e])) : S(0);
+        adv_c += fl ? ue * (S(0.5) * (cn + cm[e])) : S(0);
+        dmu += fl ? mm[e] - m0 : S(0);
+        dchi += fl ? xm[e] - chi : S(0);
     }
     S src = S(0);
     if (bnd) {
@@ -266,6 +291,122 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     }
     psin[n] = ps - adv_p + (S)p.M * dmu;
     ccn[n] = cn - adv_c + (S)p.D * dchi + src - (S)p.kd * chi;
+}
+
+// ----------------------------------------------------------- k_scalar_zm
+// The same update with each thread marching zc consecutive planes of one
+// (x, y) column: the z - 1, z, z + 1 values of psi, c, mu, chi and u_z stay
+// in registers, so a node costs five plane loads fewer than in k_scalar.
+// Blocks of (bx, by) columns; block b covers x segment b % xseg, row group
+// (b / xseg) % ygroups and z chunk b / (xseg * ygroups).
+template <class S>
+__global__ __launch_bounds__(256) void k_scalar_zm(BatchArgs A)
+{
+    const int *bst = A.bstart + 2 * (A.nbox + 1);
+    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    const LaunchShape ls = D.ls[2];
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const S *__restrict__ chiv = (const S *)D.b.chi;
+    const S *__restrict__ u = (const S *)D.b.u;
+    const uint8_t *__restrict__ own = D.b.own;
+    const DColloid *__restrict__ col = D.b.col;
+    S *__restrict__ psin = (S *)D.b.psin;
+    S *__restrict__ ccn = (S *)D.b.ccn;
+    const int b = blockIdx.x - bst[j];
+    const int ygroups = (p.ny + ls.by - 1) / ls.by;
+    const int tx = (int)threadIdx.x % ls.bx, ty = (int)threadIdx.x / ls.bx;
+    if (ty >= ls.by) return;
+    const int seg = b % ls.xseg, rest = b / ls.xseg;
+    const int x = seg * ls.bx + tx, y = (rest % ygroups) * ls.by + ty;
+    const int z0 = (rest / ygroups) * ls.zc;
+    if (x >= p.nx || y >= p.ny || z0 >= p.nz) return;
+    const int z1 = min(z0 + ls.zc, p.nz);
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const size_t N = (size_t)p.N;
+    const int xm = wrap_m(x, p.nx) - x, xp = wrap_p(x, p.nx) - x;
+    const int ym = (wrap_m(y, p.ny) - y) * sy, yp = (wrap_p(y, p.ny) - y) * sy;
+    const int col0 = x + sy * y;
+    // rolling window along z: index 0 = z - 1, 1 = z, 2 = z + 1
+    S wp[3], wc[3], wm[3], wx[3], wu[3];
+    uint8_t wo[3];
+    {
+        const int zb = wrap_m(z0, p.nz);
+        const int nb = col0 + sz * zb, n0 = col0 + sz * z0;
+        wp[0] = psi[nb]; wc[0] = cc[nb]; wm[0] = mu[nb]; wx[0] = chiv[nb]; wu[0] = u[2 * N + nb];
+        wo[0] = own[nb];
+        wp[1] = psi[n0]; wc[1] = cc[n0]; wm[1] = mu[n0]; wx[1] = chiv[n0]; wu[1] = u[2 * N + n0];
+        wo[1] = own[n0];
+    }
+    for (int z = z0; z < z1; z++) {
+        const int n = col0 + sz * z;
+        const int zn = wrap_p(z, p.nz);
+        const int na = col0 + sz * zn;
+        wp[2] = psi[na]; wc[2] = cc[na]; wm[2] = mu[na]; wx[2] = chiv[na]; wu[2] = u[2 * N + na];
+        wo[2] = own[na];
+        const uint8_t o = wo[1];
+        const S ps = wp[1], cn = wc[1];
+        if (o & OWN_SOLID) {
+            psin[n] = ps;
+            ccn[n] = cn;
+        } else {
+            const bool bnd = (o & OWN_BOUNDARY) != 0;
+            const int fn[4] = {n + xp, n + xm, n + yp, n + ym};
+            S um[6], pm[6], cm[6], mm[6], xmv[6];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int m = fn[e];
+                um[e] = u[(e >> 1) * N + m];
+                pm[e] = psi[m];
+                cm[e] = cc[m];
+                mm[e] = mu[m];
+                xmv[e] = chiv[m];
+            }
+            um[4] = wu[2]; pm[4] = wp[2]; cm[4] = wc[2]; mm[4] = wm[2]; xmv[4] = wx[2];
+            um[5] = wu[0]; pm[5] = wp[0]; cm[5] = wc[0]; mm[5] = wm[0]; xmv[5] = wx[0];
+            const S chi = wx[1], m0 = wm[1];
+            const S u0[3] = {u[n], u[N + n], wu[1]};
+            unsigned solid = 0;
+            if (bnd) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) solid |= (own[fn[e]] & OWN_SOLID) ? (1u << e) : 0u;
+                solid |= (wo[2] & OWN_SOLID) ? 16u : 0u;
+                solid |= (wo[0] & OWN_SOLID) ? 32u : 0u;
+            }
+            S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                const bool fl = !(solid & (1u << e));
+                const int ax = e >> 1;
+                const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um[e]) : S(0.5) * (u0[ax] + um[e]);
+                adv_p += fl ? ue * (S(0.5) * (ps + pm[e])) : S(0);
+                adv_c += fl ? ue * (S(0.5) * (cn + cm[e])) : S(0);
+                dmu += fl ? mm[e] - m0 : S(0);
+                dchi += fl ? xmv[e] - chi : S(0);
+            }
+            S src = S(0);
+            if (bnd) {
+                const int xo[3] = {xm, 0, xp}, yo[3] = {ym, 0, yp};
+                const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (zn - z) * sz};
+                for (int d = 1; d < 19; d++) {
+                    const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
+                    const uint8_t om = own[m] & OWN_SOLID;
+                    if (!om) continue;
+                    const DColloid &q = col[om - 1];
+                    double r[3];
+                    displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
+                    src += (S)(active_cap(q, r) ? q.am : q.ap);
+                }
+            }
+            psin[n] = ps - adv_p + (S)p.M * dmu;
+            ccn[n] = cn - adv_c + (S)p.D * dchi + src - (S)p.kd * chi;
+        }
+        wp[0] = wp[1]; wc[0] = wc[1]; wm[0] = wm[1]; wx[0] = wx[1]; wu[0] = wu[1]; wo[0] = wo[1];
+        wp[1] = wp[2]; wc[1] = wc[2]; wm[1] = wm[2]; wx[1] = wx[2]; wu[1] = wu[2]; wo[1] = wo[2];
+    }
 }
 
 // ------------------------------------------------ block reductions (FP64)
@@ -930,6 +1071,13 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz)
     const long long rows = (long long)ny * nz;
     ls.nblocks = (int)(ls.xseg * ((rows + ls.by - 1) / ls.by));
     ls.bpp = 0;
+    if (ls.zc > 0) {
+        // z-marching launch: blocks over (x segment, row group in y, z chunk)
+        if (ls.zc > nz) ls.zc = nz;
+        ls.remap = 0;
+        ls.nblocks = ls.xseg * ((ny + ls.by - 1) / ls.by) * ((nz + ls.zc - 1) / ls.zc);
+        return;
+    }
     if (ls.remap == 2) {
         // plane-wise renumbering needs whole planes per block row and
         // blocks per plane divisible by 8
@@ -956,7 +1104,10 @@ template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm)
     k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
-    k_scalar<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
+    if (B.scalar_zm)
+        k_scalar_zm<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
+    else
+        k_scalar<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
     if (tm) tm->end(2, s);
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);

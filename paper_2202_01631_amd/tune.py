@@ -30,6 +30,11 @@ def candidates(nx, ny):
             if remap == 2 and (ny % by != 0):
                 continue
             out.append((b, by, remap))
+    # z-marching forms of the psi/c update (remap code 8 + r: zc = 8)
+    for zc in (8, 16, 32):
+        for bx in (64, 32):
+            if bx <= nx:
+                out.append((bx, 256 // bx, zc))
     # distinct, natural-order default first
     seen, uniq = set(), []
     for c in [(min(nx, 256), max(1, 256 // min(nx, 256)), 0)] + out:
@@ -41,7 +46,10 @@ def candidates(nx, ny):
 
 def device_key():
     import torch
-    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    if not torch.cuda.is_available():
+        return "none"
+    pr = torch.cuda.get_device_properties(0)
+    return "%s-%dCU" % (getattr(pr, "gcnArchName", pr.name).split(":")[0], pr.multi_processor_count)
 
 
 def _key(shape, precision):
@@ -69,6 +77,23 @@ def apply(box):
     return s
 
 
+def representative_spec(shape, precision):
+    """Workload a shape is tuned on: particles change the cost of the stencil
+    kernels (boundary nodes), so boxes are tuned with them.  Cubic boxes of
+    side 256 take the benchmark workload (64 spheres of radius 6 on and near
+    the interface); other boxes one sphere of radius 4.5 on the interface."""
+    from . import inputs as I
+    if tuple(shape) == (256, 256, 256):
+        return I.workload_many(n=256, count=64, radius=6.0, precision=precision)
+    psi = I.flat_interface(shape, shape[2] / 2.0, I.WIDTH, 0.01)
+    h = [s / 2.0 for s in shape]
+    cols = []
+    if min(shape) >= 17:
+        cols = [I.janus((h[0] + 0.3, h[1] - 0.2, h[2]), (0.6, 0.0, 0.8), 4.5, mu=0.1, theta=70.0)]
+    return dict(shape=tuple(shape), precision=precision, params=dict(I.FREE_ENERGY),
+                solubility_ratio=2.0, psi=psi, c=np.zeros(psi.size), colloids=cols)
+
+
 def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log=print):
     """Time every candidate shape for the three lattice kernels; return the
     best (bx, by, remap) of each and store it in the cache."""
@@ -77,9 +102,7 @@ def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log
     from . import inputs as I
     from . import lb
     if spec is None:
-        psi = I.flat_interface(shape, shape[2] / 2.0, I.WIDTH, 0.01)
-        spec = dict(shape=tuple(shape), precision=precision, params=dict(I.FREE_ENERGY),
-                    solubility_ratio=2.0, psi=psi, c=np.zeros(psi.size), colloids=[])
+        spec = representative_spec(shape, precision)
     box = lb.from_spec(spec, precision=precision)
     results = {}
     for cand in candidates(shape[0], shape[1]):

@@ -90,6 +90,9 @@ def test_batched_fp64_matches_oracle():
     [(64, 4, 0), (64, 4, 0), (64, 4, 0)],
     [(32, 8, 2), (256, 1, 1), (16, 16, 2)],
     [(48, 5, 0), (24, 10, 0), (40, 6, 0)],
+    [(64, 4, 0), (256, 1, 0), (64, 4, 8)],
+    [(32, 8, 0), (32, 8, 0), (16, 16, 16)],
+    [(32, 8, 0), (32, 8, 0), (32, 4, 40)],
 ])
 def test_launch_shapes_do_not_change_results(shapes):
     w = I.workload_small()
@@ -99,6 +102,22 @@ def test_launch_shapes_do_not_change_results(shapes):
     ref.step(15)
     alt.step(15)
     assert _same(_state(ref), _state(alt))
+
+
+def test_batched_mixed_zmarch_equals_alone():
+    # boxes of one batch disagreeing on the z-marching psi/c form fall back
+    # to the one-node-per-thread form; results unchanged
+    import torch
+    specs = _boxes(n=3, seed=21)
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+    batch[0].set_launch_shapes([(0, 0, 0), (0, 0, 0), (0, 0, 8)])
+    alone = [lb.from_spec(s, precision="fp32") for s in specs]
+    lb.batch_step(batch, 6)
+    for b in alone:
+        b.step(6)
+    for b, a in zip(batch, alone):
+        assert _same(_state(b), _state(a))
 
 
 def test_batch_error_paths():

@@ -256,3 +256,37 @@ def test_error_paths():
     b.step(3)
     t, _ = b.observables()
     assert t["n_links"] == 0 and t["step"] == 3 and t["error_bits"] == 0
+
+
+# ------------------------------------------------------ full benchmark size
+def test_full_size_256_one_step():
+    # the benchmark workload itself (256^3, 64 moving Janus spheres), in the
+    # launch configuration bench.py times (tuned shapes): owner map and link
+    # table bit-exact at placement and after one step, FP64 fields within
+    # 1e-12 of the oracle after one step, FP32 within 2e-5
+    from paper_2202_01631_amd import tune
+    w = I.workload_many(n=256, count=64, radius=6.0, precision="fp32")
+    flush_print("[full] oracle setup 256^3")
+    o = oracle.from_spec(w)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        flush_print("[full] gpu", prec)
+        g = lb.from_spec(w, precision=prec)
+        tune.apply(g)
+        if prec == "fp64":
+            assert np.array_equal(g.owner(), o.owner())
+            assert np.array_equal(g.links(), o.links())
+        g.step(1)
+        if prec == "fp64":
+            flush_print("[full] oracle step")
+            o.step(1)
+            oown = o.owner()
+            olinks = o.links()
+            ofields = o.fields()
+        assert np.array_equal(g.owner(), oown)
+        assert np.array_equal(g.links(), olinks)
+        e = field_errors(g.fields(), ofields, oown < 0)
+        flush_print("[full] %s errors %s" % (prec, e))
+        assert max(e.values()) <= tol
+        t, _ = g.observables()
+        assert t["error_bits"] == 0
+        g.close()
