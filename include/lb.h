@@ -80,7 +80,9 @@ typedef enum {
 #define LB_ERR_LINKS 8      /* link table of a particle overflowed its capacity */
 
 typedef struct {
-    int32_t nx, ny, nz;          /* periodic box */
+    int32_t nx, ny, nz;          /* periodic box; nz <= 65535 and one scalar field
+                                    (N nodes x 8 bytes in FP64, x 4 otherwise)
+                                    below 4 GiB */
     int32_t precision;           /* lb_precision */
     double rho0, tau;            /* rest density, BGK relaxation time (> 1/2) */
     double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2, Eq. 1
@@ -114,14 +116,16 @@ typedef struct lb_ctx lb_ctx; /* opaque */
 
 /* Device bytes lb_create needs for a box with these parameters (the lattice
  * fields; particle tables are allocated by lb_add_colloids).
- * Errors: LB_E_INVALID for a NULL argument or a non-positive box size. */
+ * Errors: LB_E_INVALID for a NULL argument, a non-positive box size, a bad
+ * precision or a box beyond the size limits of lb_params. */
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes);
 
-/* Validate p and create a context for one box.  Checks: box sizes >= 1,
- * tau > 1/2, rho0 > 0, kappa, M_psi, C, D_c, k_d >= 0, explicit-Euler
+/* Validate p and create a context for one box.  Checks: the size limits of
+ * lb_params, tau > 1/2, rho0 > 0, kappa, M_psi, C, D_c, k_d >= 0, explicit-Euler
  * stability of the psi and c updates, M_psi (12|a| + 36|b| + 144 kappa) < 2
  * and 12 D_c + k_d < 2 (LB_E_INVALID otherwise).  dev_arena: device memory
- * of at least lb_footprint_bytes (borrowed), or NULL for the library to
+ * of at least lb_footprint_bytes, 256-byte aligned (borrowed; LB_E_INVALID
+ * if misaligned), or NULL for the library to
  * allocate it (LB_E_OOM if it cannot).  hip_stream: a hipStream_t, or NULL
  * for the default stream.  *out receives the context. */
 lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes,
@@ -163,7 +167,9 @@ lb_status lb_observables(lb_ctx *ctx, lb_totals *t, lb_colloid *out, int32_t n);
 lb_status lb_get_fields(lb_ctx *ctx, double *rho, double *u, double *psi, double *c);
 
 /* FP64 host copy of the populations f_i (19 planes of N, plane-major),
- * reconstructed from storage (f = stored/scale + w_i rho0). */
+ * reconstructed from storage (f = stored/scale + w_i rho0); 0 at solid
+ * nodes, whose slots carry no state (a node uncovered by a particle is
+ * refilled from equilibrium). */
 lb_status lb_get_populations(lb_ctx *ctx, double *f);
 
 /* Owner map: -1 fluid, k for a node inside particle k (int32, N). */
@@ -195,11 +201,17 @@ lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
 lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
 
 /* Launch shapes of the three lattice kernels (chemical potential,
- * collide-stream, psi/c update): for each, (bx, by, remap) = nodes per row
- * segment, rows per block (bx*by <= 256; 0 = default) and block renumbering
- * (0 natural order, 1 contiguous ranges per XCD, 2 one eighth of every z
- * plane per XCD).  Used by the autotuner; results are identical for every
- * shape.  lb_get_launch_shapes returns the shapes in effect. */
+ * collide-stream, psi/c update): for each, (bx, by, code) = nodes per row
+ * segment, rows per block (bx*by <= 256; 0 = default) and code = remap +
+ * 8 vec.  remap is the block renumbering (0 natural order, 1 contiguous
+ * ranges per XCD, 2 one eighth of every z plane per XCD); vec (0, 2 or 4;
+ * chemical potential and psi/c update only) selects the row-vector form with
+ * vec consecutive x nodes per lane (FP64 takes 2 for 4), in which bx and by
+ * are derived from nx, and which boxes with nx % vec != 0, or rows longer
+ * than 64 lanes that are not a multiple of 64 lanes, replace by the
+ * one-node form.  LB_E_INVALID for other values.  Used by the autotuner;
+ * results are identical for every shape.  lb_get_launch_shapes returns the
+ * shapes in effect. */
 lb_status lb_set_launch_shapes(lb_ctx *ctx, const int32_t *shapes9);
 lb_status lb_get_launch_shapes(lb_ctx *ctx, int32_t *shapes9);
 

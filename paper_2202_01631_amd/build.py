@@ -39,7 +39,10 @@ def _compile(src):
 
 
 def build(verbose=True):
-    """Compile every HIP source for gfx950 and link the shared library."""
+    """Compile every HIP source for gfx950 and link the shared library.  A
+    failed build leaves no library behind (never a stale one)."""
+    if os.path.exists(LIB):
+        os.remove(LIB)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -167,25 +167,25 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
             B.nlchunk_max = std::max(B.nlchunk_max, ctxs[j]->nlchunk_max);
         }
     }
-    // one psi/c kernel per launch: if the boxes disagree on z-marching, all
-    // of them take the one-node-per-thread form
-    bool all_zm = n > 0, any_zm = false;
-    for (int j = 0; j < n; j++) {
-        all_zm = all_zm && d[j].ls[2].zc > 0;
-        any_zm = any_zm || d[j].ls[2].zc > 0;
-    }
-    if (any_zm && !all_zm) {
-        for (int j = 0; j < n; j++) {
-            if (d[j].ls[2].zc > 0) {
-                d[j].ls[2].zc = 0;
-                finish_shape(d[j].ls[2], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz);
+    // one kernel form per launch: where the boxes disagree on the row-vector
+    // form of the mu or psi/c update, all of them take the one-node form
+    const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
+    for (int w = 0; w < 3; w++) {
+        bool same = true;
+        for (int j = 1; j < n; j++) same = same && d[j].ls[w].vec == d[0].ls[w].vec;
+        if (!same) {
+            for (int j = 0; j < n; j++) {
+                if (d[j].ls[w].vec > 1) {
+                    d[j].ls[w].vec = 0;
+                    finish_shape(d[j].ls[w], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ssize);
+                }
+                bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
             }
-            bst[2 * (n + 1) + j + 1] = bst[2 * (n + 1) + j] + d[j].ls[2].nblocks;
         }
+        B.vec[w] = n > 0 ? d[0].ls[w].vec : 0;
     }
     for (int w = 0; w < 3; w++) B.nblocks[w] = bst[w * (n + 1) + n];
     B.ncol = cst[n];
-    B.scalar_zm = all_zm;
     B.precision = ctxs[0]->p.precision;
     B.args.d = (const BoxDesc *)dev;
     B.args.bstart = (const int *)(dev + align256(sizeof(BoxDesc) * n));
@@ -300,13 +300,25 @@ static hipError_t capture_pair(const Batch &B0, const Batch &B1, hipStream_t s, 
 }
 
 // ------------------------------------------------------------- checks
-static lb_status check_params(const lb_params *p, std::string &why)
+static lb_status check_size(const lb_params *p, std::string &why)
 {
-    if (!p) { why = "null parameters"; return LB_E_INVALID; }
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "box sizes must be >= 1"; return LB_E_INVALID; }
     if ((double)p->nx * p->ny * p->nz >= 2147483647.0) { why = "box too large (N >= 2^31)"; return LB_E_INVALID; }
     if (p->nz > 65535) { why = "nz > 65535"; return LB_E_INVALID; }
     if (p->precision < LB_FP64 || p->precision > LB_FP16_STORAGE) { why = "bad precision"; return LB_E_INVALID; }
+    // kernels address scalar fields with 32-bit byte offsets
+    if ((double)p->nx * p->ny * p->nz * (p->precision == LB_FP64 ? 8.0 : 4.0) >= 4294967296.0) {
+        why = "box too large (one scalar field must stay below 4 GiB)";
+        return LB_E_INVALID;
+    }
+    return LB_OK;
+}
+
+static lb_status check_params(const lb_params *p, std::string &why)
+{
+    if (!p) { why = "null parameters"; return LB_E_INVALID; }
+    const lb_status sz = check_size(p, why);
+    if (sz != LB_OK) return sz;
     if (!(p->tau > 0.5)) { why = "tau must exceed 1/2"; return LB_E_INVALID; }
     if (!(p->rho0 > 0.0)) { why = "rho0 must be positive"; return LB_E_INVALID; }
     if (p->kappa < 0 || p->M_psi < 0 || p->C < 0 || p->D_c < 0 || p->k_d < 0) {
@@ -327,24 +339,31 @@ static lb_status check_params(const lb_params *p, std::string &why)
     return LB_OK;
 }
 
-// Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block;
-// blocks in natural order for mu and collide, plane-wise XCD renumbering for
-// the psi/c update (the fastest of the shapes swept on 256^3); LB_LATTICE_SHAPES="bx,by,remap;bx,by,remap;bx,by,remap"
-// (mu; collide; scalar, 0 = default) overrides them for tuning sweeps.
+// Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block
+// for collide-stream in natural block order; the row-vector forms for the mu
+// and psi/c updates, the psi/c update with plane-wise XCD renumbering.
+// LB_LATTICE_SHAPES="bx,by,remap[,vec];..." (mu; collide; psi/c, 0 = default)
+// overrides them for tuning sweeps.
 static void set_shapes(lb_ctx *c)
 {
     LaunchShape d = {0, 0, 0, 0, 0, 0, 0};
     LaunchShape v[3] = {d, d, d};
-    v[2].remap = 2;  // the psi/c update gains from plane-wise XCD renumbering
+    v[0].vec = 4;
+    v[2].vec = 4;
+    v[2].remap = 2;
     if (const char *e = getenv("LB_LATTICE_SHAPES")) {
         for (int k = 0; k < 3 && *e; k++) {
-            int bx = 0, by = 0, rm = 1, used = 0, zc = 0, used2 = 0;
+            int bx = 0, by = 0, rm = 1, used = 0, vec = 0, used2 = 0;
             if (sscanf(e, "%d,%d,%d%n", &bx, &by, &rm, &used) == 3) {
                 v[k].bx = bx;
                 v[k].by = by;
-                v[k].remap = rm;
+                v[k].remap = rm >= 0 && rm <= 2 ? rm : 0;
+                v[k].vec = 0;
                 e += used;
-                if (sscanf(e, ",%d%n", &zc, &used2) == 1) { v[k].zc = zc; e += used2; }
+                if (sscanf(e, ",%d%n", &vec, &used2) == 1) {
+                    if (k != 1 && (vec == 2 || vec == 4)) v[k].vec = vec;
+                    e += used2;
+                }
                 if (*e == ';') e++;
             } else {
                 break;
@@ -352,7 +371,7 @@ static void set_shapes(lb_ctx *c)
         }
     }
     for (int k = 0; k < 3; k++) {
-        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz);
+        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4);
         c->shapes[k] = v[k];
     }
     c->dirty = true;
@@ -426,7 +445,8 @@ extern "C" {
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(nullptr, LB_E_INVALID, "null argument");
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(nullptr, LB_E_INVALID, "box sizes must be >= 1");
+    std::string why;
+    if (check_size(p, why) != LB_OK) return fail(nullptr, LB_E_INVALID, why.c_str());
     *bytes = layout_of(*p).total;
     return LB_OK;
 }
@@ -456,6 +476,10 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     c->stream = (hipStream_t)hip_stream;
     c->L = layout_of(c->p);
     if (dev_arena) {
+        if ((uintptr_t)dev_arena & 255) {
+            delete c;
+            return fail(nullptr, LB_E_INVALID, "arena must be 256-byte aligned");
+        }
         if (arena_bytes < c->L.total) {
             delete c;
             return fail(nullptr, LB_E_OOM, "arena smaller than lb_footprint_bytes");
@@ -521,6 +545,21 @@ lb_status lb_destroy(lb_ctx *c)
 
 const char *lb_last_error(const lb_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+// The second population lattice starts as a copy of the first and u as zero:
+// slots that streaming never writes (those of solid nodes) and u at solid
+// nodes then hold defined values, so no result depends on earlier contents
+// of the device memory.
+static hipError_t define_spare_state(lb_ctx *c)
+{
+    const size_t N = (size_t)c->N;
+    hipError_t e = hipMemcpyAsync(ptr(c, c->L.f[1]), ptr(c, c->L.f[0]),
+                                  19 * N * storage_bytes(c->p.precision), hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ptr(c, c->L.u), 0, 3 * N * compute_bytes(c->p.precision), c->stream);
+    return e;
+}
+
 lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const double *rho,
                          const double *u)
 {
@@ -560,6 +599,7 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     if (e != hipSuccess) return hip_fail(c, e, "init kernel launch");
     if (e2 != hipSuccess) return hip_fail(c, e2, "init kernel");
     HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    HIP_TRY(c, define_spare_state(c));
     c->step = 0;
     c->stage = 1;
     return LB_OK;
@@ -729,15 +769,18 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
 lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)
 {
     if (!c || !shapes9) return fail(c, LB_E_INVALID, "null argument");
+    LaunchShape v[3];
     for (int k = 0; k < 3; k++) {
-        // remap values 8 + r: the same with z-marching of 8 planes (psi/c update only)
-        int rm = shapes9[3 * k + 2], zc = 0;
-        if (rm >= 8) { zc = 8 * (rm / 8); rm = rm % 8; }
-        LaunchShape v = {shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, k == 2 ? zc : 0};
-        if (v.bx < 0 || v.by < 0 || v.remap < 0 || v.remap > 2) return fail(c, LB_E_INVALID, "bad shape");
-        finish_shape(v, c->p.nx, c->p.ny, c->p.nz);
-        c->shapes[k] = v;
+        // code = remap + 8 vec
+        const int code = shapes9[3 * k + 2];
+        const int rm = code & 7, vec = code >= 0 ? code >> 3 : -1;
+        v[k] = LaunchShape{shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, vec};
+        if (v[k].bx < 0 || v[k].by < 0 || code < 0 || rm > 2 ||
+            !(vec == 0 || vec == 1 || ((vec == 2 || vec == 4) && k != 1)))
+            return fail(c, LB_E_INVALID, "bad shape");
+        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4);
     }
+    for (int k = 0; k < 3; k++) c->shapes[k] = v[k];
     c->dirty = true;
     return LB_OK;
 }
@@ -748,7 +791,7 @@ lb_status lb_get_launch_shapes(lb_ctx *c, int32_t *shapes9)
     for (int k = 0; k < 3; k++) {
         shapes9[3 * k] = c->shapes[k].bx;
         shapes9[3 * k + 1] = c->shapes[k].by;
-        shapes9[3 * k + 2] = c->shapes[k].remap + c->shapes[k].zc;
+        shapes9[3 * k + 2] = c->shapes[k].remap + 8 * (c->shapes[k].vec > 1 ? c->shapes[k].vec : 0);
     }
     return LB_OK;
 }
@@ -1000,6 +1043,7 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
         HIP_TRY(c, hipMemcpyAsync(c->ldc, o, (size_t)c->lcap * c->ncol, hipMemcpyHostToDevice, c->stream));
     }
     HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    HIP_TRY(c, define_spare_state(c));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = hd.step;
     c->stage = 2;

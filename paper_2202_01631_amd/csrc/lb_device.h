@@ -63,13 +63,41 @@ __device__ __forceinline__ void st_pop(__half *p, size_t i, float v, float sc)
     p[i] = __float2half_rn(v * sc);
 }
 
+// Access through a uniform base pointer and a 32-bit byte offset: the
+// compiler emits global loads and stores with a scalar base and one 32-bit
+// vector offset, shared by every field indexed alike (instead of a 64-bit
+// vector address per field and neighbour).  Boxes are limited to scalar
+// fields below 4 GiB, so byte offsets fit in 32 bits.
+template <class T> __device__ __forceinline__ T ldb(const T *base, unsigned off)
+{
+    return *(const T *)((const char *)base + off);
+}
+template <class T> __device__ __forceinline__ void stb(T *base, unsigned off, T v)
+{
+    *(T *)((char *)base + off) = v;
+}
+
+// the same for populations (FP16 storage scaled on the way in and out)
+__device__ __forceinline__ double ldp(const double *b, unsigned off, float) { return ldb(b, off); }
+__device__ __forceinline__ float ldp(const float *b, unsigned off, float) { return ldb(b, off); }
+__device__ __forceinline__ float ldp(const __half *b, unsigned off, float inv)
+{
+    return __half2float(ldb(b, off)) * inv;
+}
+__device__ __forceinline__ void stp(double *b, unsigned off, double v, float) { stb(b, off, v); }
+__device__ __forceinline__ void stp(float *b, unsigned off, float v, float) { stb(b, off, v); }
+__device__ __forceinline__ void stp(__half *b, unsigned off, float v, float sc)
+{
+    stb(b, off, __float2half_rn(v * sc));
+}
+
 // --------------------------------------------------------- parameter block
 // Shape of a lattice launch: blocks of (bx, by) threads cover an x segment
 // of bx nodes in by consecutive rows (rows = (y, z) flattened).
 struct LaunchShape {
     int bx, by, remap;         // remap: XCD-aware block renumbering (0 off, 1, 2)
     int xseg, nblocks, bpp;    // derived: segments per row, blocks, blocks per z plane
-    int zc;                    // > 0: each thread marches zc consecutive planes (psi/c update)
+    int vec;                   // > 1: row-vector form, vec consecutive x nodes per lane
 };
 
 struct KParams {
@@ -170,22 +198,28 @@ __host__ __device__ inline AxisBox axis_box(double c, double radius, int L)
 // renumbered XCD-aware: the hardware sends workgroup i to XCD i % 8, and each
 // XCD receives a contiguous range of blocks, so the halo rows a block reads
 // were mostly loaded by blocks of the same XCD (same L2).
-__device__ __forceinline__ bool lattice_node(const KParams &p, int i, int &x, int &y, int &z)
+__device__ __forceinline__ int block_order(const LaunchShape &ls, int i)
 {
     int b = i;
-    if (p.ls.remap == 1) {
+    if (ls.remap == 1) {
         // contiguous block ranges per XCD
-        const int q = p.ls.nblocks >> 3, r = p.ls.nblocks & 7;
+        const int q = ls.nblocks >> 3, r = ls.nblocks & 7;
         const int xcd = i & 7, slot = i >> 3;
         b = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    } else if (p.ls.remap == 2) {
+    } else if (ls.remap == 2) {
         // one eighth of every z plane per XCD, planes in order: the eight XCDs
         // sweep a plane together (no address-range camping) and the z +- 1
         // rows of a block belong to its own XCD
-        const int bpp = p.ls.bpp, G = bpp >> 3;
+        const int bpp = ls.bpp, G = bpp >> 3;
         const int xcd = i & 7, slot = i >> 3;
         b = (slot / G) * bpp + xcd * G + (slot % G);
     }
+    return b;
+}
+
+__device__ __forceinline__ bool lattice_node(const KParams &p, int i, int &x, int &y, int &z)
+{
+    const int b = block_order(p.ls, i);
     // 256 threads per block, read as (bx, by) for this box: boxes of a batch
     // may use different shapes within one launch
     const int tx = (int)threadIdx.x % p.ls.bx, ty = (int)threadIdx.x / p.ls.bx;
@@ -198,5 +232,36 @@ __device__ __forceinline__ bool lattice_node(const KParams &p, int i, int &x, in
     y = row - z * p.ny;
     return true;
 }
+
+// Row-vector launch (vec = V > 1): lane li of a group of bx lanes covers the
+// V consecutive nodes x0 .. x0 + V - 1 of one row segment (xseg segments per
+// row); a wavefront holds by = 64 / bx groups, a block four wavefronts.
+// Returns false for lanes without nodes, always whole groups, so exchanges
+// between the lanes of a live group stay inside live lanes.
+template <int V>
+__device__ __forceinline__ bool vec_node(const KParams &p, int i, int &x0, int &y, int &z, int &li,
+                                         int &gb)
+{
+    const int b = block_order(p.ls, i);
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    const int Ls = p.ls.bx, g = l / Ls;
+    if (g >= p.ls.by) return false;
+    li = l - g * Ls;
+    gb = g * Ls;
+    const int sg = (b * 4 + w) * p.ls.by + g;
+    const int row = sg / p.ls.xseg, seg = sg - row * p.ls.xseg;
+    if (row >= p.ny * p.nz) return false;
+    z = row / p.ny;
+    y = row - z * p.ny;
+    x0 = (seg * Ls + li) * V;
+    return true;
+}
+
+// V consecutive scalars moved as one 8- or 16-byte access
+template <class S, int V> struct alignas(sizeof(S) * V) SVec { S v[V]; };
+template <int V> struct OwnWord;
+template <> struct OwnWord<2> { typedef uint16_t T; };
+template <> struct OwnWord<4> { typedef uint32_t T; };
+__device__ __forceinline__ uint8_t byte_of(unsigned w, int k) { return (uint8_t)(w >> (8 * k)); }
 
 }  // namespace lbk

@@ -54,7 +54,7 @@ struct Batch {
     int nchunk_max;   // geometry chunks of the largest particle box
     int nlchunk_max;  // link chunks of the largest link table
     int precision;
-    int scalar_zm;    // psi/c update by z-marching columns (all boxes of the batch)
+    int vec[3];       // row-vector form of each lattice launch (all boxes of the batch)
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,
@@ -73,11 +73,8 @@ struct TimingHook {
     ~TimingHook();
 };
 
-// per-kernel launch shapes of the three lattice kernels
-struct LatticeShapes {
-    LaunchShape mu, collide, scalar;
-};
-void finish_shape(LaunchShape &ls, int nx, int ny, int nz);
+// derive the launch extents of a shape; ssize = bytes of a scalar field value
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize);
 
 // one time step of every box of the batch (all boxes share the precision P)
 template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm);

@@ -46,6 +46,52 @@ template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tan
 // as b psi (psi-1)(psi+1) + (a+b) psi to keep FP32 cancellation small).
 // At a solid face neighbour the Laplacian takes the ghost psi - (H/kappa)|e.n|
 // (Eq. 9, n through the face midpoint).
+// The node arithmetic lives in helpers with contraction off and explicit
+// fused forms, so every launch form of a kernel rounds identically.
+
+// psi value the Laplacian takes across face e (x+, x-, y+, y-, z+, z-) of
+// fluid node (x, y, z): the neighbour's, or the wetting ghost at a solid one
+template <class S>
+__device__ __forceinline__ S face_psi(const KParams &p, const DColloid *__restrict__ col,
+                                      uint8_t onb, int e, int x, int y, int z, S ps, S pv)
+{
+#pragma clang fp contract(off)
+    const uint8_t om = onb & OWN_SOLID;
+    if (!om) return pv;
+    const DColloid &q = col[om - 1];
+    double r[3];
+    const int ax = e >> 1, sg = (e & 1) ? -1 : 1;
+    displacement(q, x, y, z, ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0, 0.5, p.nx, p.ny,
+                 p.nz, r);
+    const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double en = fabs(r[ax]) / rn;
+    const double gh = p.kappa > 0.0 ? (q.H / p.kappa) * en : 0.0;
+    return ps - (S)gh;
+}
+
+template <class S> __device__ __forceinline__ S lap6(S ps, const S f[6])
+{
+#pragma clang fp contract(off)
+    S l = S(-6) * ps;
+#pragma unroll
+    for (int e = 0; e < 6; e++) l = l + f[e];
+    return l;
+}
+
+template <class S>
+__device__ __forceinline__ void mu_chi(const KParams &p, S ps, S lap, S cn, S &mu, S &chi)
+{
+#pragma clang fp contract(off)
+    const S a = (S)p.a, b = (S)p.b;
+    const S t = s_tanh<S>(ps);
+    chi = fma(-(S)p.E, t, cn - (S)p.cb0);
+    S m = b * ps * (ps - S(1)) * (ps + S(1));
+    m = fma(a + b, ps, m);
+    m = fma(-(S)p.kappa, lap, m);
+    mu = fma(-(S)(p.C * p.E) * chi, fma(-t, t, S(1)), m);
+}
+
+// one node per thread
 template <class S>
 __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
 {
@@ -63,44 +109,109 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
     if (!lattice_node(p, blockIdx.x - A.bstart[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
-    const uint8_t o = own[n];
-    if (o & OWN_SOLID) { mu[n] = S(0); chi_out[n] = S(0); return; }
     const int nb[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
                        n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
                        n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
-    const S ps = psi[n];
+    // all loads issued before anything depends on the owner byte
+    const uint8_t o = own[n];
+    const unsigned on = (unsigned)n * sizeof(S);
+    const S ps = ldb(psi, on), cn = ldb(cc, on);
     S pv[6];
 #pragma unroll
-    for (int e = 0; e < 6; e++) pv[e] = psi[nb[e]];
-    S lap = S(-6) * ps;
+    for (int e = 0; e < 6; e++) pv[e] = ldb(psi, (unsigned)nb[e] * sizeof(S));
+    if (o & OWN_SOLID) { stb(mu, on, S(0)); stb(chi_out, on, S(0)); return; }
     if (o & OWN_BOUNDARY) {
 #pragma unroll
-        for (int e = 0; e < 6; e++) {
-            const uint8_t om = own[nb[e]] & OWN_SOLID;
-            if (!om) {
-                lap += pv[e];
-            } else {
-                const DColloid &q = col[om - 1];
-                double r[3];
-                const int ax = e >> 1, sg = (e & 1) ? -1 : 1;
-                displacement(q, x, y, z, ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0, 0.5,
-                             p.nx, p.ny, p.nz, r);
-                const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-                const double en = fabs(r[ax]) / rn;
-                const double gh = p.kappa > 0.0 ? (q.H / p.kappa) * en : 0.0;
-                lap += ps - (S)gh;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 6; e++) lap += pv[e];
+        for (int e = 0; e < 6; e++)
+            pv[e] = face_psi<S>(p, col, ldb(own, (unsigned)nb[e]), e, x, y, z, ps, pv[e]);
     }
-    const S a = (S)p.a, b = (S)p.b;
-    const S t = s_tanh<S>(ps);
-    const S chi = cc[n] - (S)p.cb0 - (S)p.E * t;
-    mu[n] = b * ps * (ps - S(1)) * (ps + S(1)) + (a + b) * ps - (S)p.kappa * lap -
-            (S)(p.C * p.E) * chi * (S(1) - t * t);
-    chi_out[n] = chi;
+    S m, c;
+    mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
+    stb(mu, on, m);
+    stb(chi_out, on, c);
+}
+
+// Row-vector form: V consecutive x nodes per lane, 8- or 16-byte loads and
+// stores, x neighbours exchanged between lanes (the row wraps inside a lane
+// group when the group holds the whole row; segment ends of longer rows are
+// read directly).  Needs nx % V == 0.
+template <class S, int V>
+__global__ __launch_bounds__(256) void k_mu_v(BatchArgs A)
+{
+    typedef SVec<S, V> Vec;
+    typedef typename OwnWord<V>::T OW;
+    const int j = find_box(A.bstart, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    KParams p = D.p;
+    p.ls = D.ls[0];
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const uint8_t *__restrict__ own = D.b.own;
+    const DColloid *__restrict__ col = D.b.col;
+    S *__restrict__ mu = (S *)D.b.mu;
+    S *__restrict__ chi_out = (S *)D.b.chi;
+    int x0, y, z, li, gb;
+    if (!vec_node<V>(p, blockIdx.x - A.bstart[j], x0, y, z, li, gb)) return;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int n0 = x0 + sy * y + sz * z;
+    const int nyp = n0 + (wrap_p(y, p.ny) - y) * sy, nym = n0 + (wrap_m(y, p.ny) - y) * sy;
+    const int nzp = n0 + (wrap_p(z, p.nz) - z) * sz, nzm = n0 + (wrap_m(z, p.nz) - z) * sz;
+    const unsigned on = (unsigned)n0 * sizeof(S);
+    const OW ow = ldb((const OW *)own, (unsigned)n0);
+    const Vec pc = ldb((const Vec *)psi, on);
+    const Vec pyp = ldb((const Vec *)psi, (unsigned)nyp * sizeof(S));
+    const Vec pym = ldb((const Vec *)psi, (unsigned)nym * sizeof(S));
+    const Vec pzp = ldb((const Vec *)psi, (unsigned)nzp * sizeof(S));
+    const Vec pzm = ldb((const Vec *)psi, (unsigned)nzm * sizeof(S));
+    const Vec cv = ldb((const Vec *)cc, on);
+    const int Ls = p.ls.bx;
+    const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
+    S pl = __shfl(pc.v[V - 1], srcl), pr = __shfl(pc.v[0], srcr);
+    unsigned owl = __shfl((unsigned)ow, srcl), owr = __shfl((unsigned)ow, srcr);
+    if (p.ls.xseg > 1) {
+        const int rb = n0 - x0;
+        if (li == 0) {
+            const int xl = rb + (x0 == 0 ? p.nx - 1 : x0 - 1);
+            pl = ldb(psi, (unsigned)xl * sizeof(S));
+            owl = (unsigned)own[xl] << (8 * (V - 1));
+        }
+        if (li == Ls - 1) {
+            const int xr = rb + (x0 + V == p.nx ? 0 : x0 + V);
+            pr = ldb(psi, (unsigned)xr * sizeof(S));
+            owr = own[xr];
+        }
+    }
+    unsigned oyp = 0, oym = 0, ozp = 0, ozm = 0;
+    const unsigned bmask = (V == 4) ? 0x80808080u : 0x8080u;
+    if ((unsigned)ow & bmask) {
+        oyp = ldb((const OW *)own, (unsigned)nyp);
+        oym = ldb((const OW *)own, (unsigned)nym);
+        ozp = ldb((const OW *)own, (unsigned)nzp);
+        ozm = ldb((const OW *)own, (unsigned)nzm);
+    }
+    Vec mv, xv;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        const uint8_t o = byte_of(ow, k);
+        const S ps = pc.v[k];
+        S pv[6] = {k < V - 1 ? pc.v[k + 1] : pr, k > 0 ? pc.v[k - 1] : pl, pyp.v[k], pym.v[k],
+                   pzp.v[k], pzm.v[k]};
+        if (o & OWN_BOUNDARY) {
+            const uint8_t onb[6] = {k < V - 1 ? byte_of(ow, k + 1) : byte_of(owr, 0),
+                                    k > 0 ? byte_of(ow, k - 1) : byte_of(owl, V - 1),
+                                    byte_of(oyp, k), byte_of(oym, k), byte_of(ozp, k),
+                                    byte_of(ozm, k)};
+#pragma unroll
+            for (int e = 0; e < 6; e++) pv[e] = face_psi<S>(p, col, onb[e], e, x0 + k, y, z, ps, pv[e]);
+        }
+        S m, c;
+        mu_chi<S>(p, ps, lap6<S>(ps, pv), cv.v[k], m, c);
+        const bool solid = (o & OWN_SOLID) != 0;
+        mv.v[k] = solid ? S(0) : m;
+        xv.v[k] = solid ? S(0) : c;
+    }
+    stb((Vec *)mu, on, mv);
+    stb((Vec *)chi_out, on, xv);
 }
 
 // ------------------------------------------------------------- k_collide
@@ -134,17 +245,25 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
     if (!lattice_node(p, blockIdx.x - bst[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
-    const uint8_t o = own[n];
-    if (o & OWN_SOLID) return;
-    const bool bnd = (o & OWN_BOUNDARY) != 0;
     const size_t N = (size_t)p.N;
     const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
     const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
     const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
-
+    // populations and mu neighbours are loaded before anything depends on
+    // the owner byte (solid nodes discard them)
+    const uint8_t o = own[n];
+    const unsigned on = (unsigned)n * sizeof(T);
     S g[19];
 #pragma unroll
-    for (int i = 0; i < 19; i++) g[i] = ld_pop(fin, i * N + n, p.inv_scale);
+    for (int i = 0; i < 19; i++) g[i] = ldp(fin + i * N, on, p.inv_scale);
+    const unsigned os = (unsigned)n * sizeof(S);
+    const S m0 = ldb(mu, os), ps = ldb(psi, os);
+    S mv[19];
+#pragma unroll
+    for (int i = 1; i < 19; i++)
+        mv[i] = ldb(mu, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) * sizeof(S));
+    if (o & OWN_SOLID) return;
+    const bool bnd = (o & OWN_BOUNDARY) != 0;
     S drho = S(0), jx = S(0), jy = S(0), jz = S(0);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
@@ -159,24 +278,20 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 #pragma unroll
         for (int i = 1; i < 19; i++) {
             const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
-            solid |= (own[m] & OWN_SOLID) ? (1u << i) : 0u;
+            solid |= (ldb(own, (unsigned)m) & OWN_SOLID) ? (1u << i) : 0u;
         }
     }
     // body force -psi grad(mu), isotropic lattice gradient
     // grad(mu) = 3 sum_i w_i c_i mu(x + c_i), mu(x) at solid neighbours
-    const S m0 = mu[n];
     S gx = S(0), gy = S(0), gz = S(0);
 #pragma unroll
     for (int i = 1; i < 19; i++) {
-        const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
-        S mi = mu[m];
-        if (solid & (1u << i)) mi = m0;
+        const S mi = (solid & (1u << i)) ? m0 : mv[i];
         const S wi = (S)(3.0 * wgt(i));
         if (cx(i)) gx += cx(i) > 0 ? wi * mi : -wi * mi;
         if (cy(i)) gy += cy(i) > 0 ? wi * mi : -wi * mi;
         if (cz(i)) gz += cz(i) > 0 ? wi * mi : -wi * mi;
     }
-    const S ps = psi[n];
     const S Fx = -ps * gx + (S)p.fx;
     const S Fy = -ps * gy + (S)p.fy;
     const S Fz = -ps * gz + (S)p.fz;
@@ -197,18 +312,18 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
         const S geq = w * (drho + rho * (S(3) * cu + S(4.5) * cu * cu - S(1.5) * uu));
         const S gs = g[i] - om * (g[i] - geq) + pref * w * (S(3) * (cF - uF) + S(9) * cu * cF);
         if (i == 0) {
-            st_pop(fout, (size_t)n, gs, p.scale);
+            stp(fout, on, gs, p.scale);
         } else {
             const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
             if (solid & (1u << i))
-                st_pop(fout, opp(i) * N + n, gs, p.scale);
+                stp(fout + opp(i) * N, on, gs, p.scale);
             else
-                st_pop(fout, i * N + m, gs, p.scale);
+                stp(fout + i * N, (unsigned)m * sizeof(T), gs, p.scale);
         }
     }
-    uout[n] = ux;
-    uout[N + n] = uy;
-    uout[2 * N + n] = uz;
+    stb(uout, os, ux);
+    stb(uout + N, os, uy);
+    stb(uout + 2 * N, os, uz);
 }
 
 // -------------------------------------------------------------- k_scalar
@@ -217,6 +332,56 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 // J_e = 1/2 (u.e + u_e.e) 1/2 (psi + psi_e) over the 6 faces, nothing
 // through faces shared with solid nodes (Eq. 3, explicit Euler, dt = 1).
 // Emission: alpha of the cap of each link of the node (Eq. 5).
+
+// face sums of one fluid node; faces in the order x+, x-, y+, y-, z+, z-.
+// Returns psi' and the c' partial c - sum Jc + D sum (chi_e - chi).
+template <class S>
+__device__ __forceinline__ void psi_c_update(const KParams &p, S ps, S cn, S chi, S m0,
+                                             const S u0[3], const S um[6], const S pm[6],
+                                             const S cm[6], const S mm[6], const S xm[6],
+                                             unsigned solid, S &psn, S &cpart)
+{
+#pragma clang fp contract(off)
+    S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        const bool fl = !(solid & (1u << e));  // no flux through a solid face
+        const S us = u0[e >> 1] + um[e];
+        const S ue = (e & 1) ? S(-0.5) * us : S(0.5) * us;
+        adv_p = fl ? fma(ue, S(0.5) * (ps + pm[e]), adv_p) : adv_p;
+        adv_c = fl ? fma(ue, S(0.5) * (cn + cm[e]), adv_c) : adv_c;
+        dmu = fl ? dmu + (mm[e] - m0) : dmu;
+        dchi = fl ? dchi + (xm[e] - chi) : dchi;
+    }
+    psn = fma((S)p.M, dmu, ps - adv_p);
+    cpart = fma((S)p.D, dchi, cn - adv_c);
+}
+
+// Janus emission of boundary node n = (x, y, z): alpha of the cap of every
+// link to a solid neighbour, directions in ascending order
+template <class S>
+__device__ S emission(const KParams &p, const DColloid *__restrict__ col,
+                      const uint8_t *__restrict__ own, int n, int x, int y, int z)
+{
+#pragma clang fp contract(off)
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
+    const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
+    const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
+    S src = S(0);
+    for (int d = 1; d < 19; d++) {
+        const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
+        const uint8_t om = ldb(own, (unsigned)m) & OWN_SOLID;
+        if (!om) continue;
+        const DColloid &q = col[om - 1];
+        double r[3];
+        displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
+        src = src + (S)(active_cap(q, r) ? q.am : q.ap);
+    }
+    return src;
+}
+
+// one node per thread
 template <class S>
 __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
 {
@@ -229,7 +394,8 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
     const S *__restrict__ chiv = (const S *)D.b.chi;
-    const S *__restrict__ u = (const S *)D.b.u;
+    const S *__restrict__ ua[3] = {(const S *)D.b.u, (const S *)D.b.u + p.N,
+                                   (const S *)D.b.u + 2 * (size_t)p.N};
     const uint8_t *__restrict__ own = D.b.own;
     const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ psin = (S *)D.b.psin;
@@ -238,175 +404,183 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     if (!lattice_node(p, blockIdx.x - bst[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
+    const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                       n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                       n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+    // every field load is issued before anything depends on the owner byte
     const uint8_t o = own[n];
-    const S ps = psi[n], cn = cc[n];
-    if (o & OWN_SOLID) { psin[n] = ps; ccn[n] = cn; return; }
-    const bool bnd = (o & OWN_BOUNDARY) != 0;
-    const size_t N = (size_t)p.N;
-    const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
-    const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
-    const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
-    const int fn[6] = {n + xo[2], n + xo[0], n + yo[2], n + yo[0], n + zo[2], n + zo[0]};
-    const S chi = chiv[n];
-    const S m0 = mu[n];
-    const S u0[3] = {u[n], u[N + n], u[2 * N + n]};
-    // all neighbour loads issued together; solid faces masked afterwards
+    const unsigned on = (unsigned)n * sizeof(S);
+    const S ps = ldb(psi, on), cn = ldb(cc, on), chi = ldb(chiv, on), m0 = ldb(mu, on);
+    const S u0[3] = {ldb(ua[0], on), ldb(ua[1], on), ldb(ua[2], on)};
     S um[6], pm[6], cm[6], mm[6], xm[6];
 #pragma unroll
     for (int e = 0; e < 6; e++) {
-        const int m = fn[e];
-        um[e] = u[(e >> 1) * N + m];
-        pm[e] = psi[m];
-        cm[e] = cc[m];
-        mm[e] = mu[m];
-        xm[e] = chiv[m];
+        const unsigned om = (unsigned)fn[e] * sizeof(S);
+        um[e] = ldb(ua[e >> 1], om);
+        pm[e] = ldb(psi, om);
+        cm[e] = ldb(cc, om);
+        mm[e] = ldb(mu, om);
+        xm[e] = ldb(chiv, om);
     }
+    if (o & OWN_SOLID) {
+        stb(psin, on, ps);
+        stb(ccn, on, cn);
+        return;
+    }
+    const bool bnd = (o & OWN_BOUNDARY) != 0;
     unsigned solid = 0;
     if (bnd) {
 #pragma unroll
-        for (int e = 0; e < 6; e++) solid |= (own[fn[e]] & OWN_SOLID) ? (1u << e) : 0u;
+        for (int e = 0; e < 6; e++) solid |= (ldb(own, (unsigned)fn[e]) & OWN_SOLID) ? (1u << e) : 0u;
     }
-    S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
-#pragma unroll
-    for (int e = 0; e < 6; e++) {
-        const bool fl = !(solid & (1u << e));  // no flux through a solid face
-        const int ax = e >> 1;
-        const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um[e]) : S(0.5) * (u0[ax] + um[e]);
-        adv_p += fl ? ue * (S(0.5) * (ps + pm[e])) : S(0);
-        adv_c += fl ? ue * (S(0.5) * (cn + cm[e])) : S(0);
-        dmu += fl ? mm[e] - m0 : S(0);
-        dchi += fl ? xm[e] - chi : S(0);
-    }
-    S src = S(0);
+    S psn, cpart;
+    psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, solid, psn, cpart);
+    stb(psin, on, psn);
+    S chp = chi, src = S(0);
     if (bnd) {
-        for (int d = 1; d < 19; d++) {
-            const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
-            const uint8_t om = own[m] & OWN_SOLID;
-            if (!om) continue;
-            const DColloid &q = col[om - 1];
-            double r[3];
-            displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-            src += (S)(active_cap(q, r) ? q.am : q.ap);
-        }
+        // pin the partial results in registers here, so the loaded stencil
+        // values are dead during the FP64 emission loop (which otherwise
+        // sets the register budget of the whole kernel)
+        asm volatile("" : "+v"(cpart), "+v"(chp));
+        src = emission<S>(p, col, own, n, x, y, z);
     }
-    psin[n] = ps - adv_p + (S)p.M * dmu;
-    ccn[n] = cn - adv_c + (S)p.D * dchi + src - (S)p.kd * chi;
+    stb(ccn, on, fma(-(S)p.kd, chp, cpart + src));
 }
 
-// ----------------------------------------------------------- k_scalar_zm
-// The same update with each thread marching zc consecutive planes of one
-// (x, y) column: the z - 1, z, z + 1 values of psi, c, mu, chi and u_z stay
-// in registers, so a node costs five plane loads fewer than in k_scalar.
-// Blocks of (bx, by) columns; block b covers x segment b % xseg, row group
-// (b / xseg) % ygroups and z chunk b / (xseg * ygroups).
-template <class S>
-__global__ __launch_bounds__(256) void k_scalar_zm(BatchArgs A)
+// Row-vector form (as k_mu_v): V consecutive x nodes per lane, x neighbours
+// of psi, c, mu, chi and u_x exchanged between lanes.
+template <class S, int V>
+__global__ __launch_bounds__(256) void k_scalar_v(BatchArgs A)
 {
+    typedef SVec<S, V> Vec;
+    typedef typename OwnWord<V>::T OW;
     const int *bst = A.bstart + 2 * (A.nbox + 1);
     const int j = find_box(bst, A.nbox, blockIdx.x);
     const BoxDesc &D = A.d[j];
-    const KParams p = D.p;
-    const LaunchShape ls = D.ls[2];
+    KParams p = D.p;
+    p.ls = D.ls[2];
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
     const S *__restrict__ chiv = (const S *)D.b.chi;
-    const S *__restrict__ u = (const S *)D.b.u;
+    const S *__restrict__ ux = (const S *)D.b.u;
+    const S *__restrict__ uy = ux + p.N;
+    const S *__restrict__ uz = ux + 2 * (size_t)p.N;
     const uint8_t *__restrict__ own = D.b.own;
     const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
-    const int b = blockIdx.x - bst[j];
-    const int ygroups = (p.ny + ls.by - 1) / ls.by;
-    const int tx = (int)threadIdx.x % ls.bx, ty = (int)threadIdx.x / ls.bx;
-    if (ty >= ls.by) return;
-    const int seg = b % ls.xseg, rest = b / ls.xseg;
-    const int x = seg * ls.bx + tx, y = (rest % ygroups) * ls.by + ty;
-    const int z0 = (rest / ygroups) * ls.zc;
-    if (x >= p.nx || y >= p.ny || z0 >= p.nz) return;
-    const int z1 = min(z0 + ls.zc, p.nz);
+    int x0, y, z, li, gb;
+    if (!vec_node<V>(p, blockIdx.x - bst[j], x0, y, z, li, gb)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
-    const size_t N = (size_t)p.N;
-    const int xm = wrap_m(x, p.nx) - x, xp = wrap_p(x, p.nx) - x;
-    const int ym = (wrap_m(y, p.ny) - y) * sy, yp = (wrap_p(y, p.ny) - y) * sy;
-    const int col0 = x + sy * y;
-    // rolling window along z: index 0 = z - 1, 1 = z, 2 = z + 1
-    S wp[3], wc[3], wm[3], wx[3], wu[3];
-    uint8_t wo[3];
-    {
-        const int zb = wrap_m(z0, p.nz);
-        const int nb = col0 + sz * zb, n0 = col0 + sz * z0;
-        wp[0] = psi[nb]; wc[0] = cc[nb]; wm[0] = mu[nb]; wx[0] = chiv[nb]; wu[0] = u[2 * N + nb];
-        wo[0] = own[nb];
-        wp[1] = psi[n0]; wc[1] = cc[n0]; wm[1] = mu[n0]; wx[1] = chiv[n0]; wu[1] = u[2 * N + n0];
-        wo[1] = own[n0];
+    const int n0 = x0 + sy * y + sz * z;
+    const int nb[4] = {n0 + (wrap_p(y, p.ny) - y) * sy, n0 + (wrap_m(y, p.ny) - y) * sy,
+                       n0 + (wrap_p(z, p.nz) - z) * sz, n0 + (wrap_m(z, p.nz) - z) * sz};
+    const unsigned on = (unsigned)n0 * sizeof(S);
+    const OW ow = ldb((const OW *)own, (unsigned)n0);
+    // centre vectors of the four stencil fields and u, then the y, z rows
+    const Vec c0[4] = {ldb((const Vec *)psi, on), ldb((const Vec *)cc, on), ldb((const Vec *)mu, on),
+                       ldb((const Vec *)chiv, on)};
+    const Vec u0x = ldb((const Vec *)ux, on), u0y = ldb((const Vec *)uy, on),
+              u0z = ldb((const Vec *)uz, on);
+    Vec nbv[4][4];  // [field][y+, y-, z+, z-]
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const unsigned om = (unsigned)nb[e] * sizeof(S);
+        nbv[0][e] = ldb((const Vec *)psi, om);
+        nbv[1][e] = ldb((const Vec *)cc, om);
+        nbv[2][e] = ldb((const Vec *)mu, om);
+        nbv[3][e] = ldb((const Vec *)chiv, om);
     }
-    for (int z = z0; z < z1; z++) {
-        const int n = col0 + sz * z;
-        const int zn = wrap_p(z, p.nz);
-        const int na = col0 + sz * zn;
-        wp[2] = psi[na]; wc[2] = cc[na]; wm[2] = mu[na]; wx[2] = chiv[na]; wu[2] = u[2 * N + na];
-        wo[2] = own[na];
-        const uint8_t o = wo[1];
-        const S ps = wp[1], cn = wc[1];
-        if (o & OWN_SOLID) {
-            psin[n] = ps;
-            ccn[n] = cn;
-        } else {
-            const bool bnd = (o & OWN_BOUNDARY) != 0;
-            const int fn[4] = {n + xp, n + xm, n + yp, n + ym};
-            S um[6], pm[6], cm[6], mm[6], xmv[6];
+    const Vec uyp = ldb((const Vec *)uy, (unsigned)nb[0] * sizeof(S));
+    const Vec uym = ldb((const Vec *)uy, (unsigned)nb[1] * sizeof(S));
+    const Vec uzp = ldb((const Vec *)uz, (unsigned)nb[2] * sizeof(S));
+    const Vec uzm = ldb((const Vec *)uz, (unsigned)nb[3] * sizeof(S));
+    // x neighbours: last node of the lane on the left, first of the right
+    const int Ls = p.ls.bx;
+    const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
+    S fl[5], fr[5];  // psi, c, mu, chi, u_x
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int m = fn[e];
-                um[e] = u[(e >> 1) * N + m];
-                pm[e] = psi[m];
-                cm[e] = cc[m];
-                mm[e] = mu[m];
-                xmv[e] = chiv[m];
-            }
-            um[4] = wu[2]; pm[4] = wp[2]; cm[4] = wc[2]; mm[4] = wm[2]; xmv[4] = wx[2];
-            um[5] = wu[0]; pm[5] = wp[0]; cm[5] = wc[0]; mm[5] = wm[0]; xmv[5] = wx[0];
-            const S chi = wx[1], m0 = wm[1];
-            const S u0[3] = {u[n], u[N + n], wu[1]};
-            unsigned solid = 0;
-            if (bnd) {
-#pragma unroll
-                for (int e = 0; e < 4; e++) solid |= (own[fn[e]] & OWN_SOLID) ? (1u << e) : 0u;
-                solid |= (wo[2] & OWN_SOLID) ? 16u : 0u;
-                solid |= (wo[0] & OWN_SOLID) ? 32u : 0u;
-            }
-            S adv_p = S(0), adv_c = S(0), dmu = S(0), dchi = S(0);
-#pragma unroll
-            for (int e = 0; e < 6; e++) {
-                const bool fl = !(solid & (1u << e));
-                const int ax = e >> 1;
-                const S ue = (e & 1) ? S(-0.5) * (u0[ax] + um[e]) : S(0.5) * (u0[ax] + um[e]);
-                adv_p += fl ? ue * (S(0.5) * (ps + pm[e])) : S(0);
-                adv_c += fl ? ue * (S(0.5) * (cn + cm[e])) : S(0);
-                dmu += fl ? mm[e] - m0 : S(0);
-                dchi += fl ? xmv[e] - chi : S(0);
-            }
-            S src = S(0);
-            if (bnd) {
-                const int xo[3] = {xm, 0, xp}, yo[3] = {ym, 0, yp};
-                const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (zn - z) * sz};
-                for (int d = 1; d < 19; d++) {
-                    const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
-                    const uint8_t om = own[m] & OWN_SOLID;
-                    if (!om) continue;
-                    const DColloid &q = col[om - 1];
-                    double r[3];
-                    displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-                    src += (S)(active_cap(q, r) ? q.am : q.ap);
-                }
-            }
-            psin[n] = ps - adv_p + (S)p.M * dmu;
-            ccn[n] = cn - adv_c + (S)p.D * dchi + src - (S)p.kd * chi;
+    for (int f = 0; f < 4; f++) {
+        fl[f] = __shfl(c0[f].v[V - 1], srcl);
+        fr[f] = __shfl(c0[f].v[0], srcr);
+    }
+    fl[4] = __shfl(u0x.v[V - 1], srcl);
+    fr[4] = __shfl(u0x.v[0], srcr);
+    unsigned owl = __shfl((unsigned)ow, srcl), owr = __shfl((unsigned)ow, srcr);
+    if (p.ls.xseg > 1) {
+        const int rb = n0 - x0;
+        if (li == 0) {
+            const int xl = rb + (x0 == 0 ? p.nx - 1 : x0 - 1);
+            const unsigned ol = (unsigned)xl * sizeof(S);
+            fl[0] = ldb(psi, ol); fl[1] = ldb(cc, ol); fl[2] = ldb(mu, ol); fl[3] = ldb(chiv, ol);
+            fl[4] = ldb(ux, ol);
+            owl = (unsigned)own[xl] << (8 * (V - 1));
         }
-        wp[0] = wp[1]; wc[0] = wc[1]; wm[0] = wm[1]; wx[0] = wx[1]; wu[0] = wu[1]; wo[0] = wo[1];
-        wp[1] = wp[2]; wc[1] = wc[2]; wm[1] = wm[2]; wx[1] = wx[2]; wu[1] = wu[2]; wo[1] = wo[2];
+        if (li == Ls - 1) {
+            const int xr = rb + (x0 + V == p.nx ? 0 : x0 + V);
+            const unsigned orr = (unsigned)xr * sizeof(S);
+            fr[0] = ldb(psi, orr); fr[1] = ldb(cc, orr); fr[2] = ldb(mu, orr); fr[3] = ldb(chiv, orr);
+            fr[4] = ldb(ux, orr);
+            owr = own[xr];
+        }
     }
+    const unsigned bmask = (V == 4) ? 0x80808080u : 0x8080u;
+    const bool anyb = ((unsigned)ow & bmask) != 0;
+    unsigned onb4[4] = {0, 0, 0, 0};
+    if (anyb) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) onb4[e] = ldb((const OW *)own, (unsigned)nb[e]);
+    }
+    Vec pnv, cpv, chv;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        const uint8_t o = byte_of(ow, k);
+        S nbs[4][6];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            nbs[f][0] = k < V - 1 ? c0[f].v[k + 1] : fr[f];
+            nbs[f][1] = k > 0 ? c0[f].v[k - 1] : fl[f];
+#pragma unroll
+            for (int e = 0; e < 4; e++) nbs[f][2 + e] = nbv[f][e].v[k];
+        }
+        const S um[6] = {k < V - 1 ? u0x.v[k + 1] : fr[4], k > 0 ? u0x.v[k - 1] : fl[4],
+                         uyp.v[k], uym.v[k], uzp.v[k], uzm.v[k]};
+        const S u0[3] = {u0x.v[k], u0y.v[k], u0z.v[k]};
+        unsigned solid = 0;
+        if (o & OWN_BOUNDARY) {
+            const uint8_t onb[6] = {k < V - 1 ? byte_of(ow, k + 1) : byte_of(owr, 0),
+                                    k > 0 ? byte_of(ow, k - 1) : byte_of(owl, V - 1),
+                                    byte_of(onb4[0], k), byte_of(onb4[1], k),
+                                    byte_of(onb4[2], k), byte_of(onb4[3], k)};
+#pragma unroll
+            for (int e = 0; e < 6; e++) solid |= (onb[e] & OWN_SOLID) ? (1u << e) : 0u;
+        }
+        S psn, cpart;
+        psi_c_update<S>(p, c0[0].v[k], c0[1].v[k], c0[3].v[k], c0[2].v[k], u0, um, nbs[0], nbs[1],
+                        nbs[2], nbs[3], solid, psn, cpart);
+        const bool sol = (o & OWN_SOLID) != 0;
+        pnv.v[k] = sol ? c0[0].v[k] : psn;
+        cpv.v[k] = cpart;
+        chv.v[k] = c0[3].v[k];
+    }
+    stb((Vec *)psin, on, pnv);
+    S src[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) src[k] = S(0);
+    if (anyb) {
+#pragma unroll
+        for (int k = 0; k < V; k++) asm volatile("" : "+v"(cpv.v[k]), "+v"(chv.v[k]));
+        for (int k = 0; k < V; k++)
+            if (byte_of(ow, k) & OWN_BOUNDARY) src[k] = emission<S>(p, col, own, n0 + k, x0 + k, y, z);
+    }
+    Vec cnv;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        const bool sol = (byte_of(ow, k) & OWN_SOLID) != 0;
+        cnv.v[k] = sol ? c0[1].v[k] : fma(-(S)p.kd, chv.v[k], cpv.v[k] + src[k]);
+    }
+    stb((Vec *)ccn, on, cnv);
 }
 
 // ------------------------------------------------ block reductions (FP64)
@@ -1043,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_fields(KParams p, const typename Prec<P
     const bool fluid = (own[n] & OWN_SOLID) == 0;
     for (int i = 0; i < 19; i++) {
         const double g = (double)ld_pop(f, i * N + n, p.inv_scale);
-        if (fout) fout[i * N + n] = g + wgt(i) * p.rho0;
+        if (fout) fout[i * N + n] = fluid ? g + wgt(i) * p.rho0 : 0.0;
         m += g;
         jx += cx(i) * g;
         jy += cy(i) * g;
@@ -1060,8 +1234,32 @@ __global__ __launch_bounds__(256) void k_fields(KParams p, const typename Prec<P
 }
 
 // ------------------------------------------------------------ launchers
-void finish_shape(LaunchShape &ls, int nx, int ny, int nz)
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize)
 {
+    if (ls.vec > 1) {
+        const int V = (ssize == 8 && ls.vec > 2) ? 2 : ls.vec;
+        const int W = nx / V;
+        if ((V == 2 || V == 4) && nx % V == 0 && (W <= 64 || W % 64 == 0)) {
+            // row-vector launch: groups of Ls lanes per row segment, 64 / Ls
+            // groups per wavefront, four wavefronts per block
+            ls.vec = V;
+            ls.bx = W < 64 ? W : 64;
+            ls.by = 64 / ls.bx;
+            ls.xseg = W / ls.bx;
+            const long long segs = (long long)ny * nz * ls.xseg, per = 4LL * ls.by;
+            ls.nblocks = (int)((segs + per - 1) / per);
+            ls.bpp = 0;
+            if (ls.remap == 2) {
+                const long long pp = (long long)ny * ls.xseg;
+                if (pp % per == 0 && (pp / per) % 8 == 0) ls.bpp = (int)(pp / per);
+                else ls.remap = 0;
+            }
+            return;
+        }
+        ls.bx = 0;  // not available for this box: default one-node shape
+        ls.by = 0;
+    }
+    ls.vec = 0;
     if (ls.bx <= 0 || ls.bx > 256) ls.bx = nx < 256 ? nx : 256;
     if (ls.bx > nx) ls.bx = nx;
     if (ls.by <= 0) ls.by = ls.bx >= 256 ? 1 : 256 / ls.bx;
@@ -1071,13 +1269,6 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz)
     const long long rows = (long long)ny * nz;
     ls.nblocks = (int)(ls.xseg * ((rows + ls.by - 1) / ls.by));
     ls.bpp = 0;
-    if (ls.zc > 0) {
-        // z-marching launch: blocks over (x segment, row group in y, z chunk)
-        if (ls.zc > nz) ls.zc = nz;
-        ls.remap = 0;
-        ls.nblocks = ls.xseg * ((ny + ls.by - 1) / ls.by) * ((nz + ls.zc - 1) / ls.zc);
-        return;
-    }
     if (ls.remap == 2) {
         // plane-wise renumbering needs whole planes per block row and
         // blocks per plane divisible by 8
@@ -1098,14 +1289,21 @@ template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm)
 {
     typedef typename Prec<P>::S S;
     if (tm) tm->begin(0, s);
-    k_mu<S><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    if (sizeof(S) == 4 && B.vec[0] == 4)
+        k_mu_v<S, (sizeof(S) == 4 ? 4 : 2)><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else if (B.vec[0] == 2)
+        k_mu_v<S, 2><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else
+        k_mu<S><<<B.nblocks[0], 256, 0, s>>>(B.args);
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
     k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
-    if (B.scalar_zm)
-        k_scalar_zm<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
+    if (sizeof(S) == 4 && B.vec[2] == 4)
+        k_scalar_v<S, (sizeof(S) == 4 ? 4 : 2)><<<B.nblocks[2], 256, 0, s>>>(B.args);
+    else if (B.vec[2] == 2)
+        k_scalar_v<S, 2><<<B.nblocks[2], 256, 0, s>>>(B.args);
     else
         k_scalar<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
     if (tm) tm->end(2, s);

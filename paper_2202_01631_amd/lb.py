@@ -72,6 +72,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("HIP library %s is missing: build it with "
                            "`python -m paper_2202_01631_amd.build`" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that copy, so the process holds one
+    # HIP runtime (two runtimes in one process cannot both open the GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
     L.lb_footprint_bytes.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
@@ -308,14 +315,21 @@ def batch_step(boxes, nsteps):
         raise LBError(rc, load().lb_last_error(boxes[0]._ctx).decode())
 
 
-def from_spec(spec, precision=None, arena=None, stream=None, **override):
-    """Box built from a workload spec of paper_2202_01631_amd.inputs; the
-    contact angle maps to H (Eq. 10) and the solubility ratio to E through the
-    library's own host helpers."""
+def spec_params(spec, **override):
+    """Box parameters of a workload spec: its free-energy parameters, with E
+    from the solubility ratio through the library's host helper."""
     p = dict(spec["params"])
     p.update(override)
     if "E" not in p:
         p["E"] = solubility_E(spec.get("solubility_ratio", 1.0), p.get("c_b0", 0.0))
+    return p
+
+
+def from_spec(spec, precision=None, arena=None, stream=None, **override):
+    """Box built from a workload spec of paper_2202_01631_amd.inputs; the
+    contact angle maps to H (Eq. 10) and the solubility ratio to E through the
+    library's own host helpers."""
+    p = spec_params(spec, **override)
     prec = precision or spec.get("precision", "fp64")
     b = Box(spec["shape"], prec, arena=arena, stream=stream, **p)
     b.init_fields(spec["psi"], spec["c"], spec.get("rho"), spec.get("u"))

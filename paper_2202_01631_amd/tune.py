@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the three lattice kernels.
 
 For a box size and precision, time every candidate block shape (x segment
-length, rows per block, block renumbering) on the GPU with the library's
+length, rows per block, block renumbering, row-vector form) on the GPU with the library's
 per-kernel HIP-event timing, keep the fastest shape of each kernel, and cache
 the result in ``tuning.json`` next to this file, keyed by device name, box
 size and precision.  Shapes never change results (tested bit for bit); they
@@ -20,6 +20,9 @@ CACHE = os.path.join(HERE, "tuning.json")
 
 
 def candidates(nx, ny):
+    """(bx, by, code) shapes, code = remap + 8 vec.  One-node shapes apply to
+    all three kernels; row-vector shapes (vec 2 or 4) to the mu and psi/c
+    updates only."""
     out = []
     for bx in (256, 128, 64, 32, 16):
         if bx > nx and bx != min(nx, 256):
@@ -30,11 +33,10 @@ def candidates(nx, ny):
             if remap == 2 and (ny % by != 0):
                 continue
             out.append((b, by, remap))
-    # z-marching forms of the psi/c update (remap code 8 + r: zc = 8)
-    for zc in (8, 16, 32):
-        for bx in (64, 32):
-            if bx <= nx:
-                out.append((bx, 256 // bx, zc))
+    for vec in (2, 4):
+        if nx % vec == 0:
+            for remap in (0, 2):
+                out.append((0, 0, remap + 8 * vec))
     # distinct, natural-order default first
     seen, uniq = set(), []
     for c in [(min(nx, 256), max(1, 256 // min(nx, 256)), 0)] + out:
@@ -42,6 +44,10 @@ def candidates(nx, ny):
             seen.add(c)
             uniq.append(c)
     return uniq
+
+
+def is_vec(cand):
+    return cand[2] >= 16
 
 
 def device_key():
@@ -96,7 +102,7 @@ def representative_spec(shape, precision):
 
 def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log=print):
     """Time every candidate shape for the three lattice kernels; return the
-    best (bx, by, remap) of each and store it in the cache."""
+    best (bx, by, code) of each and store it in the cache."""
     import torch
 
     from . import inputs as I
@@ -106,16 +112,21 @@ def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log
     box = lb.from_spec(spec, precision=precision)
     results = {}
     for cand in candidates(shape[0], shape[1]):
-        box.set_launch_shapes([cand, cand, cand])
+        # row-vector shapes exist for the mu and psi/c updates only: collide
+        # runs its default shape then and its time is not scored
+        box.set_launch_shapes([cand, (0, 0, 0) if is_vec(cand) else cand, cand])
         box.step(warmup)
         torch.cuda.synchronize()
         box.timing_enable(True)
         box.step(steps)
         ms, calls = box.timing_read()
         box.timing_enable(False)
-        results[cand] = [float(ms[i] / max(calls[i], 1)) for i in range(3)]
+        t = [float(ms[i] / max(calls[i], 1)) for i in range(3)]
+        if is_vec(cand):
+            t[1] = float("inf")
+        results[cand] = t
         log("[tune] %s %s %s us %s" % (shape, precision, cand,
-                                        [round(1000 * t, 1) for t in results[cand]]))
+                                        [round(1000 * v, 1) for v in results[cand]]))
     box.close()
     best = [min(results, key=lambda c: results[c][k]) for k in range(3)]
     if write:

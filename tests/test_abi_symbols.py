@@ -53,3 +53,27 @@ def test_footprint_is_host_only():
     assert n16 < n32 < n64
     with pytest.raises(lb.LBError):
         lb.footprint_bytes((0, 4, 4), "fp32")
+    # scalar fields are addressed with 32-bit byte offsets: one field must
+    # stay below 4 GiB (2^29 nodes in FP64, 2^30 otherwise)
+    with pytest.raises(lb.LBError):
+        lb.footprint_bytes((1024, 1024, 512), "fp64")
+    with pytest.raises(lb.LBError):
+        lb.footprint_bytes((1024, 1024, 1024), "fp32")
+    assert lb.footprint_bytes((1024, 1024, 511), "fp64") > 0
+    assert lb.footprint_bytes((1024, 1024, 1023), "fp32") > 0
+
+
+def test_binding_shares_torch_hip_runtime():
+    # loading the library through the binding, with nothing imported before,
+    # must leave one HIP runtime in the process (torch's), not two
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2202_01631_amd import lb\n"
+            "lb.load()\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "print(sorted(set(l.split()[-1] for l in maps if 'libamdhip64' in l)))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

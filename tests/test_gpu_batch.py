@@ -90,13 +90,15 @@ def test_batched_fp64_matches_oracle():
     [(64, 4, 0), (64, 4, 0), (64, 4, 0)],
     [(32, 8, 2), (256, 1, 1), (16, 16, 2)],
     [(48, 5, 0), (24, 10, 0), (40, 6, 0)],
-    [(64, 4, 0), (256, 1, 0), (64, 4, 8)],
-    [(32, 8, 0), (32, 8, 0), (16, 16, 16)],
-    [(32, 8, 0), (32, 8, 0), (32, 4, 40)],
+    [(64, 4, 8), (256, 1, 0), (64, 4, 8)],     # vec 1: the one-node form
+    [(0, 0, 32), (32, 8, 0), (0, 0, 34)],      # row-vector, 4 nodes per lane
+    [(0, 0, 16), (32, 8, 0), (0, 0, 18)],      # row-vector, 2 nodes per lane
+    [(0, 0, 33), (32, 8, 0), (0, 0, 17)],
 ])
 def test_launch_shapes_do_not_change_results(shapes):
     w = I.workload_small()
     ref = lb.from_spec(w, precision="fp32")
+    ref.set_launch_shapes([(32, 8, 0)] * 3)
     alt = lb.from_spec(w, precision="fp32")
     alt.set_launch_shapes(shapes)
     ref.step(15)
@@ -104,14 +106,70 @@ def test_launch_shapes_do_not_change_results(shapes):
     assert _same(_state(ref), _state(alt))
 
 
-def test_batched_mixed_zmarch_equals_alone():
-    # boxes of one batch disagreeing on the z-marching psi/c form fall back
-    # to the one-node-per-thread form; results unchanged
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp16"])
+def test_row_vector_forms_long_rows(precision):
+    # rows longer than one lane group (256 nodes in x at 2 nodes per lane:
+    # two 64-lane segments per row, ends exchanged through memory) and a
+    # ragged row in y/z; particles on the interface crossing x = 0 and a
+    # segment end
+    shape = (256, 16, 20)
+    psi = I.flat_interface(shape, 10.0, I.WIDTH, 0.02, seed=3)
+    cols = [I.janus((0.4, 8.2, 10.0), (0.6, 0.0, 0.8), 3.5, mu=0.1, theta=70.0),
+            I.janus((127.6, 7.7, 10.3), (0.0, 0.6, -0.8), 3.5, mu=0.1, theta=110.0)]
+    spec = dict(shape=shape, precision=precision, params=dict(I.FREE_ENERGY), solubility_ratio=2.0,
+                psi=psi, c=np.zeros(psi.size), colloids=cols)
+    ref = lb.from_spec(spec, precision=precision)
+    ref.set_launch_shapes([(64, 4, 0)] * 3)
+    for code in (16, 32, 18):
+        alt = lb.from_spec(spec, precision=precision)
+        alt.set_launch_shapes([(0, 0, code), (64, 4, 0), (0, 0, code)])
+        eff = alt.launch_shapes()
+        flush_print("[vec] %s code %d effective %s" % (precision, code, eff))
+        assert eff[0][2] >= 16 and eff[2][2] >= 16
+        alt.step(12)
+        if code == 16:
+            ref.step(12)
+        assert _same(_state(ref), _state(alt)), code
+    if precision == "fp64":
+        o = oracle.from_spec(spec)
+        o.step(12)
+        e = field_errors(ref.fields(), o.fields(), o.owner() < 0)
+        flush_print("[vec-oracle]", e)
+        assert max(e.values()) <= 1e-12
+
+
+def test_row_vector_fallback_shapes():
+    # nx % vec != 0, or rows of 80 lanes (neither <= 64 nor a multiple of 64):
+    # the box takes the one-node form, with identical results
+    for shape, code in (((30, 16, 16), 32), ((320, 8, 8), 16)):
+        psi = I.flat_interface(shape, shape[2] / 2.0, I.WIDTH, 0.02, seed=4)
+        spec = dict(shape=shape, precision="fp32", params=dict(I.FREE_ENERGY), solubility_ratio=2.0,
+                    psi=psi, c=np.zeros(psi.size), colloids=[])
+        a = lb.from_spec(spec)
+        a.set_launch_shapes([(0, 0, code), (0, 0, 0), (0, 0, code)])
+        eff = a.launch_shapes()
+        assert eff[0][2] < 8 and eff[2][2] < 8, eff
+        b = lb.from_spec(spec)
+        b.set_launch_shapes([(0, 0, 0)] * 3)
+        a.step(5)
+        b.step(5)
+        assert _same(_state(a), _state(b))
+    with pytest.raises(lb.LBError):
+        a.set_launch_shapes([(0, 0, 24), (0, 0, 0), (0, 0, 0)])  # vec 3
+    with pytest.raises(lb.LBError):
+        a.set_launch_shapes([(0, 0, 0), (0, 0, 32), (0, 0, 0)])  # collide has no row-vector form
+    with pytest.raises(lb.LBError):
+        a.set_launch_shapes([(0, 0, 3), (0, 0, 0), (0, 0, 0)])   # remap 3
+
+
+def test_batched_mixed_vec_equals_alone():
+    # boxes of one batch disagreeing on the row-vector form fall back to the
+    # one-node form for that kernel; results unchanged
     import torch
     specs = _boxes(n=3, seed=21)
     stream = torch.cuda.Stream()
     batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
-    batch[0].set_launch_shapes([(0, 0, 0), (0, 0, 0), (0, 0, 8)])
+    batch[0].set_launch_shapes([(32, 8, 0), (0, 0, 0), (0, 0, 16)])
     alone = [lb.from_spec(s, precision="fp32") for s in specs]
     lb.batch_step(batch, 6)
     for b in alone:
@@ -128,3 +186,31 @@ def test_batch_error_paths():
         lb.batch_step([a, b], 2)  # mixed precision
     with pytest.raises(lb.LBError):
         lb.batch_step([a, a], 2)  # repeated context
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_results_independent_of_arena_contents(precision):
+    # every value the library reports, solid-node populations included, is
+    # defined by the inputs: a borrowed arena pre-filled with zeros or with
+    # 0xff bytes (NaN patterns) gives bitwise the same state, also after a
+    # save/load round trip into a dirty arena
+    import torch
+    w = I.workload_small()
+    need = lb.footprint_bytes(w["shape"], precision)
+    out = []
+    for fill in (0, 255):
+        buf = torch.full((need,), fill, dtype=torch.uint8, device="cuda")
+        b = lb.from_spec(w, precision=precision, arena=buf)
+        b.step(7)
+        out.append(_state(b))
+        if fill == 255:
+            blob = b.save_state()
+            buf2 = torch.full((need,), 255, dtype=torch.uint8, device="cuda")
+            r = lb.Box(w["shape"], precision, arena=buf2, **lb.spec_params(w))
+            r.load_state(blob)
+            r.step(4)
+            b.step(4)
+            assert _same(_state(r), _state(b))
+            r.close()
+        b.close()
+    assert _same(out[0], out[1])

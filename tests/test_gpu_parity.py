@@ -256,6 +256,13 @@ def test_error_paths():
     b.step(3)
     t, _ = b.observables()
     assert t["n_links"] == 0 and t["step"] == 3 and t["error_bits"] == 0
+    # a borrowed arena must be 256-byte aligned (vector accesses)
+    import torch
+    need = lb.footprint_bytes((16, 16, 16), "fp32")
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lb.LBError):
+        lb.Box((16, 16, 16), "fp32", arena=buf[16:])
+    lb.Box((16, 16, 16), "fp32", arena=buf[256:]).close()
 
 
 # ------------------------------------------------------ full benchmark size
