@@ -203,15 +203,16 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
 /* Launch shapes of the three lattice kernels (chemical potential,
  * collide-stream, psi/c update): for each, (bx, by, code) = nodes per row
  * segment, rows per block (bx*by <= 256; 0 = default) and code = remap +
- * 8 vec.  remap is the block renumbering (0 natural order, 1 contiguous
- * ranges per XCD, 2 one eighth of every z plane per XCD); vec (0, 2 or 4;
- * chemical potential and psi/c update only) selects the row-vector form with
- * vec consecutive x nodes per lane (FP64 takes 2 for 4), in which bx and by
- * are derived from nx, and which boxes with nx % vec != 0, or rows longer
- * than 64 lanes that are not a multiple of 64 lanes, replace by the
- * one-node form.  LB_E_INVALID for other values.  Used by the autotuner;
- * results are identical for every shape.  lb_get_launch_shapes returns the
- * shapes in effect. */
+ * 8 vec + 64 zc.  remap is the block renumbering (0 natural order, 1
+ * contiguous ranges per XCD, 2 one eighth of every z plane per XCD); vec
+ * (0, 2 or 4; chemical potential and psi/c update only) selects the
+ * row-vector form with vec consecutive x nodes per lane (FP64 takes 2 for
+ * 4), in which bx and by are derived from nx, and which boxes with
+ * nx % vec != 0, or rows longer than 64 lanes that are not a multiple of 64
+ * lanes, replace by the one-node form; zc > 1 (psi/c update with vec only)
+ * makes each lane march zc planes in z (natural block order).  LB_E_INVALID
+ * for other values.  Used by the autotuner; results are identical for every
+ * shape.  lb_get_launch_shapes returns the shapes in effect. */
 lb_status lb_set_launch_shapes(lb_ctx *ctx, const int32_t *shapes9);
 lb_status lb_get_launch_shapes(lb_ctx *ctx, int32_t *shapes9);
 

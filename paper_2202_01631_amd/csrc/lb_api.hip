@@ -80,6 +80,8 @@ struct lb_ctx {
     char *selfdev;
     bool dirty;
     hipGraphExec_t graph[2];
+    SideStream side;    // particle work beside the bulk kernels
+    bool has_side;
     std::string err;
 };
 
@@ -172,11 +174,14 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
     for (int w = 0; w < 3; w++) {
         bool same = true;
-        for (int j = 1; j < n; j++) same = same && d[j].ls[w].vec == d[0].ls[w].vec;
+        for (int j = 1; j < n; j++)
+            same = same && d[j].ls[w].vec == d[0].ls[w].vec &&
+                   (d[j].ls[w].zc > 1) == (d[0].ls[w].zc > 1);
         if (!same) {
             for (int j = 0; j < n; j++) {
                 if (d[j].ls[w].vec > 1) {
                     d[j].ls[w].vec = 0;
+                    d[j].ls[w].zc = 0;
                     finish_shape(d[j].ls[w], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ssize);
                 }
                 bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
@@ -184,13 +189,18 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         }
         B.vec[w] = n > 0 ? d[0].ls[w].vec : 0;
     }
+    B.zmarch = n > 0 && d[0].ls[2].zc > 1;
     for (int w = 0; w < 3; w++) B.nblocks[w] = bst[w * (n + 1) + n];
     B.ncol = cst[n];
+    B.nodes = 0;
+    for (int j = 0; j < n; j++) B.nodes += ctxs[j]->N;
     B.precision = ctxs[0]->p.precision;
     B.args.d = (const BoxDesc *)dev;
     B.args.bstart = (const int *)(dev + align256(sizeof(BoxDesc) * n));
     B.args.cstart = B.args.bstart + 3 * (n + 1);
     B.args.nbox = n;
+    B.args.nsec = (B.nchunk_max + BND_SCAN - 1) / BND_SCAN;
+    B.args.nfix = B.ncol > 0 ? B.args.nsec * B.ncol : 0;
 }
 
 static void drop_graphs(lb_ctx *c)
@@ -275,23 +285,46 @@ TimingHook::~TimingHook()
 }
 
 // ------------------------------------------------------------- dispatch
-static void launch_one_step(const Batch &B, hipStream_t s, TimingHook *tm)
+// The side stream of a context, created on first use (default priority,
+// non-blocking); null if it cannot be created, then steps run in order on
+// one stream.
+static const SideStream *side_of(lb_ctx *c)
+{
+    if (!c->has_side) {
+        SideStream v;
+        if (hipStreamCreateWithFlags(&v.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        int i = 0;
+        for (; i < 4; i++)
+            if (hipEventCreateWithFlags(&v.ev[i], hipEventDisableTiming) != hipSuccess) break;
+        if (i < 4) {
+            while (i > 0) hipEventDestroy(v.ev[--i]);
+            hipStreamDestroy(v.s);
+            return nullptr;
+        }
+        c->side = v;
+        c->has_side = true;
+    }
+    return &c->side;
+}
+
+static void launch_one_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm)
 {
     switch (B.precision) {
-    case LB_FP64: launch_step<LB_FP64>(B, s, tm); break;
-    case LB_FP32: launch_step<LB_FP32>(B, s, tm); break;
-    default: launch_step<LB_FP16_STORAGE>(B, s, tm); break;
+    case LB_FP64: launch_step<LB_FP64>(B, s, side, tm); break;
+    case LB_FP32: launch_step<LB_FP32>(B, s, side, tm); break;
+    default: launch_step<LB_FP16_STORAGE>(B, s, side, tm); break;
     }
 }
 
 // capture the step pair (B0 then B1) on stream s into an executable graph
-static hipError_t capture_pair(const Batch &B0, const Batch &B1, hipStream_t s, hipGraphExec_t *out)
+static hipError_t capture_pair(const Batch &B0, const Batch &B1, hipStream_t s,
+                               const SideStream *side, hipGraphExec_t *out)
 {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return e;
-    launch_one_step(B0, s, nullptr);
-    launch_one_step(B1, s, nullptr);
+    launch_one_step(B0, s, side, nullptr);
+    launch_one_step(B1, s, side, nullptr);
     e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return e;
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -346,23 +379,28 @@ static lb_status check_params(const lb_params *p, std::string &why)
 // overrides them for tuning sweeps.
 static void set_shapes(lb_ctx *c)
 {
-    LaunchShape d = {0, 0, 0, 0, 0, 0, 0};
+    LaunchShape d = {0, 0, 0, 0, 0, 0, 0, 0};
     LaunchShape v[3] = {d, d, d};
     v[0].vec = 4;
     v[2].vec = 4;
     v[2].remap = 2;
     if (const char *e = getenv("LB_LATTICE_SHAPES")) {
         for (int k = 0; k < 3 && *e; k++) {
-            int bx = 0, by = 0, rm = 1, used = 0, vec = 0, used2 = 0;
+            int bx = 0, by = 0, rm = 1, used = 0, vec = 0, zc = 0, used2 = 0;
             if (sscanf(e, "%d,%d,%d%n", &bx, &by, &rm, &used) == 3) {
                 v[k].bx = bx;
                 v[k].by = by;
                 v[k].remap = rm >= 0 && rm <= 2 ? rm : 0;
                 v[k].vec = 0;
+                v[k].zc = 0;
                 e += used;
                 if (sscanf(e, ",%d%n", &vec, &used2) == 1) {
                     if (k != 1 && (vec == 2 || vec == 4)) v[k].vec = vec;
                     e += used2;
+                    if (sscanf(e, ",%d%n", &zc, &used2) == 1) {
+                        if (k == 2 && zc > 1) v[k].zc = zc;
+                        e += used2;
+                    }
                 }
                 if (*e == ';') e++;
             } else {
@@ -538,6 +576,11 @@ lb_status lb_destroy(lb_ctx *c)
     if (c->derr) hipFree(c->derr);
     if (c->part) hipFree(c->part);
     if (c->dsum) hipFree(c->dsum);
+    if (c->has_side) {
+        hipStreamSynchronize(c->side.s);
+        for (int i = 0; i < 4; i++) hipEventDestroy(c->side.ev[i]);
+        hipStreamDestroy(c->side.s);
+    }
     delete c->timing;
     delete c;
     return LB_OK;
@@ -704,13 +747,14 @@ lb_status lb_step(lb_ctx *c, int64_t nsteps)
     if (!c->timing && c->stream && nsteps >= 2) {
         const int par = c->cur;
         if (!c->graph[par]) {
-            hipError_t e = capture_pair(c->self[par], c->self[1 - par], c->stream, &c->graph[par]);
+            hipError_t e = capture_pair(c->self[par], c->self[1 - par], c->stream, side_of(c),
+                                        &c->graph[par]);
             if (e != hipSuccess) { c->graph[par] = nullptr; return hip_fail(c, e, "graph capture"); }
         }
         for (; s + 2 <= nsteps; s += 2) HIP_TRY(c, hipGraphLaunch(c->graph[par], c->stream));
     }
     for (; s < nsteps; s++) {
-        launch_one_step(c->self[c->cur], c->stream, c->timing);
+        launch_one_step(c->self[c->cur], c->stream, side_of(c), c->timing);
         c->cur ^= 1;
     }
     c->step += nsteps;
@@ -747,11 +791,11 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
     int64_t k = 0;
     hipGraphExec_t ge = nullptr;
     if (e == hipSuccess && s && nsteps >= 2) {
-        e = capture_pair(B0, B1, s, &ge);
+        e = capture_pair(B0, B1, s, side_of(c0), &ge);
         for (; e == hipSuccess && k + 2 <= nsteps; k += 2) e = hipGraphLaunch(ge, s);
     }
     for (; e == hipSuccess && k < nsteps; k++) {
-        launch_one_step((k & 1) ? B1 : B0, s, nullptr);
+        launch_one_step((k & 1) ? B1 : B0, s, side_of(c0), nullptr);
         e = hipGetLastError();
     }
     hipError_t e2 = hipStreamSynchronize(s);
@@ -771,12 +815,13 @@ lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)
     if (!c || !shapes9) return fail(c, LB_E_INVALID, "null argument");
     LaunchShape v[3];
     for (int k = 0; k < 3; k++) {
-        // code = remap + 8 vec
+        // code = remap + 8 vec + 64 zc
         const int code = shapes9[3 * k + 2];
-        const int rm = code & 7, vec = code >= 0 ? code >> 3 : -1;
-        v[k] = LaunchShape{shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, vec};
+        const int rm = code & 7, vec = code >= 0 ? (code >> 3) & 7 : -1, zc = code >> 6;
+        v[k] = LaunchShape{shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, vec, zc};
         if (v[k].bx < 0 || v[k].by < 0 || code < 0 || rm > 2 ||
-            !(vec == 0 || vec == 1 || ((vec == 2 || vec == 4) && k != 1)))
+            !(vec == 0 || vec == 1 || ((vec == 2 || vec == 4) && k != 1)) ||
+            (zc > 1 && (k != 2 || vec < 2)) || zc > 65535)
             return fail(c, LB_E_INVALID, "bad shape");
         finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4);
     }
@@ -791,7 +836,8 @@ lb_status lb_get_launch_shapes(lb_ctx *c, int32_t *shapes9)
     for (int k = 0; k < 3; k++) {
         shapes9[3 * k] = c->shapes[k].bx;
         shapes9[3 * k + 1] = c->shapes[k].by;
-        shapes9[3 * k + 2] = c->shapes[k].remap + 8 * (c->shapes[k].vec > 1 ? c->shapes[k].vec : 0);
+        shapes9[3 * k + 2] = c->shapes[k].remap + 8 * (c->shapes[k].vec > 1 ? c->shapes[k].vec : 0) +
+                             64 * (c->shapes[k].zc > 1 ? c->shapes[k].zc : 0);
     }
     return LB_OK;
 }

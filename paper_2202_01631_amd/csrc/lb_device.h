@@ -41,6 +41,7 @@ __host__ __device__ constexpr double wgt(int i)
 constexpr uint8_t OWN_SOLID = 0x7f;
 constexpr int GCHUNK = 256;        // bounding-box nodes per geometry block
 constexpr int LINK_THREADS = 512;  // threads per particle in the link kernel
+constexpr int BND_SCAN = 4;        // geometry chunks a boundary fix-up block scans
 constexpr uint8_t OWN_BOUNDARY = 0x80;
 constexpr int MAX_COLLOIDS = 127;
 
@@ -97,7 +98,9 @@ __device__ __forceinline__ void stp(__half *b, unsigned off, float v, float sc)
 struct LaunchShape {
     int bx, by, remap;         // remap: XCD-aware block renumbering (0 off, 1, 2)
     int xseg, nblocks, bpp;    // derived: segments per row, blocks, blocks per z plane
+                               // (marching: blocks per chunk of zc planes)
     int vec;                   // > 1: row-vector form, vec consecutive x nodes per lane
+    int zc;                    // > 1 (row-vector psi/c update): planes marched per lane
 };
 
 struct KParams {

@@ -44,6 +44,8 @@ struct BatchArgs {
     const int *bstart;
     const int *cstart;
     int nbox;
+    int nsec;   // boundary fix-up blocks per particle
+    int nfix;   // fix-up blocks at the head of the mu and psi/c launches
 };
 
 // Host-side batch: device tables plus launch extents.
@@ -55,6 +57,8 @@ struct Batch {
     int nlchunk_max;  // link chunks of the largest link table
     int precision;
     int vec[3];       // row-vector form of each lattice launch (all boxes of the batch)
+    int zmarch;       // z-marching form of the psi/c update (all boxes of the batch)
+    long long nodes;  // lattice nodes over all boxes
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,
@@ -76,8 +80,17 @@ struct TimingHook {
 // derive the launch extents of a shape; ssize = bytes of a scalar field value
 void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize);
 
-// one time step of every box of the batch (all boxes share the precision P)
-template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm);
+// Second stream for the particle work of a step, with the events of its two
+// forks and joins.
+struct SideStream {
+    hipStream_t s;
+    hipEvent_t ev[4];
+};
+
+// one time step of every box of the batch (all boxes share the precision P);
+// side may be null (everything in order on s)
+template <int P>
+void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm);
 // particle geometry at placement (owner map, boundary bits, link tables)
 void launch_geometry(const Batch &B, hipStream_t s);
 

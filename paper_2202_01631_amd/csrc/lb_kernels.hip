@@ -3,10 +3,16 @@
 // colloids (arXiv:2202.01631, Sec. II).
 //
 // Step sequence on one stream (cur -> nxt buffers):
-//   k_mu             mu_psi of Eq. 2 with the wetting ghost of Eqs. 8-9
+//   k_mu             mu_psi of Eq. 2 at interior nodes (one-node or
+//                    row-vector form)
+//   k_mu_bnd         per particle box: mu at nodes next to a particle, with
+//                    the wetting ghost of Eqs. 8-9
 //   k_collide        force -psi grad(mu), moments, BGK-Guo collision, push
 //                    streaming with plain (resting-wall) bounce-back
-//   k_scalar         psi and c updates of Eq. 3 with Janus emission (Eq. 5)
+//   k_scalar         psi and c updates of Eq. 3 at interior nodes (one-node,
+//                    row-vector or z-marching row-vector form)
+//   k_scalar_bnd     per particle box: psi and c next to a particle (no-flux
+//                    solid faces, Janus emission of Eq. 5)
 //   k_link_partial   per (link chunk, particle): moving-wall and slip
 //                    correction of every link (Eqs. 4, 6), FP64 momentum
 //                    exchange partials
@@ -15,8 +21,8 @@
 //   k_cover          per particle: cover/uncover repair at the new position
 //   k_commit         per particle: owner bytes at the new position
 //   k_links          per particle: boundary bits and canonical link table
-// Lattice kernels use one thread per node, 64-wide rows in x (one wavefront
-// per row segment, coalesced structure-of-arrays access).
+// Lattice kernels run one node per thread or V consecutive x nodes per lane
+// over rows in x (coalesced structure-of-arrays access).
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -38,6 +44,21 @@ __device__ __forceinline__ int find_box(const int *__restrict__ start, int nbox,
 template <class S> __device__ __forceinline__ S s_tanh(S v);
 template <> __device__ __forceinline__ double s_tanh<double>(double v) { return tanh(v); }
 template <> __device__ __forceinline__ float s_tanh<float>(float v) { return tanhf(v); }
+
+// Store of a row vector by a bulk kernel: nodes next to a particle (owner
+// bit 7) are left to the boundary fix-up blocks of the same launch.
+template <class S, int V>
+__device__ __forceinline__ void st_interior(S *base, unsigned on, const SVec<S, V> &v, unsigned ow)
+{
+    const unsigned bm = (V == 4) ? 0x80808080u : 0x8080u;
+    if (!(ow & bm)) {
+        stb((SVec<S, V> *)base, on, v);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++)
+        if (!(byte_of(ow, k) & OWN_BOUNDARY)) stb(base, on + k * (unsigned)sizeof(S), v.v[k]);
+}
 
 // ------------------------------------------------------------------ k_mu
 // Also stores chi = c - c_b0 - E tanh psi for the solute update.
@@ -91,22 +112,44 @@ __device__ __forceinline__ void mu_chi(const KParams &p, S ps, S lap, S cn, S &m
     mu = fma(-(S)(p.C * p.E) * chi, fma(-t, t, S(1)), m);
 }
 
-// one node per thread
+// mu and chi of fluid node n = (x, y, z) next to a particle: wetting ghost
+// at every solid face
 template <class S>
-__global__ __launch_bounds__(256) void k_mu(BatchArgs A)
+__device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y,
+                                            int z)
 {
-    const int j = find_box(A.bstart, A.nbox, blockIdx.x);
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const uint8_t *__restrict__ own = D.b.own;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int nb[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                       n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                       n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+    const S ps = psi[n];
+    S pv[6];
+#pragma unroll
+    for (int e = 0; e < 6; e++)
+        pv[e] = face_psi<S>(p, D.b.col, own[nb[e]], e, x, y, z, ps, psi[nb[e]]);
+    S m, c;
+    mu_chi<S>(p, ps, lap6<S>(ps, pv), ((const S *)D.b.cc)[n], m, c);
+    ((S *)D.b.mu)[n] = m;
+    ((S *)D.b.chi)[n] = c;
+}
+
+// one node per thread
+template <class S, bool BND>
+__device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
+{
+    const int j = find_box(A.bstart, A.nbox, blk);
     const BoxDesc &D = A.d[j];
     KParams p = D.p;
     p.ls = D.ls[0];
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
-    const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ mu = (S *)D.b.mu;
     S *__restrict__ chi_out = (S *)D.b.chi;
     int x, y, z;
-    if (!lattice_node(p, blockIdx.x - A.bstart[j], x, y, z)) return;
+    if (!lattice_node(p, blk - A.bstart[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const int nb[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
@@ -120,10 +163,9 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
 #pragma unroll
     for (int e = 0; e < 6; e++) pv[e] = ldb(psi, (unsigned)nb[e] * sizeof(S));
     if (o & OWN_SOLID) { stb(mu, on, S(0)); stb(chi_out, on, S(0)); return; }
-    if (o & OWN_BOUNDARY) {
-#pragma unroll
-        for (int e = 0; e < 6; e++)
-            pv[e] = face_psi<S>(p, col, ldb(own, (unsigned)nb[e]), e, x, y, z, ps, pv[e]);
+    if (o & OWN_BOUNDARY) {  // here (BND) or in the fix-up launch
+        if (BND) mu_bnd_node<S>(D, p, n, x, y, z);
+        return;
     }
     S m, c;
     mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
@@ -135,23 +177,22 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
 // stores, x neighbours exchanged between lanes (the row wraps inside a lane
 // group when the group holds the whole row; segment ends of longer rows are
 // read directly).  Needs nx % V == 0.
-template <class S, int V>
-__global__ __launch_bounds__(256) void k_mu_v(BatchArgs A)
+template <class S, int V, bool BND>
+__device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
 {
     typedef SVec<S, V> Vec;
     typedef typename OwnWord<V>::T OW;
-    const int j = find_box(A.bstart, A.nbox, blockIdx.x);
+    const int j = find_box(A.bstart, A.nbox, blk);
     const BoxDesc &D = A.d[j];
     KParams p = D.p;
     p.ls = D.ls[0];
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
-    const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ mu = (S *)D.b.mu;
     S *__restrict__ chi_out = (S *)D.b.chi;
     int x0, y, z, li, gb;
-    if (!vec_node<V>(p, blockIdx.x - A.bstart[j], x0, y, z, li, gb)) return;
+    if (!vec_node<V>(p, blk - A.bstart[j], x0, y, z, li, gb)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n0 = x0 + sy * y + sz * z;
     const int nyp = n0 + (wrap_p(y, p.ny) - y) * sy, nym = n0 + (wrap_m(y, p.ny) - y) * sy;
@@ -167,51 +208,30 @@ __global__ __launch_bounds__(256) void k_mu_v(BatchArgs A)
     const int Ls = p.ls.bx;
     const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
     S pl = __shfl(pc.v[V - 1], srcl), pr = __shfl(pc.v[0], srcr);
-    unsigned owl = __shfl((unsigned)ow, srcl), owr = __shfl((unsigned)ow, srcr);
     if (p.ls.xseg > 1) {
         const int rb = n0 - x0;
-        if (li == 0) {
-            const int xl = rb + (x0 == 0 ? p.nx - 1 : x0 - 1);
-            pl = ldb(psi, (unsigned)xl * sizeof(S));
-            owl = (unsigned)own[xl] << (8 * (V - 1));
-        }
-        if (li == Ls - 1) {
-            const int xr = rb + (x0 + V == p.nx ? 0 : x0 + V);
-            pr = ldb(psi, (unsigned)xr * sizeof(S));
-            owr = own[xr];
-        }
-    }
-    unsigned oyp = 0, oym = 0, ozp = 0, ozm = 0;
-    const unsigned bmask = (V == 4) ? 0x80808080u : 0x8080u;
-    if ((unsigned)ow & bmask) {
-        oyp = ldb((const OW *)own, (unsigned)nyp);
-        oym = ldb((const OW *)own, (unsigned)nym);
-        ozp = ldb((const OW *)own, (unsigned)nzp);
-        ozm = ldb((const OW *)own, (unsigned)nzm);
+        if (li == 0) pl = ldb(psi, (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S));
+        if (li == Ls - 1) pr = ldb(psi, (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S));
     }
     Vec mv, xv;
 #pragma unroll
     for (int k = 0; k < V; k++) {
         const uint8_t o = byte_of(ow, k);
         const S ps = pc.v[k];
-        S pv[6] = {k < V - 1 ? pc.v[k + 1] : pr, k > 0 ? pc.v[k - 1] : pl, pyp.v[k], pym.v[k],
-                   pzp.v[k], pzm.v[k]};
-        if (o & OWN_BOUNDARY) {
-            const uint8_t onb[6] = {k < V - 1 ? byte_of(ow, k + 1) : byte_of(owr, 0),
-                                    k > 0 ? byte_of(ow, k - 1) : byte_of(owl, V - 1),
-                                    byte_of(oyp, k), byte_of(oym, k), byte_of(ozp, k),
-                                    byte_of(ozm, k)};
-#pragma unroll
-            for (int e = 0; e < 6; e++) pv[e] = face_psi<S>(p, col, onb[e], e, x0 + k, y, z, ps, pv[e]);
-        }
+        const S pv[6] = {k < V - 1 ? pc.v[k + 1] : pr, k > 0 ? pc.v[k - 1] : pl, pyp.v[k], pym.v[k],
+                         pzp.v[k], pzm.v[k]};
         S m, c;
         mu_chi<S>(p, ps, lap6<S>(ps, pv), cv.v[k], m, c);
         const bool solid = (o & OWN_SOLID) != 0;
         mv.v[k] = solid ? S(0) : m;
         xv.v[k] = solid ? S(0) : c;
     }
-    stb((Vec *)mu, on, mv);
-    stb((Vec *)chi_out, on, xv);
+    st_interior<S, V>(mu, on, mv, ow);
+    st_interior<S, V>(chi_out, on, xv, ow);
+    if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
+        for (int k = 0; k < V; k++)
+            if (byte_of(ow, k) & OWN_BOUNDARY) mu_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
+    }
 }
 
 // ------------------------------------------------------------- k_collide
@@ -368,12 +388,16 @@ __device__ S emission(const KParams &p, const DColloid *__restrict__ col,
     const int xo[3] = {wrap_m(x, p.nx) - x, 0, wrap_p(x, p.nx) - x};
     const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
     const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
+    // all 18 owner bytes are loaded before any is used
+    uint8_t om[19];
+#pragma unroll
+    for (int d = 1; d < 19; d++)
+        om[d] = ldb(own, (unsigned)(n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1])) & OWN_SOLID;
     S src = S(0);
+#pragma unroll
     for (int d = 1; d < 19; d++) {
-        const int m = n + xo[cx(d) + 1] + yo[cy(d) + 1] + zo[cz(d) + 1];
-        const uint8_t om = ldb(own, (unsigned)m) & OWN_SOLID;
-        if (!om) continue;
-        const DColloid &q = col[om - 1];
+        if (!om[d]) continue;
+        const DColloid &q = col[om[d] - 1];
         double r[3];
         displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
         src = src + (S)(active_cap(q, r) ? q.am : q.ap);
@@ -381,12 +405,48 @@ __device__ S emission(const KParams &p, const DColloid *__restrict__ col,
     return src;
 }
 
-// one node per thread
+// psi and c of fluid node n = (x, y, z) next to a particle: no flux through
+// solid faces, emission of its links
 template <class S>
-__global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
+__device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y, int z)
+{
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const S *__restrict__ chiv = (const S *)D.b.chi;
+    const S *__restrict__ ua[3] = {(const S *)D.b.u, (const S *)D.b.u + p.N,
+                                   (const S *)D.b.u + 2 * (size_t)p.N};
+    const uint8_t *__restrict__ own = D.b.own;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
+                       n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
+                       n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
+    const S ps = psi[n], cn = cc[n], chi = chiv[n], m0 = mu[n];
+    const S u0[3] = {ua[0][n], ua[1][n], ua[2][n]};
+    S um[6], pm[6], cm[6], mm[6], xm[6];
+    unsigned solid = 0;
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        const int m = fn[e];
+        um[e] = ua[e >> 1][m];
+        pm[e] = psi[m];
+        cm[e] = cc[m];
+        mm[e] = mu[m];
+        xm[e] = chiv[m];
+        solid |= (own[m] & OWN_SOLID) ? (1u << e) : 0u;
+    }
+    S psn, cpart;
+    psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, solid, psn, cpart);
+    ((S *)D.b.psin)[n] = psn;
+    ((S *)D.b.ccn)[n] = fma(-(S)p.kd, chi, cpart + emission<S>(p, D.b.col, own, n, x, y, z));
+}
+
+// one node per thread
+template <class S, bool BND>
+__device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
 {
     const int *bst = A.bstart + 2 * (A.nbox + 1);
-    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const int j = find_box(bst, A.nbox, blk);
     const BoxDesc &D = A.d[j];
     KParams p = D.p;
     p.ls = D.ls[2];
@@ -397,11 +457,10 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     const S *__restrict__ ua[3] = {(const S *)D.b.u, (const S *)D.b.u + p.N,
                                    (const S *)D.b.u + 2 * (size_t)p.N};
     const uint8_t *__restrict__ own = D.b.own;
-    const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
     int x, y, z;
-    if (!lattice_node(p, blockIdx.x - bst[j], x, y, z)) return;
+    if (!lattice_node(p, blk - bst[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n = x + sy * y + sz * z;
     const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
@@ -427,35 +486,25 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
         stb(ccn, on, cn);
         return;
     }
-    const bool bnd = (o & OWN_BOUNDARY) != 0;
-    unsigned solid = 0;
-    if (bnd) {
-#pragma unroll
-        for (int e = 0; e < 6; e++) solid |= (ldb(own, (unsigned)fn[e]) & OWN_SOLID) ? (1u << e) : 0u;
+    if (o & OWN_BOUNDARY) {  // here (BND) or in the fix-up launch
+        if (BND) psic_bnd_node<S>(D, p, n, x, y, z);
+        return;
     }
     S psn, cpart;
-    psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, solid, psn, cpart);
+    psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, 0u, psn, cpart);
     stb(psin, on, psn);
-    S chp = chi, src = S(0);
-    if (bnd) {
-        // pin the partial results in registers here, so the loaded stencil
-        // values are dead during the FP64 emission loop (which otherwise
-        // sets the register budget of the whole kernel)
-        asm volatile("" : "+v"(cpart), "+v"(chp));
-        src = emission<S>(p, col, own, n, x, y, z);
-    }
-    stb(ccn, on, fma(-(S)p.kd, chp, cpart + src));
+    stb(ccn, on, fma(-(S)p.kd, chi, cpart));
 }
 
 // Row-vector form (as k_mu_v): V consecutive x nodes per lane, x neighbours
 // of psi, c, mu, chi and u_x exchanged between lanes.
-template <class S, int V>
-__global__ __launch_bounds__(256) void k_scalar_v(BatchArgs A)
+template <class S, int V, bool BND>
+__device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
 {
     typedef SVec<S, V> Vec;
     typedef typename OwnWord<V>::T OW;
     const int *bst = A.bstart + 2 * (A.nbox + 1);
-    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const int j = find_box(bst, A.nbox, blk);
     const BoxDesc &D = A.d[j];
     KParams p = D.p;
     p.ls = D.ls[2];
@@ -467,11 +516,10 @@ __global__ __launch_bounds__(256) void k_scalar_v(BatchArgs A)
     const S *__restrict__ uy = ux + p.N;
     const S *__restrict__ uz = ux + 2 * (size_t)p.N;
     const uint8_t *__restrict__ own = D.b.own;
-    const DColloid *__restrict__ col = D.b.col;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
     int x0, y, z, li, gb;
-    if (!vec_node<V>(p, blockIdx.x - bst[j], x0, y, z, li, gb)) return;
+    if (!vec_node<V>(p, blk - bst[j], x0, y, z, li, gb)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n0 = x0 + sy * y + sz * z;
     const int nb[4] = {n0 + (wrap_p(y, p.ny) - y) * sy, n0 + (wrap_m(y, p.ny) - y) * sy,
@@ -507,32 +555,20 @@ __global__ __launch_bounds__(256) void k_scalar_v(BatchArgs A)
     }
     fl[4] = __shfl(u0x.v[V - 1], srcl);
     fr[4] = __shfl(u0x.v[0], srcr);
-    unsigned owl = __shfl((unsigned)ow, srcl), owr = __shfl((unsigned)ow, srcr);
     if (p.ls.xseg > 1) {
         const int rb = n0 - x0;
         if (li == 0) {
-            const int xl = rb + (x0 == 0 ? p.nx - 1 : x0 - 1);
-            const unsigned ol = (unsigned)xl * sizeof(S);
+            const unsigned ol = (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S);
             fl[0] = ldb(psi, ol); fl[1] = ldb(cc, ol); fl[2] = ldb(mu, ol); fl[3] = ldb(chiv, ol);
             fl[4] = ldb(ux, ol);
-            owl = (unsigned)own[xl] << (8 * (V - 1));
         }
         if (li == Ls - 1) {
-            const int xr = rb + (x0 + V == p.nx ? 0 : x0 + V);
-            const unsigned orr = (unsigned)xr * sizeof(S);
+            const unsigned orr = (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S);
             fr[0] = ldb(psi, orr); fr[1] = ldb(cc, orr); fr[2] = ldb(mu, orr); fr[3] = ldb(chiv, orr);
             fr[4] = ldb(ux, orr);
-            owr = own[xr];
         }
     }
-    const unsigned bmask = (V == 4) ? 0x80808080u : 0x8080u;
-    const bool anyb = ((unsigned)ow & bmask) != 0;
-    unsigned onb4[4] = {0, 0, 0, 0};
-    if (anyb) {
-#pragma unroll
-        for (int e = 0; e < 4; e++) onb4[e] = ldb((const OW *)own, (unsigned)nb[e]);
-    }
-    Vec pnv, cpv, chv;
+    Vec pnv, cnv;
 #pragma unroll
     for (int k = 0; k < V; k++) {
         const uint8_t o = byte_of(ow, k);
@@ -547,40 +583,174 @@ __global__ __launch_bounds__(256) void k_scalar_v(BatchArgs A)
         const S um[6] = {k < V - 1 ? u0x.v[k + 1] : fr[4], k > 0 ? u0x.v[k - 1] : fl[4],
                          uyp.v[k], uym.v[k], uzp.v[k], uzm.v[k]};
         const S u0[3] = {u0x.v[k], u0y.v[k], u0z.v[k]};
-        unsigned solid = 0;
-        if (o & OWN_BOUNDARY) {
-            const uint8_t onb[6] = {k < V - 1 ? byte_of(ow, k + 1) : byte_of(owr, 0),
-                                    k > 0 ? byte_of(ow, k - 1) : byte_of(owl, V - 1),
-                                    byte_of(onb4[0], k), byte_of(onb4[1], k),
-                                    byte_of(onb4[2], k), byte_of(onb4[3], k)};
-#pragma unroll
-            for (int e = 0; e < 6; e++) solid |= (onb[e] & OWN_SOLID) ? (1u << e) : 0u;
-        }
         S psn, cpart;
         psi_c_update<S>(p, c0[0].v[k], c0[1].v[k], c0[3].v[k], c0[2].v[k], u0, um, nbs[0], nbs[1],
-                        nbs[2], nbs[3], solid, psn, cpart);
+                        nbs[2], nbs[3], 0u, psn, cpart);
         const bool sol = (o & OWN_SOLID) != 0;
         pnv.v[k] = sol ? c0[0].v[k] : psn;
-        cpv.v[k] = cpart;
-        chv.v[k] = c0[3].v[k];
+        cnv.v[k] = sol ? c0[1].v[k] : fma(-(S)p.kd, c0[3].v[k], cpart);
     }
-    stb((Vec *)psin, on, pnv);
-    S src[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) src[k] = S(0);
-    if (anyb) {
-#pragma unroll
-        for (int k = 0; k < V; k++) asm volatile("" : "+v"(cpv.v[k]), "+v"(chv.v[k]));
+    st_interior<S, V>(psin, on, pnv, ow);
+    st_interior<S, V>(ccn, on, cnv, ow);
+    if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
         for (int k = 0; k < V; k++)
-            if (byte_of(ow, k) & OWN_BOUNDARY) src[k] = emission<S>(p, col, own, n0 + k, x0 + k, y, z);
+            if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
     }
-    Vec cnv;
+}
+
+// z-marching row-vector form: each lane also marches zc consecutive planes
+// of its row.  psi, c, mu, chi, u_z and the owner bytes of planes z - 1, z,
+// z + 1 stay in registers, and the next plane is loaded while the current
+// one is computed, so a plane costs its centre loads and the y neighbour
+// rows only.  Blocks: bpp blocks per chunk of zc planes, chunks in order.
+template <class S, int V, bool BND>
+__device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
+{
+    typedef SVec<S, V> Vec;
+    typedef typename OwnWord<V>::T OW;
+    const int *bst = A.bstart + 2 * (A.nbox + 1);
+    const int j = find_box(bst, A.nbox, blk);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    const LaunchShape ls = D.ls[2];
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ cc = (const S *)D.b.cc;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const S *__restrict__ chiv = (const S *)D.b.chi;
+    const S *__restrict__ ux = (const S *)D.b.u;
+    const S *__restrict__ uy = ux + p.N;
+    const S *__restrict__ uz = ux + 2 * (size_t)p.N;
+    const uint8_t *__restrict__ own = D.b.own;
+    S *__restrict__ psin = (S *)D.b.psin;
+    S *__restrict__ ccn = (S *)D.b.ccn;
+    const S *__restrict__ wf[5] = {psi, cc, mu, chiv, uz};  // fields kept over z
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    const int Ls = ls.bx, g = l / Ls;
+    if (g >= ls.by) return;
+    const int li = l - g * Ls, gb = g * Ls;
+    const int b = blk - bst[j];
+    const int chunk = b / ls.bpp;
+    const int sg = ((b - chunk * ls.bpp) * 4 + w) * ls.by + g;
+    const int y = sg / ls.xseg, seg = sg - y * ls.xseg;
+    if (y >= p.ny) return;
+    const int x0 = (seg * Ls + li) * V;
+    const int z0 = chunk * ls.zc;
+    const int z1 = min(z0 + ls.zc, p.nz);
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int c0 = x0 + sy * y;
+    const int dyp = (wrap_p(y, p.ny) - y) * sy, dym = (wrap_m(y, p.ny) - y) * sy;
+    const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
+    Vec W[5][3];    // [field][z - 1, z, z + 1]
+    unsigned WO[3];
+    Vec uxc, uyc;   // u_x, u_y of plane z
+    {
+        const int pl[3] = {wrap_m(z0, p.nz), z0, wrap_p(z0, p.nz)};
 #pragma unroll
-    for (int k = 0; k < V; k++) {
-        const bool sol = (byte_of(ow, k) & OWN_SOLID) != 0;
-        cnv.v[k] = sol ? c0[1].v[k] : fma(-(S)p.kd, chv.v[k], cpv.v[k] + src[k]);
+        for (int s = 0; s < 3; s++) {
+            const int n = c0 + sz * pl[s];
+#pragma unroll
+            for (int f = 0; f < 5; f++) W[f][s] = ldb((const Vec *)wf[f], (unsigned)n * sizeof(S));
+            WO[s] = ldb((const OW *)own, (unsigned)n);
+        }
+        const unsigned o0 = (unsigned)(c0 + sz * z0) * sizeof(S);
+        uxc = ldb((const Vec *)ux, o0);
+        uyc = ldb((const Vec *)uy, o0);
     }
-    stb((Vec *)ccn, on, cnv);
+    for (int z = z0; z < z1; z++) {
+        const int n0 = c0 + sz * z;
+        const unsigned on = (unsigned)n0 * sizeof(S);
+        // next plane: window fields of z + 2, u_x and u_y of z + 1
+        Vec nW[5], nux, nuy;
+        unsigned nO = 0;
+        if (z + 1 < z1) {
+            int z2 = z + 2;
+            if (z2 >= p.nz) z2 -= p.nz;
+            const int n2 = c0 + sz * z2;
+#pragma unroll
+            for (int f = 0; f < 5; f++) nW[f] = ldb((const Vec *)wf[f], (unsigned)n2 * sizeof(S));
+            nO = ldb((const OW *)own, (unsigned)n2);
+            const unsigned o1 = (unsigned)(c0 + sz * wrap_p(z, p.nz)) * sizeof(S);
+            nux = ldb((const Vec *)ux, o1);
+            nuy = ldb((const Vec *)uy, o1);
+        }
+        // y neighbour rows of plane z: psi, c, mu, chi, u_y
+        Vec Y[5][2];
+        const unsigned oyp = (unsigned)(n0 + dyp) * sizeof(S), oym = (unsigned)(n0 + dym) * sizeof(S);
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            Y[f][0] = ldb((const Vec *)wf[f], oyp);
+            Y[f][1] = ldb((const Vec *)wf[f], oym);
+        }
+        Y[4][0] = ldb((const Vec *)uy, oyp);
+        Y[4][1] = ldb((const Vec *)uy, oym);
+        // x neighbours: last node of the lane on the left, first of the right
+        S fl[5], fr[5];  // psi, c, mu, chi, u_x
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            fl[f] = __shfl(W[f][1].v[V - 1], srcl);
+            fr[f] = __shfl(W[f][1].v[0], srcr);
+        }
+        fl[4] = __shfl(uxc.v[V - 1], srcl);
+        fr[4] = __shfl(uxc.v[0], srcr);
+        const unsigned ow = WO[1];
+        if (ls.xseg > 1) {
+            const int rb = n0 - x0;
+            if (li == 0) {
+                const unsigned ol = (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S);
+#pragma unroll
+                for (int f = 0; f < 4; f++) fl[f] = ldb(wf[f], ol);
+                fl[4] = ldb(ux, ol);
+            }
+            if (li == Ls - 1) {
+                const unsigned orr = (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S);
+#pragma unroll
+                for (int f = 0; f < 4; f++) fr[f] = ldb(wf[f], orr);
+                fr[4] = ldb(ux, orr);
+            }
+        }
+        Vec pnv, cnv;
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            const uint8_t o = byte_of(ow, k);
+            S nbs[4][6];
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                nbs[f][0] = k < V - 1 ? W[f][1].v[k + 1] : fr[f];
+                nbs[f][1] = k > 0 ? W[f][1].v[k - 1] : fl[f];
+                nbs[f][2] = Y[f][0].v[k];
+                nbs[f][3] = Y[f][1].v[k];
+                nbs[f][4] = W[f][2].v[k];
+                nbs[f][5] = W[f][0].v[k];
+            }
+            const S um[6] = {k < V - 1 ? uxc.v[k + 1] : fr[4], k > 0 ? uxc.v[k - 1] : fl[4],
+                             Y[4][0].v[k], Y[4][1].v[k], W[4][2].v[k], W[4][0].v[k]};
+            const S u0[3] = {uxc.v[k], uyc.v[k], W[4][1].v[k]};
+            S psn, cpart;
+            psi_c_update<S>(p, W[0][1].v[k], W[1][1].v[k], W[3][1].v[k], W[2][1].v[k], u0, um,
+                            nbs[0], nbs[1], nbs[2], nbs[3], 0u, psn, cpart);
+            const bool sol = (o & OWN_SOLID) != 0;
+            pnv.v[k] = sol ? W[0][1].v[k] : psn;
+            cnv.v[k] = sol ? W[1][1].v[k] : fma(-(S)p.kd, W[3][1].v[k], cpart);
+        }
+        st_interior<S, V>(psin, on, pnv, ow);
+        st_interior<S, V>(ccn, on, cnv, ow);
+        if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
+            for (int k = 0; k < V; k++)
+                if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
+        }
+        // advance the window
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+            W[f][0] = W[f][1];
+            W[f][1] = W[f][2];
+            W[f][2] = nW[f];
+        }
+        WO[0] = WO[1];
+        WO[1] = WO[2];
+        WO[2] = nO;
+        uxc = nux;
+        uyc = nuy;
+    }
 }
 
 // ------------------------------------------------ block reductions (FP64)
@@ -849,6 +1019,106 @@ __device__ __forceinline__ int box_node(const BoxIter &b, int t, const KParams &
     y = b.by.at(iy);
     z = b.bz.at(iz);
     return x + p.nx * (y + p.ny * z);
+}
+
+// ------------------------------------------------------- boundary fix-ups
+// The bulk mu and psi/c blocks skip the fluid nodes next to a particle.  These
+// blocks recompute the fluid nodes next to a particle (owner bit 7).
+// Fix-up block (particle, section): it scans BND_SCAN * GCHUNK nodes of the
+// particle's bounding box, gathers the boundary nodes among them in LDS and
+// works through that list with all lanes busy.  Only these nodes have solid
+// neighbours, so the wetting ghost (Eq. 9), the no-flux faces and the
+// emission (Eq. 5) live here, off the bulk kernels' register budget.  A
+// node inside two boxes is recomputed twice with identical results.
+
+// boundary nodes (box indices) of this block's section, in any order
+__device__ __forceinline__ int gather_boundary(const BoxIter &B, const KParams &p,
+                                               const uint8_t *__restrict__ own, int sec, int *list,
+                                               int &cnt)
+{
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BND_SCAN; r++) {
+        const int t = (sec * BND_SCAN + r) * GCHUNK + (int)threadIdx.x;
+        if (t < B.total) {
+            int x, y, z;
+            if (own[box_node(B, t, p, x, y, z)] & OWN_BOUNDARY) list[atomicAdd(&cnt, 1)] = t;
+        }
+    }
+    __syncthreads();
+    return cnt;
+}
+template <class S>
+__device__ __forceinline__ void mu_fix(const BatchArgs &A, const int blk)
+{
+    const int gk = blk / A.nsec, sec = blk - gk * A.nsec;
+    const int j = find_box(A.cstart, A.nbox, gk);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    __shared__ int list[BND_SCAN * GCHUNK];
+    __shared__ int cnt;
+    const BoxIter B = box_of(D.b.col[gk - A.cstart[j]], p);
+    if (sec * BND_SCAN * GCHUNK >= B.total) return;  // whole block
+    const int count = gather_boundary(B, p, D.b.own, sec, list, cnt);
+    for (int i = threadIdx.x; i < count; i += GCHUNK) {
+        int x, y, z;
+        const int n = box_node(B, list[i], p, x, y, z);
+        mu_bnd_node<S>(D, p, n, x, y, z);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void psic_fix(const BatchArgs &A, const int blk)
+{
+    const int gk = blk / A.nsec, sec = blk - gk * A.nsec;
+    const int j = find_box(A.cstart, A.nbox, gk);
+    const BoxDesc &D = A.d[j];
+    const KParams p = D.p;
+    __shared__ int list[BND_SCAN * GCHUNK];
+    __shared__ int cnt;
+    const BoxIter B = box_of(D.b.col[gk - A.cstart[j]], p);
+    if (sec * BND_SCAN * GCHUNK >= B.total) return;  // whole block
+    const int count = gather_boundary(B, p, D.b.own, sec, list, cnt);
+    for (int i = threadIdx.x; i < count; i += GCHUNK) {
+        int x, y, z;
+        const int n = box_node(B, list[i], p, x, y, z);
+        psic_bnd_node<S>(D, p, n, x, y, z);
+    }
+}
+
+// ------------------------------------------------ mu and psi/c launches
+// Bulk launches (V = 1: one node per thread; 2, 4: row vectors; ZM:
+// z-marching row vectors) and the boundary fix-up launch, grid A.nsec
+// blocks per particle.  Bulk and fix-up blocks write disjoint nodes, so the
+// two launches of an update may run side by side on two streams.  With BND
+// the bulk launch does the boundary nodes itself (small steps, where a
+// separate fix-up launch would cost more than it saves).
+template <class S, int V, bool BND>
+__global__ __launch_bounds__(256) void k_mu(BatchArgs A)
+{
+    if (V == 1) mu_one<S, BND>(A, blockIdx.x);
+    else mu_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
+}
+
+template <class S>
+__global__ __launch_bounds__(GCHUNK) void k_mu_bnd(BatchArgs A)
+{
+    mu_fix<S>(A, blockIdx.x);
+}
+
+template <class S, int V, bool ZM, bool BND>
+__global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
+{
+    if (V == 1) psic_one<S, BND>(A, blockIdx.x);
+    else if (ZM) psic_zmarch<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
+    else psic_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
+}
+
+template <class S>
+__global__ __launch_bounds__(GCHUNK) void k_scalar_bnd(BatchArgs A)
+{
+    psic_fix<S>(A, blockIdx.x);
 }
 
 // ------------------------------------------------------------- k_cover
@@ -1249,6 +1519,15 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize)
             const long long segs = (long long)ny * nz * ls.xseg, per = 4LL * ls.by;
             ls.nblocks = (int)((segs + per - 1) / per);
             ls.bpp = 0;
+            if (ls.zc > 1) {
+                // z-marching: blocks over (row group, chunk of zc planes)
+                if (ls.zc > nz) ls.zc = nz;
+                ls.remap = 0;
+                ls.bpp = (int)(((long long)ny * ls.xseg + per - 1) / per);
+                ls.nblocks = ls.bpp * ((nz + ls.zc - 1) / ls.zc);
+                return;
+            }
+            ls.zc = 0;
             if (ls.remap == 2) {
                 const long long pp = (long long)ny * ls.xseg;
                 if (pp % per == 0 && (pp / per) % 8 == 0) ls.bpp = (int)(pp / per);
@@ -1260,6 +1539,7 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize)
         ls.by = 0;
     }
     ls.vec = 0;
+    ls.zc = 0;
     if (ls.bx <= 0 || ls.bx > 256) ls.bx = nx < 256 ? nx : 256;
     if (ls.bx > nx) ls.bx = nx;
     if (ls.by <= 0) ls.by = ls.bx >= 256 ? 1 : 256 / ls.bx;
@@ -1285,32 +1565,82 @@ static void launch_geometry_tail(const Batch &B, hipStream_t s)
     k_link_write<<<g, GCHUNK, 0, s>>>(B.args);
 }
 
-template <int P> void launch_step(const Batch &B, hipStream_t s, TimingHook *tm)
+// One step.  With a side stream (and particles, no per-kernel timing, and
+// at least SIDE_MIN_NODES nodes, below which the fork and join cost more
+// than they hide) the particle work runs beside the bulk lattice kernels:
+// the mu fix-up
+// beside the bulk mu update, and the psi/c fix-up, the link pass and the
+// rigid-body update beside the bulk psi/c update.  Fork and join go through
+// events, so a captured graph holds them as parallel branches.  The bulk
+// kernels touch neither the boundary nodes nor the particle records, and
+// the side work touches no node the bulk kernels write.
+constexpr long long SIDE_MIN_NODES = 1LL << 22;
+
+template <int P>
+void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm)
 {
     typedef typename Prec<P>::S S;
+    constexpr int V4 = sizeof(S) == 4 ? 4 : 2;  // FP64 scalars: 2 per 16-byte access
+    // split: boundary nodes in fix-up launches (on the side stream if par)
+    const bool split = B.ncol > 0 && B.nodes >= SIDE_MIN_NODES;
+    const bool par = split && side && !tm;
+    hipStream_t ss = par ? side->s : s;
+    const dim3 gfix(B.args.nfix);
     if (tm) tm->begin(0, s);
-    if (sizeof(S) == 4 && B.vec[0] == 4)
-        k_mu_v<S, (sizeof(S) == 4 ? 4 : 2)><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else if (B.vec[0] == 2)
-        k_mu_v<S, 2><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else
-        k_mu<S><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    if (par) {
+        hipEventRecord(side->ev[0], s);
+        hipStreamWaitEvent(ss, side->ev[0], 0);
+    }
+    if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(B.args);
+    const int vm = B.vec[0] == 4 ? 4 : (B.vec[0] == 2 ? 2 : 1);
+    const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
+    if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else if (vm == 2 && bi) k_mu<S, 2, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else if (vm == 2) k_mu<S, 2, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else if (bi) k_mu<S, 1, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    else k_mu<S, 1, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    if (par) {
+        hipEventRecord(side->ev[1], ss);
+        hipStreamWaitEvent(s, side->ev[1], 0);
+    }
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
     k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
-    if (sizeof(S) == 4 && B.vec[2] == 4)
-        k_scalar_v<S, (sizeof(S) == 4 ? 4 : 2)><<<B.nblocks[2], 256, 0, s>>>(B.args);
-    else if (B.vec[2] == 2)
-        k_scalar_v<S, 2><<<B.nblocks[2], 256, 0, s>>>(B.args);
-    else
-        k_scalar<S><<<B.nblocks[2], 256, 0, s>>>(B.args);
+    if (par) {
+        hipEventRecord(side->ev[2], s);
+        hipStreamWaitEvent(ss, side->ev[2], 0);
+    }
+    if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(B.args);
+    const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
+    const dim3 gs(B.nblocks[2]);
+    if (vs == 4 && B.zmarch) {
+        if (bi) k_scalar<S, V4, true, true><<<gs, 256, 0, s>>>(B.args);
+        else k_scalar<S, V4, true, false><<<gs, 256, 0, s>>>(B.args);
+    } else if (vs == 2 && B.zmarch) {
+        if (bi) k_scalar<S, 2, true, true><<<gs, 256, 0, s>>>(B.args);
+        else k_scalar<S, 2, true, false><<<gs, 256, 0, s>>>(B.args);
+    } else if (vs == 4) {
+        if (bi) k_scalar<S, V4, false, true><<<gs, 256, 0, s>>>(B.args);
+        else k_scalar<S, V4, false, false><<<gs, 256, 0, s>>>(B.args);
+    } else if (vs == 2) {
+        if (bi) k_scalar<S, 2, false, true><<<gs, 256, 0, s>>>(B.args);
+        else k_scalar<S, 2, false, false><<<gs, 256, 0, s>>>(B.args);
+    } else {
+        if (bi) k_scalar<S, 1, false, true><<<gs, 256, 0, s>>>(B.args);
+        else k_scalar<S, 1, false, false><<<gs, 256, 0, s>>>(B.args);
+    }
     if (tm) tm->end(2, s);
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
-    k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, s>>>(B.args);
-    k_colloid_update<<<B.ncol, 64, 0, s>>>(B.args);
+    k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);
+    k_colloid_update<<<B.ncol, 64, 0, ss>>>(B.args);
+    if (par) {
+        hipEventRecord(side->ev[3], ss);
+        hipStreamWaitEvent(s, side->ev[3], 0);
+    }
     if (tm) tm->end(3, s);
     if (tm) tm->begin(4, s);
     k_cover<P><<<dim3(B.nchunk_max, B.ncol), GCHUNK, 0, s>>>(B.args);
@@ -1370,7 +1700,7 @@ void launch_fields(const KParams &p, const void *f, const void *psi, const void 
 }
 
 #define LB_INSTANTIATE(P)                                                                          \
-    template void launch_step<P>(const Batch &, hipStream_t, TimingHook *);                          \
+    template void launch_step<P>(const Batch &, hipStream_t, const SideStream *, TimingHook *);                          \
     template void launch_init<P>(const KParams &, const double *, const double *, const double *,   \
                                  const double *, void *, void *, void *, uint8_t *, hipStream_t);   \
     template void launch_reduce<P>(const KParams &, const void *, const void *, const void *,       \

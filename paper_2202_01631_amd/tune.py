@@ -20,9 +20,7 @@ CACHE = os.path.join(HERE, "tuning.json")
 
 
 def candidates(nx, ny):
-    """(bx, by, code) shapes, code = remap + 8 vec.  One-node shapes apply to
-    all three kernels; row-vector shapes (vec 2 or 4) to the mu and psi/c
-    updates only."""
+    """(bx, by, code) shapes, code = remap + 8 vec + 64 zc."""
     out = []
     for bx in (256, 128, 64, 32, 16):
         if bx > nx and bx != min(nx, 256):
@@ -37,6 +35,8 @@ def candidates(nx, ny):
         if nx % vec == 0:
             for remap in (0, 2):
                 out.append((0, 0, remap + 8 * vec))
+            for zc in (4, 8, 16):
+                out.append((0, 0, 8 * vec + 64 * zc))
     # distinct, natural-order default first
     seen, uniq = set(), []
     for c in [(min(nx, 256), max(1, 256 // min(nx, 256)), 0)] + out:
@@ -48,6 +48,18 @@ def candidates(nx, ny):
 
 def is_vec(cand):
     return cand[2] >= 16
+
+
+def launch_for(cand):
+    """(shapes of the three kernels, which kernels' times count) for a
+    candidate: one-node shapes go to all three kernels; row-vector shapes to
+    the mu and psi/c updates (collide keeps its default); z-marching shapes
+    to the psi/c update only (mu takes the same row-vector form)."""
+    if not is_vec(cand):
+        return [cand, cand, cand], (True, True, True)
+    if cand[2] >= 64:
+        return [(0, 0, cand[2] & 63), (0, 0, 0), cand], (False, False, True)
+    return [cand, (0, 0, 0), cand], (True, False, True)
 
 
 def device_key():
@@ -112,18 +124,15 @@ def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log
     box = lb.from_spec(spec, precision=precision)
     results = {}
     for cand in candidates(shape[0], shape[1]):
-        # row-vector shapes exist for the mu and psi/c updates only: collide
-        # runs its default shape then and its time is not scored
-        box.set_launch_shapes([cand, (0, 0, 0) if is_vec(cand) else cand, cand])
+        shapes, scored = launch_for(cand)
+        box.set_launch_shapes(shapes)
         box.step(warmup)
         torch.cuda.synchronize()
         box.timing_enable(True)
         box.step(steps)
         ms, calls = box.timing_read()
         box.timing_enable(False)
-        t = [float(ms[i] / max(calls[i], 1)) for i in range(3)]
-        if is_vec(cand):
-            t[1] = float("inf")
+        t = [float(ms[i] / max(calls[i], 1)) if scored[i] else float("inf") for i in range(3)]
         results[cand] = t
         log("[tune] %s %s %s us %s" % (shape, precision, cand,
                                         [round(1000 * v, 1) for v in results[cand]]))

@@ -94,6 +94,9 @@ def test_batched_fp64_matches_oracle():
     [(0, 0, 32), (32, 8, 0), (0, 0, 34)],      # row-vector, 4 nodes per lane
     [(0, 0, 16), (32, 8, 0), (0, 0, 18)],      # row-vector, 2 nodes per lane
     [(0, 0, 33), (32, 8, 0), (0, 0, 17)],
+    [(0, 0, 32), (32, 8, 0), (0, 0, 32 + 64 * 8)],   # z-marching, 8 planes
+    [(0, 0, 16), (32, 8, 0), (0, 0, 16 + 64 * 5)],   # 5 planes: ragged last chunk
+    [(0, 0, 16), (32, 8, 0), (0, 0, 34 + 64 * 40)],  # one chunk (zc > nz), remap dropped
 ])
 def test_launch_shapes_do_not_change_results(shapes):
     w = I.workload_small()
@@ -120,9 +123,9 @@ def test_row_vector_forms_long_rows(precision):
                 psi=psi, c=np.zeros(psi.size), colloids=cols)
     ref = lb.from_spec(spec, precision=precision)
     ref.set_launch_shapes([(64, 4, 0)] * 3)
-    for code in (16, 32, 18):
+    for code in (16, 32, 18, 16 + 64 * 3, 32 + 64 * 8):
         alt = lb.from_spec(spec, precision=precision)
-        alt.set_launch_shapes([(0, 0, code), (64, 4, 0), (0, 0, code)])
+        alt.set_launch_shapes([(0, 0, code & 63), (64, 4, 0), (0, 0, code)])
         eff = alt.launch_shapes()
         flush_print("[vec] %s code %d effective %s" % (precision, code, eff))
         assert eff[0][2] >= 16 and eff[2][2] >= 16
@@ -160,6 +163,10 @@ def test_row_vector_fallback_shapes():
         a.set_launch_shapes([(0, 0, 0), (0, 0, 32), (0, 0, 0)])  # collide has no row-vector form
     with pytest.raises(lb.LBError):
         a.set_launch_shapes([(0, 0, 3), (0, 0, 0), (0, 0, 0)])   # remap 3
+    with pytest.raises(lb.LBError):
+        a.set_launch_shapes([(0, 0, 32 + 64 * 4), (0, 0, 0), (0, 0, 0)])  # marching: psi/c only
+    with pytest.raises(lb.LBError):
+        a.set_launch_shapes([(0, 0, 0), (0, 0, 0), (0, 0, 64 * 4)])  # marching needs vec
 
 
 def test_batched_mixed_vec_equals_alone():
@@ -170,10 +177,29 @@ def test_batched_mixed_vec_equals_alone():
     stream = torch.cuda.Stream()
     batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
     batch[0].set_launch_shapes([(32, 8, 0), (0, 0, 0), (0, 0, 16)])
+    batch[1].set_launch_shapes([(0, 0, 32), (0, 0, 0), (0, 0, 32 + 64 * 4)])
     alone = [lb.from_spec(s, precision="fp32") for s in specs]
     lb.batch_step(batch, 6)
     for b in alone:
         b.step(6)
+    for b, a in zip(batch, alone):
+        assert _same(_state(b), _state(a))
+
+
+def test_batched_zmarch_equals_alone():
+    # all boxes of a batch marching in z (different chunk lengths per box)
+    import torch
+    specs = _boxes(n=4, seed=33)
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+    for k, b in enumerate(batch):
+        b.set_launch_shapes([(0, 0, 32), (0, 0, 0), (0, 0, 32 + 64 * (3 + 2 * k))])
+    alone = [lb.from_spec(s, precision="fp32") for s in specs]
+    batch[2].step(1)
+    alone[2].step(1)
+    lb.batch_step(batch, 7)
+    for b in alone:
+        b.step(7)
     for b, a in zip(batch, alone):
         assert _same(_state(b), _state(a))
 
@@ -214,3 +240,49 @@ def test_results_independent_of_arena_contents(precision):
             r.close()
         b.close()
     assert _same(out[0], out[1])
+
+
+def _big_spec(shape, count, seed):
+    psi = I.flat_interface(shape, shape[2] / 2.0, I.WIDTH, 0.01, seed=seed)
+    pts = I.place_spheres(shape, count, 4.5, lambda a, b: shape[2] / 2.0 + (2.0 * a - 1.0) * 6.0,
+                          2.0, seed + 1)
+    ms = I.unit_vectors(seed + 2, count)
+    cols = [I.janus(pts[k], ms[k], 4.5, mu=0.1, theta=70.0) for k in range(count)]
+    return dict(shape=shape, precision="fp32", params=dict(I.FREE_ENERGY), solubility_ratio=2.0,
+                psi=psi, c=np.zeros(psi.size), colloids=cols)
+
+
+def test_side_stream_step_equals_in_order():
+    # at >= 2^22 nodes with particles, the particle work runs on a side
+    # stream beside the bulk kernels (graph replay on a non-default stream);
+    # with per-kernel timing on, everything runs in order on one stream
+    import torch
+    spec = _big_spec((256, 128, 128), 8, 41)
+    stream = torch.cuda.Stream()
+    a = lb.from_spec(spec, stream=stream)
+    b = lb.from_spec(spec, stream=stream)
+    b.timing_enable(True)
+    for k in range(3):
+        a.step(4)
+        b.step(4)
+        torch.cuda.synchronize()
+        flush_print("[side] block", k)
+        assert _same(_state(a), _state(b))
+    a.step(3)  # odd: graph pair + one eager step with the side stream
+    b.step(3)
+    assert _same(_state(a), _state(b))
+
+
+def test_batched_side_stream_equals_alone():
+    # two 128^3 boxes: 2^22 nodes together (side stream in the batch), each
+    # alone below the threshold (in order)
+    import torch
+    specs = [_big_spec((128, 128, 128), 4, 51), _big_spec((128, 128, 128), 3, 61)]
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s, stream=stream) for s in specs]
+    alone = [lb.from_spec(s) for s in specs]
+    lb.batch_step(batch, 5)
+    for b in alone:
+        b.step(5)
+    for b, a in zip(batch, alone):
+        assert _same(_state(b), _state(a))
