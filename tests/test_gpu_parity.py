@@ -297,3 +297,40 @@ def test_full_size_256_one_step():
         t, _ = g.observables()
         assert t["error_bits"] == 0
         g.close()
+
+
+# ------------------------------------------------- owner-byte capacity
+def test_fp64_127_particles_owner_byte_limit():
+    # the owner byte holds k + 1 in 7 bits: 127 particles is the maximum.
+    # 127 moving spheres of radius 2.5 (surface gaps >= 2, several across the
+    # periodic faces), FP64: owner map and link tables bit-exact, fields
+    # within 1e-12 of the oracle after 8 steps; 128 are refused
+    shape = (64, 64, 26)
+    pts = I.place_spheres(shape, 127, 2.5, lambda a, b: 26.0 * a, 2.0, 91)
+    ms = I.unit_vectors(92, 127)
+    u = I.uniform(93, 3 * 127).reshape(127, 3)
+    cols = []
+    for k in range(127):
+        q = I.janus(pts[k], ms[k], 2.5, alpha=1e-3, mu=0.1 * (2 * u[k, 0] - 1),
+                    theta=60.0 + 60.0 * u[k, 1])
+        q["vel"] = np.array([0.01 * (2 * u[k, 2] - 1), 0.0, 0.0])
+        cols.append(q)
+    spec = _spec(shape, seed=94, colloids=cols)
+    g = lb.from_spec(spec, max_colloids=127)
+    o = oracle.from_spec(spec)
+    assert g.owner().max() == 126 and o.owner().max() == 126
+    assert np.array_equal(g.owner(), o.owner())
+    assert np.array_equal(g.links(), o.links())
+    g.step(8)
+    o.step(8)
+    assert np.array_equal(g.owner(), o.owner())
+    assert np.array_equal(g.links(), o.links())
+    _compare(g, o, 1e-12, "127 particles")
+    t, _ = g.observables()
+    assert t["error_bits"] == 0
+    with pytest.raises(lb.LBError):
+        lb.Box(shape, "fp64", max_colloids=128, **spec["params"])
+    b = lb.Box(shape, "fp64", max_colloids=127, **spec["params"])
+    b.init_fields(spec["psi"], spec["c"])
+    with pytest.raises(lb.LBError):
+        b.add_colloids(cols + [I.janus((5.0, 5.0, 13.0), (0, 0, 1), 2.5)])
