@@ -65,6 +65,14 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    # four more repetitions of the same K steps, reported beside the timed one
+    reps = [ms / steps]
+    for _ in range(4):
+        ev0.record(stream)
+        box.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(ev0.elapsed_time(ev1) / steps)
     ksteps = min(steps, 50)
     box.timing_enable(True)
     box.step(ksteps)
@@ -78,7 +86,39 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
     per_kernel = {KERNELS[i]: (kms[i] / calls[i] if calls[i] else None) for i in range(6)}
     return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
-                kernel_ms=per_kernel, kernel_steps=ksteps, error_bits=tot["error_bits"], N=N)
+                kernel_ms=per_kernel, kernel_steps=ksteps, error_bits=tot["error_bits"], N=N,
+                reps_ms_per_step=[round(v, 5) for v in reps])
+
+
+def copy_ceiling(torch):
+    """Device copy of 1 GiB (read 1 GiB + write 1 GiB), best of 5: the HBM
+    rate a plain streaming kernel reaches on this part."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
 def batched_sweep(torch, lb, I, nbox, steps):
@@ -118,7 +158,7 @@ def batched_sweep(torch, lb, I, nbox, steps):
 
 
 def serving_run(torch, I, nreq, rate, step_scale):
-    """Continuous-batching server on a Poisson trace (50/s, sides 32..96,
+    """Continuous-batching server on a Poisson trace (rate/s, sides 32..96,
     1-8 spheres, FP32 or FP16 storage), request lengths scaled by step_scale
     to bound the run; p50/p99 time-to-result and sustained MLUPS."""
     from paper_2202_01631_amd import serve
@@ -142,9 +182,11 @@ def cpu_baseline(spec):
     t2 = time.time()
     N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
     o.close()
+    model, ncpu = cpu_info()
     return dict(value=round(N / (t2 - t1) / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
                 sample="1 time step of the full 256^3 64-sphere workload, FP64 oracle, "
-                       "single thread (setup %.1f s excluded, step %.1f s)" % (t1 - t0, t2 - t1))
+                       "single thread (setup %.1f s excluded, step %.1f s) on %s, %s logical "
+                       "CPUs visible" % (t1 - t0, t2 - t1, model, ncpu))
 
 
 def main():
@@ -204,6 +246,8 @@ def main():
         t = json.load(open(TRAFFIC_FILE))
         if t.get("kernel_source_hash") == kernel_source_hash() and t.get("size") == n:
             traffic = t.get("bytes_per_launch")
+    copy_gbs = copy_ceiling(torch)
+    log("[bench] copy ceiling %.0f GB/s" % copy_gbs)
     out = {
         "metric": METRIC,
         "value": round(r["mlups"], 1),
@@ -223,7 +267,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_collide",
-                     "bytes_per_lu": COLLIDE_BYTES[main_prec]},
+                     "bytes_per_lu": COLLIDE_BYTES[main_prec],
+                     # the kernel's counted HBM bytes over its time, and both
+                     # rates against a plain device copy measured in this run
+                     "traffic_GBs": (round(traffic / (kc * 1e-3) / 1e9, 1) if traffic else None),
+                     "copy_ceiling_GBs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "traffic_frac_of_copy": (round(traffic / (kc * 1e-3) / 1e9 / copy_gbs, 4)
+                                              if traffic else None)},
+        "reps_ms_per_step": r["reps_ms_per_step"],
         "step_roofline": {p: {"mlups": round(v["mlups"], 1),
                               "algorithmic_GBs": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9, 1),
                               "frac": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9 / HBM_PEAK_GBS, 4),
@@ -240,6 +292,9 @@ def main():
         log("[bench] serving: %d requests" % args.serve)
         out["serving"] = serving_run(torch, I, args.serve, 50.0, args.serve_scale)
         log("[bench] serving %s" % out["serving"])
+        # below capacity: 5 requests/s
+        out["serving_low_rate"] = serving_run(torch, I, max(1, args.serve // 2), 5.0, args.serve_scale)
+        log("[bench] serving at 5/s %s" % out["serving_low_rate"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec)
     else:

@@ -334,3 +334,31 @@ def test_fp64_127_particles_owner_byte_limit():
     b.init_fields(spec["psi"], spec["c"])
     with pytest.raises(lb.LBError):
         b.add_colloids(cols + [I.janus((5.0, 5.0, 13.0), (0, 0, 1), 2.5)])
+
+
+def test_fp16_storage_error_at_full_size():
+    # the benchmark workload (256^3, 64 moving spheres) in FP16 storage
+    # against the FP64 GPU path (itself held to the oracle above) after 100
+    # steps: error per field and of the particle velocities, stated and
+    # bounded like the small FP16 case
+    w = I.workload_many(n=256, count=64, radius=6.0, precision="fp16")
+    ref = lb.from_spec(w, precision="fp64")
+    h = lb.from_spec(w, precision="fp16")
+    ref.step(100)
+    h.step(100)
+    own = ref.owner()
+    assert np.array_equal(own, h.owner())
+    e = field_errors(h.fields(), ref.fields(), own < 0)
+    _, cr = ref.observables()
+    _, ch = h.observables()
+    vmax = max(max(np.abs(q["vel"]).max() for q in cr), 1e-6)
+    ev = max(np.abs(a["vel"] - b["vel"]).max() for a, b in zip(ch, cr)) / vmax
+    flush_print("[fp16 256^3] field errors %s, particle velocity %.3g (max |V| %.3g)" % (e, ev, vmax))
+    # bounds of the small FP16 case, the density one widened 5x: the density
+    # error is the rounding of the 19 stored deviations (11 significant bits)
+    # accumulated over steps, and here it is the maximum over 1.7e7 nodes
+    # instead of 1.4e4 (measured 2.0e-5 after 100 steps)
+    tol = dict(rho=1e-4, psi=1e-3, c=1e-2, u=1e-1)
+    for k, v in e.items():
+        assert v <= tol[k], (k, v)
+    assert ev <= 1e-1
