@@ -45,7 +45,11 @@
  *   streams         work is enqueued on the stream given to lb_create (NULL:
  *                   the default stream).  One context per stream; no internal
  *                   locking.  Calls that return host data synchronise that
- *                   stream.
+ *                   stream.  Large steps with particles also use a second,
+ *                   internal stream of default priority, forked from and
+ *                   joined back into the context's stream inside each step,
+ *                   so the caller sees plain stream order.  On a non-default
+ *                   stream, steps are replayed from captured two-step graphs.
  *   call order      lb_create -> lb_init_fields -> [lb_add_colloids] ->
  *                   lb_step* ; violations return LB_E_STATE.
  */
@@ -91,7 +95,7 @@ typedef struct {
                                     diffusivity D_c (= C M_c) and sink rate (Eq. 3a) */
     double ext_force[3];         /* uniform body force on the fluid (0 in the paper) */
     double f16_scale;            /* FP16 storage scale, a power of two; 0 -> 16384 */
-    int32_t max_colloids;        /* particle capacity, <= 255; 0 -> 64 */
+    int32_t max_colloids;        /* particle capacity, <= 127 (owner byte); 0 -> 64 */
     uint32_t flags;              /* reserved, 0 */
 } lb_params;
 
@@ -205,11 +209,11 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
  * segment, rows per block (bx*by <= 256; 0 = default) and code = remap +
  * 8 vec + 64 zc.  remap is the block renumbering (0 natural order, 1
  * contiguous ranges per XCD, 2 one eighth of every z plane per XCD); vec
- * (0, 2 or 4; chemical potential and psi/c update only) selects the
- * row-vector form with vec consecutive x nodes per lane (FP64 takes 2 for
- * 4), in which bx and by are derived from nx, and which boxes with
- * nx % vec != 0, or rows longer than 64 lanes that are not a multiple of 64
- * lanes, replace by the one-node form; zc > 1 (psi/c update with vec only)
+ * (0, 2 or 4) selects the row-vector form with vec consecutive x nodes per
+ * lane (FP64 takes 2 for 4), in which bx and by are derived from nx, and
+ * which boxes with nx % vec != 0, or rows longer than 64 lanes that are not
+ * a multiple of 64 lanes (for the collide-stream: any row longer than 64
+ * lanes), replace by the one-node form; zc > 1 (psi/c update with vec only)
  * makes each lane march zc planes in z (natural block order).  LB_E_INVALID
  * for other values.  Used by the autotuner; results are identical for every
  * shape.  lb_get_launch_shapes returns the shapes in effect. */

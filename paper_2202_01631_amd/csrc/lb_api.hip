@@ -182,7 +182,8 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
                 if (d[j].ls[w].vec > 1) {
                     d[j].ls[w].vec = 0;
                     d[j].ls[w].zc = 0;
-                    finish_shape(d[j].ls[w], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ssize);
+                    finish_shape(d[j].ls[w], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ssize,
+                                 w == 1);
                 }
                 bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
             }
@@ -395,7 +396,7 @@ static void set_shapes(lb_ctx *c)
                 v[k].zc = 0;
                 e += used;
                 if (sscanf(e, ",%d%n", &vec, &used2) == 1) {
-                    if (k != 1 && (vec == 2 || vec == 4)) v[k].vec = vec;
+                    if (vec == 2 || vec == 4) v[k].vec = vec;
                     e += used2;
                     if (sscanf(e, ",%d%n", &zc, &used2) == 1) {
                         if (k == 2 && zc > 1) v[k].zc = zc;
@@ -409,7 +410,7 @@ static void set_shapes(lb_ctx *c)
         }
     }
     for (int k = 0; k < 3; k++) {
-        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4);
+        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4, k == 1);
         c->shapes[k] = v[k];
     }
     c->dirty = true;
@@ -820,10 +821,10 @@ lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)
         const int rm = code & 7, vec = code >= 0 ? (code >> 3) & 7 : -1, zc = code >> 6;
         v[k] = LaunchShape{shapes9[3 * k], shapes9[3 * k + 1], rm, 0, 0, 0, vec, zc};
         if (v[k].bx < 0 || v[k].by < 0 || code < 0 || rm > 2 ||
-            !(vec == 0 || vec == 1 || ((vec == 2 || vec == 4) && k != 1)) ||
+            !(vec == 0 || vec == 1 || vec == 2 || vec == 4) ||
             (zc > 1 && (k != 2 || vec < 2)) || zc > 65535)
             return fail(c, LB_E_INVALID, "bad shape");
-        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4);
+        finish_shape(v[k], c->p.nx, c->p.ny, c->p.nz, c->p.precision == LB_FP64 ? 8 : 4, k == 1);
     }
     for (int k = 0; k < 3; k++) c->shapes[k] = v[k];
     c->dirty = true;

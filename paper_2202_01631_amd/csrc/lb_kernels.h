@@ -77,8 +77,11 @@ struct TimingHook {
     ~TimingHook();
 };
 
-// derive the launch extents of a shape; ssize = bytes of a scalar field value
-void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize);
+// derive the launch extents of a shape; ssize = bytes of a scalar field value;
+// whole_rows: a row-vector shape must keep each row in one lane group (the
+// row-vector collide-stream), else the shape falls back to one node per
+// thread
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize, bool whole_rows = false);
 
 // Second stream for the particle work of a step, with the events of its two
 // forks and joins.

@@ -8,7 +8,8 @@
 //   k_mu_bnd         per particle box: mu at nodes next to a particle, with
 //                    the wetting ghost of Eqs. 8-9
 //   k_collide        force -psi grad(mu), moments, BGK-Guo collision, push
-//                    streaming with plain (resting-wall) bounce-back
+//                    streaming with plain (resting-wall) bounce-back (one-node
+//                    form, or k_collide_v: row-vector form)
 //   k_scalar         psi and c updates of Eq. 3 at interior nodes (one-node,
 //                    row-vector or z-marching row-vector form)
 //   k_scalar_bnd     per particle box: psi and c next to a particle (no-flux
@@ -23,6 +24,8 @@
 //   k_links          per particle: boundary bits and canonical link table
 // Lattice kernels run one node per thread or V consecutive x nodes per lane
 // over rows in x (coalesced structure-of-arrays access).
+#include <utility>
+
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -39,6 +42,17 @@ __device__ __forceinline__ int find_box(const int *__restrict__ start, int nbox,
         if (start[mid] <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// f(integral_constant<int, I>) for I = 0 .. N-1, expanded at compile time
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F &f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
 template <class S> __device__ __forceinline__ S s_tanh(S v);
@@ -244,7 +258,74 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
 // [3(c_i - u) + 9 (c_i.u) c_i].F with geq_i = w_i [drho + rho(3 c.u +
 // 4.5 (c.u)^2 - 1.5 u.u)] (BGK with Guo forcing).  Push: g*_i goes to
 // x + c_i, or back into slot opp(i) of x when x + c_i is solid (resting-wall
-// bounce-back; the moving-wall and slip terms are added by k_links_colloid).
+// bounce-back; the moving-wall and slip terms are added by k_link_partial).
+// The node arithmetic lives in helpers with contraction off and explicit
+// fused forms, so the one-node and row-vector forms round identically.
+
+// moments and force of one fluid node
+template <class S> struct NodeMoments {
+    S drho, rho, ux, uy, uz, Fx, Fy, Fz, uu, uF;
+};
+
+// g: the 19 populations; mv[1..18]: mu at the neighbours, replaced by
+// m0 = mu(x) where bit i of solid is set
+template <class S>
+__device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, const S g[19],
+                                                          const S mv[19], S m0, unsigned solid,
+                                                          S ps)
+{
+#pragma clang fp contract(off)
+    NodeMoments<S> m;
+    S drho = S(0), jx = S(0), jy = S(0), jz = S(0);
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        drho = drho + g[i];
+        if (cx(i)) jx = cx(i) > 0 ? jx + g[i] : jx - g[i];
+        if (cy(i)) jy = cy(i) > 0 ? jy + g[i] : jy - g[i];
+        if (cz(i)) jz = cz(i) > 0 ? jz + g[i] : jz - g[i];
+    }
+    // grad(mu) = 3 sum_i w_i c_i mu(x + c_i)
+    S gx = S(0), gy = S(0), gz = S(0);
+#pragma unroll
+    for (int i = 1; i < 19; i++) {
+        const S wi = (S)(3.0 * wgt(i));
+        const S mi = (solid & (1u << i)) ? m0 : mv[i];
+        if (cx(i)) gx = fma(cx(i) > 0 ? wi : -wi, mi, gx);
+        if (cy(i)) gy = fma(cy(i) > 0 ? wi : -wi, mi, gy);
+        if (cz(i)) gz = fma(cz(i) > 0 ? wi : -wi, mi, gz);
+    }
+    m.Fx = fma(-ps, gx, (S)p.fx);
+    m.Fy = fma(-ps, gy, (S)p.fy);
+    m.Fz = fma(-ps, gz, (S)p.fz);
+    m.drho = drho;
+    m.rho = (S)p.rho0 + drho;
+    const S ir = S(1) / m.rho;
+    m.ux = fma(S(0.5), m.Fx, jx) * ir;
+    m.uy = fma(S(0.5), m.Fy, jy) * ir;
+    m.uz = fma(S(0.5), m.Fz, jz) * ir;
+    m.uu = fma(m.uz, m.uz, fma(m.uy, m.uy, m.ux * m.ux));
+    m.uF = fma(m.uz, m.Fz, fma(m.uy, m.Fy, m.ux * m.Fx));
+    return m;
+}
+
+// post-collision value of population i; om = 1/tau, pref = 1 - 1/(2 tau)
+template <class S>
+__device__ __forceinline__ S collide_pop(int i, S gi, const NodeMoments<S> &m, S om, S pref)
+{
+#pragma clang fp contract(off)
+    // c_i.u and c_i.F as signed sums (the components of c_i are 0 or +-1)
+    S cu = S(0), cF = S(0);
+    if (cx(i)) { cu = cx(i) > 0 ? m.ux : -m.ux; cF = cx(i) > 0 ? m.Fx : -m.Fx; }
+    if (cy(i)) { cu = cy(i) > 0 ? cu + m.uy : cu - m.uy; cF = cy(i) > 0 ? cF + m.Fy : cF - m.Fy; }
+    if (cz(i)) { cu = cz(i) > 0 ? cu + m.uz : cu - m.uz; cF = cz(i) > 0 ? cF + m.Fz : cF - m.Fz; }
+    const S w = (S)wgt(i);
+    const S q = fma(S(4.5) * cu, cu, fma(S(3), cu, S(-1.5) * m.uu));
+    const S geq = w * fma(m.rho, q, m.drho);
+    const S fo = fma(S(9) * cu, cF, S(3) * (cF - m.uF));
+    return fma(pref * w, fo, fma(-om, gi - geq, gi));
+}
+
+// one node per thread
 template <int P>
 __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 {
@@ -283,54 +364,21 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
     for (int i = 1; i < 19; i++)
         mv[i] = ldb(mu, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) * sizeof(S));
     if (o & OWN_SOLID) return;
-    const bool bnd = (o & OWN_BOUNDARY) != 0;
-    S drho = S(0), jx = S(0), jy = S(0), jz = S(0);
-#pragma unroll
-    for (int i = 0; i < 19; i++) {
-        drho += g[i];
-        if (cx(i)) jx += cx(i) > 0 ? g[i] : -g[i];
-        if (cy(i)) jy += cy(i) > 0 ? g[i] : -g[i];
-        if (cz(i)) jz += cz(i) > 0 ? g[i] : -g[i];
-    }
     // solid neighbours (only boundary nodes have any), as a mask over i
     unsigned solid = 0;
-    if (bnd) {
+    if (o & OWN_BOUNDARY) {
 #pragma unroll
         for (int i = 1; i < 19; i++) {
             const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
             solid |= (ldb(own, (unsigned)m) & OWN_SOLID) ? (1u << i) : 0u;
         }
     }
-    // body force -psi grad(mu), isotropic lattice gradient
-    // grad(mu) = 3 sum_i w_i c_i mu(x + c_i), mu(x) at solid neighbours
-    S gx = S(0), gy = S(0), gz = S(0);
-#pragma unroll
-    for (int i = 1; i < 19; i++) {
-        const S mi = (solid & (1u << i)) ? m0 : mv[i];
-        const S wi = (S)(3.0 * wgt(i));
-        if (cx(i)) gx += cx(i) > 0 ? wi * mi : -wi * mi;
-        if (cy(i)) gy += cy(i) > 0 ? wi * mi : -wi * mi;
-        if (cz(i)) gz += cz(i) > 0 ? wi * mi : -wi * mi;
-    }
-    const S Fx = -ps * gx + (S)p.fx;
-    const S Fy = -ps * gy + (S)p.fy;
-    const S Fz = -ps * gz + (S)p.fz;
-    const S rho = (S)p.rho0 + drho;
-    const S ir = S(1) / rho;
-    const S ux = (jx + S(0.5) * Fx) * ir;
-    const S uy = (jy + S(0.5) * Fy) * ir;
-    const S uz = (jz + S(0.5) * Fz) * ir;
-    const S uu = ux * ux + uy * uy + uz * uz;
-    const S uF = ux * Fx + uy * Fy + uz * Fz;
+    const NodeMoments<S> M = collide_moments<S>(p, g, mv, m0, solid, ps);
     const S om = (S)(1.0 / p.tau);
     const S pref = (S)(1.0 - 0.5 / p.tau);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
-        const S w = (S)wgt(i);
-        const S cu = (S)cx(i) * ux + (S)cy(i) * uy + (S)cz(i) * uz;
-        const S cF = (S)cx(i) * Fx + (S)cy(i) * Fy + (S)cz(i) * Fz;
-        const S geq = w * (drho + rho * (S(3) * cu + S(4.5) * cu * cu - S(1.5) * uu));
-        const S gs = g[i] - om * (g[i] - geq) + pref * w * (S(3) * (cF - uF) + S(9) * cu * cF);
+        const S gs = collide_pop<S>(i, g[i], M, om, pref);
         if (i == 0) {
             stp(fout, on, gs, p.scale);
         } else {
@@ -341,9 +389,242 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
                 stp(fout + i * N, (unsigned)m * sizeof(T), gs, p.scale);
         }
     }
-    stb(uout, os, ux);
-    stb(uout + N, os, uy);
-    stb(uout + 2 * N, os, uz);
+    stb(uout, os, M.ux);
+    stb(uout + N, os, M.uy);
+    stb(uout + 2 * N, os, M.uz);
+}
+
+// V consecutive populations of one plane as S values (FP16 storage through
+// its 16-bit patterns, scaled as by ldp / stp) and back
+template <int V>
+__device__ __forceinline__ void ldpv(const double *b, unsigned off, float, double out[V])
+{
+    const SVec<double, V> w = ldb((const SVec<double, V> *)b, off);
+#pragma unroll
+    for (int k = 0; k < V; k++) out[k] = w.v[k];
+}
+template <int V>
+__device__ __forceinline__ void ldpv(const float *b, unsigned off, float, float out[V])
+{
+    const SVec<float, V> w = ldb((const SVec<float, V> *)b, off);
+#pragma unroll
+    for (int k = 0; k < V; k++) out[k] = w.v[k];
+}
+template <int V>
+__device__ __forceinline__ void ldpv(const __half *b, unsigned off, float inv, float out[V])
+{
+    const SVec<unsigned short, V> w = ldb((const SVec<unsigned short, V> *)b, off);
+#pragma unroll
+    for (int k = 0; k < V; k++) out[k] = __half2float(__ushort_as_half(w.v[k])) * inv;
+}
+template <int V>
+__device__ __forceinline__ void stpv(double *b, unsigned off, const double in[V], float)
+{
+    SVec<double, V> w;
+#pragma unroll
+    for (int k = 0; k < V; k++) w.v[k] = in[k];
+    stb((SVec<double, V> *)b, off, w);
+}
+template <int V>
+__device__ __forceinline__ void stpv(float *b, unsigned off, const float in[V], float)
+{
+    SVec<float, V> w;
+#pragma unroll
+    for (int k = 0; k < V; k++) w.v[k] = in[k];
+    stb((SVec<float, V> *)b, off, w);
+}
+template <int V>
+__device__ __forceinline__ void stpv(__half *b, unsigned off, const float in[V], float sc)
+{
+    SVec<unsigned short, V> w;
+#pragma unroll
+    for (int k = 0; k < V; k++) w.v[k] = __half_as_ushort(__float2half_rn(in[k] * sc));
+    stb((SVec<unsigned short, V> *)b, off, w);
+}
+
+// Row-vector form: a lane owns V consecutive x nodes and a group of lanes a
+// whole row (the host only selects it when nx / V <= 64).  Populations, the
+// nine mu rows of the stencil, psi and u move as V-wide accesses.  The push
+// is assembled at the destination: for direction i a lane writes the V slots
+// of its own x range in row (y + c_iy, z + c_iz), taking the value that
+// crosses in from a neighbour lane by a lane exchange, so every store is
+// aligned.  A slot is written only when its source node is fluid and does
+// not face a solid node along i (the slots the one-node form leaves alone
+// stay untouched); lanes with a particle node in reach store element by
+// element.  Results equal the one-node form bit for bit.
+template <int P, int V>
+__global__ __launch_bounds__(256) void k_collide_v(BatchArgs A)
+{
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::S S;
+    typedef typename OwnWord<V>::T OW;
+    const int *bst = A.bstart + (A.nbox + 1);
+    const int j = find_box(bst, A.nbox, blockIdx.x);
+    const BoxDesc &D = A.d[j];
+    KParams p = D.p;
+    p.ls = D.ls[1];
+    const T *__restrict__ fin = (const T *)D.b.fin;
+    T *__restrict__ fout = (T *)D.b.fout;
+    const S *__restrict__ psi = (const S *)D.b.psi;
+    const S *__restrict__ mu = (const S *)D.b.mu;
+    const uint8_t *__restrict__ own = D.b.own;
+    S *__restrict__ uout = (S *)D.b.u;
+    int x0, y, z, li, gb;
+    if (!vec_node<V>(p, blockIdx.x - bst[j], x0, y, z, li, gb)) return;
+    const int sy = p.nx, sz = p.nx * p.ny;
+    const int n0 = x0 + sy * y + sz * z;
+    const size_t N = (size_t)p.N;
+    const int yo[3] = {(wrap_m(y, p.ny) - y) * sy, 0, (wrap_p(y, p.ny) - y) * sy};
+    const int zo[3] = {(wrap_m(z, p.nz) - z) * sz, 0, (wrap_p(z, p.nz) - z) * sz};
+    const int Ls = p.ls.bx;
+    const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
+    const unsigned on = (unsigned)n0 * sizeof(T), os = (unsigned)n0 * sizeof(S);
+    // every load before anything depends on the owner bytes: owner word,
+    // populations, the nine mu rows (row r = 3 (dz + 1) + dy + 1), psi
+    const OW ow = ldb((const OW *)own, (unsigned)n0);
+    S g[V][19];
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        S t[V];
+        ldpv<V>(fin + i * N, on, p.inv_scale, t);
+#pragma unroll
+        for (int k = 0; k < V; k++) g[k][i] = t[k];
+    }
+    SVec<S, V> mr[9];
+#pragma unroll
+    for (int r = 0; r < 9; r++)
+        mr[r] = ldb((const SVec<S, V> *)mu, (unsigned)(n0 + yo[r % 3] + zo[r / 3]) * sizeof(S));
+    const SVec<S, V> pv = ldb((const SVec<S, V> *)psi, os);
+    // mu just left and right of the lane's range in the five rows that hold
+    // x links (dy = 0 or dz = 0)
+    S mxl[9], mxr[9];
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+        if (r % 3 != 1 && r / 3 != 1) continue;
+        mxl[r] = __shfl(mr[r].v[V - 1], srcl);
+        mxr[r] = __shfl(mr[r].v[0], srcr);
+    }
+    const unsigned owl = __shfl((unsigned)ow, srcl), owr = __shfl((unsigned)ow, srcr);
+    const unsigned bmask = (V == 4) ? 0x80808080u : 0x8080u;
+    const unsigned smask_all = (V == 4) ? 0x7f7f7f7fu : 0x7f7fu;
+    const bool bnd = ((unsigned)ow & bmask) != 0;
+    // owner words of the other eight rows, for boundary lanes only
+    unsigned orow[9];
+#pragma unroll
+    for (int r = 0; r < 9; r++) orow[r] = (unsigned)ow;
+    if (bnd) {
+#pragma unroll
+        for (int r = 0; r < 9; r++)
+            if (r != 4) orow[r] = ldb((const OW *)own, (unsigned)(n0 + yo[r % 3] + zo[r / 3]));
+    }
+    // per node: solid neighbours, mu with substitution, moments
+    NodeMoments<S> M[V];
+    unsigned smask[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        unsigned solid = 0;
+        if (byte_of(ow, k) & OWN_BOUNDARY) {
+#pragma unroll
+            for (int i = 1; i < 19; i++) {
+                const int r = 3 * (cz(i) + 1) + cy(i) + 1;
+                const int kk = k + cx(i);
+                uint8_t b;
+                if (kk >= 0 && kk < V) {
+                    b = byte_of(orow[r], kk);
+                } else if (r == 4) {
+                    b = kk < 0 ? byte_of(owl, V - 1) : byte_of(owr, 0);
+                } else {
+                    const int xe = kk < 0 ? (x0 == 0 ? p.nx - 1 : x0 - 1)
+                                          : (x0 + V == p.nx ? 0 : x0 + V);
+                    b = own[n0 - x0 + xe + yo[r % 3] + zo[r / 3]];
+                }
+                solid |= (b & OWN_SOLID) ? (1u << i) : 0u;
+            }
+        }
+        smask[k] = solid;
+        S mi[19];
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+            const int r = 3 * (cz(i) + 1) + cy(i) + 1;
+            const int kk = k + cx(i);
+            mi[i] = kk < 0 ? mxl[r] : (kk >= V ? mxr[r] : mr[r].v[kk]);
+        }
+        S gk[19];
+#pragma unroll
+        for (int i = 0; i < 19; i++) gk[i] = g[k][i];
+        M[k] = collide_moments<S>(p, gk, mi, mr[4].v[k], solid, pv.v[k]);
+    }
+    const S om = (S)(1.0 / p.tau);
+    const S pref = (S)(1.0 - 0.5 / p.tau);
+    // sources of this lane's slots: its own nodes and the two nodes next to
+    // its range; all fluid away from particles -> whole-vector stores
+    const uint8_t oL = byte_of(owl, V - 1), oR = byte_of(owr, 0);
+    const bool clean = (unsigned)ow == 0u && oL == 0 && oR == 0;
+    const unsigned smL = __shfl(smask[V - 1], srcl), smR = __shfl(smask[0], srcr);
+    // the direction loop is expanded at compile time: the unroller leaves
+    // loops with lane exchanges under direction-dependent branches rolled
+    static_for<19>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        S gs[V];
+#pragma unroll
+        for (int k = 0; k < V; k++) gs[k] = collide_pop<S>(i, g[k][i], M[k], om, pref);
+        // slot k of the destination range takes source k - cx(i)
+        S v[V];
+        if (cx(i) == 0) {
+#pragma unroll
+            for (int k = 0; k < V; k++) v[k] = gs[k];
+        } else if (cx(i) > 0) {
+            v[0] = __shfl(gs[V - 1], srcl);
+#pragma unroll
+            for (int k = 1; k < V; k++) v[k] = gs[k - 1];
+        } else {
+#pragma unroll
+            for (int k = 0; k < V - 1; k++) v[k] = gs[k + 1];
+            v[V - 1] = __shfl(gs[0], srcr);
+        }
+        const unsigned dst = (unsigned)(n0 + yo[cy(i) + 1] + zo[cz(i) + 1]) * sizeof(T);
+        if (clean) {
+            stpv<V>(fout + i * N, dst, v, p.scale);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                const int ks = k - cx(i);
+                const uint8_t so = ks < 0 ? oL : (ks >= V ? oR : byte_of(ow, ks));
+                const unsigned sm = ks < 0 ? smL : (ks >= V ? smR : smask[ks]);
+                if (!(so & OWN_SOLID) && !(sm & (1u << i)))
+                    stp(fout + i * N, dst + k * (unsigned)sizeof(T), v[k], p.scale);
+            }
+            // resting-wall bounce-back of this lane's boundary nodes
+            if (i > 0) {
+#pragma unroll
+                for (int k = 0; k < V; k++)
+                    if (smask[k] & (1u << i))
+                        stp(fout + opp(i) * N, on + k * (unsigned)sizeof(T), gs[k], p.scale);
+            }
+        }
+    });
+    // u at fluid nodes
+    if (!((unsigned)ow & smask_all)) {
+        SVec<S, V> w0, w1, w2;
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            w0.v[k] = M[k].ux;
+            w1.v[k] = M[k].uy;
+            w2.v[k] = M[k].uz;
+        }
+        stb((SVec<S, V> *)uout, os, w0);
+        stb((SVec<S, V> *)(uout + N), os, w1);
+        stb((SVec<S, V> *)(uout + 2 * N), os, w2);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            if (byte_of(ow, k) & OWN_SOLID) continue;
+            const unsigned ok = os + k * (unsigned)sizeof(S);
+            stb(uout, ok, M[k].ux);
+            stb(uout + N, ok, M[k].uy);
+            stb(uout + 2 * N, ok, M[k].uz);
+        }
+    }
 }
 
 // -------------------------------------------------------------- k_scalar
@@ -756,8 +1037,10 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
 // ------------------------------------------------ block reductions (FP64)
 // Fixed-shape reductions: wavefront butterfly, then the waves in order, so
 // results do not depend on scheduling.
+// Returns, in thread j < NV, the block total of component j (0 elsewhere);
+// each thread sums its component over the waves in order.
 template <int NV>
-__device__ void block_sum(double (&v)[NV], double *lds /* NV * nwaves */)
+__device__ double block_sum(double (&v)[NV], double *lds /* NV * nwaves */)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -771,14 +1054,13 @@ __device__ void block_sum(double (&v)[NV], double *lds /* NV * nwaves */)
     if (lane == 0)
         for (int j = 0; j < NV; j++) lds[wave * NV + j] = v[j];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int j = 0; j < NV; j++) {
-            double s = lds[j];
-            for (int w = 1; w < nw; w++) s += lds[w * NV + j];
-            v[j] = s;
-        }
+    double t = 0.0;
+    if ((int)threadIdx.x < NV) {
+        t = lds[threadIdx.x];
+        for (int w = 1; w < nw; w++) t += lds[w * NV + threadIdx.x];
     }
     __syncthreads();
+    return t;
 }
 
 __device__ __forceinline__ int node_of(const KParams &p, int n, int &x, int &y, int &z)
@@ -890,11 +1172,9 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         acc[27] += cap ? 1.0 : 0.0;
         }
     }
-    block_sum<28>(acc, lds);
-    if (threadIdx.x == 0) {
-        double *o = D.b.lpart + ((size_t)k * D.b.nlchunk_max + blockIdx.x) * 28;
-        for (int a = 0; a < 28; a++) o[a] = acc[a];
-    }
+    const double tot = block_sum<28>(acc, lds);
+    if (threadIdx.x < 28)
+        D.b.lpart[((size_t)k * D.b.nlchunk_max + blockIdx.x) * 28 + threadIdx.x] = tot;
 }
 
 // ------------------------------------------------------ k_colloid_update
@@ -1206,12 +1486,10 @@ __global__ __launch_bounds__(GCHUNK) void k_cover(BatchArgs A)
         }
     }
     const int any = __syncthreads_or(changed);
-    block_sum<6>(acc, lds);
-    if (threadIdx.x == 0) {
-        double *o = cpart + ((size_t)k * nchunk_max + c) * 8;
-        for (int a = 0; a < 6; a++) o[a] = acc[a];
-        o[6] = any ? 1.0 : 0.0;
-    }
+    const double tot = block_sum<6>(acc, lds);
+    if (threadIdx.x < 7)
+        cpart[((size_t)k * nchunk_max + c) * 8 + threadIdx.x] =
+            threadIdx.x < 6 ? tot : (any ? 1.0 : 0.0);
 }
 
 // ------------------------------------------------------------- k_commit
@@ -1454,9 +1732,8 @@ __global__ __launch_bounds__(256) void k_reduce(KParams p, const typename Prec<P
         v[5] += (double)cc[n];
         v[6] += 1.0;
     }
-    block_sum<7>(v, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < 7; j++) part[blockIdx.x * 7 + j] = v[j];
+    const double tot = block_sum<7>(v, lds);
+    if (threadIdx.x < 7) part[blockIdx.x * 7 + threadIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__ part, int nblocks,
@@ -1466,9 +1743,8 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
         for (int j = 0; j < 7; j++) v[j] += part[b * 7 + j];
-    block_sum<7>(v, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < 7; j++) out[j] = v[j];
+    const double tot = block_sum<7>(v, lds);
+    if (threadIdx.x < 7) out[threadIdx.x] = tot;
 }
 
 // ------------------------------------------------------------ k_fields
@@ -1504,12 +1780,12 @@ __global__ __launch_bounds__(256) void k_fields(KParams p, const typename Prec<P
 }
 
 // ------------------------------------------------------------ launchers
-void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize)
+void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize, bool whole_rows)
 {
     if (ls.vec > 1) {
         const int V = (ssize == 8 && ls.vec > 2) ? 2 : ls.vec;
         const int W = nx / V;
-        if ((V == 2 || V == 4) && nx % V == 0 && (W <= 64 || W % 64 == 0)) {
+        if ((V == 2 || V == 4) && nx % V == 0 && (W <= 64 || (W % 64 == 0 && !whole_rows))) {
             // row-vector launch: groups of Ls lanes per row segment, 64 / Ls
             // groups per wavefront, four wavefronts per block
             ls.vec = V;
@@ -1606,7 +1882,9 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
-    k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    if (B.vec[1] == 4) k_collide_v<P, V4><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    else if (B.vec[1] == 2) k_collide_v<P, 2><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    else k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
     if (par) {

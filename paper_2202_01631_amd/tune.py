@@ -52,14 +52,13 @@ def is_vec(cand):
 
 def launch_for(cand):
     """(shapes of the three kernels, which kernels' times count) for a
-    candidate: one-node shapes go to all three kernels; row-vector shapes to
-    the mu and psi/c updates (collide keeps its default); z-marching shapes
-    to the psi/c update only (mu takes the same row-vector form)."""
-    if not is_vec(cand):
-        return [cand, cand, cand], (True, True, True)
+    candidate: one-node and row-vector shapes go to all three kernels (the
+    collide-stream keeps its one-node form where a row does not fit one lane
+    group; its time then does not count); z-marching shapes to the psi/c
+    update only (mu takes the same row-vector form, collide its default)."""
     if cand[2] >= 64:
         return [(0, 0, cand[2] & 63), (0, 0, 0), cand], (False, False, True)
-    return [cand, (0, 0, 0), cand], (True, False, True)
+    return [cand, cand, cand], (True, True, True)
 
 
 def device_key():
@@ -126,6 +125,8 @@ def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log
     for cand in candidates(shape[0], shape[1]):
         shapes, scored = launch_for(cand)
         box.set_launch_shapes(shapes)
+        if is_vec(cand) and not is_vec(box.launch_shapes()[1]):
+            scored = (scored[0], False, scored[2])
         box.step(warmup)
         torch.cuda.synchronize()
         box.timing_enable(True)

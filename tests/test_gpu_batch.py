@@ -97,6 +97,9 @@ def test_batched_fp64_matches_oracle():
     [(0, 0, 32), (32, 8, 0), (0, 0, 32 + 64 * 8)],   # z-marching, 8 planes
     [(0, 0, 16), (32, 8, 0), (0, 0, 16 + 64 * 5)],   # 5 planes: ragged last chunk
     [(0, 0, 16), (32, 8, 0), (0, 0, 34 + 64 * 40)],  # one chunk (zc > nz), remap dropped
+    [(32, 8, 0), (0, 0, 32), (32, 8, 0)],      # row-vector collide-stream, 4 nodes per lane
+    [(0, 0, 16), (0, 0, 16), (0, 0, 18)],      # row-vector collide-stream, 2 nodes per lane
+    [(0, 0, 32), (0, 0, 34), (0, 0, 34)],
 ])
 def test_launch_shapes_do_not_change_results(shapes):
     w = I.workload_small()
@@ -104,6 +107,9 @@ def test_launch_shapes_do_not_change_results(shapes):
     ref.set_launch_shapes([(32, 8, 0)] * 3)
     alt = lb.from_spec(w, precision="fp32")
     alt.set_launch_shapes(shapes)
+    eff = alt.launch_shapes()
+    for k in range(3):
+        assert (eff[k][2] >= 16) == (shapes[k][2] >= 16), eff
     ref.step(15)
     alt.step(15)
     assert _same(_state(ref), _state(alt))
@@ -123,12 +129,15 @@ def test_row_vector_forms_long_rows(precision):
                 psi=psi, c=np.zeros(psi.size), colloids=cols)
     ref = lb.from_spec(spec, precision=precision)
     ref.set_launch_shapes([(64, 4, 0)] * 3)
-    for code in (16, 32, 18, 16 + 64 * 3, 32 + 64 * 8):
+    for code in (16, 32, 18, 34, 16 + 64 * 3, 32 + 64 * 8):
+        # the collide-stream takes the row-vector form only where a row fits
+        # one lane group: 4 nodes per lane in FP32 and FP16 storage
         alt = lb.from_spec(spec, precision=precision)
-        alt.set_launch_shapes([(0, 0, code & 63), (64, 4, 0), (0, 0, code)])
+        alt.set_launch_shapes([(0, 0, code & 63), (0, 0, code & 63), (0, 0, code)])
         eff = alt.launch_shapes()
         flush_print("[vec] %s code %d effective %s" % (precision, code, eff))
         assert eff[0][2] >= 16 and eff[2][2] >= 16
+        assert (eff[1][2] >= 16) == ((code & 63) >= 32 and precision != "fp64")
         alt.step(12)
         if code == 16:
             ref.step(12)
@@ -144,14 +153,17 @@ def test_row_vector_forms_long_rows(precision):
 def test_row_vector_fallback_shapes():
     # nx % vec != 0, or rows of 80 lanes (neither <= 64 nor a multiple of 64):
     # the box takes the one-node form, with identical results
-    for shape, code in (((30, 16, 16), 32), ((320, 8, 8), 16)):
+    # (the collide-stream also falls back for rows of 128 lanes)
+    for shape, code, fb in (((30, 16, 16), 32, (0, 1, 2)), ((320, 8, 8), 16, (0, 1, 2)),
+                            ((256, 8, 8), 16, (1,))):
         psi = I.flat_interface(shape, shape[2] / 2.0, I.WIDTH, 0.02, seed=4)
         spec = dict(shape=shape, precision="fp32", params=dict(I.FREE_ENERGY), solubility_ratio=2.0,
                     psi=psi, c=np.zeros(psi.size), colloids=[])
         a = lb.from_spec(spec)
-        a.set_launch_shapes([(0, 0, code), (0, 0, 0), (0, 0, code)])
+        a.set_launch_shapes([(0, 0, code)] * 3)
         eff = a.launch_shapes()
-        assert eff[0][2] < 8 and eff[2][2] < 8, eff
+        for k in range(3):
+            assert (eff[k][2] < 8) == (k in fb), eff
         b = lb.from_spec(spec)
         b.set_launch_shapes([(0, 0, 0)] * 3)
         a.step(5)
@@ -160,7 +172,7 @@ def test_row_vector_fallback_shapes():
     with pytest.raises(lb.LBError):
         a.set_launch_shapes([(0, 0, 24), (0, 0, 0), (0, 0, 0)])  # vec 3
     with pytest.raises(lb.LBError):
-        a.set_launch_shapes([(0, 0, 0), (0, 0, 32), (0, 0, 0)])  # collide has no row-vector form
+        a.set_launch_shapes([(0, 0, 0), (0, 0, 32 + 64 * 4), (0, 0, 0)])  # marching: psi/c only
     with pytest.raises(lb.LBError):
         a.set_launch_shapes([(0, 0, 3), (0, 0, 0), (0, 0, 0)])   # remap 3
     with pytest.raises(lb.LBError):
@@ -176,12 +188,32 @@ def test_batched_mixed_vec_equals_alone():
     specs = _boxes(n=3, seed=21)
     stream = torch.cuda.Stream()
     batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
-    batch[0].set_launch_shapes([(32, 8, 0), (0, 0, 0), (0, 0, 16)])
-    batch[1].set_launch_shapes([(0, 0, 32), (0, 0, 0), (0, 0, 32 + 64 * 4)])
+    batch[0].set_launch_shapes([(32, 8, 0), (0, 0, 32), (0, 0, 16)])
+    batch[1].set_launch_shapes([(0, 0, 32), (0, 0, 16), (0, 0, 32 + 64 * 4)])
     alone = [lb.from_spec(s, precision="fp32") for s in specs]
     lb.batch_step(batch, 6)
     for b in alone:
         b.step(6)
+    for b, a in zip(batch, alone):
+        assert _same(_state(b), _state(a))
+
+
+def test_batched_row_vector_collide_equals_alone():
+    # every box of a batch in the row-vector collide-stream (different lane
+    # group sizes per box side), the boxes alone in the one-node form
+    import torch
+    specs = _boxes(n=4, seed=45)
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s, precision="fp16", stream=stream) for s in specs]
+    for b in batch:
+        b.set_launch_shapes([(0, 0, 32), (0, 0, 32), (0, 0, 34)])
+        assert b.launch_shapes()[1][2] >= 32
+    alone = [lb.from_spec(s, precision="fp16") for s in specs]
+    for b in alone:
+        b.set_launch_shapes([(0, 0, 0)] * 3)
+    lb.batch_step(batch, 9)
+    for b in alone:
+        b.step(9)
     for b, a in zip(batch, alone):
         assert _same(_state(b), _state(a))
 

@@ -27,10 +27,13 @@ def test_tuner_candidates_are_valid_codes(nx, ny):
             assert 1 <= bx <= 256 and bx * by <= 256 and zc == 0
         shapes, scored = tune.launch_for((bx, by, code))
         assert len(shapes) == 3
-        # collide never gets a row-vector or marching code, mu never a marching one
-        assert _decode(shapes[1][2])[1] == 0 and _decode(shapes[0][2])[2] == 0
+        # only the psi/c update marches in z
+        assert _decode(shapes[0][2])[2] == 0 and _decode(shapes[1][2])[2] == 0
         if zc:
             assert scored == (False, False, True)
+            assert shapes[1] == (0, 0, 0)
+        else:
+            assert shapes == [(bx, by, code)] * 3 and scored == (True, True, True)
 
 
 def test_tuning_cache_entries_decode():
@@ -47,7 +50,6 @@ def test_tuning_cache_entries_decode():
             rm, vec, zc = _decode(code)
             assert rm <= 2 and vec in (0, 1, 2, 4)
             assert k == 2 or zc == 0
-            assert k != 1 or vec in (0, 1)
 
 
 def test_serving_request_bytes_cover_the_arena():
