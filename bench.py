@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
-    ap.add_argument("--batch", type=int, default=64, help="boxes in the batched sweep (0: skip)")
+    ap.add_argument("--batch", type=int, default=512, help="boxes in the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving run (0: skip)")
     ap.add_argument("--serve-scale", type=float, default=0.02,

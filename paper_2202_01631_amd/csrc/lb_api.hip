@@ -506,7 +506,7 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     c->N = (long long)p->nx * p->ny * p->nz;
     KParams &k = c->kp;
     k.nx = p->nx; k.ny = p->ny; k.nz = p->nz; k.N = (int)c->N;
-    k.rho0 = p->rho0; k.tau = p->tau; k.a = p->a; k.b = p->b; k.kappa = p->kappa;
+    k.rho0 = p->rho0; k.tau = p->tau; k.om = 1.0 / p->tau; k.pref = 1.0 - 0.5 / p->tau; k.a = p->a; k.b = p->b; k.kappa = p->kappa;
     k.M = p->M_psi; k.C = p->C; k.E = p->E; k.cb0 = p->c_b0; k.D = p->D_c; k.kd = p->k_d;
     k.fx = p->ext_force[0]; k.fy = p->ext_force[1]; k.fz = p->ext_force[2];
     k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;

@@ -107,6 +107,7 @@ struct KParams {
     int nx, ny, nz, N;         // N = nx*ny*nz < 2^31
     LaunchShape ls;            // shape of the current lattice launch
     double rho0, tau, a, b, kappa, M, C, E, cb0, D, kd;
+    double om, pref;           // 1/tau and 1 - 1/(2 tau), formed once on the host
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
 };

@@ -285,14 +285,21 @@ __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, cons
         if (cz(i)) jz = cz(i) > 0 ? jz + g[i] : jz - g[i];
     }
     // grad(mu) = 3 sum_i w_i c_i mu(x + c_i)
+    S mi[19];
+#pragma unroll
+    for (int i = 1; i < 19; i++) mi[i] = mv[i];
+    if (solid) {
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            if (solid & (1u << i)) mi[i] = m0;
+    }
     S gx = S(0), gy = S(0), gz = S(0);
 #pragma unroll
     for (int i = 1; i < 19; i++) {
         const S wi = (S)(3.0 * wgt(i));
-        const S mi = (solid & (1u << i)) ? m0 : mv[i];
-        if (cx(i)) gx = fma(cx(i) > 0 ? wi : -wi, mi, gx);
-        if (cy(i)) gy = fma(cy(i) > 0 ? wi : -wi, mi, gy);
-        if (cz(i)) gz = fma(cz(i) > 0 ? wi : -wi, mi, gz);
+        if (cx(i)) gx = fma(cx(i) > 0 ? wi : -wi, mi[i], gx);
+        if (cy(i)) gy = fma(cy(i) > 0 ? wi : -wi, mi[i], gy);
+        if (cz(i)) gz = fma(cz(i) > 0 ? wi : -wi, mi[i], gz);
     }
     m.Fx = fma(-ps, gx, (S)p.fx);
     m.Fy = fma(-ps, gy, (S)p.fy);
@@ -313,11 +320,26 @@ template <class S>
 __device__ __forceinline__ S collide_pop(int i, S gi, const NodeMoments<S> &m, S om, S pref)
 {
 #pragma clang fp contract(off)
-    // c_i.u and c_i.F as signed sums (the components of c_i are 0 or +-1)
+    // c_i.u and c_i.F as signed sums (the components of c_i are 0 or +-1),
+    // starting from the first nonzero component
     S cu = S(0), cF = S(0);
-    if (cx(i)) { cu = cx(i) > 0 ? m.ux : -m.ux; cF = cx(i) > 0 ? m.Fx : -m.Fx; }
-    if (cy(i)) { cu = cy(i) > 0 ? cu + m.uy : cu - m.uy; cF = cy(i) > 0 ? cF + m.Fy : cF - m.Fy; }
-    if (cz(i)) { cu = cz(i) > 0 ? cu + m.uz : cu - m.uz; cF = cz(i) > 0 ? cF + m.Fz : cF - m.Fz; }
+    bool any = false;
+    if (cx(i)) {
+        cu = cx(i) > 0 ? m.ux : -m.ux;
+        cF = cx(i) > 0 ? m.Fx : -m.Fx;
+        any = true;
+    }
+    if (cy(i)) {
+        const S a = cy(i) > 0 ? m.uy : -m.uy, b = cy(i) > 0 ? m.Fy : -m.Fy;
+        cu = any ? cu + a : a;
+        cF = any ? cF + b : b;
+        any = true;
+    }
+    if (cz(i)) {
+        const S a = cz(i) > 0 ? m.uz : -m.uz, b = cz(i) > 0 ? m.Fz : -m.Fz;
+        cu = any ? cu + a : a;
+        cF = any ? cF + b : b;
+    }
     const S w = (S)wgt(i);
     const S q = fma(S(4.5) * cu, cu, fma(S(3), cu, S(-1.5) * m.uu));
     const S geq = w * fma(m.rho, q, m.drho);
@@ -374,14 +396,20 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
         }
     }
     const NodeMoments<S> M = collide_moments<S>(p, g, mv, m0, solid, ps);
-    const S om = (S)(1.0 / p.tau);
-    const S pref = (S)(1.0 - 0.5 / p.tau);
+    const S om = (S)p.om;
+    const S pref = (S)p.pref;
+    // nodes without solid neighbours store along a straight line (FP64
+    // keeps the per-direction test: faster there, measured)
+    if (sizeof(T) != sizeof(double) && !solid) {
 #pragma unroll
-    for (int i = 0; i < 19; i++) {
-        const S gs = collide_pop<S>(i, g[i], M, om, pref);
-        if (i == 0) {
-            stp(fout, on, gs, p.scale);
-        } else {
+        for (int i = 0; i < 19; i++) {
+            const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
+            stp(fout + i * N, (unsigned)m * sizeof(T), collide_pop<S>(i, g[i], M, om, pref), p.scale);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 19; i++) {
+            const S gs = collide_pop<S>(i, g[i], M, om, pref);
             const int m = n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
             if (solid & (1u << i))
                 stp(fout + opp(i) * N, on, gs, p.scale);
@@ -554,8 +582,8 @@ __global__ __launch_bounds__(256) void k_collide_v(BatchArgs A)
         for (int i = 0; i < 19; i++) gk[i] = g[k][i];
         M[k] = collide_moments<S>(p, gk, mi, mr[4].v[k], solid, pv.v[k]);
     }
-    const S om = (S)(1.0 / p.tau);
-    const S pref = (S)(1.0 - 0.5 / p.tau);
+    const S om = (S)p.om;
+    const S pref = (S)p.pref;
     // sources of this lane's slots: its own nodes and the two nodes next to
     // its range; all fluid away from particles -> whole-vector stores
     const uint8_t oL = byte_of(owl, V - 1), oR = byte_of(owr, 0);
