@@ -295,9 +295,9 @@ static const SideStream *side_of(lb_ctx *c)
         SideStream v;
         if (hipStreamCreateWithFlags(&v.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
         int i = 0;
-        for (; i < 4; i++)
+        for (; i < SIDE_EVENTS; i++)
             if (hipEventCreateWithFlags(&v.ev[i], hipEventDisableTiming) != hipSuccess) break;
-        if (i < 4) {
+        if (i < SIDE_EVENTS) {
             while (i > 0) hipEventDestroy(v.ev[--i]);
             hipStreamDestroy(v.s);
             return nullptr;
@@ -308,24 +308,26 @@ static const SideStream *side_of(lb_ctx *c)
     return &c->side;
 }
 
-static void launch_one_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm)
+static void launch_one_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm,
+                            bool defer_links = false)
 {
     switch (B.precision) {
-    case LB_FP64: launch_step<LB_FP64>(B, s, side, tm); break;
-    case LB_FP32: launch_step<LB_FP32>(B, s, side, tm); break;
-    default: launch_step<LB_FP16_STORAGE>(B, s, side, tm); break;
+    case LB_FP64: launch_step<LB_FP64>(B, s, side, tm, defer_links); break;
+    case LB_FP32: launch_step<LB_FP32>(B, s, side, tm, defer_links); break;
+    default: launch_step<LB_FP16_STORAGE>(B, s, side, tm, defer_links); break;
     }
 }
 
-// capture the step pair (B0 then B1) on stream s into an executable graph
+// capture the step pair (B0 then B1) on stream s into an executable graph;
+// the first step's link table write overlaps the second step's mu update
 static hipError_t capture_pair(const Batch &B0, const Batch &B1, hipStream_t s,
                                const SideStream *side, hipGraphExec_t *out)
 {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return e;
-    launch_one_step(B0, s, side, nullptr);
-    launch_one_step(B1, s, side, nullptr);
+    launch_one_step(B0, s, side, nullptr, true);
+    launch_one_step(B1, s, side, nullptr, false);
     e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return e;
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -579,7 +581,7 @@ lb_status lb_destroy(lb_ctx *c)
     if (c->dsum) hipFree(c->dsum);
     if (c->has_side) {
         hipStreamSynchronize(c->side.s);
-        for (int i = 0; i < 4; i++) hipEventDestroy(c->side.ev[i]);
+        for (int i = 0; i < SIDE_EVENTS; i++) hipEventDestroy(c->side.ev[i]);
         hipStreamDestroy(c->side.s);
     }
     delete c->timing;

@@ -83,17 +83,22 @@ struct TimingHook {
 // thread
 void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize, bool whole_rows = false);
 
-// Second stream for the particle work of a step, with the events of its two
+// Second stream for the particle work of a step, with the events of its
 // forks and joins.
+constexpr int SIDE_EVENTS = 5;
 struct SideStream {
     hipStream_t s;
-    hipEvent_t ev[4];
+    hipEvent_t ev[SIDE_EVENTS];
 };
 
 // one time step of every box of the batch (all boxes share the precision P);
-// side may be null (everything in order on s)
+// side may be null (everything in order on s).  defer_links: the link table
+// write of the step's tail may stay on the side stream, unjoined; the caller
+// guarantees that another step follows on s (its side-stream work is ordered
+// after it and joined before its collide-stream).
 template <int P>
-void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm);
+void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm,
+                 bool defer_links = false);
 // particle geometry at placement (owner map, boundary bits, link tables)
 void launch_geometry(const Batch &B, hipStream_t s);
 

@@ -1861,12 +1861,15 @@ void finish_shape(LaunchShape &ls, int nx, int ny, int nz, int ssize, bool whole
     }
 }
 
-static void launch_geometry_tail(const Batch &B, hipStream_t s)
+// The link table write goes to stream sw (the next step's bulk mu and
+// collide-stream kernels read owner bytes and boundary bits, which
+// k_link_count finishes, but not the table).
+static void launch_geometry_tail(const Batch &B, hipStream_t s, hipStream_t sw)
 {
     const dim3 g(B.nchunk_max, B.ncol);
     k_commit<<<g, GCHUNK, 0, s>>>(B.args);
     k_link_count<<<g, GCHUNK, 0, s>>>(B.args);
-    k_link_write<<<g, GCHUNK, 0, s>>>(B.args);
+    k_link_write<<<g, GCHUNK, 0, sw>>>(B.args);
 }
 
 // One step.  With a side stream (and particles, no per-kernel timing, and
@@ -1881,7 +1884,8 @@ static void launch_geometry_tail(const Batch &B, hipStream_t s)
 constexpr long long SIDE_MIN_NODES = 1LL << 22;
 
 template <int P>
-void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm)
+void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHook *tm,
+                 bool defer_links)
 {
     typedef typename Prec<P>::S S;
     constexpr int V4 = sizeof(S) == 4 ? 4 : 2;  // FP64 scalars: 2 per 16-byte access
@@ -1952,7 +1956,19 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     k_cover<P><<<dim3(B.nchunk_max, B.ncol), GCHUNK, 0, s>>>(B.args);
     if (tm) tm->end(4, s);
     if (tm) tm->begin(5, s);
-    launch_geometry_tail(B, s);
+    if (par && defer_links) {
+        // the link table write of this step runs beside the next step's bulk
+        // mu update; the next step's side work is ordered after it and
+        // joined before its collide-stream, ahead of the link pass
+        const dim3 g(B.nchunk_max, B.ncol);
+        k_commit<<<g, GCHUNK, 0, s>>>(B.args);
+        k_link_count<<<g, GCHUNK, 0, s>>>(B.args);
+        hipEventRecord(side->ev[4], s);
+        hipStreamWaitEvent(ss, side->ev[4], 0);
+        k_link_write<<<g, GCHUNK, 0, ss>>>(B.args);
+    } else {
+        launch_geometry_tail(B, s, s);
+    }
     if (tm) tm->end(5, s);
 }
 
@@ -1973,7 +1989,7 @@ void launch_geometry(const Batch &B, hipStream_t s)
 {
     if (B.ncol <= 0) return;
     k_mark_placed<<<B.ncol, 64, 0, s>>>(B.args);
-    launch_geometry_tail(B, s);
+    launch_geometry_tail(B, s, s);
 }
 
 template <int P>
@@ -2006,7 +2022,8 @@ void launch_fields(const KParams &p, const void *f, const void *psi, const void 
 }
 
 #define LB_INSTANTIATE(P)                                                                          \
-    template void launch_step<P>(const Batch &, hipStream_t, const SideStream *, TimingHook *);                          \
+    template void launch_step<P>(const Batch &, hipStream_t, const SideStream *, TimingHook *,      \
+                                 bool);                                                             \
     template void launch_init<P>(const KParams &, const double *, const double *, const double *,   \
                                  const double *, void *, void *, void *, uint8_t *, hipStream_t);   \
     template void launch_reduce<P>(const KParams &, const void *, const void *, const void *,       \
