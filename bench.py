@@ -87,7 +87,8 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     per_kernel = {KERNELS[i]: (kms[i] / calls[i] if calls[i] else None) for i in range(6)}
     return dict(ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6,
                 kernel_ms=per_kernel, kernel_steps=ksteps, error_bits=tot["error_bits"], N=N,
-                reps_ms_per_step=[round(v, 5) for v in reps])
+                reps_ms_per_step=[round(v, 5) for v in reps],
+                median_ms_per_step=round(float(sorted(reps)[len(reps) // 2]), 5))
 
 
 def copy_ceiling(torch):
@@ -276,6 +277,7 @@ def main():
                      "traffic_frac_of_copy": (round(traffic / (kc * 1e-3) / 1e9 / copy_gbs, 4)
                                               if traffic else None)},
         "reps_ms_per_step": r["reps_ms_per_step"],
+        "median_ms_per_step": r["median_ms_per_step"],
         "step_roofline": {p: {"mlups": round(v["mlups"], 1),
                               "algorithmic_GBs": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9, 1),
                               "frac": round(v["mlups"] * 1e6 * STEP_BYTES[p] / 1e9 / HBM_PEAK_GBS, 4),

@@ -218,6 +218,34 @@ def test_batched_row_vector_collide_equals_alone():
         assert _same(_state(b), _state(a))
 
 
+def test_full_batch_512_equals_alone():
+    # the full 512-box sweep (sides 32/48/64, one sphere each) in the form
+    # bench.py times (tuned shapes, one batched graph pair per two steps)
+    # against every box stepped alone: psi, c, owner map and link table of
+    # every box, populations of every 16th box, bit for bit
+    import torch
+    from paper_2202_01631_amd import tune
+    specs = I.batch_boxes(count=512, steps=4)
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+    for b in batch:
+        tune.apply(b)
+    flush_print("[batch512] batched steps")
+    lb.batch_step(batch, 4)
+    torch.cuda.synchronize()
+    for j, s in enumerate(specs):
+        a = lb.from_spec(s, precision="fp32")
+        a.step(4)
+        b = batch[j]
+        fa, fb = a.fields(), b.fields()
+        assert np.array_equal(fa["psi"], fb["psi"]) and np.array_equal(fa["c"], fb["c"]), j
+        assert np.array_equal(a.owner(), b.owner()) and np.array_equal(a.links(), b.links()), j
+        if j % 16 == 0:
+            assert np.array_equal(a.populations(), b.populations()), j
+        a.close()
+        b.close()
+
+
 def test_batched_zmarch_equals_alone():
     # all boxes of a batch marching in z (different chunk lengths per box)
     import torch

@@ -266,26 +266,29 @@ def test_error_paths():
 
 
 # ------------------------------------------------------ full benchmark size
-def test_full_size_256_one_step():
+def test_full_size_256_step_pair():
     # the benchmark workload itself (256^3, 64 moving Janus spheres), in the
-    # launch configuration bench.py times (tuned shapes): owner map and link
-    # table bit-exact at placement and after one step, FP64 fields within
-    # 1e-12 of the oracle after one step, FP32 within 2e-5
+    # launch configuration bench.py times: tuned shapes, a non-default
+    # stream, so the two steps run as one replay of the captured step-pair
+    # graph with the particle work on the side stream.  Owner map and link
+    # table bit-exact at placement and after the pair, FP64 fields within
+    # 1e-12 of the oracle after two steps, FP32 within 2e-5
+    import torch
     from paper_2202_01631_amd import tune
     w = I.workload_many(n=256, count=64, radius=6.0, precision="fp32")
     flush_print("[full] oracle setup 256^3")
     o = oracle.from_spec(w)
     for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
         flush_print("[full] gpu", prec)
-        g = lb.from_spec(w, precision=prec)
+        g = lb.from_spec(w, precision=prec, stream=torch.cuda.Stream())
         tune.apply(g)
         if prec == "fp64":
             assert np.array_equal(g.owner(), o.owner())
             assert np.array_equal(g.links(), o.links())
-        g.step(1)
+        g.step(2)
         if prec == "fp64":
-            flush_print("[full] oracle step")
-            o.step(1)
+            flush_print("[full] oracle steps")
+            o.step(2)
             oown = o.owner()
             olinks = o.links()
             ofields = o.fields()
@@ -296,6 +299,32 @@ def test_full_size_256_one_step():
         assert max(e.values()) <= tol
         t, _ = g.observables()
         assert t["error_bits"] == 0
+        g.close()
+
+
+def test_single_sphere_128_workload():
+    # the 128^3 one-sphere workload in its production launch configuration
+    # (tuned or default shapes, non-default stream: replays of the captured
+    # step-pair graph; below the side-stream size the boundary nodes stay in
+    # the bulk kernels): FP64 within 1e-12 of the oracle after 6 steps, FP32
+    # within 2e-5, owner map and link table bit-exact
+    import torch
+    from paper_2202_01631_amd import tune
+    w = I.workload_single(n=128)
+    o = oracle.from_spec(w)
+    flush_print("[single] oracle 6 steps at 128^3")
+    o.step(6)
+    oown, olinks, ofields = o.owner(), o.links(), o.fields()
+    o.close()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        g = lb.from_spec(w, precision=prec, stream=torch.cuda.Stream())
+        tune.apply(g)
+        g.step(6)
+        assert np.array_equal(g.owner(), oown)
+        assert np.array_equal(g.links(), olinks)
+        e = field_errors(g.fields(), ofields, oown < 0)
+        flush_print("[single] %s errors %s" % (prec, e))
+        assert max(e.values()) <= tol
         g.close()
 
 
