@@ -200,9 +200,10 @@ def main():
     ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
     ap.add_argument("--batch", type=int, default=512, help="boxes in the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--serve", type=int, default=24, help="requests in the serving run (0: skip)")
-    ap.add_argument("--serve-scale", type=float, default=0.02,
-                    help="request length scale of the serving run")
+    ap.add_argument("--serve", type=int, default=100, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.25,
+                    help="request length scale of the serving run (at 0.25 the offered load "
+                         "at 50 requests/s is ~45k MLUPS, above one GPU's capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (torch) five times, for "
                          "scaling the HBM byte counters against a kernel of known traffic")
@@ -295,7 +296,8 @@ def main():
         out["serving"] = serving_run(torch, I, args.serve, 50.0, args.serve_scale)
         log("[bench] serving %s" % out["serving"])
         # below capacity: 5 requests/s
-        out["serving_low_rate"] = serving_run(torch, I, max(1, args.serve // 2), 5.0, args.serve_scale)
+        out["serving_low_rate"] = serving_run(torch, I, max(1, min(12, args.serve)), 5.0,
+                                              args.serve_scale)
         log("[bench] serving at 5/s %s" % out["serving_low_rate"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec)
