@@ -328,6 +328,54 @@ def test_single_sphere_128_workload():
         g.close()
 
 
+# ------------------------------------------------------- largest box
+def test_largest_fp32_box_equals_its_tile():
+    # The largest FP32 box the library accepts (one scalar field just below
+    # 4 GiB, the limit of its 32-bit byte offsets): 1024 x 1024 x 1023 nodes,
+    # built as 32 x 32 x 33 periodic copies of a 32 x 32 x 31 box without
+    # particles.  Every node sees the same neighbourhood as its image in the
+    # small box, so after one graph-replayed step pair the fields must equal
+    # the small box's, tiled, bit for bit (the small box itself is checked
+    # against the oracle in the tests above).
+    import torch
+    tile, reps = (32, 32, 31), (32, 32, 33)
+    shape = tuple(t * r for t, r in zip(tile, reps))
+    n_tile = int(np.prod(tile))
+    psi = I.slab(tile, I.WIDTH, amp=0.05, seed=17)
+    c = 0.3 + I.noise(18, n_tile, 0.05)
+    p = dict(I.FREE_ENERGY)
+    small = dict(shape=tile, precision="fp32", params=p, solubility_ratio=2.0, psi=psi, c=c,
+                 colloids=[])
+    a = lb.from_spec(small, precision="fp32", stream=torch.cuda.Stream())
+    a.step(2)
+    fa = a.fields()
+    a.close()
+    t3 = (tile[2], tile[1], tile[0])
+    r3 = (reps[2], reps[1], reps[0])
+
+    def tiled(v):
+        return np.tile(v.reshape(t3), r3).ravel()
+
+    flush_print("[largest] building %s inputs" % (shape,))
+    big = dict(shape=shape, precision="fp32", params=p, solubility_ratio=2.0, psi=tiled(psi),
+               c=tiled(c), colloids=[])
+    b = lb.from_spec(big, precision="fp32", stream=torch.cuda.Stream())
+    del big
+    flush_print("[largest] stepping")
+    b.step(2)
+    flush_print("[largest] reading back")
+    fb = b.fields()
+    b.close()
+    six = (reps[2], tile[2], reps[1], tile[1], reps[0], tile[0])
+    one = (1, tile[2], 1, tile[1], 1, tile[0])
+    for name, vb, va in (("rho", fb["rho"], fa["rho"]), ("psi", fb["psi"], fa["psi"]),
+                         ("c", fb["c"], fa["c"]), ("ux", fb["u"][0], fa["u"][0]),
+                         ("uy", fb["u"][1], fa["u"][1]), ("uz", fb["u"][2], fa["u"][2])):
+        same = bool((vb.reshape(six) == va.reshape(one)).all())
+        flush_print("[largest] %s %s" % (name, "equal" if same else "DIFFERS"))
+        assert same, name
+
+
 # ------------------------------------------------- owner-byte capacity
 def test_fp64_127_particles_owner_byte_limit():
     # the owner byte holds k + 1 in 7 bits: 127 particles is the maximum.
