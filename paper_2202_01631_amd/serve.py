@@ -6,8 +6,11 @@ advances all of them together: between chunks of steps it admits new
 arrivals as slots and HBM budget free up (admission by ``lb_footprint_bytes``
 plus the particle tables), groups the live requests by storage precision,
 and advances each group with one batched launch per kernel
-(``lb_batch_step``).  A request whose steps are done is read back (FP64
-totals and particle states) and its memory released at once.
+(``lb_batch_step``).  Groups given streams of their own run concurrently
+(one host thread per group; the library releases the interpreter lock), so
+one group's particle work overlaps the other's lattice kernels.  A request
+whose steps are done is read back (FP64 totals and particle states) and its
+memory released at once.
 
 Time-to-result = completion time - arrival time.  Each result is identical
 to the same request run alone (the batched step is bitwise equal to the
@@ -16,6 +19,7 @@ single-box step).
 import heapq
 import math
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 from . import inputs as I
 from . import lb
@@ -37,11 +41,13 @@ def request_bytes(spec):
 
 
 class Server:
-    """One GPU, one stream; ``budget_bytes`` caps the resident state,
-    ``max_slots`` the number of live requests, ``chunk`` the steps taken
-    between admission points."""
+    """One GPU; ``budget_bytes`` caps the resident state, ``max_slots`` the
+    number of live requests, ``chunk`` the steps taken between admission
+    points.  Boxes of precision p live on ``streams[p]`` if given, else on
+    ``stream``; precision groups on distinct streams advance concurrently."""
 
-    def __init__(self, budget_bytes, max_slots=256, chunk=200, stream=None, collect=None):
+    def __init__(self, budget_bytes, max_slots=256, chunk=200, stream=None, collect=None,
+                 streams=None):
         self.collect = collect  # optional box -> dict, read on retirement
         self.peak_used = 0
         self.peak_live = 0
@@ -49,6 +55,8 @@ class Server:
         self.max_slots = max_slots
         self.chunk = chunk
         self.stream = stream
+        self.streams = dict(streams or {})
+        self.pool = None
         self.used = 0
         self.live = []        # dicts: id, box, spec, remaining, arrival, bytes
         self.queue = []       # (arrival, seq, id, spec) waiting for admission
@@ -72,7 +80,7 @@ class Server:
             if self.used + need > self.budget:
                 break  # wait for memory to free up (first come, first served)
             heapq.heappop(self.queue)
-            box = lb.from_spec(spec, stream=self.stream,
+            box = lb.from_spec(spec, stream=self._stream_of(spec["precision"]),
                                max_colloids=max(1, len(spec.get("colloids", []))))
             self.used += need
             self.peak_used = max(self.peak_used, self.used)
@@ -80,13 +88,26 @@ class Server:
                                   arrival=arrival, bytes=need, admitted=now))
             self.peak_live = max(self.peak_live, len(self.live))
 
+    def _stream_of(self, precision):
+        return self.streams.get(precision, self.stream)
+
     def _advance(self):
         k = min(self.chunk, min(r["remaining"] for r in self.live))
         groups = {}
         for r in self.live:
             groups.setdefault(r["spec"]["precision"], []).append(r)
-        for reqs in groups.values():
-            lb.batch_step([r["box"] for r in reqs], k)
+        batches = [[r["box"] for r in reqs] for reqs in groups.values()]
+        keys = [id(self._stream_of(p)) if self._stream_of(p) is not None else None
+                for p in groups]
+        if len(batches) > 1 and None not in keys and len(set(keys)) == len(keys):
+            # distinct streams: one host thread per group
+            if self.pool is None:
+                self.pool = ThreadPoolExecutor(max_workers=4)
+            for f in [self.pool.submit(lb.batch_step, b, k) for b in batches]:
+                f.result()
+        else:
+            for b in batches:
+                lb.batch_step(b, k)
         for r in self.live:
             r["remaining"] -= k
             s = r["spec"]["shape"]
@@ -129,16 +150,20 @@ class Server:
                 continue
             self._advance()
             self._retire(now_fn)
+        if self.pool is not None:
+            self.pool.shutdown()
+            self.pool = None
         return self.done
 
 
 def replay(trace, budget_bytes, max_slots=256, chunk=200, step_scale=1.0, stream=None,
-           limit=None, collect=None):
+           limit=None, collect=None, streams=None):
     """Serve a Poisson trace from ``inputs.serving_trace`` on the wall clock.
     step_scale shortens every request (for bounded runs).  Returns
     (results by request id, summary with p50/p99 time-to-result and
     sustained MLUPS)."""
-    srv = Server(budget_bytes, max_slots=max_slots, chunk=chunk, stream=stream, collect=collect)
+    srv = Server(budget_bytes, max_slots=max_slots, chunk=chunk, stream=stream, collect=collect,
+                 streams=streams)
     reqs = trace[:limit] if limit else trace
     specs = []
     for i, r in enumerate(reqs):

@@ -17,13 +17,19 @@ def _collect(box):
     return dict(pop=box.populations(), psi=f["psi"], c=f["c"], links=box.links())
 
 
-def test_served_equals_alone():
+@pytest.mark.parametrize("per_precision_streams", [False, True])
+def test_served_equals_alone(per_precision_streams):
+    # one stream for everything, or one per storage precision (the FP32 and
+    # FP16-storage groups then advance concurrently from two host threads)
     import torch
     trace = I.serving_trace(n_requests=8, rate=50.0, sides=(32, 44), steps=(40, 120))
+    assert len({r["precision"] for r in trace}) == 2
     stream = torch.cuda.Stream()
+    streams = ({"fp32": torch.cuda.Stream(), "fp16": torch.cuda.Stream()}
+               if per_precision_streams else None)
     budget = 6 * serve.request_bytes(I.serving_request(dict(trace[0], side=44, spheres=8)))
     res, summ, specs = serve.replay(trace, budget, max_slots=3, chunk=16, stream=stream,
-                                    collect=_collect)
+                                    collect=_collect, streams=streams)
     flush_print("[serve] summary", summ)
     assert summ["completed"] == 8
     assert summ["peak_live"] <= 3
