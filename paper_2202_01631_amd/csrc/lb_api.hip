@@ -170,7 +170,8 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         }
     }
     // one kernel form per launch: where the boxes disagree on the row-vector
-    // form of the mu or psi/c update, all of them take the one-node form
+    // (or z-marching) form of a lattice kernel, all of them take the
+    // one-node form of that kernel
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
     for (int w = 0; w < 3; w++) {
         bool same = true;
@@ -378,8 +379,8 @@ static lb_status check_params(const lb_params *p, std::string &why)
 // Launch shapes of the lattice kernels: whole rows (up to 256 nodes) per block
 // for collide-stream in natural block order; the row-vector forms for the mu
 // and psi/c updates, the psi/c update with plane-wise XCD renumbering.
-// LB_LATTICE_SHAPES="bx,by,remap[,vec];..." (mu; collide; psi/c, 0 = default)
-// overrides them for tuning sweeps.
+// LB_LATTICE_SHAPES="bx,by,remap[,vec[,zc]];..." (mu; collide; psi/c, 0 =
+// default; zc for the psi/c update only) overrides them for tuning sweeps.
 static void set_shapes(lb_ctx *c)
 {
     LaunchShape d = {0, 0, 0, 0, 0, 0, 0, 0};

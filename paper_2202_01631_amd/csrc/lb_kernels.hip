@@ -2,7 +2,9 @@
 // the multiphase-multicomponent LB model for self-diffusiophoretic Janus
 // colloids (arXiv:2202.01631, Sec. II).
 //
-// Step sequence on one stream (cur -> nxt buffers):
+// Step sequence (cur -> nxt buffers; in large steps with particles the
+// boundary fix-ups and the particle kernels run on a side stream beside the
+// bulk kernels, see launch_step):
 //   k_mu             mu_psi of Eq. 2 at interior nodes (one-node or
 //                    row-vector form)
 //   k_mu_bnd         per particle box: mu at nodes next to a particle, with
@@ -21,7 +23,8 @@
 //                    rigid-body update
 //   k_cover          per particle: cover/uncover repair at the new position
 //   k_commit         per particle: owner bytes at the new position
-//   k_links          per particle: boundary bits and canonical link table
+//   k_link_count     per particle: boundary bits, link count per chunk
+//   k_link_write     per particle: canonical link table
 // Lattice kernels run one node per thread or V consecutive x nodes per lane
 // over rows in x (coalesced structure-of-arrays access).
 #include <utility>
