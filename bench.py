@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,10 +36,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_box256_fp32_traffic.jso
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and whitespace removed: the
+    stored HBM counters stay valid across comment edits, not code changes."""
     h = hashlib.sha256()
     for f in ("lb_kernels.hip", "lb_device.h", "lb_kernels.h"):
-        with open(os.path.join(ROOT, "paper_2202_01631_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2202_01631_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
