@@ -830,32 +830,81 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
-    int x0, y, z, li, gb;
-    if (!vec_node<V>(p, blk - bst[j], x0, y, z, li, gb)) return;
+    // The block's lane groups hold consecutive row segments, so most y
+    // neighbour rows are the centre rows of another group of the block:
+    // those come from LDS, only rows outside the block from memory.  Every
+    // thread reaches the barrier (no early return before it).
+    __shared__ Vec shr[5][256];  // psi, c, mu, chi, u_y centre vectors
+    int x0 = 0, y = 0, z = 0, li = 0, gb = 0;
+    const bool live = vec_node<V>(p, blk - bst[j], x0, y, z, li, gb);
     const int sy = p.nx, sz = p.nx * p.ny;
     const int n0 = x0 + sy * y + sz * z;
     const int nb[4] = {n0 + (wrap_p(y, p.ny) - y) * sy, n0 + (wrap_m(y, p.ny) - y) * sy,
                        n0 + (wrap_p(z, p.nz) - z) * sz, n0 + (wrap_m(z, p.nz) - z) * sz};
-    const unsigned on = (unsigned)n0 * sizeof(S);
-    const OW ow = ldb((const OW *)own, (unsigned)n0);
-    // centre vectors of the four stencil fields and u, then the y, z rows
-    const Vec c0[4] = {ldb((const Vec *)psi, on), ldb((const Vec *)cc, on), ldb((const Vec *)mu, on),
-                       ldb((const Vec *)chiv, on)};
-    const Vec u0x = ldb((const Vec *)ux, on), u0y = ldb((const Vec *)uy, on),
-              u0z = ldb((const Vec *)uz, on);
-    Vec nbv[4][4];  // [field][y+, y-, z+, z-]
+    // lane holding the same x range of the y +- 1 row, if inside the block
+    int src[2] = {-1, -1};
+    {
+        const int by = p.ls.by, xs = p.ls.xseg;
+        const int w = (int)threadIdx.x >> 6, g = gb / p.ls.bx;
+        // group slot of this lane in the block; the group of row r, segment
+        // s is slot + (r - row) * xseg
+        const int slot = w * by + g;
+        const int yn[2] = {wrap_p(y, p.ny), wrap_m(y, p.ny)};
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-        const unsigned om = (unsigned)nb[e] * sizeof(S);
-        nbv[0][e] = ldb((const Vec *)psi, om);
-        nbv[1][e] = ldb((const Vec *)cc, om);
-        nbv[2][e] = ldb((const Vec *)mu, om);
-        nbv[3][e] = ldb((const Vec *)chiv, om);
+        for (int e = 0; e < 2; e++) {
+            const int st = slot + (yn[e] - y) * xs;
+            if (live && st >= 0 && st < 4 * by) src[e] = (st / by) * 64 + (st % by) * p.ls.bx + li;
+        }
     }
-    const Vec uyp = ldb((const Vec *)uy, (unsigned)nb[0] * sizeof(S));
-    const Vec uym = ldb((const Vec *)uy, (unsigned)nb[1] * sizeof(S));
-    const Vec uzp = ldb((const Vec *)uz, (unsigned)nb[2] * sizeof(S));
-    const Vec uzm = ldb((const Vec *)uz, (unsigned)nb[3] * sizeof(S));
+    const unsigned on = (unsigned)n0 * sizeof(S);
+    OW ow = 0;
+    Vec c0[4], u0x, u0y, u0z, nbv[4][4], uyp, uym, uzp, uzm;  // nbv: [field][y+, y-, z+, z-]
+    if (live) {
+        ow = ldb((const OW *)own, (unsigned)n0);
+        // centre vectors of the four stencil fields and u, then the rows
+        // from memory: z +- 1 always, y +- 1 outside the block
+        c0[0] = ldb((const Vec *)psi, on);
+        c0[1] = ldb((const Vec *)cc, on);
+        c0[2] = ldb((const Vec *)mu, on);
+        c0[3] = ldb((const Vec *)chiv, on);
+        u0x = ldb((const Vec *)ux, on);
+        u0y = ldb((const Vec *)uy, on);
+        u0z = ldb((const Vec *)uz, on);
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            if (src[e] >= 0) continue;
+            const unsigned om = (unsigned)nb[e] * sizeof(S);
+            nbv[0][e] = ldb((const Vec *)psi, om);
+            nbv[1][e] = ldb((const Vec *)cc, om);
+            nbv[2][e] = ldb((const Vec *)mu, om);
+            nbv[3][e] = ldb((const Vec *)chiv, om);
+            if (e == 0) uyp = ldb((const Vec *)uy, om);
+            else uym = ldb((const Vec *)uy, om);
+        }
+#pragma unroll
+        for (int e = 2; e < 4; e++) {
+            const unsigned om = (unsigned)nb[e] * sizeof(S);
+            nbv[0][e] = ldb((const Vec *)psi, om);
+            nbv[1][e] = ldb((const Vec *)cc, om);
+            nbv[2][e] = ldb((const Vec *)mu, om);
+            nbv[3][e] = ldb((const Vec *)chiv, om);
+        }
+        uzp = ldb((const Vec *)uz, (unsigned)nb[2] * sizeof(S));
+        uzm = ldb((const Vec *)uz, (unsigned)nb[3] * sizeof(S));
+#pragma unroll
+        for (int f = 0; f < 4; f++) shr[f][threadIdx.x] = c0[f];
+        shr[4][threadIdx.x] = u0y;
+    }
+    __syncthreads();
+    if (!live) return;
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        if (src[e] < 0) continue;
+#pragma unroll
+        for (int f = 0; f < 4; f++) nbv[f][e] = shr[f][src[e]];
+        if (e == 0) uyp = shr[4][src[e]];
+        else uym = shr[4][src[e]];
+    }
     // x neighbours: last node of the lane on the left, first of the right
     const int Ls = p.ls.bx;
     const int srcl = gb + (li == 0 ? Ls - 1 : li - 1), srcr = gb + (li == Ls - 1 ? 0 : li + 1);
