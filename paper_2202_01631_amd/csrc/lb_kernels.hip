@@ -1274,9 +1274,18 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
     const int nl = min(q.nlinks, D.b.lcap);
     const int nch = (nl + LINK_THREADS - 1) / LINK_THREADS;
     if (threadIdx.x < 28) {
+        // partials loaded eight chunks at a time (one memory round trip per
+        // eight, not per chunk), summed in chunk order
         const double *o = D.b.lpart + (size_t)k * D.b.nlchunk_max * 28 + threadIdx.x;
         double s = 0.0;
-        for (int c = 0; c < nch; c++) s += o[(size_t)c * 28];
+        for (int c0 = 0; c0 < nch; c0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] = c0 + i < nch ? o[(size_t)(c0 + i) * 28] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                if (c0 + i < nch) s += v[i];
+        }
         sacc[threadIdx.x] = s;
     }
     __syncthreads();
