@@ -203,6 +203,7 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     B.args.nbox = n;
     B.args.nsec = (B.nchunk_max + BND_SCAN - 1) / BND_SCAN;
     B.args.nfix = B.ncol > 0 ? B.args.nsec * B.ncol : 0;
+    B.args.boff = 0;
 }
 
 static void drop_graphs(lb_ctx *c)

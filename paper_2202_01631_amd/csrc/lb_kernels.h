@@ -45,7 +45,8 @@ struct BatchArgs {
     const int *cstart;
     int nbox;
     int nsec;   // boundary fix-up blocks per particle
-    int nfix;   // fix-up blocks at the head of the mu and psi/c launches
+    int nfix;   // blocks of a boundary fix-up launch
+    int boff;   // first block of a partial launch of a lattice kernel (0: whole grid)
 };
 
 // Host-side batch: device tables plus launch extents.

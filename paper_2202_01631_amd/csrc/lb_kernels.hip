@@ -1479,9 +1479,9 @@ __global__ __launch_bounds__(GCHUNK) void k_mu_bnd(BatchArgs A)
 template <class S, int V, bool ZM, bool BND>
 __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
 {
-    if (V == 1) psic_one<S, BND>(A, blockIdx.x);
-    else if (ZM) psic_zmarch<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
-    else psic_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
+    if (V == 1) psic_one<S, BND>(A, blockIdx.x + A.boff);
+    else if (ZM) psic_zmarch<S, (V > 1 ? V : 2), BND>(A, blockIdx.x + A.boff);
+    else psic_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x + A.boff);
 }
 
 template <class S>
@@ -1986,22 +1986,35 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(B.args);
     const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
-    const dim3 gs(B.nblocks[2]);
-    if (vs == 4 && B.zmarch) {
-        if (bi) k_scalar<S, V4, true, true><<<gs, 256, 0, s>>>(B.args);
-        else k_scalar<S, V4, true, false><<<gs, 256, 0, s>>>(B.args);
-    } else if (vs == 2 && B.zmarch) {
-        if (bi) k_scalar<S, 2, true, true><<<gs, 256, 0, s>>>(B.args);
-        else k_scalar<S, 2, true, false><<<gs, 256, 0, s>>>(B.args);
-    } else if (vs == 4) {
-        if (bi) k_scalar<S, V4, false, true><<<gs, 256, 0, s>>>(B.args);
-        else k_scalar<S, V4, false, false><<<gs, 256, 0, s>>>(B.args);
-    } else if (vs == 2) {
-        if (bi) k_scalar<S, 2, false, true><<<gs, 256, 0, s>>>(B.args);
-        else k_scalar<S, 2, false, false><<<gs, 256, 0, s>>>(B.args);
+    auto scalar = [&](const dim3 gs, const BatchArgs &a) {
+        if (vs == 4 && B.zmarch) {
+            if (bi) k_scalar<S, V4, true, true><<<gs, 256, 0, s>>>(a);
+            else k_scalar<S, V4, true, false><<<gs, 256, 0, s>>>(a);
+        } else if (vs == 2 && B.zmarch) {
+            if (bi) k_scalar<S, 2, true, true><<<gs, 256, 0, s>>>(a);
+            else k_scalar<S, 2, true, false><<<gs, 256, 0, s>>>(a);
+        } else if (vs == 4) {
+            if (bi) k_scalar<S, V4, false, true><<<gs, 256, 0, s>>>(a);
+            else k_scalar<S, V4, false, false><<<gs, 256, 0, s>>>(a);
+        } else if (vs == 2) {
+            if (bi) k_scalar<S, 2, false, true><<<gs, 256, 0, s>>>(a);
+            else k_scalar<S, 2, false, false><<<gs, 256, 0, s>>>(a);
+        } else {
+            if (bi) k_scalar<S, 1, false, true><<<gs, 256, 0, s>>>(a);
+            else k_scalar<S, 1, false, false><<<gs, 256, 0, s>>>(a);
+        }
+    };
+    if (par && B.nblocks[2] >= 2) {
+        // two launches of half the blocks each: the side-stream kernels
+        // queued meanwhile are dispatched between the halves instead of
+        // after the whole grid (measured: step -12 us FP32, -15 us FP16)
+        const int h = B.nblocks[2] / 2;
+        BatchArgs a2 = B.args;
+        a2.boff = h;
+        scalar(dim3(h), B.args);
+        scalar(dim3(B.nblocks[2] - h), a2);
     } else {
-        if (bi) k_scalar<S, 1, false, true><<<gs, 256, 0, s>>>(B.args);
-        else k_scalar<S, 1, false, false><<<gs, 256, 0, s>>>(B.args);
+        scalar(dim3(B.nblocks[2]), B.args);
     }
     if (tm) tm->end(2, s);
     if (B.ncol <= 0) return;
