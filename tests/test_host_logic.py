@@ -60,3 +60,38 @@ def test_serving_request_bytes_cover_the_arena():
         arena = lb.footprint_bytes(spec["shape"], spec["precision"])
         assert need > arena  # plus the particle tables
         assert need < 2 * arena + (64 << 20)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark is single-GPU: asking for more exits with a message
+    # before touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_bench_kernel_hash_ignores_comments(tmp_path):
+    # the stored HBM counters stay valid across comment and whitespace edits
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    h0 = bench.kernel_source_hash()
+    csrc = os.path.join(root, "paper_2202_01631_amd", "csrc")
+    copy = tmp_path / "paper_2202_01631_amd" / "csrc"
+    copy.mkdir(parents=True)
+    for f in ("lb_kernels.hip", "lb_device.h", "lb_kernels.h"):
+        src = open(os.path.join(csrc, f)).read()
+        if f == "lb_kernels.hip":
+            src = "// a new comment\n/* and a block\n comment */\n" + src.replace("\n", "\n\n", 3)
+        (copy / f).write_text(src)
+    bench.ROOT = str(tmp_path)
+    assert bench.kernel_source_hash() == h0
+    (copy / "lb_device.h").write_text(open(os.path.join(csrc, "lb_device.h")).read() + "\nint x;\n")
+    assert bench.kernel_source_hash() != h0
