@@ -37,7 +37,8 @@
  *      bounce-back on the links of R(t) with wall velocity V + W x r + slip,
  *      momentum exchange accumulated per colloid                 (Sec. II.B, Eq. 4, 6)
  *   3. psi and c updates with u(t), mu(t), chi(t) and emission      (Eq. 3, 5)
- *   4. colloid update (implicit in V, W), position and orientation
+ *   4. colloid update (implicit in V, W; explicit under OR_EXPLICIT_COLLOID),
+ *      position and orientation
  *   5. geometry at R(t+1): cover/uncover repair, owner map, link table
  */
 #include <math.h>
@@ -197,6 +198,7 @@ int or_create(const or_params *p, or_ctx **out)
     if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
         return OR_E_INVALID;
     if (12.0 * p->D_c + p->k_d >= 2.0) return OR_E_INVALID;
+    if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID)) return OR_E_INVALID;
 
     or_ctx *c = (or_ctx *)zalloc(sizeof *c);
     if (!c) return OR_E_INVALID;
@@ -468,10 +470,23 @@ static void collide_stream(or_ctx *c)
             gm[1] += wt(i) * CY[i] * mi;
             gm[2] += wt(i) * CZ[i] * mi;
         }
-        for (int a = 0; a < 3; a++) {
-            F[a] = -c->psi[n] * 3.0 * gm[a] + p->ext_force[a];
-            sumF[a] += F[a];
+        for (int a = 0; a < 3; a++) F[a] = -c->psi[n] * 3.0 * gm[a] + p->ext_force[a];
+        if (p->flags & OR_SOLUTE_FORCE) {
+            /* option: the solvent also feels -c grad(mu_c) with mu_c = C chi,
+             * the c-derivative of the coupling term of Eq. 1; same stencil,
+             * chi(x) at solid neighbours */
+            double chi0 = c->cc[n] - p->c_b0 - p->E * tanh(c->psi[n]);
+            double gc[3] = {0.0, 0.0, 0.0};
+            for (int i = 1; i < 19; i++) {
+                long m = nbr(c, n, i);
+                double xm = c->owner[m] < 0 ? c->cc[m] - p->c_b0 - p->E * tanh(c->psi[m]) : chi0;
+                gc[0] += wt(i) * CX[i] * xm;
+                gc[1] += wt(i) * CY[i] * xm;
+                gc[2] += wt(i) * CZ[i] * xm;
+            }
+            for (int a = 0; a < 3; a++) F[a] += -c->cc[n] * p->C * 3.0 * gc[a];
         }
+        for (int a = 0; a < 3; a++) sumF[a] += F[a];
         double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 19; i++) {
             double fi = c->f[i * N + n];
@@ -621,21 +636,32 @@ static void colloid_update(or_ctx *c)
             Fk[3 + a] = c->T0[3 * k + a] + c->trT[3 * k + a];
         }
         double Xn[6];
+        const int expl = (c->p.flags & OR_EXPLICIT_COLLOID) != 0;
         if (q->fixed) {
             for (int i = 0; i < 6; i++) Xn[i] = X[i];
         } else {
             double mass = q->rho_p * (4.0 * M_PI / 3.0) * q->radius * q->radius * q->radius;
             double inertia = 0.4 * mass * q->radius * q->radius;
             double Mv[6] = {mass, mass, mass, inertia, inertia, inertia};
-            double A[36], b[6];
-            for (int i = 0; i < 36; i++) A[i] = Z[i];
-            for (int i = 0; i < 6; i++) { A[6 * i + i] += Mv[i]; b[i] = Mv[i] * X[i] + Fk[i]; }
-            solve6(A, b, Xn);
+            if (expl) {
+                /* option: explicit update (Ladd), M X' = M X + F0 - zeta X */
+                for (int i = 0; i < 6; i++) {
+                    double s = Fk[i];
+                    for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * X[j];
+                    Xn[i] = X[i] + s / Mv[i];
+                }
+            } else {
+                double A[36], b[6];
+                for (int i = 0; i < 36; i++) A[i] = Z[i];
+                for (int i = 0; i < 6; i++) { A[6 * i + i] += Mv[i]; b[i] = Mv[i] * X[i] + Fk[i]; }
+                solve6(A, b, Xn);
+            }
         }
-        /* force and torque actually acting: F0 - zeta X' */
+        /* force and torque actually acting: F0 - zeta X' (implicit), F0 - zeta X
+         * (explicit: the links saw the old velocity) */
         for (int i = 0; i < 6; i++) {
             double s = Fk[i];
-            for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * Xn[j];
+            for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * (expl ? X[j] : Xn[j]);
             if (i < 3) c->Flast[3 * k + i] = s; else c->Tlast[3 * k + i - 3] = s;
         }
         if (!q->fixed) {

@@ -37,7 +37,16 @@ typedef struct {
     double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2 (Eq. 1) */
     double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); Eq. 3a */
     double ext_force[3];         /* uniform body force on the fluid (tests) */
+    uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID (0: neither) */
 } or_params;
+
+/* options (readings of what the paper leaves open):
+ * OR_SOLUTE_FORCE      the solvent also feels -c grad(mu_c), mu_c = C chi
+ *                      (off by default: phoresis enters through the slip)
+ * OR_EXPLICIT_COLLOID  explicit rigid-body update M X' = M X + F0 - zeta X
+ *                      (Ladd) instead of the implicit one */
+#define OR_SOLUTE_FORCE 1u
+#define OR_EXPLICIT_COLLOID 2u
 
 typedef struct {
     double pos[3], m[3], vel[3], omega[3];

@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("M_psi", C.c_double),
                 ("C", C.c_double), ("E", C.c_double), ("c_b0", C.c_double),
                 ("D_c", C.c_double), ("k_d", C.c_double),
-                ("ext_force", C.c_double * 3)]
+                ("ext_force", C.c_double * 3), ("flags", C.c_uint32)]
 
 
 class Colloid(C.Structure):
@@ -102,6 +102,7 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+SOLUTE_FORCE, EXPLICIT_COLLOID = 1, 2   # option flags (oracle.h)
 PARAM_KEYS = ("rho0", "tau", "a", "b", "kappa", "M_psi", "C", "E", "c_b0", "D_c", "k_d")
 COLLOID_SCALARS = ("radius", "alpha_minus", "alpha_plus", "mu_minus", "mu_plus", "H", "rho_p")
 
@@ -117,6 +118,7 @@ def make_params(shape, **kw):
     ef = kw.get("ext_force", (0.0, 0.0, 0.0))
     for a in range(3):
         p.ext_force[a] = float(ef[a])
+    p.flags = int(kw.get("flags", 0))
     return p
 
 

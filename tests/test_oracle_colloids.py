@@ -248,3 +248,38 @@ def test_self_propulsion_direction_and_linearity():
     o.step(60)
     v = o.observables()[1][0]["vel"]
     assert v @ m > 0.9 * np.linalg.norm(v)
+
+
+def test_explicit_update_conserves_momentum():
+    # option OR_EXPLICIT_COLLOID (Ladd): the particle takes exactly the link
+    # momentum computed with its old velocity, F0 - zeta X, so fluid +
+    # particle + pending cover/uncover momentum changes per step by the body
+    # force alone (the implicit update leaves the defect zeta (X - X'))
+    shape = (16, 14, 14)
+    N = int(np.prod(shape))
+    p = dict(a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0625, E=0.0, c_b0=0.0, D_c=0.1,
+             k_d=0.01, tau=1.0)
+    o = oracle.Oracle(shape, flags=oracle.EXPLICIT_COLLOID, **p)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    o.add_colloids([dict(pos=(5.2, 7.1, 6.9), m=(0, 0, 1), radius=3.2, vel=(0.05, 0.01, -0.02),
+                         omega=(0.0, 0.0, 0.02), rho_p=1.5, alpha_minus=1e-3, mu_minus=0.2,
+                         mu_plus=0.2)])
+    mass = 1.5 * 4.0 / 3.0 * math.pi * 3.2 ** 3
+    n_changed, defect = 0, 0.0
+    for _ in range(25):
+        ob = o.owner()
+        pb, _ = _fluid_momentum(o)
+        _, cb = o.observables()
+        trb = o.colloid_diag(0)["trF"] if o.observables()[0]["step"] > 0 else np.zeros(3)
+        Xb = np.concatenate([cb[0]["vel"], cb[0]["omega"]])
+        o.step(1)
+        pa, _ = _fluid_momentum(o)
+        _, ca = o.observables()
+        dgc = o.colloid_diag(0)
+        Xa = np.concatenate([ca[0]["vel"], ca[0]["omega"]])
+        n_changed += int((o.owner() != ob).sum())
+        lhs = (pa + mass * ca[0]["vel"] + dgc["trF"]) - (pb + mass * cb[0]["vel"] + trb)
+        assert np.allclose(lhs, o.step_diag()["sum_force"], rtol=0, atol=256 * N * EPS)
+        defect = max(defect, float(np.abs((dgc["zeta"] @ (Xb - Xa))[:3]).max()))
+    assert n_changed > 0  # cover/uncover exercised
+    assert defect > 1e3 * 256 * N * EPS  # the implicit defect would have been visible

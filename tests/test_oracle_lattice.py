@@ -184,3 +184,35 @@ def test_linearised_update_has_no_growing_mode():
             p[j - 19 * N] += h
         J[:, j] = (step(f.reshape(19, N), p) - base) / h
     assert np.abs(np.linalg.eigvals(J)).max() <= 1.0 + 1e-6
+
+
+def test_solute_force_option_closed_form():
+    # option OR_SOLUTE_FORCE: the solvent also feels -c grad(mu_c), mu_c =
+    # C chi.  With psi = 0 (no psi force, tanh psi = 0: chi = c - c_b0) and
+    # c = c0 + A sin(kx), the isotropic stencil reduces to the central
+    # difference along x, grad_x chi = A sin(k) cos(kx) exactly, so
+    # F = (-C c(x) A sin(k) cos(kx), 0, 0); without the option F = 0.
+    shape = (32, 4, 3)
+    N = int(np.prod(shape))
+    x = I.coords(shape)[0]
+    k = 2.0 * np.pi / shape[0]
+    c0, A, C = 0.7, 0.2, 0.35
+    c = c0 + A * np.sin(k * x)
+    p = dict(a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.0, C=C, E=-0.2, c_b0=0.5, D_c=0.0,
+             k_d=0.0, tau=1.0)
+    for flags, expect in ((0, np.zeros((3, N))),
+                          (oracle.SOLUTE_FORCE,
+                           np.stack([-C * c * A * np.sin(k) * np.cos(k * x), np.zeros(N), np.zeros(N)]))):
+        o = oracle.Oracle(shape, flags=flags, **p)
+        o.init_fields(np.zeros(N), c)
+        o.step(1)
+        F = o.aux()["force"]
+        o.close()
+        assert np.allclose(F, expect, rtol=0, atol=64 * EPS * C * A * c0)
+    # the force pushes solute-rich fluid down its own gradient: F_x < 0 where c rises
+    assert (expect[0][np.cos(k * x) > 0.1] < 0).all()
+
+
+def test_option_flags_validated():
+    with pytest.raises(RuntimeError):
+        oracle.Oracle((4, 4, 4), flags=4)
