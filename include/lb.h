@@ -96,8 +96,22 @@ typedef struct {
     double ext_force[3];         /* uniform body force on the fluid (0 in the paper) */
     double f16_scale;            /* FP16 storage scale, a power of two; 0 -> 16384 */
     int32_t max_colloids;        /* particle capacity, <= 127 (owner byte); 0 -> 64 */
-    uint32_t flags;              /* reserved, 0 */
+    uint32_t flags;              /* options, 0 or a combination of the LB_* bits below */
 } lb_params;
+
+/* lb_params.flags: readings the paper leaves open, off by default.
+ * LB_SOLUTE_FORCE      the solvent also feels -c grad(mu_c), mu_c = C chi the
+ *                      c-derivative of the coupling term of Eq. 1 (same
+ *                      isotropic gradient as the psi force, chi(x) at solid
+ *                      neighbours).  Off: phoresis reaches the fluid through
+ *                      the slip of Eq. 4 only.  Selects the one-node form of
+ *                      collide-stream.
+ * LB_EXPLICIT_COLLOID  explicit rigid-body update (Ladd), M X' = M X + F0 -
+ *                      zeta X + transfers, instead of the implicit
+ *                      (M + zeta) X' = M X + F0 + transfers.
+ * Other bits: LB_E_INVALID at lb_create. */
+#define LB_SOLUTE_FORCE 1u
+#define LB_EXPLICIT_COLLOID 2u
 
 typedef struct {                 /* FP64, caller-owned */
     double pos[3], m[3], vel[3], omega[3]; /* centre, axis (normalised on add), V, Omega */

@@ -172,12 +172,17 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // one kernel form per launch: where the boxes disagree on the row-vector
     // (or z-marching) form of a lattice kernel, all of them take the
     // one-node form of that kernel
+    // (the solute-force term lives in the one-node collide-stream only)
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
+    B.solute_force = 0;
+    for (int j = 0; j < n; j++)
+        if (ctxs[j]->p.flags & LB_SOLUTE_FORCE) B.solute_force = 1;
     for (int w = 0; w < 3; w++) {
         bool same = true;
         for (int j = 1; j < n; j++)
             same = same && d[j].ls[w].vec == d[0].ls[w].vec &&
                    (d[j].ls[w].zc > 1) == (d[0].ls[w].zc > 1);
+        if (w == 1 && B.solute_force) same = n > 0 && d[0].ls[1].vec <= 1 && same;
         if (!same) {
             for (int j = 0; j < n; j++) {
                 if (d[j].ls[w].vec > 1) {
@@ -363,6 +368,10 @@ static lb_status check_params(const lb_params *p, std::string &why)
         why = "kappa, M_psi, C, D_c, k_d must be >= 0";
         return LB_E_INVALID;
     }
+    if (p->flags & ~(LB_SOLUTE_FORCE | LB_EXPLICIT_COLLOID)) {
+        why = "unknown option flags";
+        return LB_E_INVALID;
+    }
     if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
         why = "M_psi above the explicit-Euler stability bound M (12|a| + 36|b| + 144 kappa) < 2";
         return LB_E_INVALID;
@@ -515,6 +524,7 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     k.fx = p->ext_force[0]; k.fy = p->ext_force[1]; k.fz = p->ext_force[2];
     k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;
     k.inv_scale = 1.0f / k.scale;
+    k.flags = p->flags;
     set_shapes(c);
     c->stream = (hipStream_t)hip_stream;
     c->L = layout_of(c->p);

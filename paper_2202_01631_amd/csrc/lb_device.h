@@ -110,6 +110,7 @@ struct KParams {
     double om, pref;           // 1/tau and 1 - 1/(2 tau), formed once on the host
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
+    unsigned flags;            // LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID
 };
 
 // ---------------------------------------------------------- particle record

@@ -60,6 +60,7 @@ struct Batch {
     int vec[3];       // row-vector form of each lattice launch (all boxes of the batch)
     int zmarch;       // z-marching form of the psi/c update (all boxes of the batch)
     long long nodes;  // lattice nodes over all boxes
+    int solute_force; // some box has LB_SOLUTE_FORCE (one-node collide-stream with the term)
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,

@@ -272,10 +272,11 @@ template <class S> struct NodeMoments {
 
 // g: the 19 populations; mv[1..18]: mu at the neighbours, replaced by
 // m0 = mu(x) where bit i of solid is set
-template <class S>
+template <class S, bool SF = false>
 __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, const S g[19],
                                                           const S mv[19], S m0, unsigned solid,
-                                                          S ps)
+                                                          S ps, const S *xv = nullptr,
+                                                          S x0 = S(0), S cn = S(0))
 {
 #pragma clang fp contract(off)
     NodeMoments<S> m;
@@ -307,6 +308,23 @@ __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, cons
     m.Fx = fma(-ps, gx, (S)p.fx);
     m.Fy = fma(-ps, gy, (S)p.fy);
     m.Fz = fma(-ps, gz, (S)p.fz);
+    if (SF) {
+        // option: -c grad(mu_c), mu_c = C chi; xv[1..18]: chi at the
+        // neighbours, x0 = chi(x) at solid ones; cn = c(x) (0: no term)
+        S hx = S(0), hy = S(0), hz = S(0);
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+            const S wi = (S)(3.0 * wgt(i));
+            const S xi = (solid & (1u << i)) ? x0 : xv[i];
+            if (cx(i)) hx = fma(cx(i) > 0 ? wi : -wi, xi, hx);
+            if (cy(i)) hy = fma(cy(i) > 0 ? wi : -wi, xi, hy);
+            if (cz(i)) hz = fma(cz(i) > 0 ? wi : -wi, xi, hz);
+        }
+        const S cC = -cn * (S)p.C;
+        m.Fx = fma(cC, hx, m.Fx);
+        m.Fy = fma(cC, hy, m.Fy);
+        m.Fz = fma(cC, hz, m.Fz);
+    }
     m.drho = drho;
     m.rho = (S)p.rho0 + drho;
     const S ir = S(1) / m.rho;
@@ -350,8 +368,9 @@ __device__ __forceinline__ S collide_pop(int i, S gi, const NodeMoments<S> &m, S
     return fma(pref * w, fo, fma(-om, gi - geq, gi));
 }
 
-// one node per thread
-template <int P>
+// one node per thread; SF: boxes with LB_SOLUTE_FORCE get the -c grad(mu_c)
+// term
+template <int P, bool SF>
 __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 {
     typedef typename Prec<P>::T T;
@@ -398,7 +417,21 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
             solid |= (ldb(own, (unsigned)m) & OWN_SOLID) ? (1u << i) : 0u;
         }
     }
-    const NodeMoments<S> M = collide_moments<S>(p, g, mv, m0, solid, ps);
+    S xv[19], x0 = S(0), cn = S(0);
+    if (SF) {
+#pragma unroll
+        for (int i = 0; i < 19; i++) xv[i] = S(0);
+        if (p.flags & LB_SOLUTE_FORCE) {
+            const S *__restrict__ chi = (const S *)D.b.chi;
+            x0 = ldb(chi, os);
+            cn = ldb((const S *)D.b.cc, os);
+#pragma unroll
+            for (int i = 1; i < 19; i++)
+                xv[i] = ldb(chi, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) *
+                                     sizeof(S));
+        }
+    }
+    const NodeMoments<S> M = collide_moments<S, SF>(p, g, mv, m0, solid, ps, xv, x0, cn);
     const S om = (S)p.om;
     const S pref = (S)p.pref;
     // nodes without solid neighbours store along a straight line (FP64
@@ -1307,8 +1340,17 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
         Fk[a] = acc[a] + q.trF[a];
         Fk[3 + a] = acc[3 + a] + q.trT[a];
     }
+    const bool expl = (p.flags & LB_EXPLICIT_COLLOID) != 0;
     if (q.fixed) {
         for (int i = 0; i < 6; i++) Xn[i] = X[i];
+    } else if (expl) {
+        // option: explicit update (Ladd), M X' = M X + F0 + transfers - zeta X
+        const double Mv[6] = {q.mass, q.mass, q.mass, q.inertia, q.inertia, q.inertia};
+        for (int i = 0; i < 6; i++) {
+            double s = Fk[i];
+            for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * X[j];
+            Xn[i] = X[i] + s / Mv[i];
+        }
     } else {
         const double Mv[6] = {q.mass, q.mass, q.mass, q.inertia, q.inertia, q.inertia};
         double A[36], bb[6];
@@ -1327,9 +1369,10 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
             Xn[i] = s / A[6 * i + i];
         }
     }
+    // force and torque acting: F0 - zeta X' (implicit), F0 - zeta X (explicit)
     for (int i = 0; i < 6; i++) {
         double s = Fk[i];
-        for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * Xn[j];
+        for (int j = 0; j < 6; j++) s -= Z[6 * i + j] * (expl ? X[j] : Xn[j]);
         if (i < 3) q.F[i] = s; else q.T[i - 3] = s;
     }
     for (int a = 0; a < 3; a++) { q.trF[a] = 0.0; q.trT[a] = 0.0; }
@@ -1975,9 +2018,10 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
-    if (B.vec[1] == 4) k_collide_v<P, V4><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    if (B.solute_force) k_collide<P, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    else if (B.vec[1] == 4) k_collide_v<P, V4><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.vec[1] == 2) k_collide_v<P, 2><<<B.nblocks[1], 256, 0, s>>>(B.args);
-    else k_collide<P><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    else k_collide<P, false><<<B.nblocks[1], 256, 0, s>>>(B.args);
     if (tm) tm->end(1, s);
     if (tm) tm->begin(2, s);
     if (par) {

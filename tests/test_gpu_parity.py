@@ -132,6 +132,75 @@ def test_fp64_several_moving_colloids(seed):
         assert np.abs(fg["F"][k] - fo["F"]).max() <= 1e-11
 
 
+@pytest.mark.parametrize("flags", [lb.LB_SOLUTE_FORCE, lb.LB_EXPLICIT_COLLOID,
+                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID])
+def test_fp64_options_match_oracle(flags):
+    # the two options (solvent force -c grad(mu_c); explicit rigid-body
+    # update) against the oracle's: moving particles with cover/uncover,
+    # solute emitted and a nonzero E so that chi varies, 40 steps
+    shape = (40, 36, 34)
+    u = I.uniform(9, 30)
+    cols = [
+        I.janus((2.0 + u[0], 18.0 + u[1], 17.0 + u[2]), I.unit_vectors(9, 1)[0], 4.2,
+                alpha=2e-3, mu=0.3, theta=60.0),
+        I.janus((24.0 + u[6], 26.0 + u[7], 25.0 + u[8]), I.unit_vectors(11, 1)[0], 5.1,
+                alpha=1e-3, mu=-0.2, theta=90.0, rho_p=2.0),
+    ]
+    cols[0]["vel"] = np.array([0.04, -0.01, 0.02])
+    cols[1]["vel"] = np.array([-0.02, 0.03, 0.01])
+    spec = _spec(shape, seed=9, colloids=cols, flags=flags)
+    g, o = run_pair(spec, 0)
+    changed = 0
+    for _ in range(4):
+        own0 = o.owner()
+        g.step(10)
+        o.step(10)
+        changed += int((o.owner() != own0).sum())
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+    assert changed > 0
+    _compare(g, o, 1e-12, "options %d" % flags)
+    _, cg = g.observables()
+    _, co = o.observables()
+    for k in range(2):
+        for a in ("vel", "omega", "pos", "m"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+    fg = g.colloid_forces()
+    for k in range(2):
+        assert np.abs(fg["F"][k] - o.colloid_diag(k)["F"]).max() <= 1e-11
+
+
+def test_solute_force_fp32_and_forms():
+    # FP32 with the solute force within 2e-5 of the FP64 oracle after 100
+    # steps; a row-vector collide shape falls back to the one-node form and
+    # gives the same bits; a batch mixing boxes with and without the option
+    # equals each box alone
+    import torch
+    w = I.workload_small()
+    spec = dict(w, params=dict(w["params"], flags=lb.LB_SOLUTE_FORCE))
+    g, o = run_pair(spec, 100, precision="fp32")
+    _compare(g, o, 2e-5, "fp32 solute force")
+    a = lb.from_spec(spec, precision="fp32")
+    a.set_launch_shapes([(0, 0, 32), (0, 0, 32), (0, 0, 34)])
+    a.step(100)
+    assert np.array_equal(a.populations(), g.populations())
+    assert np.array_equal(a.fields()["psi"], g.fields()["psi"])
+    specs = [spec, w]
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s_, precision="fp32", stream=stream) for s_ in specs]
+    lb.batch_step(batch, 6)
+    for b_, s_ in zip(batch, specs):
+        alone = lb.from_spec(s_, precision="fp32")
+        alone.step(6)
+        assert np.array_equal(alone.populations(), b_.populations())
+        assert np.array_equal(alone.fields()["c"], b_.fields()["c"])
+
+
+def test_option_flags_validated():
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", flags=4)
+
+
 @pytest.mark.parametrize("seed", [3, 4, 5])
 def test_link_tables_bit_exact_random(seed):
     # many spheres at random non-integer positions, across the periodic
