@@ -220,21 +220,20 @@ def test_batched_row_vector_collide_equals_alone():
 
 def test_full_batch_512_equals_alone():
     # the full 512-box sweep (sides 32/48/64, one sphere each) in the form
-    # bench.py times (tuned shapes, one batched graph pair per two steps)
-    # against every box stepped alone: psi, c, owner map and link table of
-    # every box, populations of every 16th box, bit for bit
+    # bench.py times (default shapes, one batched graph pair per two steps)
+    # against every box stepped alone (tuned shapes): psi, c, owner map and
+    # link table of every box, populations of every 16th box, bit for bit
     import torch
     from paper_2202_01631_amd import tune
     specs = I.batch_boxes(count=512, steps=4)
     stream = torch.cuda.Stream()
     batch = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
-    for b in batch:
-        tune.apply(b)
     flush_print("[batch512] batched steps")
     lb.batch_step(batch, 4)
     torch.cuda.synchronize()
     for j, s in enumerate(specs):
         a = lb.from_spec(s, precision="fp32")
+        tune.apply(a)
         a.step(4)
         b = batch[j]
         fa, fb = a.fields(), b.fields()
