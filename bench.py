@@ -173,7 +173,6 @@ def serving_run(torch, I, nreq, rate, step_scale):
     from paper_2202_01631_amd import serve
     trace = I.serving_trace(n_requests=nreq, rate=rate)
     free, _ = torch.cuda.mem_get_info()
-    # one stream per storage precision: the two groups advance concurrently
     streams = {"fp32": torch.cuda.Stream(), "fp16": torch.cuda.Stream()}
     _, summ, _ = serve.replay(trace, budget_bytes=int(0.5 * free), chunk=100,
                               step_scale=step_scale, streams=streams)

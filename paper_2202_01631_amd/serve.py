@@ -6,11 +6,9 @@ advances all of them together: between chunks of steps it admits new
 arrivals as slots and HBM budget free up (admission by ``lb_footprint_bytes``
 plus the particle tables), groups the live requests by storage precision,
 and advances each group with one batched launch per kernel
-(``lb_batch_step``).  Groups given streams of their own run concurrently
-(one host thread per group; the library releases the interpreter lock), so
-one group's particle work overlaps the other's lattice kernels.  A request
-whose steps are done is read back (FP64 totals and particle states) and its
-memory released at once.
+(``lb_batch_step``), one group after the other (optionally each group on a
+stream of its own).  A request whose steps are done is read back (FP64
+totals and particle states) and its memory released at once.
 
 Time-to-result = completion time - arrival time.  Each result is identical
 to the same request run alone (the batched step is bitwise equal to the
@@ -19,7 +17,6 @@ single-box step).
 import heapq
 import math
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 from . import inputs as I
 from . import lb
@@ -44,7 +41,7 @@ class Server:
     """One GPU; ``budget_bytes`` caps the resident state, ``max_slots`` the
     number of live requests, ``chunk`` the steps taken between admission
     points.  Boxes of precision p live on ``streams[p]`` if given, else on
-    ``stream``; precision groups on distinct streams advance concurrently."""
+    ``stream``."""
 
     def __init__(self, budget_bytes, max_slots=256, chunk=200, stream=None, collect=None,
                  streams=None):
@@ -56,7 +53,6 @@ class Server:
         self.chunk = chunk
         self.stream = stream
         self.streams = dict(streams or {})
-        self.pool = None
         self.used = 0
         self.live = []        # dicts: id, box, spec, remaining, arrival, bytes
         self.queue = []       # (arrival, seq, id, spec) waiting for admission
@@ -96,18 +92,8 @@ class Server:
         groups = {}
         for r in self.live:
             groups.setdefault(r["spec"]["precision"], []).append(r)
-        batches = [[r["box"] for r in reqs] for reqs in groups.values()]
-        keys = [id(self._stream_of(p)) if self._stream_of(p) is not None else None
-                for p in groups]
-        if len(batches) > 1 and None not in keys and len(set(keys)) == len(keys):
-            # distinct streams: one host thread per group
-            if self.pool is None:
-                self.pool = ThreadPoolExecutor(max_workers=4)
-            for f in [self.pool.submit(lb.batch_step, b, k) for b in batches]:
-                f.result()
-        else:
-            for b in batches:
-                lb.batch_step(b, k)
+        for reqs in groups.values():
+            lb.batch_step([r["box"] for r in reqs], k)
         for r in self.live:
             r["remaining"] -= k
             s = r["spec"]["shape"]
@@ -150,9 +136,6 @@ class Server:
                 continue
             self._advance()
             self._retire(now_fn)
-        if self.pool is not None:
-            self.pool.shutdown()
-            self.pool = None
         return self.done
 
 

@@ -19,8 +19,7 @@ def _collect(box):
 
 @pytest.mark.parametrize("per_precision_streams", [False, True])
 def test_served_equals_alone(per_precision_streams):
-    # one stream for everything, or one per storage precision (the FP32 and
-    # FP16-storage groups then advance concurrently from two host threads)
+    # one stream for everything, or one per storage precision
     import torch
     trace = I.serving_trace(n_requests=8, rate=50.0, sides=(32, 44), steps=(40, 120))
     assert len({r["precision"] for r in trace}) == 2
