@@ -334,6 +334,37 @@ def test_error_paths():
     lb.Box((16, 16, 16), "fp32", arena=buf[256:]).close()
 
 
+def test_degenerate_particles_and_zero_steps():
+    # a particle too small to own a node (no solid node, no link: it drifts
+    # with its initial velocity and pushes nothing), one centred exactly on
+    # a node and on the periodic corner, a zero-step call; FP64 against the
+    # oracle over 20 steps
+    shape = (24, 22, 20)
+    cols = [dict(pos=(6.3, 5.6, 9.2), m=(0.0, 0.0, 1.0), radius=0.3, vel=(0.02, -0.01, 0.005),
+                 rho_p=1.2, alpha_minus=1e-3, mu_minus=0.1, mu_plus=0.1),
+            dict(pos=(0.0, 0.0, 0.0), m=(1.0, 0.0, 0.0), radius=3.0, vel=(0.0, 0.01, 0.0),
+                 rho_p=1.5, alpha_minus=2e-3, mu_minus=0.2, mu_plus=-0.1)]
+    spec = _spec(shape, seed=21, colloids=cols)
+    g, o = run_pair(spec, 0)
+    t, _ = g.observables()
+    assert np.array_equal(g.owner(), o.owner()) and np.array_equal(g.links(), o.links())
+    assert ((g.owner() == 0).sum() == 0)  # the tiny particle owns no node
+    g.step(0)
+    t0, _ = g.observables()
+    assert t0["step"] == 0
+    g.step(20)
+    o.step(20)
+    assert np.array_equal(g.owner(), o.owner()) and np.array_equal(g.links(), o.links())
+    _compare(g, o, 1e-12, "degenerate particles")
+    _, cg = g.observables()
+    _, co = o.observables()
+    for k in range(2):
+        for a in ("vel", "omega", "pos", "m"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+    assert np.allclose(cg[0]["pos"], np.array([6.3, 5.6, 9.2]) + 20 * np.array([0.02, -0.01, 0.005]),
+                       rtol=0, atol=1e-12)
+
+
 # ------------------------------------------------------ full benchmark size
 def test_full_size_256_step_pair():
     # the benchmark workload itself (256^3, 64 moving Janus spheres), in the
