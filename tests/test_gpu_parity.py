@@ -285,6 +285,10 @@ def test_fp16_storage_error_bounds():
                 c=np.zeros(24 ** 3), colloids=[col])
     g, o = run_pair(spec, 500, precision="fp16")
     _compare(g, o, dict(rho=2e-5, psi=1e-3, c=1e-2, u=1e-1), "fp16 500 steps")
+    # the same bounds with the solute-force option (its one-node FP16 path)
+    sf = dict(spec, params=dict(spec["params"], flags=lb.LB_SOLUTE_FORCE))
+    g, o = run_pair(sf, 500, precision="fp16")
+    _compare(g, o, dict(rho=2e-5, psi=1e-3, c=1e-2, u=1e-1), "fp16 500 steps, solute force")
 
 
 # -------------------------------------------------------- state handling
