@@ -37,6 +37,7 @@
  *      bounce-back on the links of R(t) with wall velocity V + W x r + slip,
  *      momentum exchange accumulated per colloid                 (Sec. II.B, Eq. 4, 6)
  *   3. psi and c updates with u(t), mu(t), chi(t) and emission      (Eq. 3, 5)
+ *      (optionally n sub-steps of length 1/n, mu and chi recomputed)
  *   4. colloid update (implicit in V, W; explicit under OR_EXPLICIT_COLLOID),
  *      position and orientation
  *   5. geometry at R(t+1): cover/uncover repair, owner map, link table
@@ -194,10 +195,13 @@ int or_create(const or_params *p, or_ctx **out)
     if (!(p->tau > 0.5) || !(p->rho0 > 0.0)) return OR_E_INVALID;
     if (p->kappa < 0.0 || p->M_psi < 0.0 || p->D_c < 0.0 || p->k_d < 0.0 || p->C < 0.0)
         return OR_E_INVALID;
-    /* explicit-Euler stability of the 7-point schemes for psi and c */
-    if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
+    /* explicit-Euler stability of the 7-point schemes for psi and c, per
+     * sub-step of length 1/n */
+    if (p->ch_substeps < 0 || p->ch_substeps > 64) return OR_E_INVALID;
+    const double dt = 1.0 / (p->ch_substeps > 0 ? p->ch_substeps : 1);
+    if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
         return OR_E_INVALID;
-    if (12.0 * p->D_c + p->k_d >= 2.0) return OR_E_INVALID;
+    if (dt * (12.0 * p->D_c + p->k_d) >= 2.0) return OR_E_INVALID;
     if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID)) return OR_E_INVALID;
 
     or_ctx *c = (or_ctx *)zalloc(sizeof *c);
@@ -570,9 +574,10 @@ static void collide_stream(or_ctx *c)
 }
 
 /* step 3: Cahn-Hilliard update of psi and advection-diffusion-reaction update
- * of c (Eq. 3), explicit Euler, fluxes through the 6 faces of each node;
- * no flux through faces shared with solid nodes. */
-static void scalar_update(or_ctx *c)
+ * of c (Eq. 3), explicit Euler over a time step dt (1, or 1/n for n
+ * sub-steps), fluxes through the 6 faces of each node; no flux through faces
+ * shared with solid nodes.  The diagnostics sum dt-weighted source and chi. */
+static void scalar_update(or_ctx *c, double dt)
 {
     const or_params *p = &c->p;
     long N = c->N;
@@ -594,13 +599,13 @@ static void scalar_update(or_ctx *c)
             double chim = c->cc[m] - p->c_b0 - p->E * tanh(c->psi[m]);
             dchi += chim - chi;
         }
-        c->psin[n] = ps - adv_psi + p->M_psi * dmu;
-        c->ccn[n] = cn - adv_c + p->D_c * dchi + c->src[n] - p->k_d * chi;
-        sumsrc += c->src[n];
-        sumchi += chi;
+        c->psin[n] = ps - dt * adv_psi + dt * p->M_psi * dmu;
+        c->ccn[n] = cn - dt * adv_c + dt * p->D_c * dchi + dt * c->src[n] - dt * p->k_d * chi;
+        sumsrc += dt * c->src[n];
+        sumchi += dt * chi;
     }
-    c->diag[OR_DIAG_SUM_SRC] = sumsrc;
-    c->diag[OR_DIAG_SUM_CHI] = sumchi;
+    c->diag[OR_DIAG_SUM_SRC] += sumsrc;
+    c->diag[OR_DIAG_SUM_CHI] += sumchi;
 }
 
 /* solve A x = b for a symmetric positive definite 6x6 A by Gaussian
@@ -750,10 +755,23 @@ int or_step(or_ctx *c, int64_t nsteps)
     if (!c) return OR_E_INVALID;
     if (c->stage < 1) return fail(c, OR_E_STATE, "init_fields first");
     if (nsteps < 0) return fail(c, OR_E_INVALID, "negative step count");
+    const int nsub = c->p.ch_substeps > 0 ? c->p.ch_substeps : 1;
     for (int64_t s = 0; s < nsteps; s++) {
         chemical_potential(c);
         collide_stream(c);
-        scalar_update(c);
+        /* psi/c sub-steps: the first from psi(t), c(t) and mu(t); each later
+         * one from the previous result, with mu and chi recomputed and u held */
+        c->diag[OR_DIAG_SUM_SRC] = 0.0;
+        c->diag[OR_DIAG_SUM_CHI] = 0.0;
+        for (int j = 0; j < nsub; j++) {
+            if (j > 0) {
+                double *t;
+                t = c->psi; c->psi = c->psin; c->psin = t;
+                t = c->cc; c->cc = c->ccn; c->ccn = t;
+                chemical_potential(c);
+            }
+            scalar_update(c, 1.0 / nsub);
+        }
         if (c->ncol > 0) {
             colloid_update(c);
             regeometry(c);

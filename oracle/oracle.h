@@ -38,6 +38,8 @@ typedef struct {
     double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); Eq. 3a */
     double ext_force[3];         /* uniform body force on the fluid (tests) */
     uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID (0: neither) */
+    int32_t ch_substeps;         /* psi/c updates per LB step, time step 1/n each
+                                    (mu and chi recomputed between them, u held); 0 -> 1 */
 } or_params;
 
 /* options (readings of what the paper leaves open):

@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("M_psi", C.c_double),
                 ("C", C.c_double), ("E", C.c_double), ("c_b0", C.c_double),
                 ("D_c", C.c_double), ("k_d", C.c_double),
-                ("ext_force", C.c_double * 3), ("flags", C.c_uint32)]
+                ("ext_force", C.c_double * 3), ("flags", C.c_uint32),
+                ("ch_substeps", C.c_int32)]
 
 
 class Colloid(C.Structure):
@@ -119,6 +120,7 @@ def make_params(shape, **kw):
     for a in range(3):
         p.ext_force[a] = float(ef[a])
     p.flags = int(kw.get("flags", 0))
+    p.ch_substeps = int(kw.get("ch_substeps", 0))
     return p
 
 

@@ -151,14 +151,17 @@ def test_mass_and_momentum_balance_with_free_energy_force():
         assert abs((ca - cb) - (dg["sum_src"] - p["k_d"] * dg["sum_chi"])) <= tol
 
 
-def test_linearised_update_has_no_growing_mode():
+@pytest.mark.parametrize("M_psi,nsub", [(0.1, 1), (0.4, 2)])
+def test_linearised_update_has_no_growing_mode(M_psi, nsub):
     # Jacobian of one oracle step around the ordered state (psi = 1, rest
     # fluid) on a 4^3 box, by finite differences: every eigenvalue must lie in
     # the unit disk.  (With the central two-point gradient in the body force
     # instead of the isotropic lattice gradient, the explicit coupling of the
     # force with the advection of psi has modes growing by ~8% per step at
-    # kappa = 0.04; the fix is the reading documented with the oracle.)
-    FE = dict(rho0=1.0, tau=1.0, a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.1)
+    # kappa = 0.04; the fix is the reading documented with the oracle.)  The
+    # paper's mobility M_psi = 0.4 is stable with two psi/c sub-steps.
+    FE = dict(rho0=1.0, tau=1.0, a=-0.0625, b=0.0625, kappa=0.04, M_psi=M_psi,
+              ch_substeps=nsub)
     shape = (4, 4, 4)
     N = 64
     _, w = oracle.lattice()
@@ -216,3 +219,15 @@ def test_solute_force_option_closed_form():
 def test_option_flags_validated():
     with pytest.raises(RuntimeError):
         oracle.Oracle((4, 4, 4), flags=4)
+
+
+def test_paper_mobility_needs_substeps():
+    # M_psi = 0.4 (Sec. II.C) with a = -b = 0.0625, kappa = 0.04 puts the
+    # explicit psi update beyond its stability bound M (12|a| + 36|b| +
+    # 144 kappa) < 2 for a unit time step; two sub-steps of 1/2 satisfy it
+    FE = dict(a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.4)
+    with pytest.raises(RuntimeError):
+        oracle.Oracle((8, 8, 8), **FE)
+    with pytest.raises(RuntimeError):
+        oracle.Oracle((8, 8, 8), ch_substeps=1, **FE)
+    oracle.Oracle((8, 8, 8), ch_substeps=2, **FE).close()

@@ -44,6 +44,32 @@ def test_solute_fourier_mode_exact(kvec, u0):
         assert np.abs(o.fields()["psi"] - 1.0).max() == 0.0
 
 
+@pytest.mark.parametrize("nsub", [2, 3])
+def test_solute_fourier_mode_exact_substeps(nsub):
+    # the same linear scheme advanced in n psi/c sub-steps of length 1/n per
+    # LB step (u held, chi recomputed): the factor per LB step is
+    #   G = (1 - (i sum_a u_a sin k_a + D sum_a 4 sin^2(k_a/2) + k_d) / n)^n
+    kvec, u0 = (1, 2, 1), (0.03, -0.02, 0.01)
+    shape = (8, 6, 10)
+    N = int(np.prod(shape))
+    x = I.coords(shape)
+    k = [2 * np.pi * kvec[a] / shape[a] for a in range(3)]
+    phase = sum(k[a] * x[a] for a in range(3))
+    D, kd, cb0, eps = 0.1, 0.01, 0.5, 1e-3
+    o = oracle.Oracle(shape, a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.1, C=0.0625, E=0.0,
+                      c_b0=cb0, D_c=D, k_d=kd, tau=0.9, ch_substeps=nsub)
+    u = np.repeat(np.array(u0)[:, None], N, axis=1)
+    o.init_fields(np.ones(N), cb0 + eps * np.cos(phase), None, u)
+    g = 1.0 - (1j * sum(u0[a] * math.sin(k[a]) for a in range(3))
+               + D * sum(4 * math.sin(k[a] / 2) ** 2 for a in range(3)) + kd) / nsub
+    G = g ** nsub
+    for t in (1, 10, 40):
+        o.step(t - o.observables()[0]["step"])
+        want = cb0 + eps * np.real(G ** t * np.exp(1j * phase))
+        assert np.abs(o.fields()["c"] - want).max() <= 8 * nsub * t * EPS
+        assert np.abs(o.fields()["psi"] - 1.0).max() == 0.0
+
+
 # ------------------------------------------------------ discrete free energy
 def _free_energy(psi, c, shape, p, owner=None, surf=None):
     """Eq. 1 on the lattice (torch, FP64): sum over fluid nodes of
