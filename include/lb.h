@@ -97,6 +97,10 @@ typedef struct {
     double f16_scale;            /* FP16 storage scale, a power of two; 0 -> 16384 */
     int32_t max_colloids;        /* particle capacity, <= 127 (owner byte); 0 -> 64 */
     uint32_t flags;              /* options, 0 or a combination of the LB_* bits below */
+    int32_t ch_substeps;         /* psi/c updates per LB step, 1..64 (0 -> 1): each takes a
+                                    time step 1/n with mu and chi recomputed and u held, so
+                                    the explicit stability bounds apply to M_psi/n and
+                                    (12 D_c + k_d)/n (the paper's M_psi = 0.4 needs 2) */
 } lb_params;
 
 /* lb_params.flags: readings the paper leaves open, off by default.
@@ -139,9 +143,11 @@ typedef struct lb_ctx lb_ctx; /* opaque */
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes);
 
 /* Validate p and create a context for one box.  Checks: the size limits of
- * lb_params, tau > 1/2, rho0 > 0, kappa, M_psi, C, D_c, k_d >= 0, explicit-Euler
- * stability of the psi and c updates, M_psi (12|a| + 36|b| + 144 kappa) < 2
- * and 12 D_c + k_d < 2 (LB_E_INVALID otherwise).  dev_arena: device memory
+ * lb_params, tau > 1/2, rho0 > 0, kappa, M_psi, C, D_c, k_d >= 0, known
+ * flags, ch_substeps in [0, 64], explicit-Euler stability of the psi and c
+ * updates per sub-step, M_psi (12|a| + 36|b| + 144 kappa) / n < 2 and
+ * (12 D_c + k_d) / n < 2 with n = max(ch_substeps, 1) (LB_E_INVALID
+ * otherwise).  dev_arena: device memory
  * of at least lb_footprint_bytes, 256-byte aligned (borrowed; LB_E_INVALID
  * if misaligned), or NULL for the library to
  * allocate it (LB_E_OOM if it cannot).  hip_stream: a hipStream_t, or NULL
@@ -211,11 +217,12 @@ lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
 
 /* Advance n contexts by nsteps each with batched launches: every kernel of
  * the step is one launch covering all boxes (boxes may differ in size and in
- * particle count; all must share the precision), and on a non-default stream
- * the launch sequence of two steps is captured once as a HIP graph and
- * replayed.  Work goes to the stream of ctxs[0]; the call synchronises that
- * stream before returning.  LB_E_INVALID for an empty list, a repeated
- * context or mixed precisions; LB_E_STATE if a context lacks its fields. */
+ * particle count; all must share the precision and ch_substeps), and on a
+ * non-default stream the launch sequence of two steps is captured once as a
+ * HIP graph and replayed.  Work goes to the stream of ctxs[0]; the call
+ * synchronises that stream before returning.  LB_E_INVALID for an empty
+ * list, a repeated context, mixed precisions or mixed ch_substeps;
+ * LB_E_STATE if a context lacks its fields. */
 lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
 
 /* Launch shapes of the three lattice kernels (chemical potential,

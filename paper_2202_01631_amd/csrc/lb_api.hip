@@ -22,10 +22,13 @@ size_t storage_bytes(int prec) { return prec == LB_FP64 ? 8 : (prec == LB_FP32 ?
 size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 
 // Arena layout (each piece 256-byte aligned): f[2] (19 N storage), psi[2],
-// c[2], mu and chi (N compute each), u (3N compute), owner (N bytes).
+// c[2], mu and chi (N compute each), u (3N compute), owner (N bytes), and
+// with psi/c sub-steps one more psi and c pair (N compute each).
 struct Layout {
-    size_t f[2], psi[2], cc[2], mu, chi, u, own, total;
+    size_t f[2], psi[2], cc[2], mu, chi, u, own, psis, ccs, total;
 };
+
+int substeps_of(const lb_params &p) { return p.ch_substeps > 1 ? p.ch_substeps : 1; }
 
 Layout layout_of(const lb_params &p)
 {
@@ -40,6 +43,11 @@ Layout layout_of(const lb_params &p)
     L.chi = o; o = align256(o + N * cb);
     L.u = o; o = align256(o + 3 * N * cb);
     L.own = o; o = align256(o + N);
+    L.psis = L.ccs = 0;
+    if (substeps_of(p) > 1) {
+        L.psis = o; o = align256(o + N * cb);
+        L.ccs = o; o = align256(o + N * cb);
+    }
     L.total = o;
     return L;
 }
@@ -142,17 +150,35 @@ static BoxDesc box_desc(lb_ctx *c, int parity)
     return d;
 }
 
-// Host side of a batch: descriptors and block/particle start tables, laid
-// out in one device buffer: [BoxDesc x n][bstart 3(n+1)][cstart n+1].
-static size_t batch_bytes(int n)
+// psi/c sub-steps ping-pong between the next-state pair and the scratch
+// pair, the last one landing in the next-state pair: sub-step s of n writes
+// the next-state pair when n-1-s is even, else the scratch pair.  Three
+// descriptor tables besides the step's own cover them: sub-step 0 (from the
+// state at t), and the two directions between the pairs.
+static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
 {
-    return align256(sizeof(BoxDesc) * n) + sizeof(int) * (4 * (size_t)n + 4);
+    void *ps = ptr(c, c->L.psis), *cs = ptr(c, c->L.ccs);
+    const int n = substeps_of(c->p);
+    for (int k = 0; k < 3; k++) t[k] = d;
+    if (n % 2 == 0) { t[0].b.psin = ps; t[0].b.ccn = cs; }
+    t[1].b.psi = d.b.psin; t[1].b.cc = d.b.ccn; t[1].b.psin = ps; t[1].b.ccn = cs;
+    t[2].b.psi = ps; t[2].b.cc = cs;
+}
+
+// Host side of a batch: descriptors and block/particle start tables, laid
+// out in one device buffer: [BoxDesc x n][bstart 3(n+1)][cstart n+1], then
+// with psi/c sub-steps three more [BoxDesc x n] tables.
+static size_t batch_bytes(int n, int nsub)
+{
+    const size_t d = align256(sizeof(BoxDesc) * n);
+    return align256(d + sizeof(int) * (4 * (size_t)n + 4)) + (nsub > 1 ? 3 * d : 0);
 }
 
 static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vector<char> &host,
                        char *dev, Batch &B)
 {
-    host.assign(batch_bytes(n), 0);
+    const int nsub = substeps_of(ctxs[0]->p);
+    host.assign(batch_bytes(n, nsub), 0);
     BoxDesc *d = (BoxDesc *)host.data();
     int *bst = (int *)(host.data() + align256(sizeof(BoxDesc) * n));
     int *cst = bst + 3 * (n + 1);
@@ -209,6 +235,18 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     B.args.nsec = (B.nchunk_max + BND_SCAN - 1) / BND_SCAN;
     B.args.nfix = B.ncol > 0 ? B.args.nsec * B.ncol : 0;
     B.args.boff = 0;
+    B.nsub = nsub;
+    for (int k = 0; k < 3; k++) B.dsub[k] = nullptr;
+    if (nsub > 1) {
+        const size_t dbytes = align256(sizeof(BoxDesc) * n);
+        const size_t base = align256(dbytes + sizeof(int) * (4 * (size_t)n + 4));
+        for (int j = 0; j < n; j++) {
+            BoxDesc t[3];
+            substep_tables(ctxs[j], d[j], t);
+            for (int k = 0; k < 3; k++) ((BoxDesc *)(host.data() + base + k * dbytes))[j] = t[k];
+        }
+        for (int k = 0; k < 3; k++) B.dsub[k] = (const BoxDesc *)(dev + base + k * dbytes);
+    }
 }
 
 static void drop_graphs(lb_ctx *c)
@@ -222,10 +260,11 @@ static lb_status refresh_self(lb_ctx *c)
 {
     if (!c->dirty) return LB_OK;
     drop_graphs(c);
-    if (!c->selfdev) HIP_TRY(c, hipMalloc((void **)&c->selfdev, 2 * align256(batch_bytes(1))));
+    const size_t bb = align256(batch_bytes(1, substeps_of(c->p)));
+    if (!c->selfdev) HIP_TRY(c, hipMalloc((void **)&c->selfdev, 2 * bb));
     std::vector<char> host[2];
     for (int par = 0; par < 2; par++) {
-        char *dev = c->selfdev + par * align256(batch_bytes(1));
+        char *dev = c->selfdev + par * bb;
         lb_ctx *one[1] = {c};
         batch_fill(one, 1, &par, host[par], dev, c->self[par]);
         HIP_TRY(c, hipMemcpyAsync(dev, host[par].data(), host[par].size(), hipMemcpyHostToDevice, c->stream));
@@ -372,11 +411,18 @@ static lb_status check_params(const lb_params *p, std::string &why)
         why = "unknown option flags";
         return LB_E_INVALID;
     }
-    if (p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
-        why = "M_psi above the explicit-Euler stability bound M (12|a| + 36|b| + 144 kappa) < 2";
+    if (p->ch_substeps < 0 || p->ch_substeps > 64) { why = "ch_substeps in [0, 64]"; return LB_E_INVALID; }
+    // the psi/c bounds hold per sub-step, of length 1/n
+    const double dt = 1.0 / substeps_of(*p);
+    if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
+        why = "M_psi above the explicit-Euler stability bound M (12|a| + 36|b| + 144 kappa) / n < 2 "
+              "(n = ch_substeps)";
         return LB_E_INVALID;
     }
-    if (12.0 * p->D_c + p->k_d >= 2.0) { why = "12 D_c + k_d must be < 2"; return LB_E_INVALID; }
+    if (dt * (12.0 * p->D_c + p->k_d) >= 2.0) {
+        why = "(12 D_c + k_d) / n must be < 2 (n = ch_substeps)";
+        return LB_E_INVALID;
+    }
     if (p->max_colloids < 0 || p->max_colloids > MAX_COLLOIDS) { why = "max_colloids in [0, 127]"; return LB_E_INVALID; }
     if (p->precision == LB_FP16_STORAGE && p->f16_scale != 0.0) {
         int e;
@@ -520,7 +566,10 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     KParams &k = c->kp;
     k.nx = p->nx; k.ny = p->ny; k.nz = p->nz; k.N = (int)c->N;
     k.rho0 = p->rho0; k.tau = p->tau; k.om = 1.0 / p->tau; k.pref = 1.0 - 0.5 / p->tau; k.a = p->a; k.b = p->b; k.kappa = p->kappa;
-    k.M = p->M_psi; k.C = p->C; k.E = p->E; k.cb0 = p->c_b0; k.D = p->D_c; k.kd = p->k_d;
+    // psi/c coefficients per sub-step of length 1/n (exactly the given ones for n = 1)
+    const int nsub = substeps_of(*p);
+    k.sub = 1.0 / nsub;
+    k.M = p->M_psi / nsub; k.C = p->C; k.E = p->E; k.cb0 = p->c_b0; k.D = p->D_c / nsub; k.kd = p->k_d / nsub;
     k.fx = p->ext_force[0]; k.fy = p->ext_force[1]; k.fz = p->ext_force[2];
     k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;
     k.inv_scale = 1.0f / k.scale;
@@ -786,6 +835,8 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
         if (ctxs[j]->stage < 1) return fail(ctxs[j], LB_E_STATE, "lb_init_fields must come first");
         if (ctxs[j]->p.precision != ctxs[0]->p.precision)
             return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share the precision");
+        if (substeps_of(ctxs[j]->p) != substeps_of(ctxs[0]->p))
+            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share ch_substeps");
         for (int i = 0; i < j; i++)
             if (ctxs[i] == ctxs[j]) return fail(ctxs[j], LB_E_INVALID, "context twice in a batch");
     }
@@ -794,7 +845,7 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
     std::vector<int> par0(n), par1(n);
     for (int j = 0; j < n; j++) { par0[j] = ctxs[j]->cur; par1[j] = 1 - ctxs[j]->cur; }
     char *dev = nullptr;
-    const size_t bb = align256(batch_bytes(n));
+    const size_t bb = align256(batch_bytes(n, substeps_of(c0->p)));
     HIP_TRY(c0, hipMalloc((void **)&dev, 2 * bb));
     Batch B0, B1;
     std::vector<char> h0, h1;

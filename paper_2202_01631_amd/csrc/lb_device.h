@@ -108,6 +108,8 @@ struct KParams {
     LaunchShape ls;            // shape of the current lattice launch
     double rho0, tau, a, b, kappa, M, C, E, cb0, D, kd;
     double om, pref;           // 1/tau and 1 - 1/(2 tau), formed once on the host
+    double sub;                // psi/c sub-step length 1/n (M, D, kd above already carry it):
+                               // scales the emission and the stored advection velocity
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
     unsigned flags;            // LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID

@@ -61,6 +61,10 @@ struct Batch {
     int zmarch;       // z-marching form of the psi/c update (all boxes of the batch)
     long long nodes;  // lattice nodes over all boxes
     int solute_force; // some box has LB_SOLUTE_FORCE (one-node collide-stream with the term)
+    int nsub;         // psi/c sub-steps per step (all boxes of the batch)
+    // with nsub > 1: descriptor tables of sub-step 0 (state at t -> its
+    // target), next-state -> scratch and scratch -> next-state psi/c pairs
+    const BoxDesc *dsub[3];
 };
 
 // Optional per-kernel HIP-event timing (groups 0..5: mu, collide, scalar,

@@ -453,9 +453,11 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
                 stp(fout + i * N, (unsigned)m * sizeof(T), gs, p.scale);
         }
     }
-    stb(uout, os, M.ux);
-    stb(uout + N, os, M.uy);
-    stb(uout + 2 * N, os, M.uz);
+    // u as the psi/c update uses it: times the sub-step length (1 by default)
+    const S us = (S)p.sub;
+    stb(uout, os, M.ux * us);
+    stb(uout + N, os, M.uy * us);
+    stb(uout + 2 * N, os, M.uz * us);
 }
 
 // V consecutive populations of one plane as S values (FP16 storage through
@@ -667,14 +669,15 @@ __global__ __launch_bounds__(256) void k_collide_v(BatchArgs A)
             }
         }
     });
-    // u at fluid nodes
+    // u at fluid nodes, times the sub-step length (1 by default)
+    const S us = (S)p.sub;
     if (!((unsigned)ow & smask_all)) {
         SVec<S, V> w0, w1, w2;
 #pragma unroll
         for (int k = 0; k < V; k++) {
-            w0.v[k] = M[k].ux;
-            w1.v[k] = M[k].uy;
-            w2.v[k] = M[k].uz;
+            w0.v[k] = M[k].ux * us;
+            w1.v[k] = M[k].uy * us;
+            w2.v[k] = M[k].uz * us;
         }
         stb((SVec<S, V> *)uout, os, w0);
         stb((SVec<S, V> *)(uout + N), os, w1);
@@ -684,9 +687,9 @@ __global__ __launch_bounds__(256) void k_collide_v(BatchArgs A)
         for (int k = 0; k < V; k++) {
             if (byte_of(ow, k) & OWN_SOLID) continue;
             const unsigned ok = os + k * (unsigned)sizeof(S);
-            stb(uout, ok, M[k].ux);
-            stb(uout + N, ok, M[k].uy);
-            stb(uout + 2 * N, ok, M[k].uz);
+            stb(uout, ok, M[k].ux * us);
+            stb(uout + N, ok, M[k].uy * us);
+            stb(uout + 2 * N, ok, M[k].uz * us);
         }
     }
 }
@@ -745,7 +748,7 @@ __device__ S emission(const KParams &p, const DColloid *__restrict__ col,
         const DColloid &q = col[om[d] - 1];
         double r[3];
         displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-        src = src + (S)(active_cap(q, r) ? q.am : q.ap);
+        src = src + (S)((active_cap(q, r) ? q.am : q.ap) * p.sub);
     }
     return src;
 }
@@ -1993,25 +1996,29 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
 {
     typedef typename Prec<P>::S S;
     constexpr int V4 = sizeof(S) == 4 ? 4 : 2;  // FP64 scalars: 2 per 16-byte access
-    // split: boundary nodes in fix-up launches (on the side stream if par)
+    // split: boundary nodes in fix-up launches (on the side stream if par);
+    // psi/c sub-steps keep everything in order on s
     const bool split = B.ncol > 0 && B.nodes >= SIDE_MIN_NODES;
-    const bool par = split && side && !tm;
+    const bool par = split && side && !tm && B.nsub <= 1;
     hipStream_t ss = par ? side->s : s;
     const dim3 gfix(B.args.nfix);
+    const int vm = B.vec[0] == 4 ? 4 : (B.vec[0] == 2 ? 2 : 1);
+    const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
+    auto mu = [&](const BatchArgs &a) {
+        if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a);
+        if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
+        else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(a);
+        else if (vm == 2 && bi) k_mu<S, 2, true><<<B.nblocks[0], 256, 0, s>>>(a);
+        else if (vm == 2) k_mu<S, 2, false><<<B.nblocks[0], 256, 0, s>>>(a);
+        else if (bi) k_mu<S, 1, true><<<B.nblocks[0], 256, 0, s>>>(a);
+        else k_mu<S, 1, false><<<B.nblocks[0], 256, 0, s>>>(a);
+    };
     if (tm) tm->begin(0, s);
     if (par) {
         hipEventRecord(side->ev[0], s);
         hipStreamWaitEvent(ss, side->ev[0], 0);
     }
-    if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(B.args);
-    const int vm = B.vec[0] == 4 ? 4 : (B.vec[0] == 2 ? 2 : 1);
-    const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
-    if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else if (vm == 2 && bi) k_mu<S, 2, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else if (vm == 2) k_mu<S, 2, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else if (bi) k_mu<S, 1, true><<<B.nblocks[0], 256, 0, s>>>(B.args);
-    else k_mu<S, 1, false><<<B.nblocks[0], 256, 0, s>>>(B.args);
+    mu(B.args);
     if (par) {
         hipEventRecord(side->ev[1], ss);
         hipStreamWaitEvent(s, side->ev[1], 0);
@@ -2028,7 +2035,10 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
         hipEventRecord(side->ev[2], s);
         hipStreamWaitEvent(ss, side->ev[2], 0);
     }
-    if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(B.args);
+    // sub-step 0 reads the state at t and writes the pair its table names
+    BatchArgs a0 = B.args;
+    if (B.nsub > 1) a0.d = B.dsub[0];
+    if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a0);
     const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
     auto scalar = [&](const dim3 gs, const BatchArgs &a) {
         if (vs == 4 && B.zmarch) {
@@ -2058,9 +2068,23 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
         scalar(dim3(h), B.args);
         scalar(dim3(B.nblocks[2] - h), a2);
     } else {
-        scalar(dim3(B.nblocks[2]), B.args);
+        scalar(dim3(B.nblocks[2]), a0);
     }
     if (tm) tm->end(2, s);
+    // later sub-steps: mu and chi of the previous result, then its update,
+    // from whichever pair sub-step j-1 wrote (the next-state pair when
+    // n-1-(j-1) is even) into the other
+    for (int j = 1; j < B.nsub; j++) {
+        BatchArgs a = B.args;
+        a.d = B.dsub[(B.nsub - j) % 2 == 0 ? 1 : 2];
+        if (tm) tm->begin(0, s);
+        mu(a);
+        if (tm) tm->end(0, s);
+        if (tm) tm->begin(2, s);
+        if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, s>>>(a);
+        scalar(dim3(B.nblocks[2]), a);
+        if (tm) tm->end(2, s);
+    }
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
     k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);

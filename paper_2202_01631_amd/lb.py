@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("C", C.c_double), ("E", C.c_double), ("c_b0", C.c_double),
                 ("D_c", C.c_double), ("k_d", C.c_double),
                 ("ext_force", C.c_double * 3), ("f16_scale", C.c_double),
-                ("max_colloids", C.c_int32), ("flags", C.c_uint32)]
+                ("max_colloids", C.c_int32), ("flags", C.c_uint32),
+                ("ch_substeps", C.c_int32)]
 
 
 class Colloid(C.Structure):
@@ -136,6 +137,7 @@ def make_params(shape, precision="fp64", **kw):
         p.ext_force[a] = float(ef[a])
     p.f16_scale = float(kw.get("f16_scale", 0.0))
     p.max_colloids = int(kw.get("max_colloids", 0))
+    p.ch_substeps = int(kw.get("ch_substeps", 0))
     p.flags = int(kw.get("flags", 0))
     return p
 

@@ -201,6 +201,113 @@ def test_option_flags_validated():
         lb.Box((8, 8, 8), "fp32", flags=4)
 
 
+# ------------------------------------------------------ psi/c sub-steps
+PAPER_FE = dict(a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.4)   # Sec. II.C mobility
+
+
+def _substep_spec(shape, nsub, seed=9):
+    u = I.uniform(seed, 30)
+    cols = [
+        I.janus((2.0 + u[0], 18.0 + u[1], 17.0 + u[2]), I.unit_vectors(seed, 1)[0], 4.2,
+                alpha=2e-3, mu=0.3, theta=60.0),
+        I.janus((24.0 + u[6], 26.0 + u[7], 25.0 + u[8]), I.unit_vectors(seed + 2, 1)[0], 5.1,
+                alpha=1e-3, mu=-0.2, theta=90.0, rho_p=2.0),
+    ]
+    cols[0]["vel"] = np.array([0.04, -0.01, 0.02])
+    cols[1]["vel"] = np.array([-0.02, 0.03, 0.01])
+    return _spec(shape, seed=seed, colloids=cols, ch_substeps=nsub, **PAPER_FE)
+
+
+def test_substeps_validated():
+    # the paper's mobility is beyond the bound of one unit psi update and
+    # within it for two sub-steps; n outside [0, 64] is rejected
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", **PAPER_FE)
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", ch_substeps=1, **PAPER_FE)
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", ch_substeps=65)
+    lb.Box((8, 8, 8), "fp32", ch_substeps=2, **PAPER_FE).close()
+
+
+@pytest.mark.parametrize("nsub", [2, 3])
+def test_fp64_substeps_match_oracle(nsub):
+    # psi/c sub-steps at M_psi = 0.4 with moving particles, cover/uncover,
+    # emission and a varying chi, 40 steps: FP64 within 1e-12 of the oracle;
+    # even and odd n reach the next-state fields by different buffer routes
+    g, o = run_pair(_substep_spec((40, 36, 34), nsub), 0)
+    changed = 0
+    for _ in range(4):
+        own0 = o.owner()
+        g.step(10)
+        o.step(10)
+        changed += int((o.owner() != own0).sum())
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+    assert changed > 0
+    _compare(g, o, 1e-12, "substeps %d" % nsub)
+    _, cg = g.observables()
+    _, co = o.observables()
+    for k in range(2):
+        for a in ("vel", "omega", "pos", "m"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+
+
+def test_substeps_fp32_graph_and_batch():
+    # FP32 with two sub-steps on a non-default stream (graph-replayed step
+    # pairs) within 2e-5 of the oracle after 20 steps; a batch of two boxes
+    # of different sizes equals each box alone, bit for bit; a batch mixing
+    # sub-step counts is rejected
+    import torch
+    spec = _substep_spec((40, 36, 34), 2)
+    o = oracle.from_spec(spec)
+    o.step(20)
+    g = lb.from_spec(spec, precision="fp32", stream=torch.cuda.Stream())
+    g.step(20)
+    _compare(g, o, 2e-5, "fp32 substeps")
+    o.close()
+    specs = [spec, _substep_spec((44, 40, 38), 2, seed=12)]
+    stream = torch.cuda.Stream()
+    batch = [lb.from_spec(s_, precision="fp32", stream=stream) for s_ in specs]
+    lb.batch_step(batch, 6)
+    for b_, s_ in zip(batch, specs):
+        alone = lb.from_spec(s_, precision="fp32")
+        alone.step(6)
+        assert np.array_equal(alone.populations(), b_.populations())
+        f1, f2 = alone.fields(), b_.fields()
+        assert np.array_equal(f1["psi"], f2["psi"]) and np.array_equal(f1["c"], f2["c"])
+        alone.close()
+    other = lb.from_spec(_substep_spec((40, 36, 34), 3), precision="fp32", stream=stream)
+    with pytest.raises(lb.LBError):
+        lb.batch_step([batch[0], other], 1)
+
+
+def test_substeps_boundary_fixup_path():
+    # a box above the side-stream size (boundary nodes in the fix-up
+    # kernels) with 16 moving spheres and two sub-steps at M_psi = 0.4, on a
+    # non-default stream: FP64 within 1e-12 and FP32 within 2e-5 of the
+    # oracle after two steps, owner map and links bit-exact
+    import torch
+    w = I.workload_many(n=168, count=16, radius=6.0, precision="fp32")
+    w = dict(w, params=dict(w["params"], ch_substeps=2, **PAPER_FE))
+    flush_print("[substeps] oracle 2 steps at 168^3")
+    o = oracle.from_spec(w)
+    o.step(2)
+    oown, olinks, ofields = o.owner(), o.links(), o.fields()
+    o.close()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        g = lb.from_spec(w, precision=prec, stream=torch.cuda.Stream())
+        g.step(2)
+        assert np.array_equal(g.owner(), oown)
+        assert np.array_equal(g.links(), olinks)
+        e = field_errors(g.fields(), ofields, oown < 0)
+        flush_print("[substeps] %s errors %s" % (prec, e))
+        assert max(e.values()) <= tol
+        t, _ = g.observables()
+        assert t["error_bits"] == 0
+        g.close()
+
+
 @pytest.mark.parametrize("seed", [3, 4, 5])
 def test_link_tables_bit_exact_random(seed):
     # many spheres at random non-integer positions, across the periodic
