@@ -202,7 +202,7 @@ int or_create(const or_params *p, or_ctx **out)
     if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
         return OR_E_INVALID;
     if (dt * (12.0 * p->D_c + p->k_d) >= 2.0) return OR_E_INVALID;
-    if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID)) return OR_E_INVALID;
+    if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID | OR_CAPILLARY_FORCE)) return OR_E_INVALID;
 
     or_ctx *c = (or_ctx *)zalloc(sizeof *c);
     if (!c) return OR_E_INVALID;
@@ -451,6 +451,42 @@ static double hat(const or_ctx *c, const double *fld, long n, long m)
     return c->owner[m] < 0 ? fld[m] : fld[n];
 }
 
+/* option OR_CAPILLARY_FORCE: thermodynamic stress of the psi part of Eq. 1 at
+ * fluid node n,
+ *   P = (a/2 psi^2 + 3b/4 psi^4 - kappa psi lap(psi) - kappa/2 |g|^2) I + kappa g g^T,
+ * the tensor whose divergence is psi grad(mu) for f = a/2 psi^2 + b/4 psi^4 +
+ * kappa/2 |grad psi|^2.  Face neighbours that are solid take the wetting ghost
+ * of the chemical potential; g is the central difference over the faces. */
+static void stress(const or_ctx *c, long n, double P[3][3])
+{
+    const or_params *p = &c->p;
+    int x, y, z;
+    coords(c, n, &x, &y, &z);
+    double ph[7];
+    for (int e = 1; e <= 6; e++) {
+        long m = nbr(c, n, e);
+        int k = c->owner[m];
+        if (k < 0) {
+            ph[e] = c->psi[m];
+        } else {
+            double r[3];
+            disp(c, &c->col[k], x, y, z, e, 0.5, r);
+            double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            double en = fabs(r[(e - 1) / 2]) / rn;
+            ph[e] = c->psi[n];
+            if (p->kappa > 0.0) ph[e] = c->psi[n] - (c->col[k].H / p->kappa) * en;
+        }
+    }
+    double ps = c->psi[n];
+    double lap = ph[1] + ph[2] + ph[3] + ph[4] + ph[5] + ph[6] - 6.0 * ps;
+    double g[3] = {(ph[1] - ph[2]) / 2.0, (ph[3] - ph[4]) / 2.0, (ph[5] - ph[6]) / 2.0};
+    double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    double s = p->a / 2.0 * ps * ps + 3.0 * p->b / 4.0 * ps * ps * ps * ps - p->kappa * ps * lap -
+               p->kappa / 2.0 * g2;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) P[a][b] = (a == b ? s : 0.0) + p->kappa * g[a] * g[b];
+}
+
 /* step 2: force, moments, collision, streaming and bounce-back on links */
 static void collide_stream(or_ctx *c)
 {
@@ -556,6 +592,20 @@ static void collide_stream(or_ctx *c)
         /* the part of it that does not depend on V and Omega */
         double dp0[3], t0[3], rc[3];
         for (int a = 0; a < 3; a++) dp0[a] = cd[a] * (2.0 * fsd - 6.0 * w * c->p.rho0 * cus);
+        if (c->p.flags & OR_CAPILLARY_FORCE) {
+            /* option: the stress at the link's fluid node on the link's share
+             * of the surface.  For the divergence of a stress with the
+             * isotropic stencil, -3 sum_i w_i c_i.P(x + c_i) with P(x)
+             * substituted at solid neighbours, the fluid nodes together
+             * receive -6 sum_links w_d c_d.P(x); the particle takes the
+             * opposite, so that the pair conserves momentum (reading: the
+             * proper momentum exchange of Sec. II.B, the capillary force of
+             * Sec. III.B) */
+            double P[3][3];
+            stress(c, n, P);
+            for (int b = 0; b < 3; b++)
+                dp0[b] += 6.0 * w * (cd[0] * P[0][b] + cd[1] * P[1][b] + cd[2] * P[2][b]);
+        }
         cross(r, dp0, t0);
         for (int a = 0; a < 3; a++) { c->F0[3 * k + a] += dp0[a]; c->T0[3 * k + a] += t0[a]; }
         /* drag tensor zeta = sum 6 w rho0 g g^T, g = (c_d, r x c_d) */

@@ -37,7 +37,7 @@ typedef struct {
     double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2 (Eq. 1) */
     double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); Eq. 3a */
     double ext_force[3];         /* uniform body force on the fluid (tests) */
-    uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID (0: neither) */
+    uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID, OR_CAPILLARY_FORCE */
     int32_t ch_substeps;         /* psi/c updates per LB step, time step 1/n each
                                     (mu and chi recomputed between them, u held); 0 -> 1 */
 } or_params;
@@ -46,9 +46,14 @@ typedef struct {
  * OR_SOLUTE_FORCE      the solvent also feels -c grad(mu_c), mu_c = C chi
  *                      (off by default: phoresis enters through the slip)
  * OR_EXPLICIT_COLLOID  explicit rigid-body update M X' = M X + F0 - zeta X
- *                      (Ladd) instead of the implicit one */
+ *                      (Ladd) instead of the implicit one
+ * OR_CAPILLARY_FORCE   each particle also receives the thermodynamic stress of
+ *                      the psi free energy at its boundary links, the share of
+ *                      the interfacial force that the solvent force leaves out
+ *                      at the particle surface (capillary and wetting forces) */
 #define OR_SOLUTE_FORCE 1u
 #define OR_EXPLICIT_COLLOID 2u
+#define OR_CAPILLARY_FORCE 4u
 
 typedef struct {
     double pos[3], m[3], vel[3], omega[3];

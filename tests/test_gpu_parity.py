@@ -198,7 +198,7 @@ def test_solute_force_fp32_and_forms():
 
 def test_option_flags_validated():
     with pytest.raises(lb.LBError):
-        lb.Box((8, 8, 8), "fp32", flags=4)
+        lb.Box((8, 8, 8), "fp32", flags=8)
 
 
 # ------------------------------------------------------ psi/c sub-steps

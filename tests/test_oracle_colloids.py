@@ -283,3 +283,85 @@ def test_explicit_update_conserves_momentum():
         defect = max(defect, float(np.abs((dgc["zeta"] @ (Xb - Xa))[:3]).max()))
     assert n_changed > 0  # cover/uncover exercised
     assert defect > 1e3 * 256 * N * EPS  # the implicit defect would have been visible
+
+
+def _capillary_part(shape, psi, col, **fe):
+    # F0, T0 with the option minus without it, one step from the same state
+    F, T = [], []
+    for flags in (0, oracle.CAPILLARY_FORCE):
+        o = oracle.Oracle(shape, flags=flags, **fe)
+        o.init_fields(psi, np.zeros(psi.size))
+        o.add_colloids([col])
+        o.step(1)
+        dg = o.colloid_diag(0)
+        F.append(dg["F0"].copy())
+        T.append(dg["T0"].copy())
+        o.close()
+    return F[1] - F[0], T[1] - T[0]
+
+
+FE_CAP = dict(a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.1, C=0.0625, E=0.0, c_b0=0.0, D_c=0.05,
+              k_d=1e-3, tau=1.0)
+
+
+def test_capillary_force_zero_in_uniform_fluid():
+    # option OR_CAPILLARY_FORCE: with psi uniform and neutral wetting the
+    # stress is a uniform pressure, whose link sum vanishes for any closed
+    # lattice surface (sum_links w_d c_d = 0), at any particle position
+    shape = (18, 16, 17)
+    N = int(np.prod(shape))
+    for psi0, pos, R in ((0.6, (7.3, 8.1, 6.6), 3.7), (-0.9, (0.4, 15.2, 9.9), 4.4)):
+        F, _ = _capillary_part(shape, np.full(N, psi0), dict(pos=pos, m=(0, 0, 1), radius=R,
+                                                              fixed=1), **FE_CAP)
+        assert np.abs(F).max() <= 64 * EPS
+
+
+def test_capillary_force_is_the_hookean_trap():
+    # a held sphere (radius 4.5, neutral wetting) cut by a flat interface
+    # (psi = -tanh((x - 8)/w) tanh((x - 24)/w), 32^3) at height d above it:
+    # cutting the interface saves the area pi (R^2 - d^2), so the capillary
+    # force is -2 pi sigma d along the normal (the Hookean trap behind the
+    # equilibrium positions of Sec. III.B; sigma = (2/3) sqrt(2 kappa A),
+    # Sec. II.C).  The lattice force is within 20% of it for d in [0.5, 2],
+    # zero at d = 0, odd in d and normal to the interface (up to 1e-6: the
+    # two-interface profile is odd about x = 8 only up to tanh tails of
+    # order e^-12)
+    shape = (32, 32, 32)
+    psi = I.slab(shape, I.WIDTH, axis=0)
+    sigma = (2.0 / 3.0) * math.sqrt(2.0 * 0.04 * 0.0625)
+
+    def fcap(d):
+        F, T = _capillary_part(shape, psi, dict(pos=(8.0 + d, 16.0, 16.0), m=(0, 1, 0),
+                                                radius=4.5, fixed=1), **FE_CAP)
+        assert np.abs(F[1:]).max() <= 1e-12 and np.abs(T).max() <= 1e-11
+        return F[0]
+
+    assert abs(fcap(0.0)) <= 1e-6
+    for d in (0.5, 1.0, 1.5, 2.0):
+        f = fcap(d)
+        assert 0.8 <= f / (-2.0 * math.pi * sigma * d) <= 1.15, d
+        assert abs(f + fcap(-d)) <= 1e-6
+
+
+def test_capillary_force_balances_the_solvent_force():
+    # psi grad(mu) = div P, so over the fluid the solvent's free-energy force
+    # -psi grad(mu) integrates to the surface stress that the particle takes:
+    # for a smooth out-of-equilibrium psi (wavelength 32) around a held
+    # sphere with neutral wetting, the capillary force cancels the net body
+    # force on the solvent (a different code path: the potential form of the
+    # collision) to within 5%, at two positions and radii
+    shape = (32, 32, 32)
+    N = int(np.prod(shape))
+    x, y, z = I.coords(shape)
+    k = 2.0 * math.pi / 32.0
+    psi = 0.4 * np.sin(k * x + 0.3) + 0.3 * np.cos(k * y - 0.2) * np.sin(k * z + 0.7)
+    for pos, R in (((13.3, 17.6, 9.2), 5.0), ((5.1, 20.4, 25.7), 4.5)):
+        F, _ = _capillary_part(shape, psi, dict(pos=pos, m=(0, 0, 1), radius=R, fixed=1), **FE_CAP)
+        o = oracle.Oracle(shape, **FE_CAP)
+        o.init_fields(psi, np.zeros(N))
+        o.add_colloids([dict(pos=pos, m=(0, 0, 1), radius=R, fixed=1)])
+        o.step(1)
+        sf = o.step_diag()["sum_force"]
+        o.close()
+        assert np.linalg.norm(sf) > 0.1
+        assert np.linalg.norm(F + sf) <= 0.05 * np.linalg.norm(sf), (F, sf)

@@ -218,7 +218,7 @@ def test_solute_force_option_closed_form():
 
 def test_option_flags_validated():
     with pytest.raises(RuntimeError):
-        oracle.Oracle((4, 4, 4), flags=4)
+        oracle.Oracle((4, 4, 4), flags=8)
 
 
 def test_paper_mobility_needs_substeps():
