@@ -113,9 +113,19 @@ typedef struct {
  * LB_EXPLICIT_COLLOID  explicit rigid-body update (Ladd), M X' = M X + F0 -
  *                      zeta X + transfers, instead of the implicit
  *                      (M + zeta) X' = M X + F0 + transfers.
+ * LB_CAPILLARY_FORCE   each particle also takes the stress of the psi free
+ *                      energy at the fluid node of each of its links,
+ *                      6 w_d c_d.P with P = (a/2 psi^2 + 3b/4 psi^4 - kappa
+ *                      psi lap(psi) - kappa/2 |grad psi|^2) I + kappa grad psi
+ *                      grad psi^T (wetting ghosts as in mu, central
+ *                      differences): the capillary and wetting force that the
+ *                      solvent force -psi grad(mu) leaves out at the particle
+ *                      surface (Sec. II.B momentum exchange, Sec. III.B
+ *                      trapping).  Part of F0, T0.
  * Other bits: LB_E_INVALID at lb_create. */
 #define LB_SOLUTE_FORCE 1u
 #define LB_EXPLICIT_COLLOID 2u
+#define LB_CAPILLARY_FORCE 4u
 
 typedef struct {                 /* FP64, caller-owned */
     double pos[3], m[3], vel[3], omega[3]; /* centre, axis (normalised on add), V, Omega */

@@ -407,7 +407,7 @@ static lb_status check_params(const lb_params *p, std::string &why)
         why = "kappa, M_psi, C, D_c, k_d must be >= 0";
         return LB_E_INVALID;
     }
-    if (p->flags & ~(LB_SOLUTE_FORCE | LB_EXPLICIT_COLLOID)) {
+    if (p->flags & ~(LB_SOLUTE_FORCE | LB_EXPLICIT_COLLOID | LB_CAPILLARY_FORCE)) {
         why = "unknown option flags";
         return LB_E_INVALID;
     }

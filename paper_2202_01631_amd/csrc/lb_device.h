@@ -112,7 +112,7 @@ struct KParams {
                                // scales the emission and the stored advection velocity
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
-    unsigned flags;            // LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID
+    unsigned flags;            // LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID, LB_CAPILLARY_FORCE
 };
 
 // ---------------------------------------------------------- particle record

@@ -1207,6 +1207,37 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
 // zeta = sum 6 w_d rho0 g g^T, g = (c_d, r x c_d), are accumulated in FP64.
 // Then (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
 // R' = R + V', m' = m rotated by |Omega'| about Omega'.
+// Option LB_CAPILLARY_FORCE: the stress of the psi free energy at the link's
+// fluid node n,
+//   P = (a/2 psi^2 + 3b/4 psi^4 - kappa psi lap(psi) - kappa/2 |g|^2) I + kappa g g^T
+// (the tensor whose divergence is psi grad(mu)), with the wetting ghost of the
+// chemical potential at solid face neighbours and g by central differences
+// over the faces, on the link's share of the surface: 6 w_d c_d.P joins the
+// momentum the particle takes.  Under the isotropic divergence of a stress
+// with P(x) at solid neighbours the fluid nodes together take
+// -6 sum_links w_d c_d.P, so fluid and particle exchange it without loss.
+template <class S>
+__device__ void capillary_link(const KParams &p, const DColloid *__restrict__ col,
+                               const uint8_t *__restrict__ own, const S *__restrict__ psi, int n,
+                               const int fn[6], int x, int y, int z, double w, const double cd[3],
+                               double dp[3])
+{
+#pragma clang fp contract(off)
+    const S ps = psi[n];
+    double ph[6];
+    for (int e = 0; e < 6; e++) ph[e] = (double)face_psi<S>(p, col, own[fn[e]], e, x, y, z, ps, psi[fn[e]]);
+    const double s0 = (double)ps;
+    const double lap = ph[0] + ph[1] + ph[2] + ph[3] + ph[4] + ph[5] - 6.0 * s0;
+    const double g[3] = {(ph[0] - ph[1]) / 2.0, (ph[2] - ph[3]) / 2.0, (ph[4] - ph[5]) / 2.0};
+    const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const double sc = p.a / 2.0 * s0 * s0 + 3.0 * p.b / 4.0 * s0 * s0 * s0 * s0 -
+                      p.kappa * s0 * lap - p.kappa / 2.0 * g2;
+    double P[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) P[a][b] = (a == b ? sc : 0.0) + p.kappa * g[a] * g[b];
+    for (int b = 0; b < 3; b++) dp[b] += 6.0 * w * (cd[0] * P[0][b] + cd[1] * P[1][b] + cd[2] * P[2][b]);
+}
+
 template <int P>
 __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
 {
@@ -1273,10 +1304,12 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         const double cus = ex * slip[0] + ey * slip[1] + ez * slip[2];
         st_pop(fout, slot, (S)((double)gs - 6.0 * w * rho0 * cub), p.scale);
         const double mag = 2.0 * fs - 6.0 * w * rho0 * cus;
-        const double dp[3] = {ex * mag, ey * mag, ez * mag};
+        double dp[3] = {ex * mag, ey * mag, ez * mag};
+        const double cd[3] = {(double)ex, (double)ey, (double)ez};
+        if (p.flags & LB_CAPILLARY_FORCE)
+            capillary_link<S>(p, col, own, (const S *)D.b.psi, n, fn, x, y, z, w, cd, dp);
         double t[3];
         cross3(r, dp, t);
-        const double cd[3] = {(double)ex, (double)ey, (double)ez};
         double rc[3];
         cross3(r, cd, rc);
         const double gv[6] = {cd[0], cd[1], cd[2], rc[0], rc[1], rc[2]};

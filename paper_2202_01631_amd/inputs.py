@@ -137,6 +137,29 @@ def workload_small(seed=BASE_SEED):
                 colloids=[janus((16.0, 16.0, 12.0), (0.0, 0.0, 1.0), 4.0)])
 
 
+# the paper's own regime (Sec. II.C): A = C = 0.0625, kappa = 0.04,
+# M_psi = 0.4 (two psi/c sub-steps per step), M_phi = 0.8 (D_c = C M_phi =
+# 0.05), k_d = 1e-3, R = 4.5, 64 x 96 x 96 box, flat interfaces normal to x;
+# particles feel the capillary stress (option flag 4)
+PAPER_REGIME = dict(rho0=1.0, tau=1.0, a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.4,
+                    C=0.0625, c_b0=0.0, D_c=0.05, k_d=1e-3, ch_substeps=2, flags=4)
+
+
+def workload_paper(particles, E=-0.25, shape=(64, 96, 96), single_phase=False):
+    """Box of the paper's regime: psi = -tanh((x - L/4)/w) tanh((x - 3L/4)/w)
+    (interfaces at x = 16 and 48 for L = 64, psi > 0 between them), c = 0, or
+    with single_phase psi = 0 and A = kappa = E = 0.  `particles`: list of
+    janus() dicts (radius 4.5 in the paper)."""
+    p = dict(PAPER_REGIME, E=E)
+    if single_phase:
+        p.update(a=0.0, b=0.0, kappa=0.0, E=0.0)
+        psi = np.zeros(int(np.prod(shape)))
+    else:
+        psi = slab(shape, WIDTH, axis=0)
+    return dict(name="paper_%dx%dx%d" % shape, shape=shape, precision="fp32", params=p,
+                psi=psi, c=np.zeros(psi.size), colloids=list(particles))
+
+
 def workload_single(n=128, seed=BASE_SEED + 1, theta=None, ratio=None, mu=None):
     """n^3 FP32 box: flat interface at n/2, noise +-0.01, one Janus sphere of
     radius 8 centred on the interface; contact angle from {60, 90, 120},

@@ -133,11 +133,14 @@ def test_fp64_several_moving_colloids(seed):
 
 
 @pytest.mark.parametrize("flags", [lb.LB_SOLUTE_FORCE, lb.LB_EXPLICIT_COLLOID,
-                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID])
+                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID,
+                                   lb.LB_CAPILLARY_FORCE,
+                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID | lb.LB_CAPILLARY_FORCE])
 def test_fp64_options_match_oracle(flags):
-    # the two options (solvent force -c grad(mu_c); explicit rigid-body
-    # update) against the oracle's: moving particles with cover/uncover,
-    # solute emitted and a nonzero E so that chi varies, 40 steps
+    # the options (solvent force -c grad(mu_c); explicit rigid-body update;
+    # capillary stress on the particles) against the oracle's: moving
+    # particles with cover/uncover, 60 and 90 degree wetting, solute emitted
+    # and a nonzero E so that chi varies, 40 steps
     shape = (40, 36, 34)
     u = I.uniform(9, 30)
     cols = [
@@ -168,6 +171,29 @@ def test_fp64_options_match_oracle(flags):
     fg = g.colloid_forces()
     for k in range(2):
         assert np.abs(fg["F"][k] - o.colloid_diag(k)["F"]).max() <= 1e-11
+
+
+def test_capillary_force_fp32_held_sphere():
+    # the capillary stress on a held sphere cut by a flat interface (1.3 above
+    # it, 60 degree wetting) after one step: FP32 against the FP64 oracle to
+    # 1e-4 of its size; the particle force of the FP64 library to 1e-12
+    shape = (32, 32, 32)
+    N = int(np.prod(shape))
+    psi = I.slab(shape, I.WIDTH, axis=0)
+    col = I.janus((9.3, 16.2, 15.9), (0.0, 1.0, 0.0), 4.5, alpha=0.0, mu=0.0, theta=60.0, fixed=1)
+    spec = dict(shape=shape, precision="fp64", params=dict(I.FREE_ENERGY, E=0.0,
+                flags=lb.LB_CAPILLARY_FORCE), psi=psi, c=np.zeros(N), colloids=[col])
+    o = oracle.from_spec(spec)
+    o.step(1)
+    F0 = o.colloid_diag(0)["F0"]
+    assert abs(F0[0]) > 0.05
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        g = lb.from_spec(spec, precision=prec)
+        g.step(1)
+        fg = g.colloid_forces()
+        flush_print("[capillary] %s F0 %s oracle %s" % (prec, fg["F0"][0], F0))
+        assert np.abs(fg["F0"][0] - F0).max() <= tol * np.abs(F0).max()
+        g.close()
 
 
 def test_solute_force_fp32_and_forms():
