@@ -181,6 +181,40 @@ def serving_run(torch, I, nreq, rate, step_scale):
     return summ
 
 
+def paper_regime_run(torch, lb, I, steps=2000, warmup=200):
+    """The paper's own regime (Sec. II.C): 64 x 96 x 96, M_psi = 0.4 in two
+    psi/c sub-steps, D_c = 0.05, R = 4.5, capillary stress on the particles;
+    an active Janus sphere on the interface and an inactive one in the bulk,
+    FP32, graph-replayed on a non-default stream.  Beside it the same box in
+    the default form (M_psi = 0.1, one psi/c update per step, no capillary
+    stress), to show what the sub-steps and the stress cost.  Tuned launch
+    shapes where the cache has them."""
+    from paper_2202_01631_amd import tune
+    cols = [I.janus((16.3, 47.6, 48.2), (0.29, 0.94, 0.19), 4.5, alpha=1e-3, mu=0.3, theta=60.0),
+            I.janus((33.0, 20.4, 70.7), (0.0, 0.0, 1.0), 4.5, alpha=0.0, mu=0.2, theta=90.0)]
+    out = {}
+    for name, over in (("paper", {}), ("default_form", dict(M_psi=0.1, ch_substeps=1, flags=0))):
+        w = I.workload_paper(cols, E=-0.25)
+        w["params"].update(over)
+        st = torch.cuda.Stream()
+        b = lb.from_spec(w, stream=st)
+        tune.apply(b)
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        t, _ = b.observables()
+        b.close()
+        N = w["shape"][0] * w["shape"][1] * w["shape"][2]
+        out[name] = dict(ms_per_step=round(ms, 5), mlups=round(N / ms / 1e3, 1),
+                         error_bits=t["error_bits"])
+    out.update(shape=[64, 96, 96], precision="fp32", particles=2, steps=steps,
+               paper=dict(out["paper"], M_psi=0.4, ch_substeps=2, capillary_force=True))
+    return out
+
+
 def cpu_baseline(spec):
     import oracle
     log("[bench] cpu baseline: FP64 oracle, 1 step of the workload")
@@ -302,6 +336,10 @@ def main():
         log("[bench] batched sweep: %d boxes x %d steps" % (args.batch, args.batch_steps))
         out["batched_sweep"] = batched_sweep(torch, lb, I, args.batch, args.batch_steps)
         log("[bench] batched sweep %s" % out["batched_sweep"])
+    if not args.only:
+        log("[bench] paper regime 64x96x96")
+        out["paper_regime"] = paper_regime_run(torch, lb, I)
+        log("[bench] paper regime %s" % out["paper_regime"])
     if args.serve and not args.only:
         log("[bench] serving: %d requests" % args.serve)
         out["serving"] = serving_run(torch, I, args.serve, 50.0, args.serve_scale)
