@@ -203,6 +203,9 @@ int or_create(const or_params *p, or_ctx **out)
         return OR_E_INVALID;
     if (dt * (12.0 * p->D_c + p->k_d) >= 2.0) return OR_E_INVALID;
     if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID | OR_CAPILLARY_FORCE)) return OR_E_INVALID;
+    if (!(p->soft_eps >= 0.0)) return OR_E_INVALID;
+    if (p->soft_eps > 0.0 && !(p->soft_sigma > 0.0 && p->soft_nu > 0.0 && p->soft_hc > 0.0))
+        return OR_E_INVALID;
 
     or_ctx *c = (or_ctx *)zalloc(sizeof *c);
     if (!c) return OR_E_INVALID;
@@ -623,6 +626,36 @@ static void collide_stream(or_ctx *c)
     c->diag[OR_DIAG_SUM_DMASS] = dmass;
 }
 
+/* step 2b (option, soft_eps > 0): soft-sphere repulsion for close encounters
+ * (the paper mentions a soft potential for near-contact encounters without
+ * giving it).  Reading: the shifted-force soft sphere
+ *   U(h) = eps (sigma/h)^nu, force -dU/dh shifted to vanish at the cutoff hc,
+ * on the surface gap h = |R_j - R_i| - a_i - a_j (minimum image), added to
+ * the velocity-independent force F0 of both particles, from the positions at
+ * t.  Central: no torque. */
+static void soft_contacts(or_ctx *c)
+{
+    const or_params *p = &c->p;
+    if (!(p->soft_eps > 0.0)) return;
+    int L[3] = {c->nx, c->ny, c->nz};
+    for (int i = 0; i < c->ncol; i++)
+        for (int j = i + 1; j < c->ncol; j++) {
+            const or_colloid *a = &c->col[i], *b = &c->col[j];
+            double d[3];
+            for (int e = 0; e < 3; e++) d[e] = min_image(b->pos[e] - a->pos[e], L[e]);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double h = r - a->radius - b->radius;
+            if (!(h < p->soft_hc)) continue;
+            if (h < 0.01) h = 0.01;
+            double f = p->soft_nu * p->soft_eps * pow(p->soft_sigma, p->soft_nu) *
+                       (pow(h, -(p->soft_nu + 1.0)) - pow(p->soft_hc, -(p->soft_nu + 1.0)));
+            for (int e = 0; e < 3; e++) {
+                c->F0[3 * i + e] -= f * d[e] / r;
+                c->F0[3 * j + e] += f * d[e] / r;
+            }
+        }
+}
+
 /* step 3: Cahn-Hilliard update of psi and advection-diffusion-reaction update
  * of c (Eq. 3), explicit Euler over a time step dt (1, or 1/n for n
  * sub-steps), fluxes through the 6 faces of each node; no flux through faces
@@ -809,6 +842,7 @@ int or_step(or_ctx *c, int64_t nsteps)
     for (int64_t s = 0; s < nsteps; s++) {
         chemical_potential(c);
         collide_stream(c);
+        soft_contacts(c);
         /* psi/c sub-steps: the first from psi(t), c(t) and mu(t); each later
          * one from the previous result, with mu and chi recomputed and u held */
         c->diag[OR_DIAG_SUM_SRC] = 0.0;

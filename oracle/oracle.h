@@ -40,6 +40,12 @@ typedef struct {
     uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID, OR_CAPILLARY_FORCE */
     int32_t ch_substeps;         /* psi/c updates per LB step, time step 1/n each
                                     (mu and chi recomputed between them, u held); 0 -> 1 */
+    double soft_eps, soft_sigma, soft_nu, soft_hc;
+                                 /* soft-sphere repulsion between particles whose surface
+                                    gap h is below soft_hc: each takes nu eps sigma^nu
+                                    (h^-(nu+1) - hc^-(nu+1)) along the line of centres,
+                                    away from the other (h below 0.01 taken as 0.01);
+                                    soft_eps = 0: none */
 } or_params;
 
 /* options (readings of what the paper leaves open):

@@ -365,3 +365,76 @@ def test_capillary_force_balances_the_solvent_force():
         o.close()
         assert np.linalg.norm(sf) > 0.1
         assert np.linalg.norm(F + sf) <= 0.05 * np.linalg.norm(sf), (F, sf)
+
+
+SOFT = dict(soft_eps=1e-3, soft_sigma=1.0, soft_nu=1.0, soft_hc=3.0)
+
+
+def _soft_energy(h, eps, sigma, nu, hc):
+    # shifted-force soft sphere: U and -dU/dh both vanish at the cutoff
+    return (eps * (sigma / h) ** nu - eps * (sigma / hc) ** nu
+            + (h - hc) * nu * eps * sigma ** nu / hc ** (nu + 1.0))
+
+
+def _pair_F0(shape, p1, p2, R1, R2, **soft):
+    out = []
+    for s in ({}, soft):
+        o = oracle.Oracle(shape, **dict(FE_CAP, **s))
+        N = int(np.prod(shape))
+        o.init_fields(np.ones(N), np.zeros(N))
+        o.add_colloids([dict(pos=p1, m=(0, 0, 1), radius=R1, fixed=1),
+                        dict(pos=p2, m=(0, 0, 1), radius=R2, fixed=1)])
+        o.step(1)
+        out.append([(o.colloid_diag(k)["F0"].copy(), o.colloid_diag(k)["T0"].copy()) for k in range(2)])
+        o.close()
+    return [(out[1][k][0] - out[0][k][0], out[1][k][1] - out[0][k][1]) for k in range(2)]
+
+
+@pytest.mark.parametrize("nu", [1.0, 2.5])
+def test_soft_sphere_force_is_minus_the_energy_slope(nu):
+    # two held spheres (radii 3.1 and 4.3) with surface gap h below the
+    # cutoff, the second time across the periodic wrap in x: the added force is -dU/dh of the
+    # shifted-force energy (central difference of U, to 1e-7), along the line
+    # of centres, equal and opposite, with no torque; zero beyond the cutoff
+    soft = dict(SOFT, soft_nu=nu)
+    shape = (30, 20, 20)
+    d = np.array([0.6, -0.3, 0.74])
+    d /= np.linalg.norm(d)
+    for p1, h in (((8.2, 10.1, 9.7), 2.3), ((27.0, 9.0, 10.3), 1.1)):
+        c2 = np.mod(np.array(p1) + (3.1 + 4.3 + h) * d, np.array(shape, dtype=float))
+        (F1, T1), (F2, T2) = _pair_F0(shape, p1, tuple(c2), 3.1, 4.3, **soft)
+        dh = 1e-5
+        f = -(_soft_energy(h + dh, 1e-3, 1.0, nu, 3.0) - _soft_energy(h - dh, 1e-3, 1.0, nu, 3.0)) / (2 * dh)
+        assert f > 0
+        assert np.allclose(F2, f * d, rtol=1e-7, atol=0), (F2, f * d)
+        assert np.array_equal(F1, -F2)
+        assert np.abs(T1).max() == 0.0 and np.abs(T2).max() == 0.0
+    c2 = np.array((8.2, 10.1, 9.7)) + (3.1 + 4.3 + 3.01) * d
+    (F1, _), (F2, _) = _pair_F0(shape, (8.2, 10.1, 9.7), tuple(c2), 3.1, 4.3, **soft)
+    assert np.abs(F1).max() == 0.0 and np.abs(F2).max() == 0.0
+
+
+def test_soft_sphere_pushes_close_spheres_apart():
+    # two free spheres at rest in quiescent uniform fluid with surface gap
+    # 2.2 (inside the cutoff 3): with the repulsion (eps = 0.05) they move
+    # apart along the line of centres with equal and opposite velocities
+    # (equal masses) and the gap grows; without it nothing moves
+    shape = (40, 20, 20)
+    N = int(np.prod(shape))
+    gap = {}
+    for soft in ({}, dict(SOFT, soft_eps=5e-2)):
+        o = oracle.Oracle(shape, **dict(FE_CAP, **soft))
+        o.init_fields(np.ones(N), np.zeros(N))
+        o.add_colloids([dict(pos=(15.9, 10.2, 9.9), m=(0, 0, 1), radius=4.0),
+                        dict(pos=(26.1, 10.2, 9.9), m=(0, 0, 1), radius=4.0)])
+        o.step(100)
+        t, cs = o.observables()
+        assert t["error_bits"] == 0
+        gap[bool(soft)] = cs[1]["pos"][0] - cs[0]["pos"][0] - 8.0
+        if soft:
+            v0, v1 = cs[0]["vel"], cs[1]["vel"]
+            assert v0[0] < 0 < v1[0]
+            assert abs(v0[0] + v1[0]) <= 1e-6 * abs(v1[0])
+        o.close()
+    assert abs(gap[False] - 2.2) <= 1e-9   # quiescent uniform fluid: nothing moves
+    assert gap[True] - 2.2 > 1e-3
