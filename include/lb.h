@@ -101,6 +101,15 @@ typedef struct {
                                     time step 1/n with mu and chi recomputed and u held, so
                                     the explicit stability bounds apply to M_psi/n and
                                     (12 D_c + k_d)/n (the paper's M_psi = 0.4 needs 2) */
+    double soft_eps, soft_sigma, soft_nu, soft_hc;
+                                 /* soft-sphere repulsion for close encounters (soft_eps = 0:
+                                    none; else sigma, nu, hc > 0): two particles of a box
+                                    whose surface gap h (minimum image) is below hc each take
+                                    nu eps sigma^nu (h^-(nu+1) - hc^-(nu+1)) along the line of
+                                    centres, away from the other (h below 0.01 taken as
+                                    0.01), from the positions at the start of the step, as
+                                    part of F0 (the shifted-force form of the potential
+                                    eps (sigma/h)^nu) */
 } lb_params;
 
 /* lb_params.flags: readings the paper leaves open, off by default.

@@ -412,6 +412,11 @@ static lb_status check_params(const lb_params *p, std::string &why)
         return LB_E_INVALID;
     }
     if (p->ch_substeps < 0 || p->ch_substeps > 64) { why = "ch_substeps in [0, 64]"; return LB_E_INVALID; }
+    if (!(p->soft_eps >= 0.0) ||
+        (p->soft_eps > 0.0 && !(p->soft_sigma > 0.0 && p->soft_nu > 0.0 && p->soft_hc > 0.0))) {
+        why = "soft_eps must be >= 0, and with soft_eps > 0 soft_sigma, soft_nu, soft_hc > 0";
+        return LB_E_INVALID;
+    }
     // the psi/c bounds hold per sub-step, of length 1/n
     const double dt = 1.0 / substeps_of(*p);
     if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
@@ -574,6 +579,7 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     k.scale = p->precision == LB_FP16_STORAGE ? (float)c->p.f16_scale : 1.0f;
     k.inv_scale = 1.0f / k.scale;
     k.flags = p->flags;
+    k.soft_eps = p->soft_eps; k.soft_sigma = p->soft_sigma; k.soft_nu = p->soft_nu; k.soft_hc = p->soft_hc;
     set_shapes(c);
     c->stream = (hipStream_t)hip_stream;
     c->L = layout_of(c->p);

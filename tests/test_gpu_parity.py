@@ -173,6 +173,45 @@ def test_fp64_options_match_oracle(flags):
         assert np.abs(fg["F"][k] - o.colloid_diag(k)["F"]).max() <= 1e-11
 
 
+@pytest.mark.parametrize("nu", [1.0, 2.5])
+def test_soft_sphere_matches_oracle(nu):
+    # soft-sphere repulsion (eps 0.05, sigma 1, cutoff 3) among four moving
+    # spheres placed 2.2-2.5 apart, one pair across the periodic wrap in x:
+    # FP64 fields within 1e-12, particle states and reported F0 within 1e-11
+    # of the oracle after 30 steps
+    shape = (48, 36, 34)
+    soft = dict(soft_eps=0.05, soft_sigma=1.0, soft_nu=nu, soft_hc=3.0)
+    pos = [(5.0, 18.0, 17.0), (15.2, 18.0, 17.0), (15.2, 28.5, 17.0), (42.7, 18.0, 17.0)]
+    vel = [(0.01, 0.0, 0.0), (-0.01, 0.005, 0.0), (0.0, -0.01, 0.0), (0.0, 0.0, 0.005)]
+    cols = []
+    for k in range(4):
+        c = I.janus(pos[k], I.unit_vectors(40 + k, 1)[0], 4.0, alpha=1e-3, mu=0.1, theta=90.0)
+        c["vel"] = np.array(vel[k])
+        cols.append(c)
+    spec = _spec(shape, seed=21, colloids=cols, **soft)
+    g, o = run_pair(spec, 0)
+    for _ in range(3):
+        g.step(10)
+        o.step(10)
+        assert np.array_equal(g.owner(), o.owner())
+    _compare(g, o, 1e-12, "soft nu=%g" % nu)
+    _, cg = g.observables()
+    _, co = o.observables()
+    fg = g.colloid_forces()
+    for k in range(4):
+        for a in ("vel", "omega", "pos"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+        assert np.abs(fg["F0"][k] - o.colloid_diag(k)["F0"]).max() <= 1e-11
+
+
+def test_soft_sphere_parameters_validated():
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", soft_eps=-1.0)
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", soft_eps=0.1, soft_sigma=0.0, soft_nu=1.0, soft_hc=3.0)
+    lb.Box((8, 8, 8), "fp32", soft_eps=0.1, soft_sigma=1.0, soft_nu=1.0, soft_hc=3.0).close()
+
+
 def test_capillary_force_fp32_held_sphere():
     # the capillary stress on a held sphere cut by a flat interface (1.3 above
     # it, 60 degree wetting) after one step: FP32 against the FP64 oracle to

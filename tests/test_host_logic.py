@@ -1,5 +1,5 @@
 """Host-side logic that needs no GPU: autotuner candidates and cache
-format, serving admission sizes."""
+format, serving admission sizes, the binding's structure layouts."""
 import json
 import os
 
@@ -7,6 +7,8 @@ import pytest
 
 from paper_2202_01631_amd import inputs as I
 from paper_2202_01631_amd import lb, serve, tune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _decode(code):
@@ -95,3 +97,37 @@ def test_bench_kernel_hash_ignores_comments(tmp_path):
     assert bench.kernel_source_hash() == h0
     (copy / "lb_device.h").write_text(open(os.path.join(csrc, "lb_device.h")).read() + "\nint x;\n")
     assert bench.kernel_source_hash() != h0
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    # the bindings' parameter and particle structures (library and oracle)
+    # must lay out every field where the C headers do (sizeof and offsetof
+    # from a gcc-compiled probe)
+    import ctypes
+    import subprocess
+    from oracle import pyoracle
+    from paper_2202_01631_amd import lb
+    inc = os.path.join(ROOT, "include")
+    structs = (("lb_params", lb.Params), ("lb_colloid", lb.Colloid),
+               ("or_params", pyoracle.Params), ("or_colloid", pyoracle.Colloid))
+    checks = []
+    for cname, py in structs:
+        checks.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            checks.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lb.h"\n#include "oracle.h"\n'
+                   'int main(void) {\n'
+                   + "\n".join(checks) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, "-I", os.path.join(ROOT, "oracle"),
+                           "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().split("\n"):
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in structs:
+        assert got[(cname, "size")] == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
