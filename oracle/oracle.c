@@ -159,7 +159,12 @@ static int on_active_cap(const or_colloid *k, const double r[3])
 {
     double md = k->m[0] * r[0] + k->m[1] * r[1];
     md = md + k->m[2] * r[2];
-    return md <= 0.0;
+    if (k->cap_cos == 0.0) return md <= 0.0;
+    /* option: a cap of any size, m.n <= cap_cos with n = r/|r| (reading: the
+     * Janus split of Eqs. 5-6 moved to the polar angle acos(cap_cos)) */
+    double rr = r[0] * r[0] + r[1] * r[1];
+    rr = rr + r[2] * r[2];
+    return md <= k->cap_cos * sqrt(rr);
 }
 
 /* ------------------------------------------------------------ equilibrium */
@@ -371,6 +376,8 @@ int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
         double mm = sqrt(q.m[0] * q.m[0] + q.m[1] * q.m[1] + q.m[2] * q.m[2]);
         if (!(q.radius > 0.0) || !(q.rho_p > 0.0) || !(mm > 0.0))
             return fail(c, OR_E_INVALID, "colloid radius, density and axis must be positive");
+        if (!(q.cap_cos >= -1.0 && q.cap_cos <= 1.0))
+            return fail(c, OR_E_INVALID, "cap_cos must lie in [-1, 1]");
         if (q.H != 0.0 && !(c->p.kappa > 0.0))
             return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
         for (int a = 0; a < 3; a++) {

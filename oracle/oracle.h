@@ -65,6 +65,8 @@ typedef struct {
     double pos[3], m[3], vel[3], omega[3];
     double radius, alpha_minus, alpha_plus, mu_minus, mu_plus, H, rho_p;
     int32_t fixed;               /* 1: position, orientation and velocities held */
+    double cap_cos;              /* the active cap is m.n <= cap_cos, in [-1, 1]; 0 is the
+                                    half of Eqs. 5-6 (the paper's Janus particle) */
 } or_colloid;
 
 typedef struct {

@@ -26,7 +26,7 @@ def _min_image(d, L):
 def brute_links(shape, cols):
     """Link table by direct enumeration: every fluid node, every direction,
     inside test |x - R|^2 < R^2 (strict) with minimum image, cap m.r <= 0 at
-    the link midpoint.  Same FP64 operation order as the published rule
+    the link midpoint (m.r <= cap_cos |r| for a cap of another size).  Same FP64 operation order as the published rule
     ((dx*dx + dy*dy) + dz*dz), evaluated by numpy (no fused multiply-add)."""
     nx, ny, nz = shape
     X = np.stack(I.coords(shape))
@@ -51,7 +51,13 @@ def brute_links(shape, cols):
                 r = [_min_image((X[a, n] + 0.5 * CVEC[dd][a]) - q["pos"][a], Ls[a]) for a in range(3)]
                 md = q["m"][0] * r[0] + q["m"][1] * r[1]
                 md = md + q["m"][2] * r[2]
-                recs.append((k, n, dd, int(md <= 0.0)))
+                cc = q.get("cap_cos", 0.0)
+                if cc == 0.0:
+                    act = md <= 0.0
+                else:
+                    rr = r[0] * r[0] + r[1] * r[1]
+                    act = md <= cc * math.sqrt(rr + r[2] * r[2])
+                recs.append((k, n, dd, int(act)))
     return np.array(recs, dtype=np.int64).reshape(-1, 4), owner
 
 
@@ -438,3 +444,54 @@ def test_soft_sphere_pushes_close_spheres_apart():
         o.close()
     assert abs(gap[False] - 2.2) <= 1e-9   # quiescent uniform fluid: nothing moves
     assert gap[True] - 2.2 > 1e-3
+
+
+def test_cap_size_link_table_brute_force():
+    # caps of other sizes (m.n <= cap_cos): the oracle's cap bits equal the
+    # brute-force enumeration for three spheres with cap_cos -0.6, 0.35, 1;
+    # the active share of the links follows the cap's share of the sphere,
+    # (1 + cap_cos)/2, to 0.06, and cap_cos = 1 makes every link active
+    shape = (30, 28, 26)
+    N = int(np.prod(shape))
+    ms = I.unit_vectors(77, 3)
+    cols = [dict(pos=(7.3, 7.9, 8.4), m=ms[0], radius=5.2, cap_cos=-0.6),
+            dict(pos=(21.6, 18.2, 16.1), m=ms[1], radius=5.7, cap_cos=0.35),
+            dict(pos=(8.8, 21.1, 19.4), m=ms[2], radius=4.9, cap_cos=1.0)]
+    o = oracle.Oracle(shape, **FE_CAP)
+    o.init_fields(np.ones(N), np.zeros(N))
+    o.add_colloids(cols)
+    got = o.links()
+    want, _ = brute_links(shape, cols)
+    assert np.array_equal(got, want)
+    for k, q in enumerate(cols):
+        rec = want[want[:, 0] == k]
+        share = rec[:, 3].mean()
+        assert abs(share - (1.0 + q["cap_cos"]) / 2.0) <= 0.06, (k, share)
+    assert want[want[:, 0] == 2][:, 3].all()
+    o.close()
+    with pytest.raises(RuntimeError):
+        o2 = oracle.Oracle(shape, **FE_CAP)
+        o2.init_fields(np.ones(N), np.zeros(N))
+        o2.add_colloids([dict(pos=(7.3, 7.9, 8.4), m=(0, 0, 1), radius=4.0, cap_cos=1.5)])
+
+
+def test_uniformly_coated_sphere_does_not_swim():
+    # a held sphere centred on a node (the lattice sphere is mirror
+    # symmetric) emitting on its whole surface (cap_cos = 1) with one
+    # mobility: the phoretic part of its link momentum vanishes by symmetry
+    # (a uniformly coated particle does not self-propel), while the same
+    # sphere with the Janus cap (cap_cos = 0, axis +x) is pushed along +x
+    shape = (32, 32, 32)
+    N = int(np.prod(shape))
+    F = {}
+    for cc in (1.0, 0.0):
+        o = oracle.Oracle(shape, a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0625, E=0.0, c_b0=0.0,
+                          D_c=0.05, k_d=1e-3, tau=1.0)
+        o.init_fields(np.zeros(N), np.zeros(N))
+        o.add_colloids([dict(pos=(16.0, 16.0, 16.0), m=(1, 0, 0), radius=5.0, alpha_minus=1e-3,
+                             alpha_plus=0.0, mu_minus=0.2, mu_plus=0.2, fixed=1, cap_cos=cc)])
+        o.step(150)
+        F[cc] = o.colloid_diag(0)["F0"].copy()
+        o.close()
+    assert np.abs(F[1.0]).max() <= 1e-12       # round-off (measured ~1e-15)
+    assert F[0.0][0] > 0.01                      # measured 0.055
