@@ -139,11 +139,16 @@ typedef struct {
 typedef struct {                 /* FP64, caller-owned */
     double pos[3], m[3], vel[3], omega[3]; /* centre, axis (normalised on add), V, Omega */
     double radius;
-    double alpha_minus, alpha_plus;  /* production per link on the m.n <= 0 / > 0 cap (Eq. 5) */
+    double alpha_minus, alpha_plus;  /* production per link on the active cap m.n <= cap_cos /
+                                        on the rest (Eq. 5) */
     double mu_minus, mu_plus;        /* phoretic mobility on the two caps (Eq. 6) */
     double H;                        /* wetting parameter of Eqs. 8-9 (lb_wetting_H) */
     double rho_p;                    /* particle density: mass rho_p 4/3 pi R^3 */
     int32_t fixed;                   /* 1: position, axis and velocities held */
+    double cap_cos;                  /* the active cap is m.n <= cap_cos, in [-1, 1]; 0 (the
+                                        paper's Janus half, Eqs. 5-6) keeps the exact tie
+                                        rule m.n <= 0; otherwise n = r/|r| in FP64 without
+                                        contraction.  LB_E_INVALID outside [-1, 1] */
 } lb_colloid;
 
 typedef struct {

@@ -739,6 +739,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
         if (!(q.radius > 0.0) || !(q.rho_p > 0.0) || !(mm > 0.0))
             return fail(c, LB_E_INVALID, "particle radius, density and axis must be positive");
         if (q.H != 0.0 && !(c->p.kappa > 0.0)) return fail(c, LB_E_INVALID, "wetting needs kappa > 0");
+        if (!(q.cap_cos >= -1.0 && q.cap_cos <= 1.0)) return fail(c, LB_E_INVALID, "cap_cos must lie in [-1, 1]");
         for (int a = 0; a < 3; a++) {
             if (2.0 * q.radius + 8.0 > (double)Ls[a])
                 return fail(c, LB_E_INVALID, "particle too large for the box (2 R + 8 > side)");
@@ -761,6 +762,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
         d.mass = q.rho_p * (4.0 * M_PI / 3.0) * q.radius * q.radius * q.radius;
         d.inertia = 0.4 * d.mass * q.radius * q.radius;
         d.fixed = q.fixed ? 1 : 0;
+        d.capc = q.cap_cos;
         d.changed = 1;  // build the owner map and link table on placement
         rmax = std::max(rmax, q.radius);
     }
@@ -979,6 +981,7 @@ lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
             q.H = d.H;
             q.rho_p = d.rho_p;
             q.fixed = d.fixed;
+            q.cap_cos = d.capc;
         }
     }
     if (herr & LB_ERR_NAN) return fail(c, LB_E_UNSTABLE, "non-finite totals");

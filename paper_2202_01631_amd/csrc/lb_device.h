@@ -124,6 +124,7 @@ struct DColloid {
     double F[3], T[3];         // force and torque acting in the last step
     double F0[3], T0[3];       // velocity-independent link momentum of the last step
     int fixed, nlinks, nactive, changed;  // changed: owner map moved this step
+    double capc;               // active cap m.n <= capc (0: the Janus half)
 };
 
 // -------------------------------------------------------- particle geometry
@@ -165,7 +166,11 @@ __host__ __device__ inline bool active_cap(const DColloid &q, const double r[3])
 #pragma clang fp contract(off)
     double md = q.m[0] * r[0] + q.m[1] * r[1];
     md = md + q.m[2] * r[2];
-    return md <= 0.0;
+    if (q.capc == 0.0) return md <= 0.0;
+    // a cap of any size: m.n <= capc with n = r/|r|
+    double rr = r[0] * r[0] + r[1] * r[1];
+    rr = rr + r[2] * r[2];
+    return md <= q.capc * sqrt(rr);
 }
 
 // Particle bounding box along one axis, with the node coordinates visited in

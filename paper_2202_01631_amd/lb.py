@@ -47,7 +47,7 @@ class Colloid(C.Structure):
                 ("radius", C.c_double), ("alpha_minus", C.c_double),
                 ("alpha_plus", C.c_double), ("mu_minus", C.c_double),
                 ("mu_plus", C.c_double), ("H", C.c_double), ("rho_p", C.c_double),
-                ("fixed", C.c_int32)]
+                ("fixed", C.c_int32), ("cap_cos", C.c_double)]
 
 
 class Totals(C.Structure):
@@ -154,6 +154,7 @@ def make_colloid(d):
     for key in COLLOID_SCALARS:
         setattr(q, key, float(d.get(key, 1.0 if key == "rho_p" else 0.0)))
     q.fixed = int(d.get("fixed", 0))
+    q.cap_cos = float(d.get("cap_cos", 0.0))
     return q
 
 
@@ -162,6 +163,7 @@ def colloid_dict(q):
     for k in COLLOID_SCALARS:
         d[k] = getattr(q, k)
     d["fixed"] = q.fixed
+    d["cap_cos"] = q.cap_cos
     return d
 
 

@@ -204,6 +204,48 @@ def test_soft_sphere_matches_oracle(nu):
         assert np.abs(fg["F0"][k] - o.colloid_diag(k)["F0"]).max() <= 1e-11
 
 
+def test_cap_sizes_match_oracle():
+    # caps of other sizes (cap_cos -0.5, 0.4, 1) on three moving spheres with
+    # emission and slip, 30 steps: link tables (cap bits) and owner maps
+    # bit-exact, FP64 fields within 1e-12 and particle states within 1e-11 of
+    # the oracle; cap_cos = 0 gives the same bits as leaving it out; values
+    # outside [-1, 1] rejected
+    shape = (44, 36, 34)
+    pos = [(9.2, 10.3, 9.1), (30.4, 11.7, 20.2), (14.9, 26.1, 24.3)]
+    cols = []
+    for k, cc in enumerate((-0.5, 0.4, 1.0)):
+        c = I.janus(pos[k], I.unit_vectors(60 + k, 1)[0], 4.6, alpha=2e-3, mu=0.2, theta=80.0)
+        c["cap_cos"] = cc
+        c["vel"] = np.array([0.01, -0.005, 0.004]) * (k - 1)
+        cols.append(c)
+    spec = _spec(shape, seed=31, colloids=cols)
+    g, o = run_pair(spec, 0)
+    assert np.array_equal(g.links(), o.links())
+    for _ in range(3):
+        g.step(10)
+        o.step(10)
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+    _compare(g, o, 1e-12, "cap sizes")
+    _, cg = g.observables()
+    _, co = o.observables()
+    for k in range(3):
+        assert cg[k]["cap_cos"] == cols[k]["cap_cos"]
+        for a in ("vel", "omega", "pos", "m"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+    a = lb.from_spec(_spec(shape, seed=31, colloids=[dict(c, cap_cos=0.0) for c in cols]))
+    b = lb.from_spec(_spec(shape, seed=31, colloids=[{k: v for k, v in c.items() if k != "cap_cos"}
+                                                     for c in cols]))
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.links(), b.links())
+    with pytest.raises(lb.LBError):
+        bad = lb.Box(shape, "fp64", **I.FREE_ENERGY)
+        bad.init_fields(np.zeros(int(np.prod(shape))), np.zeros(int(np.prod(shape))))
+        bad.add_colloids([dict(cols[0], cap_cos=-1.5, H=0.0)])
+
+
 def test_soft_sphere_parameters_validated():
     with pytest.raises(lb.LBError):
         lb.Box((8, 8, 8), "fp32", soft_eps=-1.0)
