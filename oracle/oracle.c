@@ -161,10 +161,15 @@ static int on_active_cap(const or_colloid *k, const double r[3])
     md = md + k->m[2] * r[2];
     if (k->cap_cos == 0.0) return md <= 0.0;
     /* option: a cap of any size, m.n <= cap_cos with n = r/|r| (reading: the
-     * Janus split of Eqs. 5-6 moved to the polar angle acos(cap_cos)) */
+     * Janus split of Eqs. 5-6 moved to the polar angle acos(cap_cos)),
+     * i.e. m.r <= cap_cos |r|, decided in squares: for cap_cos > 0 true when
+     * m.r <= 0, else when (m.r)^2 <= cap_cos^2 |r|^2; for cap_cos < 0 only
+     * when m.r < 0 and (m.r)^2 >= cap_cos^2 |r|^2 */
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
-    return md <= k->cap_cos * sqrt(rr);
+    double lhs = md * md, rhs = (k->cap_cos * k->cap_cos) * rr;
+    if (k->cap_cos > 0.0) return md <= 0.0 || lhs <= rhs;
+    return md < 0.0 && lhs >= rhs;
 }
 
 /* ------------------------------------------------------------ equilibrium */

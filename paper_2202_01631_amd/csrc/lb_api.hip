@@ -201,8 +201,11 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // (the solute-force term lives in the one-node collide-stream only)
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
     B.solute_force = 0;
-    for (int j = 0; j < n; j++)
+    B.soft = 0;
+    for (int j = 0; j < n; j++) {
         if (ctxs[j]->p.flags & LB_SOLUTE_FORCE) B.solute_force = 1;
+        if (ctxs[j]->p.soft_eps > 0.0) B.soft = 1;
+    }
     for (int w = 0; w < 3; w++) {
         bool same = true;
         for (int j = 1; j < n; j++)

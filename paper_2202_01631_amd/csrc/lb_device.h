@@ -125,6 +125,7 @@ struct DColloid {
     double F0[3], T0[3];       // velocity-independent link momentum of the last step
     int fixed, nlinks, nactive, changed;  // changed: owner map moved this step
     double capc;               // active cap m.n <= capc (0: the Janus half)
+    double sF[3];              // soft-sphere force of this step (when the box has it)
 };
 
 // -------------------------------------------------------- particle geometry
@@ -167,10 +168,11 @@ __host__ __device__ inline bool active_cap(const DColloid &q, const double r[3])
     double md = q.m[0] * r[0] + q.m[1] * r[1];
     md = md + q.m[2] * r[2];
     if (q.capc == 0.0) return md <= 0.0;
-    // a cap of any size: m.n <= capc with n = r/|r|
+    // a cap of any size: m.r <= capc |r|, compared in squares (no sqrt)
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
-    return md <= q.capc * sqrt(rr);
+    const double lhs = md * md, rhs = (q.capc * q.capc) * rr;
+    return q.capc > 0.0 ? (md <= 0.0 || lhs <= rhs) : (md < 0.0 && lhs >= rhs);
 }
 
 // Particle bounding box along one axis, with the node coordinates visited in

@@ -1238,30 +1238,40 @@ __device__ void capillary_link(const KParams &p, const DColloid *__restrict__ co
     for (int b = 0; b < 3; b++) dp[b] += 6.0 * w * (cd[0] * P[0][b] + cd[1] * P[1][b] + cd[2] * P[2][b]);
 }
 
-// Soft-sphere repulsion (soft_eps > 0) on particle k from every other
-// particle of its box (nb of them) whose surface gap h is below the cutoff:
-// nu eps sigma^nu (h^-(nu+1) - hc^-(nu+1)) along the line of centres, away
-// from the other (h below 0.01 taken as 0.01), added to the F0 partial.  The
-// positions are those at the start of the step (the rigid-body update runs
-// after this pass).
-__device__ void soft_pairs(const KParams &p, const DColloid *__restrict__ col, int nb, int k,
-                           double acc[28])
+// Soft-sphere repulsion (boxes with soft_eps > 0), one thread per particle:
+// the force on particle k from every other particle of its box whose surface
+// gap h is below the cutoff, nu eps sigma^nu (h^-(nu+1) - hc^-(nu+1)) along
+// the line of centres, away from the other (h below 0.01 taken as 0.01), into
+// sF for the rigid-body update.  Runs before that update rewrites the
+// positions, so all pairs see the positions at the start of the step.
+__global__ __launch_bounds__(64) void k_soft(BatchArgs A, int ncol)
 {
 #pragma clang fp contract(off)
-    const DColloid &a = col[k];
-    for (int i = 0; i < nb; i++) {
-        if (i == k) continue;
-        const DColloid &b = col[i];
-        const double d[3] = {min_image(b.pos[0] - a.pos[0], p.nx), min_image(b.pos[1] - a.pos[1], p.ny),
-                             min_image(b.pos[2] - a.pos[2], p.nz)};
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        double h = r - a.radius - b.radius;
-        if (!(h < p.soft_hc)) continue;
-        if (h < 0.01) h = 0.01;
-        const double f = p.soft_nu * p.soft_eps * pow(p.soft_sigma, p.soft_nu) *
-                         (pow(h, -(p.soft_nu + 1.0)) - pow(p.soft_hc, -(p.soft_nu + 1.0)));
-        for (int e = 0; e < 3; e++) acc[e] -= f * d[e] / r;
+    const int g = blockIdx.x * 64 + (int)threadIdx.x;
+    if (g >= ncol) return;
+    const int j = find_box(A.cstart, A.nbox, g);
+    const BoxDesc &D = A.d[j];
+    const KParams &p = D.p;
+    DColloid *__restrict__ col = D.b.col;
+    const int k = g - A.cstart[j], nb = A.cstart[j + 1] - A.cstart[j];
+    double F[3] = {0.0, 0.0, 0.0};
+    if (p.soft_eps > 0.0) {
+        const DColloid &a = col[k];
+        for (int i = 0; i < nb; i++) {
+            if (i == k) continue;
+            const DColloid &o = col[i];
+            const double d[3] = {min_image(o.pos[0] - a.pos[0], p.nx), min_image(o.pos[1] - a.pos[1], p.ny),
+                                 min_image(o.pos[2] - a.pos[2], p.nz)};
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double h = r - a.radius - o.radius;
+            if (!(h < p.soft_hc)) continue;
+            if (h < 0.01) h = 0.01;
+            const double f = p.soft_nu * p.soft_eps * pow(p.soft_sigma, p.soft_nu) *
+                             (pow(h, -(p.soft_nu + 1.0)) - pow(p.soft_hc, -(p.soft_nu + 1.0)));
+            for (int e = 0; e < 3; e++) F[e] -= f * d[e] / r;
+        }
     }
+    for (int e = 0; e < 3; e++) col[k].sF[e] = F[e];
 }
 
 template <int P>
@@ -1284,14 +1294,12 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
     const DColloid &q = col[k];
     const int nl = min(q.nlinks, lcap);
     const int l0 = blockIdx.x * LINK_THREADS;
-    if (l0 >= nl && blockIdx.x > 0) return;  // chunk 0 always reports (pair forces)
+    if (l0 >= nl) return;
     const size_t N = (size_t)p.N;
     const double rho0 = p.rho0;
     double acc[28];
 #pragma unroll
     for (int jj = 0; jj < 28; jj++) acc[jj] = 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && p.soft_eps > 0.0)
-        soft_pairs(p, col, A.cstart[j + 1] - A.cstart[j], k, acc);
     const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
     const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
     {
@@ -1369,7 +1377,7 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
     const int k = blockIdx.x - A.cstart[j];
     DColloid &q = col[k];
     const int nl = min(q.nlinks, D.b.lcap);
-    const int nch = max(1, (nl + LINK_THREADS - 1) / LINK_THREADS);  // chunk 0 always written
+    const int nch = (nl + LINK_THREADS - 1) / LINK_THREADS;
     if (threadIdx.x < 28) {
         // partials loaded eight chunks at a time (one memory round trip per
         // eight, not per chunk), summed in chunk order
@@ -1389,6 +1397,8 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
     if (threadIdx.x != 0) return;
     double acc[28];
     for (int a = 0; a < 28; a++) acc[a] = sacc[a];
+    if (p.soft_eps > 0.0)
+        for (int e = 0; e < 3; e++) acc[e] += q.sF[e];  // soft-sphere force joins F0
     const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
     const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
     double Z[36];
@@ -2148,6 +2158,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
+    if (B.soft) k_soft<<<(B.ncol + 63) / 64, 64, 0, ss>>>(B.args, B.ncol);
     k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);
     k_colloid_update<<<B.ncol, 64, 0, ss>>>(B.args);
     if (par) {
