@@ -216,6 +216,7 @@ int or_create(const or_params *p, or_ctx **out)
     if (!(p->soft_eps >= 0.0)) return OR_E_INVALID;
     if (p->soft_eps > 0.0 && !(p->soft_sigma > 0.0 && p->soft_nu > 0.0 && p->soft_hc > 0.0))
         return OR_E_INVALID;
+    if (!(p->lub_hc >= 0.0)) return OR_E_INVALID;
 
     or_ctx *c = (or_ctx *)zalloc(sizeof *c);
     if (!c) return OR_E_INVALID;
@@ -638,17 +639,21 @@ static void collide_stream(or_ctx *c)
     c->diag[OR_DIAG_SUM_DMASS] = dmass;
 }
 
-/* step 2b (option, soft_eps > 0): soft-sphere repulsion for close encounters
+/* step 2b (options, soft_eps > 0 or lub_hc > 0): soft-sphere repulsion and
+ * normal lubrication for close encounters.  Soft sphere:
  * (the paper mentions a soft potential for near-contact encounters without
  * giving it).  Reading: the shifted-force soft sphere
  *   U(h) = eps (sigma/h)^nu, force -dU/dh shifted to vanish at the cutoff hc,
  * on the surface gap h = |R_j - R_i| - a_i - a_j (minimum image), added to
  * the velocity-independent force F0 of both particles, from the positions at
- * t.  Central: no torque. */
+ * t.  Lubrication (reading: the normal term of Nguyen and Ladd, explicit in
+ * the velocities at t, gap floored at 0.1 for stability): -6 pi eta (a_i
+ * a_j/(a_i + a_j))^2 (1/h - 1/lub_hc) U_n along the line of centres.
+ * Central: no torque. */
 static void soft_contacts(or_ctx *c)
 {
     const or_params *p = &c->p;
-    if (!(p->soft_eps > 0.0)) return;
+    if (!(p->soft_eps > 0.0) && !(p->lub_hc > 0.0)) return;
     int L[3] = {c->nx, c->ny, c->nz};
     for (int i = 0; i < c->ncol; i++)
         for (int j = i + 1; j < c->ncol; j++) {
@@ -656,11 +661,24 @@ static void soft_contacts(or_ctx *c)
             double d[3];
             for (int e = 0; e < 3; e++) d[e] = min_image(b->pos[e] - a->pos[e], L[e]);
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            double h = r - a->radius - b->radius;
-            if (!(h < p->soft_hc)) continue;
-            if (h < 0.01) h = 0.01;
-            double f = p->soft_nu * p->soft_eps * pow(p->soft_sigma, p->soft_nu) *
-                       (pow(h, -(p->soft_nu + 1.0)) - pow(p->soft_hc, -(p->soft_nu + 1.0)));
+            double h0 = r - a->radius - b->radius;
+            double f = 0.0;
+            if (p->soft_eps > 0.0 && h0 < p->soft_hc) {
+                double h = h0 < 0.01 ? 0.01 : h0;
+                f += p->soft_nu * p->soft_eps * pow(p->soft_sigma, p->soft_nu) *
+                     (pow(h, -(p->soft_nu + 1.0)) - pow(p->soft_hc, -(p->soft_nu + 1.0)));
+            }
+            if (p->lub_hc > 0.0 && h0 < p->lub_hc) {
+                /* option: normal lubrication (Nguyen and Ladd), explicit in
+                 * the velocities at t; un > 0 when the pair approaches */
+                double h = h0 < 0.1 ? 0.1 : h0;
+                double un = ((a->vel[0] - b->vel[0]) * d[0] + (a->vel[1] - b->vel[1]) * d[1] +
+                             (a->vel[2] - b->vel[2]) * d[2]) / r;
+                double ae = a->radius * b->radius / (a->radius + b->radius);
+                double eta = p->rho0 * (p->tau - 0.5) / 3.0;
+                f += 6.0 * M_PI * eta * ae * ae * (1.0 / h - 1.0 / p->lub_hc) * un;
+            }
+            /* f > 0 pushes the pair apart */
             for (int e = 0; e < 3; e++) {
                 c->F0[3 * i + e] -= f * d[e] / r;
                 c->F0[3 * j + e] += f * d[e] / r;

@@ -46,6 +46,12 @@ typedef struct {
                                     (h^-(nu+1) - hc^-(nu+1)) along the line of centres,
                                     away from the other (h below 0.01 taken as 0.01);
                                     soft_eps = 0: none */
+    double lub_hc;               /* normal lubrication between particles whose surface gap
+                                    h is below lub_hc (0: none): each takes -6 pi eta
+                                    (a_i a_j/(a_i + a_j))^2 (1/h - 1/lub_hc) U_n along the
+                                    line of centres, U_n the approach speed at the start of
+                                    the step, eta = rho0 (tau - 1/2)/3 (h below 0.1 taken
+                                    as 0.1) */
 } or_params;
 
 /* options (readings of what the paper leaves open):

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("D_c", C.c_double), ("k_d", C.c_double),
                 ("ext_force", C.c_double * 3), ("flags", C.c_uint32),
                 ("ch_substeps", C.c_int32), ("soft_eps", C.c_double), ("soft_sigma", C.c_double),
-                ("soft_nu", C.c_double), ("soft_hc", C.c_double)]
+                ("soft_nu", C.c_double), ("soft_hc", C.c_double), ("lub_hc", C.c_double)]
 
 
 class Colloid(C.Structure):
@@ -122,7 +122,7 @@ def make_params(shape, **kw):
         p.ext_force[a] = float(ef[a])
     p.flags = int(kw.get("flags", 0))
     p.ch_substeps = int(kw.get("ch_substeps", 0))
-    for k in ("soft_eps", "soft_sigma", "soft_nu", "soft_hc"):
+    for k in ("soft_eps", "soft_sigma", "soft_nu", "soft_hc", "lub_hc"):
         setattr(p, k, float(kw.get(k, 0.0)))
     return p
 

@@ -495,3 +495,39 @@ def test_uniformly_coated_sphere_does_not_swim():
         o.close()
     assert np.abs(F[1.0]).max() <= 1e-12       # round-off (measured ~1e-15)
     assert F[0.0][0] > 0.01                      # measured 0.055
+
+
+def test_lubrication_is_the_reynolds_force():
+    # normal lubrication (lub_hc > 0) between two held equal spheres (radius
+    # 4, surface gap 0.5 < lub_hc = 2) approaching along x at relative speed
+    # U: the classical Reynolds force between equal spheres, (3/2) pi eta a^2
+    # U / h, less its value at the cutoff, pushes them apart (eta = rho0 (tau
+    # - 1/2)/3, tau = 0.8); doubling the speeds doubles it; tangential
+    # relative motion gives none; the pair force is equal and opposite
+    shape = (30, 20, 20)
+    N = int(np.prod(shape))
+    tau, a, h, hc = 0.8, 4.0, 0.5, 2.0
+    eta = (tau - 0.5) / 3.0
+
+    def lub(v1, v2):
+        out = []
+        for extra in ({}, dict(lub_hc=hc)):
+            o = oracle.Oracle(shape, **dict(FE_CAP, tau=tau, **extra))
+            o.init_fields(np.ones(N), np.zeros(N))
+            o.add_colloids([dict(pos=(10.0, 10.3, 9.8), m=(0, 0, 1), radius=a, vel=v1, fixed=1),
+                            dict(pos=(10.0 + 2 * a + h, 10.3, 9.8), m=(0, 0, 1), radius=a, vel=v2,
+                                 fixed=1)])
+            o.step(1)
+            out.append((o.colloid_diag(0)["F0"].copy(), o.colloid_diag(1)["F0"].copy()))
+            o.close()
+        return out[1][0] - out[0][0], out[1][1] - out[0][1]
+
+    U = 0.02
+    F1, F2 = lub((0.01, 0, 0), (-0.01, 0, 0))
+    want = 1.5 * math.pi * eta * a * a * U * (1.0 / h - 1.0 / hc)
+    assert F1[0] == pytest.approx(-want, rel=1e-12)
+    assert np.abs(F1[1:]).max() == 0.0 and np.array_equal(F2, -F1)
+    G1, _ = lub((0.02, 0, 0), (-0.02, 0, 0))
+    assert G1[0] == pytest.approx(2.0 * F1[0], rel=1e-12)
+    T1, T2 = lub((0, 0.01, 0), (0, -0.01, 0.005))
+    assert np.abs(T1).max() == 0.0 and np.abs(T2).max() == 0.0
