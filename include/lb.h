@@ -110,6 +110,12 @@ typedef struct {
                                     0.01), from the positions at the start of the step, as
                                     part of F0 (the shifted-force form of the potential
                                     eps (sigma/h)^nu) */
+    double lub_hc;               /* normal lubrication between particles whose surface gap
+                                    h is below lub_hc (0: none, else > 0): each takes
+                                    -6 pi eta (a_i a_j/(a_i + a_j))^2 (1/h - 1/lub_hc) U_n
+                                    along the line of centres, U_n the approach speed at the
+                                    start of the step (explicit), eta = rho0 (tau - 1/2)/3,
+                                    h below 0.1 taken as 0.1; part of F0 */
 } lb_params;
 
 /* lb_params.flags: readings the paper leaves open, off by default.

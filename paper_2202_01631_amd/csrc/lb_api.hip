@@ -204,7 +204,7 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     B.soft = 0;
     for (int j = 0; j < n; j++) {
         if (ctxs[j]->p.flags & LB_SOLUTE_FORCE) B.solute_force = 1;
-        if (ctxs[j]->p.soft_eps > 0.0) B.soft = 1;
+        if (ctxs[j]->p.soft_eps > 0.0 || ctxs[j]->p.lub_hc > 0.0) B.soft = 1;
     }
     for (int w = 0; w < 3; w++) {
         bool same = true;
@@ -420,6 +420,7 @@ static lb_status check_params(const lb_params *p, std::string &why)
         why = "soft_eps must be >= 0, and with soft_eps > 0 soft_sigma, soft_nu, soft_hc > 0";
         return LB_E_INVALID;
     }
+    if (!(p->lub_hc >= 0.0)) { why = "lub_hc must be >= 0"; return LB_E_INVALID; }
     // the psi/c bounds hold per sub-step, of length 1/n
     const double dt = 1.0 / substeps_of(*p);
     if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0) {
@@ -583,6 +584,7 @@ lb_status lb_create(const lb_params *p, void *dev_arena, size_t arena_bytes, voi
     k.inv_scale = 1.0f / k.scale;
     k.flags = p->flags;
     k.soft_eps = p->soft_eps; k.soft_sigma = p->soft_sigma; k.soft_nu = p->soft_nu; k.soft_hc = p->soft_hc;
+    k.lub_hc = p->lub_hc;
     set_shapes(c);
     c->stream = (hipStream_t)hip_stream;
     c->L = layout_of(c->p);

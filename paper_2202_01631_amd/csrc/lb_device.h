@@ -111,6 +111,7 @@ struct KParams {
     double sub;                // psi/c sub-step length 1/n (M, D, kd above already carry it):
                                // scales the emission and the stored advection velocity
     double soft_eps, soft_sigma, soft_nu, soft_hc;  // soft-sphere repulsion (eps 0: none)
+    double lub_hc;             // normal lubrication cutoff (0: none)
     double fx, fy, fz;
     float scale, inv_scale;    // FP16 storage scale and its inverse (1 otherwise)
     unsigned flags;            // LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID, LB_CAPILLARY_FORCE

@@ -1238,12 +1238,15 @@ __device__ void capillary_link(const KParams &p, const DColloid *__restrict__ co
     for (int b = 0; b < 3; b++) dp[b] += 6.0 * w * (cd[0] * P[0][b] + cd[1] * P[1][b] + cd[2] * P[2][b]);
 }
 
-// Soft-sphere repulsion (boxes with soft_eps > 0), one thread per particle:
-// the force on particle k from every other particle of its box whose surface
-// gap h is below the cutoff, nu eps sigma^nu (h^-(nu+1) - hc^-(nu+1)) along
-// the line of centres, away from the other (h below 0.01 taken as 0.01), into
-// sF for the rigid-body update.  Runs before that update rewrites the
-// positions, so all pairs see the positions at the start of the step.
+// Close-encounter pair forces, one thread per particle: on particle k from
+// every other particle of its box, the soft-sphere repulsion (soft_eps > 0,
+// gap h below soft_hc) nu eps sigma^nu (h^-(nu+1) - hc^-(nu+1)) (h below 0.01
+// taken as 0.01) and the normal lubrication (lub_hc > 0, gap below lub_hc)
+// 6 pi eta (a_k a_i/(a_k + a_i))^2 (1/h - 1/lub_hc) U_n (h below 0.1 taken as
+// 0.1; U_n the approach speed), both along the line of centres, pushing the
+// pair apart when positive, into sF for the rigid-body update.  Runs before
+// that update rewrites positions and velocities, so all pairs see the state
+// at the start of the step.
 __global__ __launch_bounds__(64) void k_soft(BatchArgs A, int ncol)
 {
 #pragma clang fp contract(off)
@@ -1255,19 +1258,29 @@ __global__ __launch_bounds__(64) void k_soft(BatchArgs A, int ncol)
     DColloid *__restrict__ col = D.b.col;
     const int k = g - A.cstart[j], nb = A.cstart[j + 1] - A.cstart[j];
     double F[3] = {0.0, 0.0, 0.0};
-    if (p.soft_eps > 0.0) {
+    if (p.soft_eps > 0.0 || p.lub_hc > 0.0) {
         const DColloid &a = col[k];
+        const double eta = p.rho0 * (p.tau - 0.5) / 3.0;
         for (int i = 0; i < nb; i++) {
             if (i == k) continue;
             const DColloid &o = col[i];
             const double d[3] = {min_image(o.pos[0] - a.pos[0], p.nx), min_image(o.pos[1] - a.pos[1], p.ny),
                                  min_image(o.pos[2] - a.pos[2], p.nz)};
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            double h = r - a.radius - o.radius;
-            if (!(h < p.soft_hc)) continue;
-            if (h < 0.01) h = 0.01;
-            const double f = p.soft_nu * p.soft_eps * pow(p.soft_sigma, p.soft_nu) *
-                             (pow(h, -(p.soft_nu + 1.0)) - pow(p.soft_hc, -(p.soft_nu + 1.0)));
+            const double h0 = r - a.radius - o.radius;
+            double f = 0.0;
+            if (p.soft_eps > 0.0 && h0 < p.soft_hc) {
+                const double h = h0 < 0.01 ? 0.01 : h0;
+                f += p.soft_nu * p.soft_eps * pow(p.soft_sigma, p.soft_nu) *
+                     (pow(h, -(p.soft_nu + 1.0)) - pow(p.soft_hc, -(p.soft_nu + 1.0)));
+            }
+            if (p.lub_hc > 0.0 && h0 < p.lub_hc) {
+                const double h = h0 < 0.1 ? 0.1 : h0;
+                const double un = ((a.vel[0] - o.vel[0]) * d[0] + (a.vel[1] - o.vel[1]) * d[1] +
+                                   (a.vel[2] - o.vel[2]) * d[2]) / r;
+                const double ae = a.radius * o.radius / (a.radius + o.radius);
+                f += 6.0 * M_PI * eta * ae * ae * (1.0 / h - 1.0 / p.lub_hc) * un;
+            }
             for (int e = 0; e < 3; e++) F[e] -= f * d[e] / r;
         }
     }
@@ -1397,8 +1410,8 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
     if (threadIdx.x != 0) return;
     double acc[28];
     for (int a = 0; a < 28; a++) acc[a] = sacc[a];
-    if (p.soft_eps > 0.0)
-        for (int e = 0; e < 3; e++) acc[e] += q.sF[e];  // soft-sphere force joins F0
+    if (p.soft_eps > 0.0 || p.lub_hc > 0.0)
+        for (int e = 0; e < 3; e++) acc[e] += q.sF[e];  // close-encounter forces join F0
     const double V[3] = {q.vel[0], q.vel[1], q.vel[2]};
     const double W[3] = {q.omega[0], q.omega[1], q.omega[2]};
     double Z[36];

@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("ext_force", C.c_double * 3), ("f16_scale", C.c_double),
                 ("max_colloids", C.c_int32), ("flags", C.c_uint32),
                 ("ch_substeps", C.c_int32), ("soft_eps", C.c_double), ("soft_sigma", C.c_double),
-                ("soft_nu", C.c_double), ("soft_hc", C.c_double)]
+                ("soft_nu", C.c_double), ("soft_hc", C.c_double), ("lub_hc", C.c_double)]
 
 
 class Colloid(C.Structure):
@@ -139,7 +139,7 @@ def make_params(shape, precision="fp64", **kw):
     p.f16_scale = float(kw.get("f16_scale", 0.0))
     p.max_colloids = int(kw.get("max_colloids", 0))
     p.ch_substeps = int(kw.get("ch_substeps", 0))
-    for k in ("soft_eps", "soft_sigma", "soft_nu", "soft_hc"):
+    for k in ("soft_eps", "soft_sigma", "soft_nu", "soft_hc", "lub_hc"):
         setattr(p, k, float(kw.get(k, 0.0)))
     p.flags = int(kw.get("flags", 0))
     return p

@@ -173,14 +173,15 @@ def test_fp64_options_match_oracle(flags):
         assert np.abs(fg["F"][k] - o.colloid_diag(k)["F"]).max() <= 1e-11
 
 
-@pytest.mark.parametrize("nu", [1.0, 2.5])
-def test_soft_sphere_matches_oracle(nu):
-    # soft-sphere repulsion (eps 0.05, sigma 1, cutoff 3) among four moving
-    # spheres placed 2.2-2.5 apart, one pair across the periodic wrap in x:
-    # FP64 fields within 1e-12, particle states and reported F0 within 1e-11
-    # of the oracle after 30 steps
+@pytest.mark.parametrize("nu,eps,lub", [(1.0, 0.05, 0.0), (2.5, 0.05, 3.0), (1.0, 0.0, 3.0)])
+def test_soft_sphere_matches_oracle(nu, eps, lub):
+    # close-encounter forces among four moving spheres placed 2.2-2.5 apart,
+    # one pair across the periodic wrap in x: soft-sphere repulsion (eps
+    # 0.05, sigma 1, cutoff 3), normal lubrication (cutoff 3), and both; FP64
+    # fields within 1e-12, particle states and reported F0 within 1e-11 of
+    # the oracle after 30 steps
     shape = (48, 36, 34)
-    soft = dict(soft_eps=0.05, soft_sigma=1.0, soft_nu=nu, soft_hc=3.0)
+    soft = dict(soft_eps=eps, soft_sigma=1.0, soft_nu=nu, soft_hc=3.0, lub_hc=lub)
     pos = [(5.0, 18.0, 17.0), (15.2, 18.0, 17.0), (15.2, 28.5, 17.0), (42.7, 18.0, 17.0)]
     vel = [(0.01, 0.0, 0.0), (-0.01, 0.005, 0.0), (0.0, -0.01, 0.0), (0.0, 0.0, 0.005)]
     cols = []
@@ -194,7 +195,7 @@ def test_soft_sphere_matches_oracle(nu):
         g.step(10)
         o.step(10)
         assert np.array_equal(g.owner(), o.owner())
-    _compare(g, o, 1e-12, "soft nu=%g" % nu)
+    _compare(g, o, 1e-12, "soft nu=%g eps=%g lub=%g" % (nu, eps, lub))
     _, cg = g.observables()
     _, co = o.observables()
     fg = g.colloid_forces()
@@ -251,6 +252,8 @@ def test_soft_sphere_parameters_validated():
         lb.Box((8, 8, 8), "fp32", soft_eps=-1.0)
     with pytest.raises(lb.LBError):
         lb.Box((8, 8, 8), "fp32", soft_eps=0.1, soft_sigma=0.0, soft_nu=1.0, soft_hc=3.0)
+    with pytest.raises(lb.LBError):
+        lb.Box((8, 8, 8), "fp32", lub_hc=-1.0)
     lb.Box((8, 8, 8), "fp32", soft_eps=0.1, soft_sigma=1.0, soft_nu=1.0, soft_hc=3.0).close()
 
 
