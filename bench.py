@@ -355,13 +355,21 @@ def main():
                                             for k, x in v["kernel_ms"].items()},
                               "error_bits": v["error_bits"]} for p, v in res.items()},
     }
+    # secondary legs: a library error there is recorded in the line rather
+    # than losing it
     if args.batch and not args.only:
         log("[bench] batched sweep: %d boxes x %d steps" % (args.batch, args.batch_steps))
-        out["batched_sweep"] = batched_sweep(torch, lb, I, args.batch, args.batch_steps)
+        try:
+            out["batched_sweep"] = batched_sweep(torch, lb, I, args.batch, args.batch_steps)
+        except lb.LBError as e:
+            out["batched_sweep"] = {"error": str(e)}
         log("[bench] batched sweep %s" % out["batched_sweep"])
     if not args.only:
         log("[bench] paper regime 64x96x96")
-        out["paper_regime"] = paper_regime_run(torch, lb, I)
+        try:
+            out["paper_regime"] = paper_regime_run(torch, lb, I)
+        except lb.LBError as e:
+            out["paper_regime"] = {"error": str(e)}
         log("[bench] paper regime %s" % out["paper_regime"])
     if args.serve and not args.only:
         log("[bench] serving: %d requests" % args.serve)
