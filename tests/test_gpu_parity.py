@@ -506,6 +506,12 @@ def test_fp16_storage_error_bounds():
     sf = dict(spec, params=dict(spec["params"], flags=lb.LB_SOLUTE_FORCE))
     g, o = run_pair(sf, 500, precision="fp16")
     _compare(g, o, dict(rho=2e-5, psi=1e-3, c=1e-2, u=1e-1), "fp16 500 steps, solute force")
+    # and in the paper's regime: M_psi = 0.4 in two psi/c sub-steps (the
+    # stored velocity carries the sub-step length) with the capillary stress
+    pr = dict(spec, params=dict(spec["params"], M_psi=0.4, ch_substeps=2,
+                                flags=lb.LB_CAPILLARY_FORCE))
+    g, o = run_pair(pr, 500, precision="fp16")
+    _compare(g, o, dict(rho=2e-5, psi=1e-3, c=1e-2, u=1e-1), "fp16 500 steps, sub-steps")
 
 
 # -------------------------------------------------------- state handling
