@@ -236,7 +236,9 @@ lb_status lb_get_links(lb_ctx *ctx, int32_t *rec4, int64_t cap, int64_t *n);
 
 /* Per particle k, 12 FP64 values: force and torque acting on it in the last
  * step (F0 - zeta X', including cover/uncover transfers) and the part F0,
- * T0 of the link momentum that does not depend on its velocity. */
+ * T0 that does not depend on its velocity at t+1: the link momentum without
+ * the wall-velocity term, plus, where enabled, the capillary stress
+ * (LB_CAPILLARY_FORCE) and the close-encounter forces (soft_eps, lub_hc). */
 lb_status lb_colloid_forces(lb_ctx *ctx, double *out12, int32_t n);
 
 /* Raw state for bitwise resume: stored populations, psi, c, owner map,
