@@ -345,3 +345,51 @@ def test_batched_side_stream_equals_alone():
         b.step(5)
     for b, a in zip(batch, alone):
         assert _same(_state(b), _state(a))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_options_equal_alone(precision):
+    # per-box options through the batched launch (graph-replayed on a
+    # non-default stream): a box with soft-sphere repulsion and lubrication
+    # between two approaching spheres, one with the capillary stress and caps
+    # of two other sizes, and a plain box (psi/c sub-step counts must agree
+    # within a batch, so all take one).  Each equals the same box stepped
+    # alone, bit for bit
+    import torch
+    shape = (40, 36, 34)
+    N = int(np.prod(shape))
+
+    def spec(seed, params, cols):
+        p = dict(I.FREE_ENERGY, E=-0.2)
+        p.update(params)
+        return dict(shape=shape, precision=precision, params=p,
+                    psi=I.slab(shape, I.WIDTH, amp=0.05, seed=seed),
+                    c=0.3 + I.noise(seed + 1, N, 0.05), colloids=cols)
+
+    def sph(pos, k, **kw):
+        c = I.janus(pos, I.unit_vectors(k, 1)[0], 4.2, alpha=1e-3, mu=0.2, theta=70.0)
+        c.update(kw)
+        return c
+
+    specs = [
+        spec(3, dict(soft_eps=0.05, soft_sigma=1.0, soft_nu=1.0, soft_hc=3.0, lub_hc=3.0),
+             [sph((8.0, 18.0, 17.0), 1, vel=np.array([0.01, 0, 0])),
+              sph((18.6, 18.0, 17.0), 2, vel=np.array([-0.01, 0, 0]))]),
+        spec(5, dict(flags=lb.LB_CAPILLARY_FORCE),
+             [sph((10.3, 9.4, 16.6), 3, cap_cos=0.4), sph((27.5, 24.2, 18.3), 4, cap_cos=-0.3)]),
+        spec(7, {}, [sph((20.2, 17.9, 16.1), 5)]),
+    ]
+    st = torch.cuda.Stream()
+    batch = [lb.from_spec(s_, precision=precision, stream=st) for s_ in specs]
+    lb.batch_step(batch, 6)
+    for b_, s_ in zip(batch, specs):
+        alone = lb.from_spec(s_, precision=precision)
+        alone.step(6)
+        assert np.array_equal(alone.populations(), b_.populations())
+        fa, fb = alone.fields(), b_.fields()
+        assert np.array_equal(fa["psi"], fb["psi"]) and np.array_equal(fa["c"], fb["c"])
+        assert np.array_equal(alone.links(), b_.links())
+        ca, cb = alone.observables()[1], b_.observables()[1]
+        for qa, qb in zip(ca, cb):
+            assert np.array_equal(qa["vel"], qb["vel"]) and np.array_equal(qa["pos"], qb["pos"])
+        alone.close()
