@@ -210,6 +210,22 @@ def paper_regime_run(torch, lb, I, steps=2000, warmup=200):
         N = w["shape"][0] * w["shape"][1] * w["shape"][2]
         out[name] = dict(ms_per_step=round(ms, 5), mlups=round(N / ms / 1e3, 1),
                          error_bits=t["error_bits"])
+    # the single-phase runs of Fig. 3 (A = kappa = E = 0, psi = 0): no mu
+    # pass, chi read from c
+    col = dict(cols[0], H=0.0)
+    w = I.workload_paper([col], single_phase=True)
+    b = lb.from_spec(w, stream=torch.cuda.Stream())
+    tune.apply(b)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    t, _ = b.observables()
+    b.close()
+    out["single_phase"] = dict(ms_per_step=round(ms, 5), mlups=round(64 * 96 * 96 / ms / 1e3, 1),
+                               error_bits=t["error_bits"], particles=1, ch_substeps=2)
     out.update(shape=[64, 96, 96], precision="fp32", particles=2, steps=steps,
                paper=dict(out["paper"], M_psi=0.4, ch_substeps=2, capillary_force=True))
     # a parameter scan of the kind behind Figs. 3-4: 8 boxes of the regime

@@ -90,6 +90,9 @@ struct lb_ctx {
     hipGraphExec_t graph[2];
     SideStream side;    // particle work beside the bulk kernels
     bool has_side;
+    // single phase: a = b = kappa = E = c_b0 = 0 and psi = 0 at init, so mu
+    // is 0 and chi is c at every step (set by lb_init_fields)
+    bool nopsi;
     std::string err;
 };
 
@@ -155,7 +158,7 @@ static BoxDesc box_desc(lb_ctx *c, int parity)
 // the next-state pair when n-1-s is even, else the scratch pair.  Three
 // descriptor tables besides the step's own cover them: sub-step 0 (from the
 // state at t), and the two directions between the pairs.
-static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
+static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3], bool chi_is_c)
 {
     void *ps = ptr(c, c->L.psis), *cs = ptr(c, c->L.ccs);
     const int n = substeps_of(c->p);
@@ -163,6 +166,8 @@ static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
     if (n % 2 == 0) { t[0].b.psin = ps; t[0].b.ccn = cs; }
     t[1].b.psi = d.b.psin; t[1].b.cc = d.b.ccn; t[1].b.psin = ps; t[1].b.ccn = cs;
     t[2].b.psi = ps; t[2].b.cc = cs;
+    if (chi_is_c)
+        for (int k = 0; k < 3; k++) t[k].b.chi = const_cast<void *>(t[k].b.cc);
 }
 
 // Host side of a batch: descriptors and block/particle start tables, laid
@@ -200,6 +205,11 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // one-node form of that kernel
     // (the solute-force term lives in the one-node collide-stream only)
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
+    // single-phase batch (every box): no mu launches, chi read from c
+    B.nopsi = n > 0;
+    for (int j = 0; j < n; j++) B.nopsi = B.nopsi && ctxs[j]->nopsi;
+    if (B.nopsi)
+        for (int j = 0; j < n; j++) d[j].b.chi = const_cast<void *>(d[j].b.cc);
     B.solute_force = 0;
     B.soft = 0;
     for (int j = 0; j < n; j++) {
@@ -245,7 +255,7 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         const size_t base = align256(dbytes + sizeof(int) * (4 * (size_t)n + 4));
         for (int j = 0; j < n; j++) {
             BoxDesc t[3];
-            substep_tables(ctxs[j], d[j], t);
+            substep_tables(ctxs[j], d[j], t, B.nopsi != 0);
             for (int k = 0; k < 3; k++) ((BoxDesc *)(host.data() + base + k * dbytes))[j] = t[k];
         }
         for (int k = 0; k < 3; k++) B.dsub[k] = (const BoxDesc *)(dev + base + k * dbytes);
@@ -718,6 +728,13 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     if (e2 != hipSuccess) return hip_fail(c, e2, "init kernel");
     HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
     HIP_TRY(c, define_spare_state(c));
+    // single phase (A = kappa = E = 0, c_b0 = 0, psi = 0): mu stays 0 and chi
+    // equals c, and psi stays 0 through the psi/c update and cover/uncover;
+    // batches of such boxes skip the mu pass and read chi from c
+    bool np = c->p.a == 0.0 && c->p.b == 0.0 && c->p.kappa == 0.0 && c->p.E == 0.0 && c->p.c_b0 == 0.0;
+    for (size_t n = 0; np && n < N; n++) np = psi[n] == 0.0;
+    c->nopsi = np;
+    if (np) HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.mu), 0, N * compute_bytes(c->p.precision), c->stream));
     c->step = 0;
     c->stage = 1;
     return LB_OK;
@@ -1171,6 +1188,8 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
     HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
     HIP_TRY(c, define_spare_state(c));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->nopsi = false;  // the loaded psi need not be zero: general path
+    c->dirty = true;
     c->step = hd.step;
     c->stage = 2;
     c->dirty = true;

@@ -2089,6 +2089,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     const int vm = B.vec[0] == 4 ? 4 : (B.vec[0] == 2 ? 2 : 1);
     const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
     auto mu = [&](const BatchArgs &a) {
+        if (B.nopsi) return;  // single phase: mu stays 0, chi is read from c
         if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a);
         if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(a);

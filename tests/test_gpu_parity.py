@@ -247,6 +247,56 @@ def test_cap_sizes_match_oracle():
         bad.add_colloids([dict(cols[0], cap_cos=-1.5, H=0.0)])
 
 
+def _single_phase_spec(shape, seed, **kw):
+    # A = kappa = E = 0, c_b0 = 0, psi = 0: the single-phase form (Sec. III.A)
+    N = int(np.prod(shape))
+    p = dict(I.FREE_ENERGY, a=0.0, b=0.0, kappa=0.0, E=0.0, c_b0=0.0)
+    p.update(kw)
+    h = [s / 2.0 for s in shape]
+    col = I.janus((h[0] + 0.3, h[1] - 0.2, h[2] + 0.1), I.unit_vectors(seed, 1)[0], 4.5,
+                  alpha=1e-3, mu_minus=0.2, mu_plus=0.05)
+    col["H"] = 0.0
+    return dict(shape=shape, precision="fp64", params=p, psi=np.zeros(N),
+                c=0.1 * I.uniform(seed + 1, N), colloids=[col])
+
+
+@pytest.mark.parametrize("nsub", [1, 2])
+def test_single_phase_fast_path(nsub):
+    # single-phase boxes skip the mu pass and read chi from c: FP64 within
+    # 1e-12 and FP32 within 2e-5 of the oracle after 60 steps (one and two
+    # psi/c sub-steps); the same box in a batch with a two-phase box (the
+    # general path, mu pass included) gives the same bits; a saved and
+    # reloaded state (general path after the load) continues bit for bit
+    import torch
+    shape = (36, 34, 32)
+    spec = _single_phase_spec(shape, 5, ch_substeps=nsub)
+    g, o = run_pair(spec, 60)
+    _compare(g, o, 1e-12, "single phase nsub=%d" % nsub)
+    _, cg = g.observables()
+    _, co = o.observables()
+    assert np.abs(cg[0]["vel"] - co[0]["vel"]).max() <= 1e-11
+    g32 = lb.from_spec(spec, precision="fp32")
+    g32.step(60)
+    _compare(g32, o, 2e-5, "single phase fp32 nsub=%d" % nsub)
+    st = torch.cuda.Stream()
+    two = _spec(shape, seed=9, ch_substeps=nsub, M_psi=0.1)
+    mixed = [lb.from_spec(spec, precision="fp32", stream=st), lb.from_spec(two, precision="fp32", stream=st)]
+    lb.batch_step(mixed, 60)
+    assert np.array_equal(mixed[0].populations(), g32.populations())
+    f1, f2 = mixed[0].fields(), g32.fields()
+    assert np.array_equal(f1["c"], f2["c"]) and np.array_equal(f1["psi"], f2["psi"])
+    a = lb.from_spec(spec, precision="fp32")
+    a.step(30)
+    blob = a.save_state()
+    a.step(30)
+    b = lb.from_spec(spec, precision="fp32")
+    b.load_state(blob)
+    b.step(30)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.fields()["c"], b.fields()["c"])
+    assert np.array_equal(a.populations(), g32.populations())
+
+
 def test_soft_sphere_parameters_validated():
     with pytest.raises(lb.LBError):
         lb.Box((8, 8, 8), "fp32", soft_eps=-1.0)
