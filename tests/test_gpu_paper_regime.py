@@ -146,3 +146,38 @@ def test_interface_trapping_against_phoretic_push():
     assert dx[(0.2, -0.25, 4)] >= dx[(0.1, -0.25, 4)] >= dx[(0.05, -0.25, 4)] >= dx[(0.025, -0.25, 4)] - 0.05
     assert moved[(0.05, -0.25, 0)] > 0.3
     assert dx[(0.05, -0.25, 0)] > dx[(0.05, -0.25, 4)] + 0.5
+
+
+def test_interface_displacement_linear_in_mu_E_at_twice_the_radius():
+    # Fig. 4's Delta X ~ mu E, resolved at R = 9 (twice the paper's radius;
+    # at R = 4.5 the trapped particle pins at half-lattice positions): box
+    # 128 x 160 x 160, interfaces at x = 32 and 96, E = -0.25, mu = 0.025,
+    # 0.05, 0.1, 0.2, capillary stress on, solute at equilibrium.  After 7500
+    # steps (before the slow instability this option shows at this radius
+    # after ~8000 steps) Delta X / (-mu E) agrees to 15% of its mean across
+    # the eightfold range of mu.  The path is deterministic, so the run
+    # reproduces bit for bit.
+    import torch
+    shape = (128, 160, 160)
+    st = torch.cuda.Stream()
+    boxes, mus = [], (0.025, 0.05, 0.1, 0.2)
+    for mu in mus:
+        col = I.janus((32.0, 80.0, 80.0), (0.0, 1.0, 0.0), 9.0, alpha=0.0, mu=mu, theta=90.0)
+        w = I.workload_paper([col], E=-0.25, shape=shape)
+        w["c"] = w["params"]["c_b0"] - 0.25 * np.tanh(w["psi"])
+        boxes.append(lb.from_spec(w, stream=st))
+    lb.batch_step(boxes, 7500)
+    ratio = []
+    for b, mu in zip(boxes, mus):
+        t, c = b.observables()
+        assert t["error_bits"] == 0
+        f = b.fields()["psi"].reshape(shape[2], shape[1], shape[0])
+        col = f[:, :40, :].reshape(-1, shape[0]).mean(axis=0)
+        i = 24 + int(np.argmax((col[24:40] < 0) & (col[25:41] >= 0)))
+        xint = i + col[i] / (col[i] - col[i + 1])
+        dx = c[0]["pos"][0] - xint
+        ratio.append(dx / (0.25 * mu))
+        flush_print("[trap R=9] mu %s Delta X %.4f ratio %.1f" % (mu, dx, ratio[-1]))
+        b.close()
+    m = np.mean(ratio)
+    assert m > 0 and all(abs(r - m) <= 0.15 * m for r in ratio)
