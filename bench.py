@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default=None, help="time one precision only (profiling runs)")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run only the paper-regime leg (profiling runs)")
     ap.add_argument("--batch", type=int, default=512, help="boxes in the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--serve", type=int, default=0,
@@ -293,8 +295,7 @@ def main():
                          "scaling the HBM byte counters against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: one GPU only (--gpus 1); no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -313,6 +314,11 @@ def main():
     from paper_2202_01631_amd import lb
     lb.load()
     torch.cuda.set_device(0)
+    if args.paper_only:
+        # the paper-regime leg alone (profiling runs)
+        print(json.dumps({"paper_regime": paper_regime_run(torch, lb, I, steps=args.steps,
+                                                           warmup=args.warmup)}), flush=True)
+        return
     n = args.size
     spec = I.workload_many(n=n, count=64, radius=6.0, precision="fp32")
     res = {}
