@@ -4,4 +4,5 @@ Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark import this package; the solver never does.
 """
 from .pyoracle import (Oracle, OracleError, build, lattice, wetting_H, from_spec,  # noqa: F401
-                       solubility_E, SOLUTE_FORCE, EXPLICIT_COLLOID, CAPILLARY_FORCE)
+                       solubility_E, set_threads, SOLUTE_FORCE, EXPLICIT_COLLOID,
+                       CAPILLARY_FORCE)

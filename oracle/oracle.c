@@ -31,6 +31,12 @@
  *     face neighbours, signed so that kappa n.grad(psi) = H with n pointing out
  *     of the particle; contact angle from Eq. 10.
  *
+ * Threads: the per-node loops (chemical potential, collision, streaming,
+ * psi/c update, owner map) may run on several OpenMP threads; each node's
+ * result depends only on its own inputs, and every sum over nodes or links is
+ * taken sequentially in node or link order afterwards, so results are
+ * bitwise the same for any thread count.
+ *
  * Order of one step t -> t+1:
  *   1. mu_psi(t) at fluid nodes                                    (Eq. 2, 9)
  *   2. body force, moments, BGK-Guo collision; pull streaming;
@@ -43,6 +49,9 @@
  *   5. geometry at R(t+1): cover/uncover repair, owner map, link table
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -74,7 +83,7 @@ struct or_ctx {
     long N;
     double *f, *fs, *fn;          /* pre-collision state f(t), post-collision, f(t+1) */
     double *psi, *cc, *psin, *ccn;
-    double *mu, *force, *uf, *src;
+    double *mu, *force, *uf, *src, *chi;
     int *owner, *owner_new;
     or_colloid *col;
     int ncol;
@@ -162,14 +171,10 @@ static int on_active_cap(const or_colloid *k, const double r[3])
     if (k->cap_cos == 0.0) return md <= 0.0;
     /* option: a cap of any size, m.n <= cap_cos with n = r/|r| (reading: the
      * Janus split of Eqs. 5-6 moved to the polar angle acos(cap_cos)),
-     * i.e. m.r <= cap_cos |r|, decided in squares: for cap_cos > 0 true when
-     * m.r <= 0, else when (m.r)^2 <= cap_cos^2 |r|^2; for cap_cos < 0 only
-     * when m.r < 0 and (m.r)^2 >= cap_cos^2 |r|^2 */
+     * written as m.r <= cap_cos |r| */
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
-    double lhs = md * md, rhs = (k->cap_cos * k->cap_cos) * rr;
-    if (k->cap_cos > 0.0) return md <= 0.0 || lhs <= rhs;
-    return md < 0.0 && lhs >= rhs;
+    return md <= k->cap_cos * sqrt(rr);
 }
 
 /* ------------------------------------------------------------ equilibrium */
@@ -237,10 +242,11 @@ int or_create(const or_params *p, or_ctx **out)
     c->force = zalloc(sizeof(double) * 3 * N);
     c->uf = zalloc(sizeof(double) * 3 * N);
     c->src = zalloc(sizeof(double) * N);
+    c->chi = zalloc(sizeof(double) * N);
     c->owner = zalloc(sizeof(int) * N);
     c->owner_new = zalloc(sizeof(int) * N);
     if (!c->f || !c->fs || !c->fn || !c->psi || !c->cc || !c->psin || !c->ccn || !c->mu ||
-        !c->force || !c->uf || !c->src || !c->owner || !c->owner_new) {
+        !c->force || !c->uf || !c->src || !c->chi || !c->owner || !c->owner_new) {
         or_destroy(c);
         return OR_E_INVALID;
     }
@@ -263,7 +269,7 @@ int or_destroy(or_ctx *c)
 {
     if (!c) return OR_OK;
     free(c->f); free(c->fs); free(c->fn); free(c->psi); free(c->cc); free(c->psin);
-    free(c->ccn); free(c->mu); free(c->force); free(c->uf); free(c->src);
+    free(c->ccn); free(c->mu); free(c->force); free(c->uf); free(c->src); free(c->chi);
     free(c->owner); free(c->owner_new);
     free_colloids(c);
     free(c);
@@ -304,6 +310,7 @@ int or_init_fields(or_ctx *c, const double *psi, const double *cc, const double 
 static int owner_map(or_ctx *c, int *own)
 {
     int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|:bad)
     for (long n = 0; n < c->N; n++) {
         int x, y, z;
         coords(c, n, &x, &y, &z);
@@ -433,6 +440,7 @@ static void cross(const double a[3], const double b[3], double o[3])
 static void chemical_potential(or_ctx *c)
 {
     const or_params *p = &c->p;
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < c->N; n++) {
         if (c->owner[n] >= 0) { c->mu[n] = 0.0; continue; }
         int x, y, z;
@@ -509,6 +517,7 @@ static void collide_stream(or_ctx *c)
     const or_params *p = &c->p;
     long N = c->N;
     double sumF[3] = {0.0, 0.0, 0.0};
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         if (c->owner[n] >= 0) {
             for (int i = 0; i < 19; i++) c->fs[i * N + n] = c->f[i * N + n];
@@ -542,7 +551,6 @@ static void collide_stream(or_ctx *c)
             }
             for (int a = 0; a < 3; a++) F[a] += -c->cc[n] * p->C * 3.0 * gc[a];
         }
-        for (int a = 0; a < 3; a++) sumF[a] += F[a];
         double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 19; i++) {
             double fi = c->f[i * N + n];
@@ -559,7 +567,12 @@ static void collide_stream(or_ctx *c)
         }
         for (int a = 0; a < 3; a++) { c->force[a * N + n] = F[a]; c->uf[a * N + n] = u[a]; }
     }
+    /* summed body force over the fluid nodes, in node order */
+    for (long n = 0; n < N; n++)
+        if (c->owner[n] < 0)
+            for (int a = 0; a < 3; a++) sumF[a] += c->force[a * N + n];
     /* pull streaming from fluid upstream neighbours */
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         if (c->owner[n] >= 0) {
             for (int i = 0; i < 19; i++) c->fn[i * N + n] = c->f[i * N + n];
@@ -695,6 +708,7 @@ static void scalar_update(or_ctx *c, double dt)
     const or_params *p = &c->p;
     long N = c->N;
     double sumsrc = 0.0, sumchi = 0.0;
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         if (c->owner[n] >= 0) { c->psin[n] = c->psi[n]; c->ccn[n] = c->cc[n]; continue; }
         double ps = c->psi[n], cn = c->cc[n];
@@ -714,8 +728,13 @@ static void scalar_update(or_ctx *c, double dt)
         }
         c->psin[n] = ps - dt * adv_psi + dt * p->M_psi * dmu;
         c->ccn[n] = cn - dt * adv_c + dt * p->D_c * dchi + dt * c->src[n] - dt * p->k_d * chi;
+        c->chi[n] = chi;
+    }
+    /* emitted solute and summed chi over the fluid nodes, in node order */
+    for (long n = 0; n < N; n++) {
+        if (c->owner[n] >= 0) continue;
         sumsrc += dt * c->src[n];
-        sumchi += dt * chi;
+        sumchi += dt * c->chi[n];
     }
     c->diag[OR_DIAG_SUM_SRC] += sumsrc;
     c->diag[OR_DIAG_SUM_CHI] += sumchi;
@@ -1033,6 +1052,20 @@ int or_lattice(int32_t *cvec57, double *w19)
         if (w19) w19[i] = wt(i);
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------- threads */
+/* OpenMP threads of the per-node loops (n <= 0: the OpenMP default); returns
+ * the count now in effect (1 without OpenMP).  Results do not depend on it. */
+int or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------ parameter maps */

@@ -115,6 +115,7 @@ int or_observables(or_ctx *c, or_totals *t, or_colloid *out, int32_t n);
 int or_colloid_diag(or_ctx *c, int32_t k, double *out40); /* F0[3] T0[3] zeta[36] -> see .c */
 int or_step_diag(or_ctx *c, double *out);              /* OR_DIAG_N doubles */
 int or_lattice(int32_t *cvec57, double *w19);
+int or_set_threads(int32_t n);                         /* per-node loops; results unchanged */
 double or_wetting_H(double theta_deg, double kappa, double b);
 double or_solubility_E(double ratio, double c_b0);
 const char *or_last_error(const or_ctx *c);

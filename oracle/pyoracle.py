@@ -23,7 +23,7 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+    cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
            "-shared", "-D_DEFAULT_SOURCE", "-Wall", "-Wno-unused-function",
            "-o", tmp, SRC, "-lm"]
     subprocess.check_call(cmd)
@@ -90,6 +90,10 @@ def lib():
         L.or_colloid_diag.argtypes = [vp, C.c_int32, dp]
         L.or_step_diag.argtypes = [vp, dp]
         L.or_lattice.argtypes = [C.POINTER(C.c_int32), dp]
+        L.or_set_threads.argtypes = [C.c_int32]
+        L.or_set_threads.restype = C.c_int
+        # one thread unless asked (test workers run side by side)
+        L.or_set_threads(int(os.environ.get("ORACLE_THREADS", "1")))
         L.or_wetting_H.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_wetting_H.restype = C.c_double
         L.or_solubility_E.argtypes = [C.c_double, C.c_double]
@@ -256,6 +260,13 @@ def lattice():
     w = np.empty(19)
     lib().or_lattice(c.ctypes.data_as(C.POINTER(C.c_int32)), _dp(w))
     return c.reshape(19, 3), w
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's per-node loops (one by default, or
+    ORACLE_THREADS; n <= 0: the OpenMP default); returns the count in effect.  Results are bitwise the same for
+    any count (every sum is taken sequentially)."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def wetting_H(theta_deg, kappa, b):

@@ -169,11 +169,10 @@ __host__ __device__ inline bool active_cap(const DColloid &q, const double r[3])
     double md = q.m[0] * r[0] + q.m[1] * r[1];
     md = md + q.m[2] * r[2];
     if (q.capc == 0.0) return md <= 0.0;
-    // a cap of any size: m.r <= capc |r|, compared in squares (no sqrt)
+    // a cap of any size: m.r <= capc |r| (correctly rounded square root)
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
-    const double lhs = md * md, rhs = (q.capc * q.capc) * rr;
-    return q.capc > 0.0 ? (md <= 0.0 || lhs <= rhs) : (md < 0.0 && lhs >= rhs);
+    return md <= q.capc * sqrt(rr);
 }
 
 // Particle bounding box along one axis, with the node coordinates visited in

@@ -144,6 +144,53 @@ def test_bounce_back_momentum_exchange_fixed_sphere():
     assert abs(dg["sum_dmass"]) > 0
 
 
+def _feq(rho, u):
+    """Second-order D3Q19 equilibrium, textbook form w_i rho (1 + 3 c.u +
+    9/2 (c.u)^2 - 3/2 u.u), weights 1/3, 1/18, 1/36."""
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    cu = CVEC @ np.asarray(u, dtype=np.float64)
+    uu = float(np.dot(u, u))
+    return w * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
+
+
+@pytest.mark.parametrize("V", [(1e-6, -7e-7, 4e-7), (0.0, 2e-6, -1e-6)])
+def test_moving_wall_term_is_galilean(V):
+    # Galilean check of the moving-wall term (Sec. II.B): a sphere held at
+    # velocity V inside fluid moving with V everywhere.  In the sphere's frame
+    # nothing moves, so after one step
+    #   (1) every fluid population is still f^eq(rho0, V): the bounced
+    #       population f*_d - 6 w_d rho0 c_d.V equals f^eq of the opposite
+    #       direction, because f^eq_d - 6 w_d c_d.V = f^eq_dbar exactly (the
+    #       2/c_s^2 = 6 of the wall term against the 3 c.u of f^eq);
+    #   (2) the force on the sphere, F0 - zeta V, vanishes to O(V^2): F0 =
+    #       sum over links of 2 f*_d c_d = 6 sum w c (c.V) + O(V^2) (the zero-
+    #       order part sum w_d c_d vanishes for any solid set: each direction
+    #       and its opposite cut the surface equally often), and zeta V is the
+    #       wall term's 6 sum w c (c.V); likewise the torque.
+    # A wrong wall coefficient (3 or 12 instead of 6) leaves O(V) ~ 1e-7
+    # errors in (1) and a force of order zeta V ~ 4e-5 in (2).
+    shape = (24, 22, 20)
+    N = int(np.prod(shape))
+    o = oracle.Oracle(shape, a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0, E=0.0, c_b0=0.0,
+                      D_c=0.1, k_d=0.0, tau=0.8)
+    u = np.repeat(np.array(V)[:, None], N, axis=1)
+    o.init_fields(np.zeros(N), np.zeros(N), None, u)
+    o.add_colloids([dict(pos=(11.3, 10.8, 9.6), m=(0.0, 0.6, 0.8), radius=4.3, vel=V,
+                         fixed=1)])
+    fl = o.owner() < 0
+    o.step(1)
+    f = o.populations()
+    want = _feq(1.0, V)
+    assert np.abs(f[:, fl] - want[:, None]).max() <= 1e-15
+    d = o.colloid_diag(0)
+    zeta = d["zeta"]
+    assert np.abs(zeta[:3, :3] @ np.array(V)).max() > 1e-5   # the wall term is there
+    assert np.abs(d["F0"] - zeta[:3, :3] @ np.array(V)).max() <= 1e-10
+    assert np.abs(d["T0"] - zeta[3:, :3] @ np.array(V)).max() <= 1e-9
+    assert np.abs(d["F"]).max() <= 1e-10 and np.abs(d["T"]).max() <= 1e-9
+    o.close()
+
+
 def test_moving_colloid_momentum_balance():
     # free colloid launched through a quiescent fluid with cover/uncover:
     # fluid momentum + particle momentum + pending cover/uncover transfer

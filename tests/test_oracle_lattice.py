@@ -231,3 +231,24 @@ def test_paper_mobility_needs_substeps():
     with pytest.raises(RuntimeError):
         oracle.Oracle((8, 8, 8), ch_substeps=1, **FE)
     oracle.Oracle((8, 8, 8), ch_substeps=2, **FE).close()
+
+
+def test_threads_do_not_change_results():
+    # the per-node loops may run on several OpenMP threads; every sum is taken
+    # in node or link order afterwards, so one thread and many give the same
+    # bits (32^3 workload with a moving Janus sphere, 6 steps)
+    from paper_2202_01631_amd import inputs as I
+    w = I.workload_small()
+    out = []
+    for nt in (1, 4):
+        assert oracle.set_threads(nt) == nt
+        o = oracle.from_spec(w)
+        o.step(6)
+        f = o.populations()
+        fl = o.fields()
+        _, cols = o.observables()
+        out.append((f, fl["psi"], fl["c"], o.links(), o.owner(), cols[0]["pos"], cols[0]["vel"]))
+        o.close()
+    oracle.set_threads(1)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

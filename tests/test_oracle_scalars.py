@@ -70,6 +70,69 @@ def test_solute_fourier_mode_exact_substeps(nsub):
         assert np.abs(o.fields()["psi"] - 1.0).max() == 0.0
 
 
+def _iso_gradient_symbol(k):
+    """Fourier symbol g of the D3Q19 isotropic gradient 3 sum_i w_i c_i f(x + c_i):
+    for f = exp(i k.x) it returns i g(k) exp(i k.x).  Worked out by hand from
+    the weights 1/18 (faces) and 1/36 (edges):
+    g_x = sin(k_x) (1 + cos k_y + cos k_z) / 3, and cyclically."""
+    s = [math.sin(v) for v in k]
+    c = [math.cos(v) for v in k]
+    return [s[0] * (1 + c[1] + c[2]) / 3, s[1] * (1 + c[2] + c[0]) / 3,
+            s[2] * (1 + c[0] + c[1]) / 3]
+
+
+@pytest.mark.parametrize("kvec,u0", [
+    ((1, 0, 0), (0.0, 0.0, 0.0)),
+    ((1, 1, 2), (0.0, 0.0, 0.0)),
+    ((2, 1, 3), (0.0, 0.0, 0.0)),
+    ((1, 2, 1), (0.03, -0.02, 0.01)),
+])
+def test_psi_update_one_step_fourier_mode(kvec, u0):
+    # Eq. 3b linearised about psi = 1 (with a = -b, mu(1) = 0) for one small
+    # Fourier mode psi = 1 + eps cos(k.x), E = 0 (no solute coupling), rest
+    # populations at density 1 and uniform velocity u0.  One step of the
+    # method then gives, to first order in eps:
+    #   mu   = eps m_k cos(k.x),  m_k = a + 3b + kappa lam,  lam = sum_a 4 sin^2(k_a/2)
+    #          (Eq. 2 with the 7-point Laplacian);
+    #   F    = -psi grad(mu) = eps m_k g(k) sin(k.x) (isotropic gradient symbol g);
+    #   u    = u0 + F/2 (first moment plus half the force, density 1);
+    #   psi' = 1 + eps Re(G exp(i k.x)) with
+    #   G    = 1 - i sum_a u0_a sin k_a - m_k (M_psi lam + 1/2 sum_a sin(k_a) g_a),
+    #          the three terms being the central-flux advection by u0, the
+    #          diffusion M_psi lap(mu) and the central-flux divergence of F/2.
+    # The second-order remainder is ~eps^2 = 1e-14; a wrong factor on M_psi,
+    # on the flux, on F/2 or on the gradient stencil moves psi' by >= 1e-10.
+    shape = (8, 6, 10)
+    N = int(np.prod(shape))
+    x = I.coords(shape)
+    k = [2 * np.pi * kvec[a] / shape[a] for a in range(3)]
+    phase = sum(k[a] * x[a] for a in range(3))
+    a, b, kap, M, eps = -0.0625, 0.0625, 0.04, 0.1, 1e-7
+    o = oracle.Oracle(shape, a=a, b=b, kappa=kap, M_psi=M, C=0.0625, E=0.0, c_b0=0.3,
+                      D_c=0.1, k_d=1e-3, tau=0.9)
+    u = np.repeat(np.array(u0)[:, None], N, axis=1)
+    o.init_fields(1.0 + eps * np.cos(phase), np.full(N, 0.3), None, u)
+    o.step(1)
+    lam = sum(4 * math.sin(v / 2) ** 2 for v in k)
+    mk = a + 3 * b + kap * lam
+    g = _iso_gradient_symbol(k)
+    aux = o.aux()
+    # first-order fields; the remainder is the eps^2 term (3 b eps^2 = 2e-15 in mu)
+    assert np.abs(aux["mu"] - eps * mk * np.cos(phase)).max() <= 1e-14
+    for ax in range(3):
+        F = eps * mk * g[ax] * np.sin(phase)
+        assert np.abs(aux["force"][ax] - F).max() <= 1e-14
+        assert np.abs(aux["u"][ax] - (u0[ax] + F / 2)).max() <= 1e-14
+    G = (1.0 - 1j * sum(u0[ax] * math.sin(k[ax]) for ax in range(3))
+         - mk * (M * lam + 0.5 * sum(math.sin(k[ax]) * g[ax] for ax in range(3))))
+    want = 1.0 + eps * np.real(G * np.exp(1j * phase))
+    err = np.abs(o.fields()["psi"] - want).max()
+    assert err <= 2e-13, err
+    # the mode really moved: the first-order change is far above the bound
+    assert eps * abs(1.0 - G) >= 1e-3 * eps
+    o.close()
+
+
 # ------------------------------------------------------ discrete free energy
 def _free_energy(psi, c, shape, p, owner=None, surf=None):
     """Eq. 1 on the lattice (torch, FP64): sum over fluid nodes of
