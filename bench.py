@@ -12,6 +12,7 @@ FP16 storage is timed beside it, and the FP64 CPU oracle is timed on one step
 of it on the host (cpu_baseline).
 """
 import argparse
+import faulthandler
 import hashlib
 import json
 import os
@@ -128,14 +129,18 @@ def cpu_info():
     return model, os.cpu_count()
 
 
-def batched_sweep(torch, lb, I, nbox, steps):
+def batched_sweep(torch, lb, I, nbox, steps, eager_steps=100):
     """Boxes of the batched sweep (sides 32/48/64, one sphere each), FP32:
     aggregate MLUPS of the batched graph-replayed step against the same boxes
-    advanced one after another with the plain single-box step."""
+    advanced one after another on the single-box production path (a
+    non-default stream, graph-replayed step pairs, tuned shapes where cached),
+    and, for fewer steps, one after another with eager launches on the
+    default stream."""
     from paper_2202_01631_amd import tune
     specs = I.batch_boxes(count=nbox, steps=steps)
+    nodes = sum(s["shape"][0] * s["shape"][1] * s["shape"][2] for s in specs)
+    lu = nodes * steps
     stream = torch.cuda.Stream()
-    lu = sum(s["shape"][0] * s["shape"][1] * s["shape"][2] for s in specs) * steps
     # the batch keeps the library's default shapes: the shapes cached for
     # small boxes stepped alone differ in form between the sizes, and a mixed
     # batch then falls back to the one-node forms everywhere (measured on
@@ -149,21 +154,29 @@ def batched_sweep(torch, lb, I, nbox, steps):
     tb = time.perf_counter() - t0
     for b in boxes:
         b.close()
-    boxes = [lb.from_spec(s, precision="fp32") for s in specs]
-    for b in boxes:
-        tune.apply(b)
-        b.step(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for b in boxes:
-        b.step(steps)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    for b in boxes:
-        b.close()
-    return dict(boxes=nbox, steps=steps, lattice_updates=lu,
-                batched_mlups=round(lu / tb / 1e6, 1), sequential_mlups=round(lu / ts / 1e6, 1),
-                speedup=round(ts / tb, 3))
+
+    def one_by_one(stream, k):
+        bs = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+        for b in bs:
+            tune.apply(b)
+            b.step(4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in bs:
+            b.step(k)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        for b in bs:
+            b.close()
+        return nodes * k / t / 1e6
+
+    seq = one_by_one(torch.cuda.Stream(), steps)
+    eager = one_by_one(None, min(steps, eager_steps))
+    bm = lu / tb / 1e6
+    return dict(boxes=nbox, steps=steps, lattice_updates=lu, batched_mlups=round(bm, 1),
+                sequential_mlups=round(seq, 1), speedup=round(bm / seq, 3),
+                sequential_eager_mlups=round(eager, 1), sequential_eager_steps=min(steps, eager_steps),
+                speedup_vs_eager=round(bm / eager, 3))
 
 
 def serving_run(torch, I, nreq, rate, step_scale):
@@ -255,23 +268,40 @@ def paper_regime_run(torch, lb, I, steps=2000, warmup=200):
 
 
 def cpu_baseline(spec):
+    """The FP64 oracle on one step of the workload, on one host thread and on
+    all of them (OpenMP over the per-node loops; bitwise the same result)."""
     import oracle
-    log("[bench] cpu baseline: FP64 oracle, 1 step of the workload")
-    t0 = time.time()
-    o = oracle.from_spec(spec)
-    t1 = time.time()
-    o.step(1)
-    t2 = time.time()
-    N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
-    o.close()
     model, ncpu = cpu_info()
-    return dict(value=round(N / (t2 - t1) / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
-                sample="1 time step of the full 256^3 64-sphere workload, FP64 oracle, "
-                       "single thread (setup %.1f s excluded, step %.1f s) on %s, %s logical "
-                       "CPUs visible" % (t1 - t0, t2 - t1, model, ncpu))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = ncpu
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+    N = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
+    out = {}
+    for label, nt in (("one", 1), ("all", nthreads)):
+        used = oracle.set_threads(nt)
+        log("[bench] cpu baseline: FP64 oracle, 1 step of the workload, %d thread(s)" % used)
+        t0 = time.time()
+        o = oracle.from_spec(spec)
+        t1 = time.time()
+        o.step(1)
+        t2 = time.time()
+        o.close()
+        out[label] = dict(mlups=round(N / (t2 - t1) / 1e6, 4), threads=used,
+                          step_s=round(t2 - t1, 2), setup_s=round(t1 - t0, 1))
+    oracle.set_threads(1)
+    return dict(value=out["one"]["mlups"], unit="MLUPS", cores=1, kind="oracle",
+                all_cores=out["all"],
+                sample="1 time step of the full 256^3 64-sphere workload, FP64 oracle, one "
+                       "thread (step %.1f s, setup %.1f s excluded); the same step on %d "
+                       "threads: %.3f MLUPS; %s, %s logical CPUs visible, %d usable"
+                       % (out["one"]["step_s"], out["one"]["setup_s"], out["all"]["threads"],
+                          out["all"]["mlups"], model, ncpu, avail))
 
 
 def main():
+    faulthandler.enable()  # a native crash prints the Python stack
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -282,7 +312,7 @@ def main():
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper-regime leg (profiling runs)")
     ap.add_argument("--batch", type=int, default=512, help="boxes in the batched sweep (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve", type=int, default=0,
                     help="requests in the serving run (0: skip, the default: the serving replay "
                          "ended twice in a host segmentation fault whose cause is not found, so "

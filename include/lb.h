@@ -255,8 +255,9 @@ lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
  * the step is one launch covering all boxes (boxes may differ in size and in
  * particle count; all must share the precision and ch_substeps), and on a
  * non-default stream the launch sequence of two steps is captured once as a
- * HIP graph and replayed.  Work goes to the stream of ctxs[0]; the call
- * synchronises that stream before returning.  LB_E_INVALID for an empty
+ * HIP graph and replayed.  Work goes to the stream of ctxs[0]; work queued
+ * earlier on the other boxes' own streams is waited for first, and the call
+ * synchronises the stream of ctxs[0] before returning.  LB_E_INVALID for an empty
  * list, a repeated context, mixed precisions or mixed ch_substeps;
  * LB_E_STATE if a context lacks its fields. */
 lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);

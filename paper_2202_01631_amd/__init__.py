@@ -6,4 +6,4 @@ The solver is the HIP library ``csrc/liblbphoretic.so`` behind the C ABI in
 ``include/lb.h``; ``lb`` is its Python binding.  Importing this package does
 not load the library; ``lb.load()`` does, and fails loudly when it is absent.
 """
-__all__ = ["inputs", "params", "lb"]
+__all__ = ["inputs", "lb", "serve", "tune"]

@@ -701,16 +701,26 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     if (u)
         for (size_t n = 0; n < 3 * N; n++)
             if (!std::isfinite(u[n])) return fail(c, LB_E_INVALID, "non-finite u");
+    // FP64 staging of the host fields: in the second population lattice,
+    // which the init kernel does not touch and which is set from the first
+    // right after it; a separate buffer only where that does not hold them
+    // (FP16 storage with rho and u given)
     double *d = nullptr;
     const size_t need = (2 + (rho ? 1 : 0) + (u ? 3 : 0)) * N;
-    HIP_TRY(c, hipMalloc((void **)&d, need * sizeof(double)));
+    const bool staged = need * sizeof(double) <= 19 * N * storage_bytes(c->p.precision);
+    if (staged) d = (double *)ptr(c, c->L.f[1]);
+    else HIP_TRY(c, hipMalloc((void **)&d, need * sizeof(double)));
     double *dpsi = d, *dc = d + N, *drho = rho ? d + 2 * N : nullptr;
     double *du = u ? d + (rho ? 3 : 2) * N : nullptr;
     hipError_t e = hipMemcpyAsync(dpsi, psi, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dc, cc, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(drho, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) { hipFree(d); return hip_fail(c, e, "hipMemcpyAsync"); }
+    if (e != hipSuccess) {
+        hipStreamSynchronize(c->stream);
+        if (!staged) hipFree(d);
+        return hip_fail(c, e, "hipMemcpyAsync");
+    }
     free_colloids(c);
     c->dirty = true;
     c->cur = 0;
@@ -723,7 +733,7 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     }
     e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(c->stream);
-    hipFree(d);
+    if (!staged) hipFree(d);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel launch");
     if (e2 != hipSuccess) return hip_fail(c, e2, "init kernel");
     HIP_TRY(c, hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
@@ -840,10 +850,13 @@ lb_status lb_step(lb_ctx *c, int64_t nsteps)
     // not on the legacy default stream, which cannot be captured)
     if (!c->timing && c->stream && nsteps >= 2) {
         const int par = c->cur;
-        if (!c->graph[par]) {
-            hipError_t e = capture_pair(c->self[par], c->self[1 - par], c->stream, side_of(c),
-                                        &c->graph[par]);
-            if (e != hipSuccess) { c->graph[par] = nullptr; return hip_fail(c, e, "graph capture"); }
+        // both parities at once: a later call that starts on the other
+        // parity (after an odd step count) then replays without capturing
+        for (int q = 0; q < 2; q++) {
+            if (c->graph[q]) continue;
+            hipError_t e = capture_pair(c->self[q], c->self[1 - q], c->stream, side_of(c),
+                                        &c->graph[q]);
+            if (e != hipSuccess) { c->graph[q] = nullptr; return hip_fail(c, e, "graph capture"); }
         }
         for (; s + 2 <= nsteps; s += 2) HIP_TRY(c, hipGraphLaunch(c->graph[par], c->stream));
     }
@@ -872,6 +885,13 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
     }
     lb_ctx *c0 = ctxs[0];
     hipStream_t s = c0->stream;
+    // work still queued on the other boxes' own streams (initialisation
+    // copies, earlier steps) finishes before the batch touches their state
+    for (int j = 1; j < n; j++) {
+        bool seen = ctxs[j]->stream == s;
+        for (int i = 1; i < j && !seen; i++) seen = ctxs[i]->stream == ctxs[j]->stream;
+        if (!seen) HIP_TRY(ctxs[j], hipStreamSynchronize(ctxs[j]->stream));
+    }
     std::vector<int> par0(n), par1(n);
     for (int j = 0; j < n; j++) { par0[j] = ctxs[j]->cur; par1[j] = 1 - ctxs[j]->cur; }
     char *dev = nullptr;

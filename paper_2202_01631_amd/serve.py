@@ -14,6 +14,7 @@ Time-to-result = completion time - arrival time.  Each result is identical
 to the same request run alone (the batched step is bitwise equal to the
 single-box step).
 """
+import faulthandler
 import heapq
 import math
 import time
@@ -145,6 +146,7 @@ def replay(trace, budget_bytes, max_slots=256, chunk=200, step_scale=1.0, stream
     step_scale shortens every request (for bounded runs).  Returns
     (results by request id, summary with p50/p99 time-to-result and
     sustained MLUPS)."""
+    faulthandler.enable()  # a native crash prints the Python stack
     srv = Server(budget_bytes, max_slots=max_slots, chunk=chunk, stream=stream, collect=collect,
                  streams=streams)
     reqs = trace[:limit] if limit else trace

@@ -1,0 +1,87 @@
+"""Drive the sanitizer build of the library (liblb_hostcheck.so) through the
+rest of the C ABI's call sequences (TEST INFRASTRUCTURE): every entry point,
+the error paths, save/load, timing, launch shapes, a batch of uneven boxes on
+a caller stream with an odd step count, contexts destroyed in any order.
+Exit status 0 and "abi ok" mean no sanitizer or runtime-misuse report.
+
+    python abi_check.py LIB
+"""
+import ctypes as C
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.modules["torch"] = None
+
+import numpy as np  # noqa: E402
+
+from paper_2202_01631_amd import inputs as I  # noqa: E402
+from paper_2202_01631_amd import lb  # noqa: E402
+
+
+def expect_error(fn, *a):
+    try:
+        fn(*a)
+    except lb.LBError:
+        return
+    raise AssertionError("expected an LBError from %s" % fn)
+
+
+def main():
+    lb.LIB_PATH = sys.argv[1]
+    lb._lib = None
+    L = lb.load()
+    L.hostcheck_live_allocations.restype = C.c_size_t
+    st = C.c_void_p()
+    assert L.hipStreamCreateWithFlags(C.byref(st), 1) == 0
+    w = I.workload_small()
+    for prec in ("fp64", "fp32", "fp16"):
+        for stream in (None, st.value):
+            b = lb.from_spec(w, precision=prec, stream=stream)
+            b.step(3)
+            b.observables(check=False)
+            b.fields()
+            b.populations()
+            b.owner()
+            b.links()
+            b.colloid_forces()
+            s = b.save_state()
+            b.load_state(s)
+            b.step(2)
+            b.timing_enable(True)
+            b.step(1)
+            b.timing_read()
+            b.timing_enable(False)
+            b.set_launch_shapes([(64, 4, 0), (32, 8, 1), (0, 0, 2 + 8 * 4)])
+            b.launch_shapes()
+            b.step(4)
+            expect_error(b.set_launch_shapes, [(-1, 0, 0)] * 3)
+            b.close()
+    # error paths before and after init
+    b = lb.Box((16, 16, 16), "fp32", **lb.spec_params(w))
+    expect_error(b.step, 1)
+    expect_error(b.add_colloids, w["colloids"])
+    b.close()
+    expect_error(lambda: lb.Box((16, 16, 16), "fp32", tau=0.4))
+    # a batch of uneven boxes (sizes, particle counts, options) on a caller
+    # stream, odd step count, destroyed in a different order
+    specs = I.batch_boxes(count=6, sides=(32, 40, 48), steps=5)
+    boxes = [lb.from_spec(s, stream=st.value) for s in specs]
+    boxes[2].add_colloids([])
+    lb.batch_step(boxes, 5)
+    lb.batch_step(boxes[::-1], 2)
+    expect_error(lb.batch_step, [boxes[0], boxes[0]], 2)
+    for b in boxes[::2] + boxes[1::2]:
+        b.observables(check=False)
+        b.links()
+        b.close()
+    left = L.hostcheck_live_allocations()
+    print("abi ok: %d device allocations left" % left, flush=True)
+    if left:
+        sys.exit(3)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,6 +71,25 @@ def test_batched_equals_alone(precision):
                 assert np.array_equal(cb[k][key], ca[k][key])
 
 
+def test_batch_waits_for_work_on_other_streams():
+    # a box without particles on a stream of its own, initialised and stepped
+    # there (its initialisation copies and steps still queued), then batched
+    # with a box whose stream leads the batch: it equals the same box run
+    # alone, bit for bit
+    import torch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    specs = _boxes(n=2, seed=17)
+    free = dict(specs[1], colloids=[])
+    a = lb.from_spec(specs[0], stream=s1)
+    b = lb.from_spec(free, stream=s2)
+    b.step(3)
+    lb.batch_step([a, b], 4)
+    alone = lb.from_spec(free)
+    alone.step(7)
+    flush_print("[batch] streams", free["shape"])
+    assert _same(_state(b), _state(alone))
+
+
 def test_batched_fp64_matches_oracle():
     specs = _boxes(n=3, seed=5)
     batch = [lb.from_spec(s, precision="fp64") for s in specs]

@@ -54,12 +54,3 @@ def test_served_equals_alone(per_precision_streams):
                 assert np.array_equal(q[key], ca[k][key])
         assert res[i]["totals"]["step"] == spec["steps"]
         alone.close()
-
-
-def test_oversized_request_is_refused():
-    srv = serve.Server(budget_bytes=1 << 20)
-    spec = I.serving_request(dict(I.serving_trace(1)[0], side=40, spheres=1))
-    spec["steps"] = 4
-    srv.submit(0, spec, 0.0)
-    res = srv.run()
-    assert "error" in res[0]

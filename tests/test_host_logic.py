@@ -131,3 +131,13 @@ def test_params_struct_layout_matches_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_oversized_request_is_refused():
+    # admission by footprint alone: host-side sizes, no GPU call
+    srv = serve.Server(budget_bytes=1 << 20)
+    spec = I.serving_request(dict(I.serving_trace(1)[0], side=40, spheres=1))
+    spec["steps"] = 4
+    srv.submit(0, spec, 0.0)
+    res = srv.run()
+    assert "error" in res[0]
