@@ -28,7 +28,9 @@ METRIC = ("MLUPS & % HBM roofline (256³ FP32 vs FP64 plain); batched sweep p50/
 # algorithmic bytes per lattice update: 19 populations and psi, c read once
 # and written once (storage bytes 8 / 4 / 2, psi and c in the compute type)
 STEP_BYTES = {"fp64": 19 * 2 * 8 + 2 * 2 * 8, "fp32": 19 * 2 * 4 + 2 * 2 * 4,
-              "fp16": 19 * 2 * 2 + 2 * 2 * 4}
+              "fp16": 19 * 2 * 2 + 2 * 2 * 4,
+              # single phase (Sec. III.A, psi absent): populations and c only
+              "fp32_single_phase": 19 * 2 * 4 + 2 * 4}
 # the collide-stream kernel alone moves the populations: 19 read + 19 written
 COLLIDE_BYTES = {"fp64": 19 * 2 * 8, "fp32": 19 * 2 * 4, "fp16": 19 * 2 * 2}
 KERNELS = ("k_mu", "k_collide", "k_scalar", "k_link_partial+k_colloid_update", "k_cover",
@@ -96,6 +98,16 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
                 kernel_ms=per_kernel, kernel_steps=ksteps, error_bits=tot["error_bits"], N=N,
                 reps_ms_per_step=[round(v, 5) for v in reps],
                 median_ms_per_step=round(float(sorted(reps)[len(reps) // 2]), 5))
+
+
+def single_phase_spec(spec):
+    """The same box and particles in the single-phase form of Sec. III.A:
+    A = kappa = E = c_b0 = 0 and psi = 0 (no interface, no wetting)."""
+    import numpy as np
+    p = dict(spec["params"], a=0.0, b=0.0, kappa=0.0, E=0.0, c_b0=0.0)
+    cols = [dict(q, H=0.0) for q in spec["colloids"]]
+    return dict(spec, name=spec.get("name", "") + "_single_phase", params=p,
+                psi=np.zeros_like(spec["psi"]), colloids=cols)
 
 
 def copy_ceiling(torch):
@@ -358,6 +370,12 @@ def main():
         res[prec] = time_gpu(spec, prec, args.steps, args.warmup, torch, lb)
         log("[bench] %s: %.3f ms/step, %.0f MLUPS, kernels %s" % (
             prec, res[prec]["ms_per_step"], res[prec]["mlups"], res[prec]["kernel_ms"]))
+    if not args.only:
+        log("[bench] %d^3 fp32 single phase: warmup %d, timed %d" % (n, args.warmup, args.steps))
+        res["fp32_single_phase"] = time_gpu(single_phase_spec(spec), "fp32", args.steps,
+                                            args.warmup, torch, lb)
+        log("[bench] single phase: %.3f ms/step, %.0f MLUPS" % (
+            res["fp32_single_phase"]["ms_per_step"], res["fp32_single_phase"]["mlups"]))
     main_prec = precs[0]
     r = res[main_prec]
     N = r["N"]

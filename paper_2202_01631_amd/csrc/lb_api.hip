@@ -22,10 +22,10 @@ size_t storage_bytes(int prec) { return prec == LB_FP64 ? 8 : (prec == LB_FP32 ?
 size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 
 // Arena layout (each piece 256-byte aligned): f[2] (19 N storage), psi[2],
-// c[2], mu and chi (N compute each), u (3N compute), owner (N bytes), and
-// with psi/c sub-steps one more psi and c pair (N compute each).
+// c[2], mu (N compute), u (3N compute), owner (N bytes), and with psi/c
+// sub-steps one more psi and c pair (N compute each).
 struct Layout {
-    size_t f[2], psi[2], cc[2], mu, chi, u, own, psis, ccs, total;
+    size_t f[2], psi[2], cc[2], mu, u, own, psis, ccs, total;
 };
 
 int substeps_of(const lb_params &p) { return p.ch_substeps > 1 ? p.ch_substeps : 1; }
@@ -40,7 +40,6 @@ Layout layout_of(const lb_params &p)
     for (int b = 0; b < 2; b++) { L.psi[b] = o; o = align256(o + N * cb); }
     for (int b = 0; b < 2; b++) { L.cc[b] = o; o = align256(o + N * cb); }
     L.mu = o; o = align256(o + N * cb);
-    L.chi = o; o = align256(o + N * cb);
     L.u = o; o = align256(o + 3 * N * cb);
     L.own = o; o = align256(o + N);
     L.psis = L.ccs = 0;
@@ -126,7 +125,6 @@ static StepBuffers buffers(lb_ctx *c, int cu)
     b.psin = ptr(c, c->L.psi[nx]);
     b.ccn = ptr(c, c->L.cc[nx]);
     b.mu = ptr(c, c->L.mu);
-    b.chi = ptr(c, c->L.chi);
     b.u = ptr(c, c->L.u);
     b.own = (uint8_t *)ptr(c, c->L.own);
     b.col = c->dcol;
@@ -158,7 +156,7 @@ static BoxDesc box_desc(lb_ctx *c, int parity)
 // the next-state pair when n-1-s is even, else the scratch pair.  Three
 // descriptor tables besides the step's own cover them: sub-step 0 (from the
 // state at t), and the two directions between the pairs.
-static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3], bool chi_is_c)
+static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
 {
     void *ps = ptr(c, c->L.psis), *cs = ptr(c, c->L.ccs);
     const int n = substeps_of(c->p);
@@ -166,8 +164,6 @@ static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3], bool chi_i
     if (n % 2 == 0) { t[0].b.psin = ps; t[0].b.ccn = cs; }
     t[1].b.psi = d.b.psin; t[1].b.cc = d.b.ccn; t[1].b.psin = ps; t[1].b.ccn = cs;
     t[2].b.psi = ps; t[2].b.cc = cs;
-    if (chi_is_c)
-        for (int k = 0; k < 3; k++) t[k].b.chi = const_cast<void *>(t[k].b.cc);
 }
 
 // Host side of a batch: descriptors and block/particle start tables, laid
@@ -205,11 +201,26 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // one-node form of that kernel
     // (the solute-force term lives in the one-node collide-stream only)
     const int ssize = ctxs[0]->p.precision == LB_FP64 ? 8 : 4;
-    // single-phase batch (every box): no mu launches, chi read from c
+    // single-phase batch (every box): no mu launches, single-phase kernels
     B.nopsi = n > 0;
     for (int j = 0; j < n; j++) B.nopsi = B.nopsi && ctxs[j]->nopsi;
-    if (B.nopsi)
-        for (int j = 0; j < n; j++) d[j].b.chi = const_cast<void *>(d[j].b.cc);
+    if (B.nopsi) {
+        // single-phase kernels exist in the one-node collide-stream and the
+        // one-node and row-vector psi/c updates: other forms drop to those
+        for (int j = 0; j < n; j++) {
+            const int ss = ctxs[j]->p.precision == LB_FP64 ? 8 : 4;
+            if (d[j].ls[1].vec > 1) {
+                d[j].ls[1].vec = 0;
+                d[j].ls[1].bx = d[j].ls[1].by = 0;
+                finish_shape(d[j].ls[1], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ss, true);
+            }
+            if (d[j].ls[2].zc > 1) {
+                d[j].ls[2].zc = 0;
+                finish_shape(d[j].ls[2], ctxs[j]->p.nx, ctxs[j]->p.ny, ctxs[j]->p.nz, ss);
+            }
+            for (int w = 1; w < 3; w++) bst[w * (n + 1) + j + 1] = bst[w * (n + 1) + j] + d[j].ls[w].nblocks;
+        }
+    }
     B.solute_force = 0;
     B.soft = 0;
     for (int j = 0; j < n; j++) {
@@ -255,7 +266,7 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         const size_t base = align256(dbytes + sizeof(int) * (4 * (size_t)n + 4));
         for (int j = 0; j < n; j++) {
             BoxDesc t[3];
-            substep_tables(ctxs[j], d[j], t, B.nopsi != 0);
+            substep_tables(ctxs[j], d[j], t);
             for (int k = 0; k < 3; k++) ((BoxDesc *)(host.data() + base + k * dbytes))[j] = t[k];
         }
         for (int k = 0; k < 3; k++) B.dsub[k] = (const BoxDesc *)(dev + base + k * dbytes);
@@ -557,6 +568,73 @@ static lb_status alloc_colloid_tables(lb_ctx *c, double rmax, int lcap)
     return LB_OK;
 }
 
+// ------------------------------------------------------------ batches
+// checks shared by the batched entry points; work still queued on the other
+// boxes' own streams (initialisation copies, earlier steps) is waited for,
+// so that it finishes before the batch touches their state
+static lb_status batch_check(lb_ctx *const *ctxs, int n, int64_t nsteps)
+{
+    if (!ctxs || n < 1) return fail(nullptr, LB_E_INVALID, "empty batch");
+    if (nsteps < 0) return fail(nullptr, LB_E_INVALID, "negative step count");
+    for (int j = 0; j < n; j++) {
+        if (!ctxs[j]) return fail(nullptr, LB_E_INVALID, "null context in batch");
+        if (ctxs[j]->stage < 1) return fail(ctxs[j], LB_E_STATE, "lb_init_fields must come first");
+        if (ctxs[j]->p.precision != ctxs[0]->p.precision)
+            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share the precision");
+        if (substeps_of(ctxs[j]->p) != substeps_of(ctxs[0]->p))
+            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share ch_substeps");
+        for (int i = 0; i < j; i++)
+            if (ctxs[i] == ctxs[j]) return fail(ctxs[j], LB_E_INVALID, "context twice in a batch");
+    }
+    hipStream_t s = ctxs[0]->stream;
+    for (int j = 1; j < n; j++) {
+        bool seen = ctxs[j]->stream == s;
+        for (int i = 1; i < j && !seen; i++) seen = ctxs[i]->stream == ctxs[j]->stream;
+        if (!seen) HIP_TRY(ctxs[j], hipStreamSynchronize(ctxs[j]->stream));
+    }
+    return LB_OK;
+}
+
+// nsteps steps of every box, descriptor tables of the two buffer parities at
+// dev and dev + bb (device memory of at least 2 bb bytes), on the stream of
+// ctxs[0]; step pairs replayed from a captured graph when graphs is set and
+// the stream is not the legacy default one, else launched one by one.
+// Synchronises the stream before returning.
+static lb_status batch_run(lb_ctx *const *ctxs, int n, int64_t nsteps, char *dev, size_t bb,
+                           bool graphs, const SideStream *side)
+{
+    lb_ctx *c0 = ctxs[0];
+    hipStream_t s = c0->stream;
+    std::vector<int> par0(n), par1(n);
+    for (int j = 0; j < n; j++) { par0[j] = ctxs[j]->cur; par1[j] = 1 - ctxs[j]->cur; }
+    Batch B0, B1;
+    std::vector<char> h0, h1;
+    batch_fill(ctxs, n, par0.data(), h0, dev, B0);
+    batch_fill(ctxs, n, par1.data(), h1, dev + bb, B1);
+    hipError_t e = hipMemcpyAsync(dev, h0.data(), h0.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev + bb, h1.data(), h1.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int64_t k = 0;
+    hipGraphExec_t ge = nullptr;
+    if (graphs && e == hipSuccess && s && nsteps >= 2) {
+        e = capture_pair(B0, B1, s, side, &ge);
+        for (; e == hipSuccess && k + 2 <= nsteps; k += 2) e = hipGraphLaunch(ge, s);
+    }
+    for (; e == hipSuccess && k < nsteps; k++) {
+        launch_one_step((k & 1) ? B1 : B0, s, side, nullptr);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (ge) hipGraphExecDestroy(ge);
+    if (e != hipSuccess) return hip_fail(c0, e, "batched step");
+    if (e2 != hipSuccess) return hip_fail(c0, e2, "batched step");
+    for (int j = 0; j < n; j++) {
+        if (nsteps & 1) ctxs[j]->cur ^= 1;
+        ctxs[j]->step += nsteps;
+    }
+    return LB_OK;
+}
+
 extern "C" {
 
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes)
@@ -744,7 +822,14 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     bool np = c->p.a == 0.0 && c->p.b == 0.0 && c->p.kappa == 0.0 && c->p.E == 0.0 && c->p.c_b0 == 0.0;
     for (size_t n = 0; np && n < N; n++) np = psi[n] == 0.0;
     c->nopsi = np;
-    if (np) HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.mu), 0, N * compute_bytes(c->p.precision), c->stream));
+    if (np) {
+        // the single-phase kernels neither compute mu nor write psi: both
+        // psi buffers (and the sub-step one) and mu hold zeros from here on
+        const size_t sb = N * compute_bytes(c->p.precision);
+        HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.mu), 0, sb, c->stream));
+        HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.psi[1]), 0, sb, c->stream));
+        if (substeps_of(c->p) > 1) HIP_TRY(c, hipMemsetAsync(ptr(c, c->L.psis), 0, sb, c->stream));
+    }
     c->step = 0;
     c->stage = 1;
     return LB_OK;
@@ -871,59 +956,15 @@ lb_status lb_step(lb_ctx *c, int64_t nsteps)
 
 lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
 {
-    if (!ctxs || n < 1) return fail(nullptr, LB_E_INVALID, "empty batch");
-    if (nsteps < 0) return fail(nullptr, LB_E_INVALID, "negative step count");
-    for (int j = 0; j < n; j++) {
-        if (!ctxs[j]) return fail(nullptr, LB_E_INVALID, "null context in batch");
-        if (ctxs[j]->stage < 1) return fail(ctxs[j], LB_E_STATE, "lb_init_fields must come first");
-        if (ctxs[j]->p.precision != ctxs[0]->p.precision)
-            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share the precision");
-        if (substeps_of(ctxs[j]->p) != substeps_of(ctxs[0]->p))
-            return fail(ctxs[j], LB_E_INVALID, "boxes of a batch must share ch_substeps");
-        for (int i = 0; i < j; i++)
-            if (ctxs[i] == ctxs[j]) return fail(ctxs[j], LB_E_INVALID, "context twice in a batch");
-    }
+    lb_status st = batch_check(ctxs, n, nsteps);
+    if (st != LB_OK) return st;
     lb_ctx *c0 = ctxs[0];
-    hipStream_t s = c0->stream;
-    // work still queued on the other boxes' own streams (initialisation
-    // copies, earlier steps) finishes before the batch touches their state
-    for (int j = 1; j < n; j++) {
-        bool seen = ctxs[j]->stream == s;
-        for (int i = 1; i < j && !seen; i++) seen = ctxs[i]->stream == ctxs[j]->stream;
-        if (!seen) HIP_TRY(ctxs[j], hipStreamSynchronize(ctxs[j]->stream));
-    }
-    std::vector<int> par0(n), par1(n);
-    for (int j = 0; j < n; j++) { par0[j] = ctxs[j]->cur; par1[j] = 1 - ctxs[j]->cur; }
     char *dev = nullptr;
     const size_t bb = align256(batch_bytes(n, substeps_of(c0->p)));
     HIP_TRY(c0, hipMalloc((void **)&dev, 2 * bb));
-    Batch B0, B1;
-    std::vector<char> h0, h1;
-    batch_fill(ctxs, n, par0.data(), h0, dev, B0);
-    batch_fill(ctxs, n, par1.data(), h1, dev + bb, B1);
-    hipError_t e = hipMemcpyAsync(dev, h0.data(), h0.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dev + bb, h1.data(), h1.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    int64_t k = 0;
-    hipGraphExec_t ge = nullptr;
-    if (e == hipSuccess && s && nsteps >= 2) {
-        e = capture_pair(B0, B1, s, side_of(c0), &ge);
-        for (; e == hipSuccess && k + 2 <= nsteps; k += 2) e = hipGraphLaunch(ge, s);
-    }
-    for (; e == hipSuccess && k < nsteps; k++) {
-        launch_one_step((k & 1) ? B1 : B0, s, side_of(c0), nullptr);
-        e = hipGetLastError();
-    }
-    hipError_t e2 = hipStreamSynchronize(s);
-    if (ge) hipGraphExecDestroy(ge);
+    st = batch_run(ctxs, n, nsteps, dev, bb, true, side_of(c0));
     hipFree(dev);
-    if (e != hipSuccess) return hip_fail(c0, e, "batched step");
-    if (e2 != hipSuccess) return hip_fail(c0, e2, "batched step");
-    for (int j = 0; j < n; j++) {
-        if (nsteps & 1) ctxs[j]->cur ^= 1;
-        ctxs[j]->step += nsteps;
-    }
-    return LB_OK;
+    return st;
 }
 
 lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)

@@ -13,7 +13,7 @@ struct StepBuffers {
     void *fout;
     const void *psi, *cc;   // state at t
     void *psin, *ccn;       // state at t+1
-    void *mu, *chi, *u;     // derived fields of step t
+    void *mu, *u;           // derived fields of step t
     uint8_t *own;
     DColloid *col;
     int *lnode;
@@ -63,7 +63,7 @@ struct Batch {
     int solute_force; // some box has LB_SOLUTE_FORCE (one-node collide-stream with the term)
     int nsub;         // psi/c sub-steps per step (all boxes of the batch)
     int soft;         // some box has soft-sphere repulsion (k_soft runs)
-    int nopsi;        // every box single phase: no mu launches, chi read from c
+    int nopsi;        // every box single phase: no mu launches, single-phase kernels
     // with nsub > 1: descriptor tables of sub-step 0 (state at t -> its
     // target), next-state -> scratch and scratch -> next-state psi/c pairs
     const BoxDesc *dsub[3];

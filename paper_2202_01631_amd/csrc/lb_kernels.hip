@@ -78,7 +78,6 @@ __device__ __forceinline__ void st_interior(S *base, unsigned on, const SVec<S, 
 }
 
 // ------------------------------------------------------------------ k_mu
-// Also stores chi = c - c_b0 - E tanh psi for the solute update.
 // mu_psi = a psi + b psi^3 - kappa lap(psi) - C E chi (1 - tanh^2 psi),
 // chi = c - c_b0 - E tanh psi (Eq. 2; 1/cosh^2 = 1 - tanh^2, cubic factored
 // as b psi (psi-1)(psi+1) + (a+b) psi to keep FP32 cancellation small).
@@ -116,21 +115,30 @@ template <class S> __device__ __forceinline__ S lap6(S ps, const S f[6])
     return l;
 }
 
+// chi = c - c_b0 - E tanh psi, the solute's distance from its equilibrium
+// c0(psi) (Eq. 1); not stored: every kernel that needs it forms it from psi
+// and c with this one expression
+template <class S> __device__ __forceinline__ S chi_of(const KParams &p, S ps, S cn)
+{
+#pragma clang fp contract(off)
+    return fma(-(S)p.E, s_tanh<S>(ps), cn - (S)p.cb0);
+}
+
 template <class S>
 __device__ __forceinline__ void mu_chi(const KParams &p, S ps, S lap, S cn, S &mu, S &chi)
 {
 #pragma clang fp contract(off)
     const S a = (S)p.a, b = (S)p.b;
     const S t = s_tanh<S>(ps);
-    chi = fma(-(S)p.E, t, cn - (S)p.cb0);
+    chi = fma(-(S)p.E, t, cn - (S)p.cb0);  // chi_of, sharing t
     S m = b * ps * (ps - S(1)) * (ps + S(1));
     m = fma(a + b, ps, m);
     m = fma(-(S)p.kappa, lap, m);
     mu = fma(-(S)(p.C * p.E) * chi, fma(-t, t, S(1)), m);
 }
 
-// mu and chi of fluid node n = (x, y, z) next to a particle: wetting ghost
-// at every solid face
+// mu of fluid node n = (x, y, z) next to a particle: wetting ghost at every
+// solid face
 template <class S>
 __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y,
                                             int z)
@@ -149,7 +157,6 @@ __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, 
     S m, c;
     mu_chi<S>(p, ps, lap6<S>(ps, pv), ((const S *)D.b.cc)[n], m, c);
     ((S *)D.b.mu)[n] = m;
-    ((S *)D.b.chi)[n] = c;
 }
 
 // one node per thread
@@ -164,7 +171,6 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ mu = (S *)D.b.mu;
-    S *__restrict__ chi_out = (S *)D.b.chi;
     int x, y, z;
     if (!lattice_node(p, blk - A.bstart[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
@@ -179,7 +185,7 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     S pv[6];
 #pragma unroll
     for (int e = 0; e < 6; e++) pv[e] = ldb(psi, (unsigned)nb[e] * sizeof(S));
-    if (o & OWN_SOLID) { stb(mu, on, S(0)); stb(chi_out, on, S(0)); return; }
+    if (o & OWN_SOLID) { stb(mu, on, S(0)); return; }
     if (o & OWN_BOUNDARY) {  // here (BND) or in the fix-up launch
         if (BND) mu_bnd_node<S>(D, p, n, x, y, z);
         return;
@@ -187,7 +193,6 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     S m, c;
     mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
     stb(mu, on, m);
-    stb(chi_out, on, c);
 }
 
 // Row-vector form: V consecutive x nodes per lane, 8- or 16-byte loads and
@@ -207,7 +212,6 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ mu = (S *)D.b.mu;
-    S *__restrict__ chi_out = (S *)D.b.chi;
     int x0, y, z, li, gb;
     if (!vec_node<V>(p, blk - A.bstart[j], x0, y, z, li, gb)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
@@ -230,7 +234,7 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
         if (li == 0) pl = ldb(psi, (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S));
         if (li == Ls - 1) pr = ldb(psi, (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S));
     }
-    Vec mv, xv;
+    Vec mv;
 #pragma unroll
     for (int k = 0; k < V; k++) {
         const uint8_t o = byte_of(ow, k);
@@ -241,10 +245,8 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
         mu_chi<S>(p, ps, lap6<S>(ps, pv), cv.v[k], m, c);
         const bool solid = (o & OWN_SOLID) != 0;
         mv.v[k] = solid ? S(0) : m;
-        xv.v[k] = solid ? S(0) : c;
     }
     st_interior<S, V>(mu, on, mv, ow);
-    st_interior<S, V>(chi_out, on, xv, ow);
     if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
         for (int k = 0; k < V; k++)
             if (byte_of(ow, k) & OWN_BOUNDARY) mu_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
@@ -272,7 +274,7 @@ template <class S> struct NodeMoments {
 
 // g: the 19 populations; mv[1..18]: mu at the neighbours, replaced by
 // m0 = mu(x) where bit i of solid is set
-template <class S, bool SF = false>
+template <class S, bool SF = false, bool SP = false>
 __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, const S g[19],
                                                           const S mv[19], S m0, unsigned solid,
                                                           S ps, const S *xv = nullptr,
@@ -288,6 +290,12 @@ __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, cons
         if (cy(i)) jy = cy(i) > 0 ? jy + g[i] : jy - g[i];
         if (cz(i)) jz = cz(i) > 0 ? jz + g[i] : jz - g[i];
     }
+    if (SP) {
+        // single phase: psi = 0, so -psi grad(mu) adds nothing
+        m.Fx = (S)p.fx;
+        m.Fy = (S)p.fy;
+        m.Fz = (S)p.fz;
+    } else {
     // grad(mu) = 3 sum_i w_i c_i mu(x + c_i)
     S mi[19];
 #pragma unroll
@@ -308,6 +316,7 @@ __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, cons
     m.Fx = fma(-ps, gx, (S)p.fx);
     m.Fy = fma(-ps, gy, (S)p.fy);
     m.Fz = fma(-ps, gz, (S)p.fz);
+    }
     if (SF) {
         // option: -c grad(mu_c), mu_c = C chi; xv[1..18]: chi at the
         // neighbours, x0 = chi(x) at solid ones; cn = c(x) (0: no term)
@@ -369,8 +378,9 @@ __device__ __forceinline__ S collide_pop(int i, S gi, const NodeMoments<S> &m, S
 }
 
 // one node per thread; SF: boxes with LB_SOLUTE_FORCE get the -c grad(mu_c)
-// term
-template <int P, bool SF>
+// term; SP: every box single phase (psi and mu zero everywhere, so the force
+// is the external one): psi and mu are not read, with the same results
+template <int P, bool SF, bool SP = false>
 __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 {
     typedef typename Prec<P>::T T;
@@ -402,11 +412,18 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 #pragma unroll
     for (int i = 0; i < 19; i++) g[i] = ldp(fin + i * N, on, p.inv_scale);
     const unsigned os = (unsigned)n * sizeof(S);
-    const S m0 = ldb(mu, os), ps = ldb(psi, os);
+    S m0 = S(0), ps = S(0);
     S mv[19];
 #pragma unroll
-    for (int i = 1; i < 19; i++)
-        mv[i] = ldb(mu, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) * sizeof(S));
+    for (int i = 0; i < 19; i++) mv[i] = S(0);
+    if (!SP) {
+        m0 = ldb(mu, os);
+        ps = ldb(psi, os);
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            mv[i] = ldb(mu, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) *
+                                sizeof(S));
+    }
     if (o & OWN_SOLID) return;
     // solid neighbours (only boundary nodes have any), as a mask over i
     unsigned solid = 0;
@@ -422,16 +439,18 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
 #pragma unroll
         for (int i = 0; i < 19; i++) xv[i] = S(0);
         if (p.flags & LB_SOLUTE_FORCE) {
-            const S *__restrict__ chi = (const S *)D.b.chi;
-            x0 = ldb(chi, os);
-            cn = ldb((const S *)D.b.cc, os);
+            const S *__restrict__ cc = (const S *)D.b.cc;
+            cn = ldb(cc, os);
+            x0 = chi_of<S>(p, ps, cn);
 #pragma unroll
-            for (int i = 1; i < 19; i++)
-                xv[i] = ldb(chi, (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) *
-                                     sizeof(S));
+            for (int i = 1; i < 19; i++) {
+                const unsigned om =
+                    (unsigned)(n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1]) * sizeof(S);
+                xv[i] = chi_of<S>(p, ldb(psi, om), ldb(cc, om));
+            }
         }
     }
-    const NodeMoments<S> M = collide_moments<S, SF>(p, g, mv, m0, solid, ps, xv, x0, cn);
+    const NodeMoments<S> M = collide_moments<S, SF, SP>(p, g, mv, m0, solid, ps, xv, x0, cn);
     const S om = (S)p.om;
     const S pref = (S)p.pref;
     // nodes without solid neighbours store along a straight line (FP64
@@ -761,7 +780,6 @@ __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, 
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
-    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S *__restrict__ ua[3] = {(const S *)D.b.u, (const S *)D.b.u + p.N,
                                    (const S *)D.b.u + 2 * (size_t)p.N};
     const uint8_t *__restrict__ own = D.b.own;
@@ -769,7 +787,7 @@ __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, 
     const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
                        n + (wrap_p(y, p.ny) - y) * sy, n + (wrap_m(y, p.ny) - y) * sy,
                        n + (wrap_p(z, p.nz) - z) * sz, n + (wrap_m(z, p.nz) - z) * sz};
-    const S ps = psi[n], cn = cc[n], chi = chiv[n], m0 = mu[n];
+    const S ps = psi[n], cn = cc[n], chi = chi_of<S>(p, ps, cn), m0 = mu[n];
     const S u0[3] = {ua[0][n], ua[1][n], ua[2][n]};
     S um[6], pm[6], cm[6], mm[6], xm[6];
     unsigned solid = 0;
@@ -780,7 +798,7 @@ __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, 
         pm[e] = psi[m];
         cm[e] = cc[m];
         mm[e] = mu[m];
-        xm[e] = chiv[m];
+        xm[e] = chi_of<S>(p, pm[e], cm[e]);
         solid |= (own[m] & OWN_SOLID) ? (1u << e) : 0u;
     }
     S psn, cpart;
@@ -789,8 +807,10 @@ __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, 
     ((S *)D.b.ccn)[n] = fma(-(S)p.kd, chi, cpart + emission<S>(p, D.b.col, own, n, x, y, z));
 }
 
-// one node per thread
-template <class S, bool BND>
+// one node per thread.  SP (every box single phase: psi and mu zero, chi =
+// c): psi, mu and chi are not read and psi is not written (it stays zero),
+// with the same results for c
+template <class S, bool BND, bool SP = false>
 __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
 {
     const int *bst = A.bstart + 2 * (A.nbox + 1);
@@ -801,7 +821,6 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
-    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S *__restrict__ ua[3] = {(const S *)D.b.u, (const S *)D.b.u + p.N,
                                    (const S *)D.b.u + 2 * (size_t)p.N};
     const uint8_t *__restrict__ own = D.b.own;
@@ -817,20 +836,20 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
     // every field load is issued before anything depends on the owner byte
     const uint8_t o = own[n];
     const unsigned on = (unsigned)n * sizeof(S);
-    const S ps = ldb(psi, on), cn = ldb(cc, on), chi = ldb(chiv, on), m0 = ldb(mu, on);
+    const S cn = ldb(cc, on);
+    const S ps = SP ? S(0) : ldb(psi, on), m0 = SP ? S(0) : ldb(mu, on);
     const S u0[3] = {ldb(ua[0], on), ldb(ua[1], on), ldb(ua[2], on)};
     S um[6], pm[6], cm[6], mm[6], xm[6];
 #pragma unroll
     for (int e = 0; e < 6; e++) {
         const unsigned om = (unsigned)fn[e] * sizeof(S);
         um[e] = ldb(ua[e >> 1], om);
-        pm[e] = ldb(psi, om);
         cm[e] = ldb(cc, om);
-        mm[e] = ldb(mu, om);
-        xm[e] = ldb(chiv, om);
+        pm[e] = SP ? S(0) : ldb(psi, om);
+        mm[e] = SP ? S(0) : ldb(mu, om);
     }
     if (o & OWN_SOLID) {
-        stb(psin, on, ps);
+        if (!SP) stb(psin, on, ps);
         stb(ccn, on, cn);
         return;
     }
@@ -838,15 +857,20 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
         if (BND) psic_bnd_node<S>(D, p, n, x, y, z);
         return;
     }
+    // chi from psi and c (single phase: c itself)
+    const S chi = SP ? cn : chi_of<S>(p, ps, cn);
+#pragma unroll
+    for (int e = 0; e < 6; e++) xm[e] = SP ? cm[e] : chi_of<S>(p, pm[e], cm[e]);
     S psn, cpart;
     psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, 0u, psn, cpart);
-    stb(psin, on, psn);
+    if (!SP) stb(psin, on, psn);
     stb(ccn, on, fma(-(S)p.kd, chi, cpart));
 }
 
 // Row-vector form (as k_mu_v): V consecutive x nodes per lane, x neighbours
-// of psi, c, mu, chi and u_x exchanged between lanes.
-template <class S, int V, bool BND>
+// of psi, c, mu, chi and u_x exchanged between lanes.  SP as for psic_one:
+// only c and u are read, only c is written.
+template <class S, int V, bool BND, bool SP = false>
 __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
 {
     typedef SVec<S, V> Vec;
@@ -859,7 +883,6 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
-    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S *__restrict__ ux = (const S *)D.b.u;
     const S *__restrict__ uy = ux + p.N;
     const S *__restrict__ uz = ux + 2 * (size_t)p.N;
@@ -870,7 +893,10 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     // neighbour rows are the centre rows of another group of the block:
     // those come from LDS, only rows outside the block from memory.  Every
     // thread reaches the barrier (no early return before it).
-    __shared__ Vec shr[5][256];  // psi, c, mu, chi, u_y centre vectors
+    // psi, c, mu, chi, u_y centre vectors (SP: c, u_y)
+    constexpr int NS = SP ? 2 : 5;
+    __shared__ Vec shr[NS][256];
+    auto sf = [](int f) { return SP ? (f == 4 ? 1 : 0) : f; };  // field -> LDS slot
     int x0 = 0, y = 0, z = 0, li = 0, gb = 0;
     const bool live = vec_node<V>(p, blk - bst[j], x0, y, z, li, gb);
     const int sy = p.nx, sz = p.nx * p.ny;
@@ -899,10 +925,9 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
         ow = ldb((const OW *)own, (unsigned)n0);
         // centre vectors of the four stencil fields and u, then the rows
         // from memory: z +- 1 always, y +- 1 outside the block
-        c0[0] = ldb((const Vec *)psi, on);
+        if (!SP) c0[0] = ldb((const Vec *)psi, on);
         c0[1] = ldb((const Vec *)cc, on);
-        c0[2] = ldb((const Vec *)mu, on);
-        c0[3] = ldb((const Vec *)chiv, on);
+        if (!SP) c0[2] = ldb((const Vec *)mu, on);
         u0x = ldb((const Vec *)ux, on);
         u0y = ldb((const Vec *)uy, on);
         u0z = ldb((const Vec *)uz, on);
@@ -910,26 +935,36 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
         for (int e = 0; e < 2; e++) {
             if (src[e] >= 0) continue;
             const unsigned om = (unsigned)nb[e] * sizeof(S);
-            nbv[0][e] = ldb((const Vec *)psi, om);
+            if (!SP) nbv[0][e] = ldb((const Vec *)psi, om);
             nbv[1][e] = ldb((const Vec *)cc, om);
-            nbv[2][e] = ldb((const Vec *)mu, om);
-            nbv[3][e] = ldb((const Vec *)chiv, om);
+            if (!SP) nbv[2][e] = ldb((const Vec *)mu, om);
             if (e == 0) uyp = ldb((const Vec *)uy, om);
             else uym = ldb((const Vec *)uy, om);
         }
 #pragma unroll
         for (int e = 2; e < 4; e++) {
             const unsigned om = (unsigned)nb[e] * sizeof(S);
-            nbv[0][e] = ldb((const Vec *)psi, om);
+            if (!SP) nbv[0][e] = ldb((const Vec *)psi, om);
             nbv[1][e] = ldb((const Vec *)cc, om);
-            nbv[2][e] = ldb((const Vec *)mu, om);
-            nbv[3][e] = ldb((const Vec *)chiv, om);
+            if (!SP) nbv[2][e] = ldb((const Vec *)mu, om);
         }
         uzp = ldb((const Vec *)uz, (unsigned)nb[2] * sizeof(S));
         uzm = ldb((const Vec *)uz, (unsigned)nb[3] * sizeof(S));
+        if (!SP) {
+            // chi of the centre vector and of the rows read from memory
 #pragma unroll
-        for (int f = 0; f < 4; f++) shr[f][threadIdx.x] = c0[f];
-        shr[4][threadIdx.x] = u0y;
+            for (int k = 0; k < V; k++) c0[3].v[k] = chi_of<S>(p, c0[0].v[k], c0[1].v[k]);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (e < 2 && src[e] >= 0) continue;
+#pragma unroll
+                for (int k = 0; k < V; k++) nbv[3][e].v[k] = chi_of<S>(p, nbv[0][e].v[k], nbv[1][e].v[k]);
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; f++)
+            if (!SP || f == 1) shr[sf(f)][threadIdx.x] = c0[f];
+        shr[sf(4)][threadIdx.x] = u0y;
     }
     __syncthreads();
     if (!live) return;
@@ -937,9 +972,22 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     for (int e = 0; e < 2; e++) {
         if (src[e] < 0) continue;
 #pragma unroll
-        for (int f = 0; f < 4; f++) nbv[f][e] = shr[f][src[e]];
-        if (e == 0) uyp = shr[4][src[e]];
-        else uym = shr[4][src[e]];
+        for (int f = 0; f < 4; f++)
+            if (!SP || f == 1) nbv[f][e] = shr[sf(f)][src[e]];
+        if (e == 0) uyp = shr[sf(4)][src[e]];
+        else uym = shr[sf(4)][src[e]];
+    }
+    if (SP) {
+        // psi and mu zero, chi the solute itself
+#pragma unroll
+        for (int k = 0; k < V; k++) { c0[0].v[k] = S(0); c0[2].v[k] = S(0); }
+        c0[3] = c0[1];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            nbv[0][e] = c0[0];
+            nbv[2][e] = c0[0];
+            nbv[3][e] = nbv[1][e];
+        }
     }
     // x neighbours: last node of the lane on the left, first of the right
     const int Ls = p.ls.bx;
@@ -947,6 +995,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     S fl[5], fr[5];  // psi, c, mu, chi, u_x
 #pragma unroll
     for (int f = 0; f < 4; f++) {
+        if (SP && f != 1) continue;
         fl[f] = __shfl(c0[f].v[V - 1], srcl);
         fr[f] = __shfl(c0[f].v[0], srcr);
     }
@@ -956,14 +1005,29 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
         const int rb = n0 - x0;
         if (li == 0) {
             const unsigned ol = (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S);
-            fl[0] = ldb(psi, ol); fl[1] = ldb(cc, ol); fl[2] = ldb(mu, ol); fl[3] = ldb(chiv, ol);
+            fl[1] = ldb(cc, ol);
+            if (!SP) {
+                fl[0] = ldb(psi, ol);
+                fl[2] = ldb(mu, ol);
+                fl[3] = chi_of<S>(p, fl[0], fl[1]);
+            }
             fl[4] = ldb(ux, ol);
         }
         if (li == Ls - 1) {
             const unsigned orr = (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S);
-            fr[0] = ldb(psi, orr); fr[1] = ldb(cc, orr); fr[2] = ldb(mu, orr); fr[3] = ldb(chiv, orr);
+            fr[1] = ldb(cc, orr);
+            if (!SP) {
+                fr[0] = ldb(psi, orr);
+                fr[2] = ldb(mu, orr);
+                fr[3] = chi_of<S>(p, fr[0], fr[1]);
+            }
             fr[4] = ldb(ux, orr);
         }
+    }
+    if (SP) {
+        fl[0] = fr[0] = fl[2] = fr[2] = S(0);
+        fl[3] = fl[1];
+        fr[3] = fr[1];
     }
     Vec pnv, cnv;
 #pragma unroll
@@ -987,7 +1051,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
         pnv.v[k] = sol ? c0[0].v[k] : psn;
         cnv.v[k] = sol ? c0[1].v[k] : fma(-(S)p.kd, c0[3].v[k], cpart);
     }
-    st_interior<S, V>(psin, on, pnv, ow);
+    if (!SP) st_interior<S, V>(psin, on, pnv, ow);
     st_interior<S, V>(ccn, on, cnv, ow);
     if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
         for (int k = 0; k < V; k++)
@@ -1013,14 +1077,18 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
-    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S *__restrict__ ux = (const S *)D.b.u;
     const S *__restrict__ uy = ux + p.N;
     const S *__restrict__ uz = ux + 2 * (size_t)p.N;
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
-    const S *__restrict__ wf[5] = {psi, cc, mu, chiv, uz};  // fields kept over z
+    // fields kept over z; chi (slot 3) is formed from psi and c, not loaded
+    const S *__restrict__ wf[5] = {psi, cc, mu, nullptr, uz};
+    auto chi_vec = [&](Vec &x, const Vec &ps, const Vec &cv) {
+#pragma unroll
+        for (int k = 0; k < V; k++) x.v[k] = chi_of<S>(p, ps.v[k], cv.v[k]);
+    };
     const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
     const int Ls = ls.bx, g = l / Ls;
     if (g >= ls.by) return;
@@ -1046,7 +1114,9 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
         for (int s = 0; s < 3; s++) {
             const int n = c0 + sz * pl[s];
 #pragma unroll
-            for (int f = 0; f < 5; f++) W[f][s] = ldb((const Vec *)wf[f], (unsigned)n * sizeof(S));
+            for (int f = 0; f < 5; f++)
+                if (f != 3) W[f][s] = ldb((const Vec *)wf[f], (unsigned)n * sizeof(S));
+            chi_vec(W[3][s], W[0][s], W[1][s]);
             WO[s] = ldb((const OW *)own, (unsigned)n);
         }
         const unsigned o0 = (unsigned)(c0 + sz * z0) * sizeof(S);
@@ -1064,7 +1134,9 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
             if (z2 >= p.nz) z2 -= p.nz;
             const int n2 = c0 + sz * z2;
 #pragma unroll
-            for (int f = 0; f < 5; f++) nW[f] = ldb((const Vec *)wf[f], (unsigned)n2 * sizeof(S));
+            for (int f = 0; f < 5; f++)
+                if (f != 3) nW[f] = ldb((const Vec *)wf[f], (unsigned)n2 * sizeof(S));
+            chi_vec(nW[3], nW[0], nW[1]);
             nO = ldb((const OW *)own, (unsigned)n2);
             const unsigned o1 = (unsigned)(c0 + sz * wrap_p(z, p.nz)) * sizeof(S);
             nux = ldb((const Vec *)ux, o1);
@@ -1074,10 +1146,12 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
         Vec Y[5][2];
         const unsigned oyp = (unsigned)(n0 + dyp) * sizeof(S), oym = (unsigned)(n0 + dym) * sizeof(S);
 #pragma unroll
-        for (int f = 0; f < 4; f++) {
+        for (int f = 0; f < 3; f++) {
             Y[f][0] = ldb((const Vec *)wf[f], oyp);
             Y[f][1] = ldb((const Vec *)wf[f], oym);
         }
+        chi_vec(Y[3][0], Y[0][0], Y[1][0]);
+        chi_vec(Y[3][1], Y[0][1], Y[1][1]);
         Y[4][0] = ldb((const Vec *)uy, oyp);
         Y[4][1] = ldb((const Vec *)uy, oym);
         // x neighbours: last node of the lane on the left, first of the right
@@ -1095,13 +1169,15 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
             if (li == 0) {
                 const unsigned ol = (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S);
 #pragma unroll
-                for (int f = 0; f < 4; f++) fl[f] = ldb(wf[f], ol);
+                for (int f = 0; f < 3; f++) fl[f] = ldb(wf[f], ol);
+                fl[3] = chi_of<S>(p, fl[0], fl[1]);
                 fl[4] = ldb(ux, ol);
             }
             if (li == Ls - 1) {
                 const unsigned orr = (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S);
 #pragma unroll
-                for (int f = 0; f < 4; f++) fr[f] = ldb(wf[f], orr);
+                for (int f = 0; f < 3; f++) fr[f] = ldb(wf[f], orr);
+                fr[3] = chi_of<S>(p, fr[0], fr[1]);
                 fr[4] = ldb(ux, orr);
             }
         }
@@ -1606,12 +1682,12 @@ __global__ __launch_bounds__(GCHUNK) void k_mu_bnd(BatchArgs A)
     mu_fix<S>(A, blockIdx.x);
 }
 
-template <class S, int V, bool ZM, bool BND>
+template <class S, int V, bool ZM, bool BND, bool SP = false>
 __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
 {
-    if (V == 1) psic_one<S, BND>(A, blockIdx.x + A.boff);
+    if (V == 1) psic_one<S, BND, SP>(A, blockIdx.x + A.boff);
     else if (ZM) psic_zmarch<S, (V > 1 ? V : 2), BND>(A, blockIdx.x + A.boff);
-    else psic_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x + A.boff);
+    else psic_vec<S, (V > 1 ? V : 2), BND, SP>(A, blockIdx.x + A.boff);
 }
 
 template <class S>
@@ -2089,7 +2165,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     const int vm = B.vec[0] == 4 ? 4 : (B.vec[0] == 2 ? 2 : 1);
     const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
     auto mu = [&](const BatchArgs &a) {
-        if (B.nopsi) return;  // single phase: mu stays 0, chi is read from c
+        if (B.nopsi) return;  // single phase: mu stays 0
         if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a);
         if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(a);
@@ -2111,6 +2187,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
     if (B.solute_force) k_collide<P, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    else if (B.nopsi && B.vec[1] <= 1) k_collide<P, false, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.vec[1] == 4) k_collide_v<P, V4><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.vec[1] == 2) k_collide_v<P, 2><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else k_collide<P, false><<<B.nblocks[1], 256, 0, s>>>(B.args);
@@ -2126,6 +2203,20 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a0);
     const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
     auto scalar = [&](const dim3 gs, const BatchArgs &a) {
+        if (B.nopsi && !B.zmarch) {
+            // single phase: c and u only
+            if (vs == 4) {
+                if (bi) k_scalar<S, V4, false, true, true><<<gs, 256, 0, s>>>(a);
+                else k_scalar<S, V4, false, false, true><<<gs, 256, 0, s>>>(a);
+            } else if (vs == 2) {
+                if (bi) k_scalar<S, 2, false, true, true><<<gs, 256, 0, s>>>(a);
+                else k_scalar<S, 2, false, false, true><<<gs, 256, 0, s>>>(a);
+            } else {
+                if (bi) k_scalar<S, 1, false, true, true><<<gs, 256, 0, s>>>(a);
+                else k_scalar<S, 1, false, false, true><<<gs, 256, 0, s>>>(a);
+            }
+            return;
+        }
         if (vs == 4 && B.zmarch) {
             if (bi) k_scalar<S, V4, true, true><<<gs, 256, 0, s>>>(a);
             else k_scalar<S, V4, true, false><<<gs, 256, 0, s>>>(a);

@@ -36,6 +36,7 @@ constexpr uint64_t STREAM_MAGIC = 0x53545245414d2121ull, EVENT_MAGIC = 0x4556454
 std::recursive_mutex g_mu;
 std::map<uintptr_t, size_t> g_mem;  // live device allocations
 hipError_t g_last = hipSuccess;
+size_t g_registered_vars = 0;  // entries of g_mem that are __device__ variables
 
 [[noreturn]] void die(const char *what)
 {
@@ -364,6 +365,13 @@ hipError_t hipGetLastError(void)
     return e;
 }
 
+hipError_t hipGetDevice(int *d)
+{
+    if (!d) die("hipGetDevice with a null argument");
+    *d = 0;
+    return hipSuccess;
+}
+
 hipError_t hipGetSymbolAddress(void **p, const void *sym)
 {
     if (!p || !sym) die("hipGetSymbolAddress with a null argument");
@@ -415,7 +423,13 @@ hipError_t hipLaunchKernel(const void *, dim3 g, dim3 b, void **, size_t, hipStr
 void **__hipRegisterFatBinary(const void *) { static void *h = nullptr; return &h; }
 void __hipRegisterFunction(void **, const void *, char *, const char *, int, void *, void *,
                            void *, void *, int *) {}
-void __hipRegisterVar(void **, char *, char *, const char *, int, size_t, int, int) {}
+// a __device__ variable: its host shadow stands for the device copy
+void __hipRegisterVar(void **, char *var, char *, const char *, int, size_t size, int, int)
+{
+    std::lock_guard<std::recursive_mutex> l(g_mu);
+    g_mem[(uintptr_t)var] = size;
+    g_registered_vars++;
+}
 void __hipUnregisterFatBinary(void **) {}
 
 // for the harness: live device allocations, and a stream it can hand to the
@@ -423,7 +437,7 @@ void __hipUnregisterFatBinary(void **) {}
 size_t hostcheck_live_allocations(void)
 {
     std::lock_guard<std::recursive_mutex> l(g_mu);
-    return g_mem.size();
+    return g_mem.size() - g_registered_vars;
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@
 #define __forceinline__ inline __attribute__((always_inline))
 #define __launch_bounds__(...) __attribute__((amdgpu_flat_work_group_size(1, 1024)))
 #define HIP_SYMBOL(x) (&(x))
+#define __align__(n) __attribute__((aligned(n)))
 
 struct dim3 {
     unsigned x, y, z;
@@ -79,6 +80,7 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t x);
 hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s);
 hipError_t hipGetLastError(void);
 hipError_t hipGetSymbolAddress(void **p, const void *sym);
+hipError_t hipGetDevice(int *d);
 const char *hipGetErrorString(hipError_t e);
 // kernel launch interface that clang's HIP mode emits for <<<...>>>
 hipError_t hipLaunchKernel(const void *f, dim3 g, dim3 b, void **args, size_t shm, hipStream_t s);

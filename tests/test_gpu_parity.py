@@ -299,6 +299,46 @@ def test_single_phase_fast_path(nsub):
     assert np.array_equal(a.populations(), g32.populations())
 
 
+@pytest.mark.parametrize("shape,prec,nspheres", [((35, 34, 32), "fp32", 1),
+                                                  ((36, 34, 32), "fp16", 1),
+                                                  ((168, 168, 168), "fp32", 16)])
+def test_single_phase_kernels_equal_general_path(shape, prec, nspheres):
+    # the single-phase kernels (collide-stream without the psi and mu reads,
+    # psi/c update of c alone) against the general kernels on the same box:
+    # a single-phase box alone takes them, the same box batched with a
+    # two-phase box takes the general ones; 40 steps, bit for bit.  35 wide
+    # takes the one-node psi/c form, 168^3 the split form with the boundary
+    # fix-ups on the side stream (above 2^22 nodes)
+    import torch
+    spec = _single_phase_spec(shape, 13)
+    if nspheres > 1:
+        cols = []
+        pts = I.place_spheres(shape, nspheres, 4.5, lambda a, b: a * shape[2], 3.0, 77)
+        ms = I.unit_vectors(78, nspheres)
+        for k in range(nspheres):
+            q = I.janus(pts[k], ms[k], 4.5, alpha=1e-3, mu_minus=0.2, mu_plus=0.05)
+            q["H"] = 0.0
+            cols.append(q)
+        spec = dict(spec, colloids=cols)
+    flush_print("[single phase] kernels", shape, prec, nspheres)
+    st = torch.cuda.Stream()
+    alone = lb.from_spec(spec, precision=prec, stream=st)
+    two = _spec((32, 32, 32), seed=9, M_psi=0.1)
+    mixed = [lb.from_spec(spec, precision=prec, stream=st), lb.from_spec(two, precision=prec, stream=st)]
+    alone.step(40)
+    lb.batch_step(mixed, 40)
+    assert np.array_equal(alone.populations(), mixed[0].populations())
+    fa, fm = alone.fields(), mixed[0].fields()
+    for k in ("c", "psi", "rho", "u"):
+        assert np.array_equal(fa[k], fm[k]), k
+    assert np.array_equal(alone.links(), mixed[0].links())
+    _, ca = alone.observables()
+    _, cm = mixed[0].observables()
+    for a, b in zip(ca, cm):
+        assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert not fa["psi"].any()
+
+
 def test_soft_sphere_parameters_validated():
     with pytest.raises(lb.LBError):
         lb.Box((8, 8, 8), "fp32", soft_eps=-1.0)
