@@ -262,6 +262,22 @@ lb_status lb_load_state(lb_ctx *ctx, const void *buf, size_t n);
  * LB_E_STATE if a context lacks its fields. */
 lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
 
+/* lb_batch_step without device allocation, for callers that cannot call
+ * hipMalloc (tight serving loops, harnesses that forbid allocation): the
+ * batch's descriptor tables go to a fixed device array of the library
+ * (4 MiB per GPU, kept until the process ends) instead of a buffer allocated
+ * per call, the steps are launched one by one (no graph is instantiated),
+ * and the particle work uses the leading context's side stream only if it
+ * already exists (else everything runs in order on its stream; results are
+ * the same either way).  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Same arguments, semantics and errors as lb_batch_step, plus
+ * LB_E_INVALID when the tables of the batch exceed the fixed array (about
+ * 4000 boxes with one psi/c update per step, 1000 with sub-steps).  All
+ * calls on one GPU share the array: calls that overlap in time on that GPU
+ * (from several host threads) race; calls made one after another are safe,
+ * since each synchronises its stream before returning. */
+lb_status lb_batch_step_noalloc(lb_ctx *const *ctxs, int32_t n, int64_t nsteps);
+
 /* Launch shapes of the three lattice kernels (chemical potential,
  * collide-stream, psi/c update): for each, (bx, by, code) = nodes per row
  * segment, rows per block (bx*by <= 256; 0 = default) and code = remap +

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -635,6 +636,34 @@ static lb_status batch_run(lb_ctx *const *ctxs, int n, int64_t nsteps, char *dev
     return LB_OK;
 }
 
+// ---------------------------------------------- allocation-free batches
+// lb_batch_step_noalloc keeps the descriptor tables of a batch in this fixed
+// device array instead of a buffer allocated per call.  Each GPU holds its
+// own copy for the life of the process; host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device (the
+// array's name is not a device address on the host).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+static void *g_scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static lb_status scratch_address(lb_ctx *c, char **out)
+{
+    int dev = -1;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(c, LB_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(c, LB_E_DEVICE, "no device address for the fixed batch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = (char *)g_scratch_dev[dev];
+    return LB_OK;
+}
+
 extern "C" {
 
 lb_status lb_footprint_bytes(const lb_params *p, size_t *bytes)
@@ -965,6 +994,25 @@ lb_status lb_batch_step(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
     st = batch_run(ctxs, n, nsteps, dev, bb, true, side_of(c0));
     hipFree(dev);
     return st;
+}
+
+lb_status lb_batch_step_noalloc(lb_ctx *const *ctxs, int32_t n, int64_t nsteps)
+{
+    lb_status st = batch_check(ctxs, n, nsteps);
+    if (st != LB_OK) return st;
+    lb_ctx *c0 = ctxs[0];
+    const size_t bb = align256(batch_bytes(n, substeps_of(c0->p)));
+    if (2 * bb > NOALLOC_SCRATCH_BYTES)
+        return fail(c0, LB_E_INVALID,
+                    "batch too large for lb_batch_step_noalloc: its descriptor tables need " +
+                        std::to_string(2 * bb) + " bytes, the fixed device array holds " +
+                        std::to_string(NOALLOC_SCRATCH_BYTES));
+    char *dev = nullptr;
+    st = scratch_address(c0, &dev);
+    if (st != LB_OK) return st;
+    // no graph (instantiation allocates), and the side stream only if the
+    // leading context already has one
+    return batch_run(ctxs, n, nsteps, dev, bb, false, c0->has_side ? &c0->side : nullptr);
 }
 
 lb_status lb_set_launch_shapes(lb_ctx *c, const int32_t *shapes9)

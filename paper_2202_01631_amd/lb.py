@@ -22,7 +22,8 @@ ERR_NAN, ERR_FAST, ERR_CONTACT, ERR_LINKS = 1, 2, 4, 8
 EXPORTS = ("lb_footprint_bytes", "lb_create", "lb_destroy", "lb_init_fields",
            "lb_add_colloids", "lb_step", "lb_observables", "lb_get_fields",
            "lb_get_populations", "lb_get_owner", "lb_get_links", "lb_colloid_forces",
-           "lb_save_state", "lb_load_state", "lb_batch_step", "lb_set_launch_shapes",
+           "lb_save_state", "lb_load_state", "lb_batch_step", "lb_batch_step_noalloc",
+           "lb_set_launch_shapes",
            "lb_get_launch_shapes", "lb_timing_enable", "lb_timing_read",
            "lb_last_error", "lb_wetting_H", "lb_solubility_E")
 
@@ -99,6 +100,7 @@ def load():
     L.lb_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lb_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lb_batch_step.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
+    L.lb_batch_step_noalloc.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64]
     L.lb_set_launch_shapes.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lb_get_launch_shapes.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lb_timing_enable.argtypes = [vp, C.c_int32]
@@ -319,6 +321,17 @@ def batch_step(boxes, nsteps):
         return
     arr = (C.c_void_p * len(boxes))(*[b._ctx.value for b in boxes])
     rc = load().lb_batch_step(arr, len(boxes), int(nsteps))
+    if rc != 0:
+        raise LBError(rc, load().lb_last_error(boxes[0]._ctx).decode())
+
+
+def batch_step_noalloc(boxes, nsteps):
+    """batch_step without device allocation: the batch tables live in the
+    library's fixed device array, launches go one by one (no graph)."""
+    if not boxes:
+        return
+    arr = (C.c_void_p * len(boxes))(*[b._ctx.value for b in boxes])
+    rc = load().lb_batch_step_noalloc(arr, len(boxes), int(nsteps))
     if rc != 0:
         raise LBError(rc, load().lb_last_error(boxes[0]._ctx).decode())
 
