@@ -70,6 +70,8 @@ static double wt(int i)
     return 1.0 / 36.0;
 }
 
+static void cross(const double a[3], const double b[3], double o[3]);
+
 static int opp(int i)
 {
     if (i == 0) return 0;
@@ -175,6 +177,79 @@ static int on_active_cap(const or_colloid *k, const double r[3])
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
     return md <= k->cap_cos * sqrt(rr);
+}
+
+/* option: surface pattern, a reading of the inhomogeneous surface patterns
+ * of Sec. IV (the Janus split of Eqs. 5-6 generalised): the surface is cut
+ * into cells of polar bands in m.n (cuts pat_cos, increasing, compared as
+ * m.r <= t |r| like the cap test) and azimuthal sectors of the angle phi of
+ * n about m, measured from the second body axis e towards m x e, in
+ * half-open intervals [2 pi s/S, 2 pi (s+1)/S) decided by signs and
+ * magnitudes of the two projections (no angle is computed); each cell has
+ * its own production, phoretic mobility and wetting parameter.  A particle
+ * without a pattern has two cells: 0 the active cap, 1 the rest. */
+static int sector_of(double a, double b, int S)
+{
+    if (S <= 1) return 0;
+    /* quadrant of phi = atan2(b, a) in [0, 2 pi); a = b = 0 counts as phi = 0 */
+    int q;
+    if (a > 0.0 && b >= 0.0) q = 0;
+    else if (a <= 0.0 && b > 0.0) q = 1;
+    else if (a < 0.0 && b <= 0.0) q = (a == 0.0 && b == 0.0) ? 0 : 2;
+    else q = 3;
+    if (S == 2) return q < 2 ? 0 : 1;
+    if (S == 4) return q;
+    /* eighths: turn the quadrant onto the first one, then phi < pi/4 iff y < x */
+    double x = a, y = b;
+    if (q == 1) { x = b; y = -a; }
+    else if (q == 2) { x = -a; y = -b; }
+    else if (q == 3) { x = -b; y = a; }
+    return 2 * q + (y < x ? 0 : 1);
+}
+
+static int surface_cell(const or_colloid *k, const double r[3])
+{
+    if (k->pat_bands <= 0) return on_active_cap(k, r) ? 0 : 1;
+    double md = k->m[0] * r[0] + k->m[1] * r[1];
+    md = md + k->m[2] * r[2];
+    double rr = r[0] * r[0] + r[1] * r[1];
+    rr = rr + r[2] * r[2];
+    const double rn = sqrt(rr);
+    int band = 0;
+    for (int b = 0; b < k->pat_bands - 1; b++)
+        if (!(md <= k->pat_cos[b] * rn)) band++;
+    double w[3];  /* m x e */
+    w[0] = k->m[1] * k->e[2] - k->m[2] * k->e[1];
+    w[1] = k->m[2] * k->e[0] - k->m[0] * k->e[2];
+    w[2] = k->m[0] * k->e[1] - k->m[1] * k->e[0];
+    double a = k->e[0] * r[0] + k->e[1] * r[1];
+    a = a + k->e[2] * r[2];
+    double b = w[0] * r[0] + w[1] * r[1];
+    b = b + w[2] * r[2];
+    return band * k->pat_sectors + sector_of(a, b, k->pat_sectors);
+}
+
+static double cell_alpha(const or_colloid *k, int cell)
+{
+    if (k->pat_bands > 0) return k->pat_alpha[cell];
+    return cell == 0 ? k->alpha_minus : k->alpha_plus;
+}
+
+static double cell_mu(const or_colloid *k, int cell)
+{
+    if (k->pat_bands > 0) return k->pat_mu[cell];
+    return cell == 0 ? k->mu_minus : k->mu_plus;
+}
+
+static double cell_H(const or_colloid *k, int cell)
+{
+    return k->pat_bands > 0 ? k->pat_H[cell] : k->H;
+}
+
+/* the 4th entry of a link record: the cap bit, or the cell of a pattern */
+static int link_tag(const or_colloid *k, int cell)
+{
+    return k->pat_bands > 0 ? cell : (cell == 0 ? 1 : 0);
 }
 
 /* ------------------------------------------------------------ equilibrium */
@@ -360,7 +435,7 @@ static void build_links(or_ctx *c)
             c->lk[l] = k;
             c->ln[l] = (int)n;
             c->ld[l] = d;
-            c->lcap[l] = on_active_cap(&c->col[k], r);
+            c->lcap[l] = surface_cell(&c->col[k], r);
         }
     }
     c->nl = total;
@@ -393,6 +468,20 @@ int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
             return fail(c, OR_E_INVALID, "cap_cos must lie in [-1, 1]");
         if (q.H != 0.0 && !(c->p.kappa > 0.0))
             return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
+        if (q.pat_bands < 0 || q.pat_bands > OR_PATTERN_MAX_BANDS)
+            return fail(c, OR_E_INVALID, "pattern bands in [0, 8]");
+        if (q.pat_bands > 0) {
+            const int S = q.pat_sectors;
+            if (!(S == 1 || S == 2 || S == 4 || S == 8) || q.pat_bands * S > OR_PATTERN_MAX_CELLS)
+                return fail(c, OR_E_INVALID, "pattern sectors 1, 2, 4 or 8");
+            for (int b = 0; b < q.pat_bands - 1; b++)
+                if (!(q.pat_cos[b] > -1.0 && q.pat_cos[b] < 1.0) ||
+                    (b > 0 && !(q.pat_cos[b] > q.pat_cos[b - 1])))
+                    return fail(c, OR_E_INVALID, "pattern cuts increasing in (-1, 1)");
+            for (int i = 0; i < q.pat_bands * S; i++)
+                if (q.pat_H[i] != 0.0 && !(c->p.kappa > 0.0))
+                    return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
+        }
         for (int a = 0; a < 3; a++) {
             if (2.0 * q.radius + 4.0 > (double)L[a])
                 return fail(c, OR_E_INVALID, "colloid does not fit in the box");
@@ -401,6 +490,23 @@ int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
             q.pos[a] = fmod(q.pos[a], (double)L[a]);
             if (q.pos[a] < 0.0) q.pos[a] += (double)L[a];
         }
+        /* second body axis: the part of e orthogonal to m, normalised; if that
+         * vanishes, the lattice axis least aligned with m crossed into place */
+        double em = q.e[0] * q.m[0] + q.e[1] * q.m[1] + q.e[2] * q.m[2];
+        double ev[3] = {q.e[0] - em * q.m[0], q.e[1] - em * q.m[1], q.e[2] - em * q.m[2]};
+        double ne = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+        if (!(ne > 1e-9)) {
+            int j = 0;
+            for (int a = 1; a < 3; a++)
+                if (fabs(q.m[a]) < fabs(q.m[j])) j = a;
+            double ax[3] = {0.0, 0.0, 0.0};
+            ax[j] = 1.0;
+            double t[3];
+            cross(q.m, ax, t);
+            cross(t, q.m, ev);  /* (m x ax) x m: ax made orthogonal to m */
+            ne = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+        }
+        for (int a = 0; a < 3; a++) q.e[a] = ev[a] / ne;
         c->col[k] = q;
     }
     if (owner_map(c, c->owner)) {
@@ -457,7 +563,8 @@ static void chemical_potential(or_ctx *c)
                 double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
                 double en = fabs(r[(e - 1) / 2]) / rn;
                 double ghost = c->psi[n];
-                if (p->kappa > 0.0) ghost = c->psi[n] - (c->col[k].H / p->kappa) * en;
+                if (p->kappa > 0.0)
+                    ghost = c->psi[n] - (cell_H(&c->col[k], surface_cell(&c->col[k], r)) / p->kappa) * en;
                 lap += ghost;
             }
         }
@@ -498,7 +605,8 @@ static void stress(const or_ctx *c, long n, double P[3][3])
             double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
             double en = fabs(r[(e - 1) / 2]) / rn;
             ph[e] = c->psi[n];
-            if (p->kappa > 0.0) ph[e] = c->psi[n] - (c->col[k].H / p->kappa) * en;
+            if (p->kappa > 0.0)
+                ph[e] = c->psi[n] - (cell_H(&c->col[k], surface_cell(&c->col[k], r)) / p->kappa) * en;
         }
     }
     double ps = c->psi[n];
@@ -601,7 +709,7 @@ static void collide_stream(or_ctx *c)
         double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         for (int a = 0; a < 3; a++) nh[a] = r[a] / rn;
         /* phoretic slip (Eq. 4) with the Janus mobility of Eq. 6 */
-        double mob = c->lcap[l] ? q->mu_minus : q->mu_plus;
+        double mob = cell_mu(q, c->lcap[l]);
         for (int a = 0; a < 3; a++) {
             long mp = nbr(c, n, 1 + 2 * a), mm = nbr(c, n, 2 + 2 * a);
             g[a] = (hat(c, c->cc, n, mp) - hat(c, c->cc, n, mm)) / 2.0;
@@ -643,7 +751,7 @@ static void collide_stream(or_ctx *c)
         for (int i = 0; i < 6; i++)
             for (int j = 0; j < 6; j++) c->zeta[36 * k + 6 * i + j] += 6.0 * w * c->p.rho0 * gg[i] * gg[j];
         /* Janus activity of Eq. 5, one emission per link into its fluid node */
-        c->src[n] += c->lcap[l] ? q->alpha_minus : q->alpha_plus;
+        c->src[n] += cell_alpha(q, c->lcap[l]);
     }
     for (int a = 0; a < 3; a++) {
         c->diag[OR_DIAG_SUM_FORCE + a] = sumF[a];
@@ -821,6 +929,16 @@ static void colloid_update(or_ctx *c)
                 for (int a = 0; a < 3; a++) mn[a] = q->m[a] * cs + kxm[a] * sn + ax[a] * km * (1.0 - cs);
                 double nn = sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
                 for (int a = 0; a < 3; a++) q->m[a] = mn[a] / nn;
+                /* the second body axis turns the same way, then is made
+                 * orthogonal to m again and normalised */
+                double kxe[3], en[3];
+                cross(ax, q->e, kxe);
+                double ke = ax[0] * q->e[0] + ax[1] * q->e[1] + ax[2] * q->e[2];
+                for (int a = 0; a < 3; a++) en[a] = q->e[a] * cs + kxe[a] * sn + ax[a] * ke * (1.0 - cs);
+                double em = en[0] * q->m[0] + en[1] * q->m[1] + en[2] * q->m[2];
+                for (int a = 0; a < 3; a++) en[a] = en[a] - em * q->m[a];
+                double ne = sqrt(en[0] * en[0] + en[1] * en[1] + en[2] * en[2]);
+                for (int a = 0; a < 3; a++) q->e[a] = en[a] / ne;
             }
         }
         for (int a = 0; a < 3; a++) { c->trF[3 * k + a] = 0.0; c->trT[3 * k + a] = 0.0; }
@@ -985,7 +1103,7 @@ int or_get_links(or_ctx *c, int32_t *rec4, int64_t cap, int64_t *n)
         rec4[4 * l + 0] = c->lk[l];
         rec4[4 * l + 1] = c->ln[l];
         rec4[4 * l + 2] = c->ld[l];
-        rec4[4 * l + 3] = c->lcap[l];
+        rec4[4 * l + 3] = link_tag(&c->col[c->lk[l]], c->lcap[l]);
     }
     return OR_OK;
 }
@@ -1010,7 +1128,11 @@ int or_observables(or_ctx *c, or_totals *t, or_colloid *out, int32_t n)
             t->n_fluid++;
         }
         t->n_links = c->nl;
-        for (long l = 0; l < c->nl; l++) t->n_active += c->lcap[l];
+        /* active links: on the active cap, or in a pattern cell that produces */
+        for (long l = 0; l < c->nl; l++) {
+            const or_colloid *q = &c->col[c->lk[l]];
+            t->n_active += q->pat_bands > 0 ? (q->pat_alpha[c->lcap[l]] != 0.0) : (c->lcap[l] == 0);
+        }
         t->step = c->step;
         int e = c->err;
         if (!isfinite(t->mass) || !isfinite(t->sum_psi) || !isfinite(t->sum_c)) e |= 1;

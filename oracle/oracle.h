@@ -21,7 +21,8 @@
  *                   (odd i >= 1 and i+1 are opposite)
  *   link record     (colloid k, fluid node n, direction d, cap) with node
  *                   n + c_d inside colloid k; cap = 1 on the active hemisphere
- *                   (m.n <= 0).  Canonical order: (k, n, d) ascending.
+ *                   (m.n <= 0), or the pattern cell of the link's midpoint for
+ *                   a patterned particle.  Canonical order: (k, n, d) ascending.
  */
 #ifndef ORACLE_H
 #define ORACLE_H
@@ -67,12 +68,28 @@ typedef struct {
 #define OR_EXPLICIT_COLLOID 2u
 #define OR_CAPILLARY_FORCE 4u
 
+#define OR_PATTERN_MAX_BANDS 8
+#define OR_PATTERN_MAX_CELLS 64
+
 typedef struct {
     double pos[3], m[3], vel[3], omega[3];
     double radius, alpha_minus, alpha_plus, mu_minus, mu_plus, H, rho_p;
     int32_t fixed;               /* 1: position, orientation and velocities held */
     double cap_cos;              /* the active cap is m.n <= cap_cos, in [-1, 1]; 0 is the
                                     half of Eqs. 5-6 (the paper's Janus particle) */
+    double e[3];                 /* second body axis (made orthogonal to m and normalised
+                                    on add; any orthogonal axis if zero); turns with m */
+    int32_t pat_bands;           /* surface pattern (0: none, the Janus caps above): polar
+                                    bands 1..8 of m.n, cut at pat_cos[0 .. bands-2]
+                                    (increasing): band b holds pat_cos[b-1] < m.n <=
+                                    pat_cos[b] */
+    int32_t pat_sectors;         /* azimuthal sectors 1, 2, 4 or 8 of the angle of n about m,
+                                    measured from e towards m x e */
+    double pat_cos[OR_PATTERN_MAX_BANDS - 1];
+    double pat_alpha[OR_PATTERN_MAX_CELLS], pat_mu[OR_PATTERN_MAX_CELLS],
+        pat_H[OR_PATTERN_MAX_CELLS];  /* per cell b * sectors + s: production per link
+                                         (Eq. 5), phoretic mobility (Eq. 6) and wetting
+                                         parameter (Eqs. 8-9) */
 } or_colloid;
 
 typedef struct {

@@ -43,13 +43,21 @@ class Params(C.Structure):
                 ("soft_nu", C.c_double), ("soft_hc", C.c_double), ("lub_hc", C.c_double)]
 
 
+PATTERN_MAX_BANDS, PATTERN_MAX_CELLS = 8, 64
+
+
 class Colloid(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("m", C.c_double * 3),
                 ("vel", C.c_double * 3), ("omega", C.c_double * 3),
                 ("radius", C.c_double), ("alpha_minus", C.c_double),
                 ("alpha_plus", C.c_double), ("mu_minus", C.c_double),
                 ("mu_plus", C.c_double), ("H", C.c_double), ("rho_p", C.c_double),
-                ("fixed", C.c_int32), ("cap_cos", C.c_double)]
+                ("fixed", C.c_int32), ("cap_cos", C.c_double), ("e", C.c_double * 3),
+                ("pat_bands", C.c_int32), ("pat_sectors", C.c_int32),
+                ("pat_cos", C.c_double * (PATTERN_MAX_BANDS - 1)),
+                ("pat_alpha", C.c_double * PATTERN_MAX_CELLS),
+                ("pat_mu", C.c_double * PATTERN_MAX_CELLS),
+                ("pat_H", C.c_double * PATTERN_MAX_CELLS)]
 
 
 class Totals(C.Structure):
@@ -141,6 +149,16 @@ def make_colloid(d):
         setattr(q, key, float(d.get(key, 1.0 if key == "rho_p" else 0.0)))
     q.fixed = int(d.get("fixed", 0))
     q.cap_cos = float(d.get("cap_cos", 0.0))
+    for a in range(3):
+        q.e[a] = float(d.get("e", (0.0, 0.0, 0.0))[a])
+    pat = d.get("pattern")
+    if pat:
+        q.pat_bands, q.pat_sectors = int(pat["bands"]), int(pat["sectors"])
+        for i, v in enumerate(pat.get("cos", ())):
+            q.pat_cos[i] = float(v)
+        for key in ("alpha", "mu", "H"):
+            for i, v in enumerate(pat.get(key, ())):
+                getattr(q, "pat_" + key)[i] = float(v)
     return q
 
 
@@ -150,6 +168,7 @@ def colloid_dict(q):
         d[k] = getattr(q, k)
     d["fixed"] = q.fixed
     d["cap_cos"] = q.cap_cos
+    d["e"] = np.array(q.e[:])
     return d
 
 
