@@ -37,8 +37,9 @@
  *                   (odd i >= 1 and i+1 are opposite); weights 1/3, 1/18, 1/36.
  *   links           (particle k, fluid node n, direction d, cap): node n + c_d
  *                   lies strictly inside particle k; cap = 1 when the link
- *                   midpoint is on the active hemisphere m.n <= 0 (Eqs. 5-6).
- *                   Canonical order (k, n, d) ascending.
+ *                   midpoint is on the active hemisphere m.n <= 0 (Eqs. 5-6),
+ *                   or, for a particle with a surface pattern, the pattern
+ *                   cell of the midpoint.  Canonical order (k, n, d) ascending.
  *   device memory   the context owns its device state.  If the caller hands
  *                   in an arena (e.g. a torch uint8 tensor), the context only
  *                   borrows it; it must outlive lb_destroy.
@@ -146,6 +147,9 @@ typedef struct {
 #define LB_EXPLICIT_COLLOID 2u
 #define LB_CAPILLARY_FORCE 4u
 
+#define LB_PATTERN_MAX_BANDS 8
+#define LB_PATTERN_MAX_CELLS 64
+
 typedef struct {                 /* FP64, caller-owned */
     double pos[3], m[3], vel[3], omega[3]; /* centre, axis (normalised on add), V, Omega */
     double radius;
@@ -157,14 +161,34 @@ typedef struct {                 /* FP64, caller-owned */
     int32_t fixed;                   /* 1: position, axis and velocities held */
     double cap_cos;                  /* the active cap is m.n <= cap_cos, in [-1, 1]; 0 (the
                                         paper's Janus half, Eqs. 5-6) keeps the exact tie
-                                        rule m.n <= 0; otherwise n = r/|r| in FP64 without
+                                        rule m.n <= 0; otherwise m.r <= cap_cos |r|, |r| the
+                                        correctly rounded square root, FP64 without
                                         contraction.  LB_E_INVALID outside [-1, 1] */
+    double e[3];                     /* second body axis: made orthogonal to m and normalised
+                                        on add (zero: an axis chosen orthogonal to m), turned
+                                        with the particle; used by surface patterns */
+    /* Surface pattern (the inhomogeneous surface patterns of Sec. IV; 0 bands: none,
+     * the Janus caps above apply).  The surface is cut into cells: polar bands of
+     * m.n, band b holding pattern_cos[b-1] < m.n <= pattern_cos[b] (cuts increasing
+     * in (-1, 1), compared as m.r <= t |r| like the cap test), times azimuthal
+     * sectors of the angle of n about m from e towards m x e, sector s covering
+     * [2 pi s/S, 2 pi (s+1)/S) (decided from the signs and sizes of r.e and
+     * r.(m x e); a point on the axis is in sector 0).  Cell b S + s has its own
+     * production per link (Eq. 5), phoretic mobility (Eq. 6) and wetting parameter
+     * (Eqs. 8-9), taken at the link midpoint or the face midpoint.  Bands 1..8,
+     * sectors S in {1, 2, 4, 8}; LB_E_INVALID otherwise, or for wetting with
+     * kappa = 0. */
+    int32_t pattern_bands, pattern_sectors;
+    double pattern_cos[LB_PATTERN_MAX_BANDS - 1];
+    double pattern_alpha[LB_PATTERN_MAX_CELLS], pattern_mu[LB_PATTERN_MAX_CELLS],
+        pattern_H[LB_PATTERN_MAX_CELLS];
 } lb_colloid;
 
 typedef struct {
     double mass, mom[3], sum_psi, sum_c; /* FP64 sums over fluid nodes of sum_i f_i,
                                             sum_i f_i c_i, psi, c */
-    int64_t n_fluid, n_links, n_active, step;
+    int64_t n_fluid, n_links, n_active, step; /* n_active: links on an active cap, or in a
+                                                 producing cell of a pattern */
     int32_t error_bits;                  /* LB_ERR_* */
 } lb_totals;
 

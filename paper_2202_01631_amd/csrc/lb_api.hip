@@ -23,10 +23,10 @@ size_t storage_bytes(int prec) { return prec == LB_FP64 ? 8 : (prec == LB_FP32 ?
 size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 
 // Arena layout (each piece 256-byte aligned): f[2] (19 N storage), psi[2],
-// c[2], mu (N compute), u (3N compute), owner (N bytes), and with psi/c
-// sub-steps one more psi and c pair (N compute each).
+// c[2], mu (N compute), in FP64 chi (N), u (3N compute), owner (N bytes),
+// and with psi/c sub-steps one more psi and c pair (N compute each).
 struct Layout {
-    size_t f[2], psi[2], cc[2], mu, u, own, psis, ccs, total;
+    size_t f[2], psi[2], cc[2], mu, chi, u, own, psis, ccs, total;
 };
 
 int substeps_of(const lb_params &p) { return p.ch_substeps > 1 ? p.ch_substeps : 1; }
@@ -41,6 +41,8 @@ Layout layout_of(const lb_params &p)
     for (int b = 0; b < 2; b++) { L.psi[b] = o; o = align256(o + N * cb); }
     for (int b = 0; b < 2; b++) { L.cc[b] = o; o = align256(o + N * cb); }
     L.mu = o; o = align256(o + N * cb);
+    L.chi = 0;
+    if (p.precision == LB_FP64) { L.chi = o; o = align256(o + N * cb); }
     L.u = o; o = align256(o + 3 * N * cb);
     L.own = o; o = align256(o + N);
     L.psis = L.ccs = 0;
@@ -93,6 +95,7 @@ struct lb_ctx {
     // single phase: a = b = kappa = E = c_b0 = 0 and psi = 0 at init, so mu
     // is 0 and chi is c at every step (set by lb_init_fields)
     bool nopsi;
+    bool pattern;       // some particle carries a surface pattern
     std::string err;
 };
 
@@ -104,6 +107,14 @@ static lb_status fail(lb_ctx *c, lb_status s, const std::string &m)
 
 static lb_status hip_fail(lb_ctx *c, hipError_t e, const char *what)
 {
+    // copies queued before the failing call may still target host buffers
+    // of the caller's frame: let the stream finish them before returning
+    // (not while it captures: nothing it holds has run)
+    if (c) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+            (void)hipStreamSynchronize(c->stream);
+    }
     return fail(c, LB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -126,6 +137,7 @@ static StepBuffers buffers(lb_ctx *c, int cu)
     b.psin = ptr(c, c->L.psi[nx]);
     b.ccn = ptr(c, c->L.cc[nx]);
     b.mu = ptr(c, c->L.mu);
+    b.chi = c->p.precision == LB_FP64 ? ptr(c, c->L.chi) : nullptr;
     b.u = ptr(c, c->L.u);
     b.own = (uint8_t *)ptr(c, c->L.own);
     b.col = c->dcol;
@@ -157,7 +169,7 @@ static BoxDesc box_desc(lb_ctx *c, int parity)
 // the next-state pair when n-1-s is even, else the scratch pair.  Three
 // descriptor tables besides the step's own cover them: sub-step 0 (from the
 // state at t), and the two directions between the pairs.
-static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
+static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3], bool chi_is_c)
 {
     void *ps = ptr(c, c->L.psis), *cs = ptr(c, c->L.ccs);
     const int n = substeps_of(c->p);
@@ -165,6 +177,9 @@ static void substep_tables(lb_ctx *c, const BoxDesc &d, BoxDesc t[3])
     if (n % 2 == 0) { t[0].b.psin = ps; t[0].b.ccn = cs; }
     t[1].b.psi = d.b.psin; t[1].b.cc = d.b.ccn; t[1].b.psin = ps; t[1].b.ccn = cs;
     t[2].b.psi = ps; t[2].b.cc = cs;
+    if (chi_is_c)
+        for (int k = 0; k < 3; k++)
+            if (t[k].b.chi) t[k].b.chi = const_cast<void *>(t[k].b.cc);
 }
 
 // Host side of a batch: descriptors and block/particle start tables, laid
@@ -205,10 +220,14 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // single-phase batch (every box): no mu launches, single-phase kernels
     B.nopsi = n > 0;
     for (int j = 0; j < n; j++) B.nopsi = B.nopsi && ctxs[j]->nopsi;
+    B.pattern = 0;
+    for (int j = 0; j < n; j++) B.pattern |= (ctxs[j]->pattern && ctxs[j]->ncol > 0) ? 1 : 0;
     if (B.nopsi) {
         // single-phase kernels exist in the one-node collide-stream and the
         // one-node and row-vector psi/c updates: other forms drop to those
         for (int j = 0; j < n; j++) {
+            // a stored chi (FP64) is c itself: the mu pass that writes it does not run
+            if (d[j].b.chi) d[j].b.chi = const_cast<void *>(d[j].b.cc);
             const int ss = ctxs[j]->p.precision == LB_FP64 ? 8 : 4;
             if (d[j].ls[1].vec > 1) {
                 d[j].ls[1].vec = 0;
@@ -267,15 +286,18 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         const size_t base = align256(dbytes + sizeof(int) * (4 * (size_t)n + 4));
         for (int j = 0; j < n; j++) {
             BoxDesc t[3];
-            substep_tables(ctxs[j], d[j], t);
+            substep_tables(ctxs[j], d[j], t, B.nopsi != 0);
             for (int k = 0; k < 3; k++) ((BoxDesc *)(host.data() + base + k * dbytes))[j] = t[k];
         }
         for (int k = 0; k < 3; k++) B.dsub[k] = (const BoxDesc *)(dev + base + k * dbytes);
     }
 }
 
+// the captured step pairs; the stream first finishes a replay still in flight
 static void drop_graphs(lb_ctx *c)
 {
+    if (!c->graph[0] && !c->graph[1]) return;
+    (void)hipStreamSynchronize(c->stream);
     for (int g = 0; g < 2; g++)
         if (c->graph[g]) { hipGraphExecDestroy(c->graph[g]); c->graph[g] = nullptr; }
 }
@@ -536,7 +558,9 @@ struct StateHeader {
     int32_t nx, ny, nz, precision, ncol, lcap;
     int64_t step;
 };
-static const uint64_t STATE_MAGIC = 0x4c42504852534131ull;
+// (the last byte counts layouts of the particle record: "2" has the second
+// body axis and the surface pattern)
+static const uint64_t STATE_MAGIC = 0x4c42504852534132ull;
 
 static size_t state_size(lb_ctx *c)
 {
@@ -754,6 +778,7 @@ static void free_colloids(lb_ctx *c)
     c->ccount = nullptr;
     c->ncol = 0;
     c->lcap = 0;
+    c->pattern = false;
     c->dirty = true;  // descriptors hold the particle-table pointers
 }
 
@@ -886,6 +911,32 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
             return fail(c, LB_E_INVALID, "particle radius, density and axis must be positive");
         if (q.H != 0.0 && !(c->p.kappa > 0.0)) return fail(c, LB_E_INVALID, "wetting needs kappa > 0");
         if (!(q.cap_cos >= -1.0 && q.cap_cos <= 1.0)) return fail(c, LB_E_INVALID, "cap_cos must lie in [-1, 1]");
+        if (q.pattern_bands < 0 || q.pattern_bands > LB_PATTERN_MAX_BANDS)
+            return fail(c, LB_E_INVALID, "pattern bands must lie in [0, 8]");
+        if (q.pattern_bands > 0) {
+            const int S = q.pattern_sectors;
+            if (!(S == 1 || S == 2 || S == 4 || S == 8) || q.pattern_bands * S > LB_PATTERN_MAX_CELLS)
+                return fail(c, LB_E_INVALID, "pattern sectors must be 1, 2, 4 or 8");
+            for (int b = 0; b < q.pattern_bands - 1; b++)
+                if (!(q.pattern_cos[b] > -1.0 && q.pattern_cos[b] < 1.0) ||
+                    (b > 0 && !(q.pattern_cos[b] > q.pattern_cos[b - 1])))
+                    return fail(c, LB_E_INVALID, "pattern cuts must increase within (-1, 1)");
+            for (int i = 0; i < q.pattern_bands * S; i++) {
+                if (!std::isfinite(q.pattern_alpha[i]) || !std::isfinite(q.pattern_mu[i]) ||
+                    !std::isfinite(q.pattern_H[i]))
+                    return fail(c, LB_E_INVALID, "non-finite pattern value");
+                if (q.pattern_H[i] != 0.0 && !(c->p.kappa > 0.0))
+                    return fail(c, LB_E_INVALID, "wetting needs kappa > 0");
+            }
+            d.pb = q.pattern_bands;
+            d.ps = S;
+            for (int b = 0; b < q.pattern_bands - 1; b++) d.pcos[b] = q.pattern_cos[b];
+            for (int i = 0; i < q.pattern_bands * S; i++) {
+                d.palpha[i] = q.pattern_alpha[i];
+                d.pmu[i] = q.pattern_mu[i];
+                d.pH[i] = q.pattern_H[i];
+            }
+        }
         for (int a = 0; a < 3; a++) {
             if (2.0 * q.radius + 8.0 > (double)Ls[a])
                 return fail(c, LB_E_INVALID, "particle too large for the box (2 R + 8 > side)");
@@ -909,6 +960,31 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
         d.inertia = 0.4 * d.mass * q.radius * q.radius;
         d.fixed = q.fixed ? 1 : 0;
         d.capc = q.cap_cos;
+        {
+            // second body axis: e made orthogonal to m and normalised; where
+            // that part vanishes, the lattice axis least aligned with m,
+            // (m x a) x m, in its place
+#pragma clang fp contract(off)
+            if (!std::isfinite(q.e[0]) || !std::isfinite(q.e[1]) || !std::isfinite(q.e[2]))
+                return fail(c, LB_E_INVALID, "non-finite particle axis");
+            const double em = q.e[0] * d.m[0] + q.e[1] * d.m[1] + q.e[2] * d.m[2];
+            double ev[3] = {q.e[0] - em * d.m[0], q.e[1] - em * d.m[1], q.e[2] - em * d.m[2]};
+            double ne = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+            if (!(ne > 1e-9)) {
+                int j = 0;
+                for (int a = 1; a < 3; a++)
+                    if (fabs(d.m[a]) < fabs(d.m[j])) j = a;
+                double ax[3] = {0.0, 0.0, 0.0};
+                ax[j] = 1.0;
+                const double t[3] = {d.m[1] * ax[2] - d.m[2] * ax[1], d.m[2] * ax[0] - d.m[0] * ax[2],
+                                     d.m[0] * ax[1] - d.m[1] * ax[0]};
+                ev[0] = t[1] * d.m[2] - t[2] * d.m[1];
+                ev[1] = t[2] * d.m[0] - t[0] * d.m[2];
+                ev[2] = t[0] * d.m[1] - t[1] * d.m[0];
+                ne = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+            }
+            for (int a = 0; a < 3; a++) d.e[a] = ev[a] / ne;
+        }
         d.changed = 1;  // build the owner map and link table on placement
         rmax = std::max(rmax, q.radius);
     }
@@ -937,6 +1013,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
     }
     HIP_TRY(c, hipMemcpyAsync(c->dcol, h.data(), sizeof(DColloid) * n, hipMemcpyHostToDevice, c->stream));
     c->ncol = n;
+    for (int k = 0; k < n; k++) c->pattern = c->pattern || h[k].pb > 0;
     c->dirty = true;
     {
         lb_status st = refresh_self(c);
@@ -1084,7 +1161,12 @@ lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
             st = lb_get_links(c, rec.data(), nl, &nl);
             if (st != LB_OK) return st;
             t->n_links = nl;
-            for (int64_t l = 0; l < nl; l++) t->n_active += rec[4 * l + 3];
+            // active links: the cap bit, or a producing cell of a pattern
+            for (int64_t l = 0; l < nl; l++) {
+                const DColloid &q = h[rec[4 * l]];
+                const int tag = rec[4 * l + 3];
+                t->n_active += q.pb > 0 ? (q.palpha[tag] != 0.0 ? 1 : 0) : tag;
+            }
         }
         t->step = c->step;
         int e = herr;
@@ -1113,6 +1195,15 @@ lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
             q.rho_p = d.rho_p;
             q.fixed = d.fixed;
             q.cap_cos = d.capc;
+            for (int a = 0; a < 3; a++) q.e[a] = d.e[a];
+            q.pattern_bands = d.pb;
+            q.pattern_sectors = d.ps;
+            for (int b = 0; b < LB_PATTERN_MAX_BANDS - 1; b++) q.pattern_cos[b] = d.pcos[b];
+            for (int i = 0; i < LB_PATTERN_MAX_CELLS; i++) {
+                q.pattern_alpha[i] = d.palpha[i];
+                q.pattern_mu[i] = d.pmu[i];
+                q.pattern_H[i] = d.pH[i];
+            }
         }
     }
     if (herr & LB_ERR_NAN) return fail(c, LB_E_UNSTABLE, "non-finite totals");
@@ -1195,12 +1286,14 @@ lb_status lb_get_links(lb_ctx *c, int32_t *rec4, int64_t cap, int64_t *nout)
             const size_t s = (size_t)k * c->lcap + j;
             rec4[4 * l + 0] = k;
             rec4[4 * l + 1] = nodes[s];
-            const int d = dcs[s] & 31, n = nodes[s];
+            const int d = dcs[s], n = nodes[s];
             const int z = n / (c->p.nx * c->p.ny), y = (n / c->p.nx) % c->p.ny, x = n % c->p.nx;
             double r[3];
             displacement(h[k], x, y, z, cx(d), cy(d), cz(d), 0.5, c->p.nx, c->p.ny, c->p.nz, r);
             rec4[4 * l + 2] = d;
-            rec4[4 * l + 3] = active_cap(h[k], r) ? 1 : 0;  // cap from the current axis
+            // from the current axes: the cap bit, or the cell of a pattern
+            const int cell = surface_cell(h[k], r);
+            rec4[4 * l + 3] = h[k].pb > 0 ? cell : (cell == 0 ? 1 : 0);
             l++;
         }
     return LB_OK;
@@ -1275,6 +1368,7 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
             return fail(c, LB_E_INVALID, "state too short");
         double rmax = 0.0;
         for (int k = 0; k < hd.ncol; k++) rmax = std::max(rmax, hc[k].radius);
+        for (int k = 0; k < hd.ncol; k++) c->pattern = c->pattern || hc[k].pb > 0;
         lb_status st = alloc_colloid_tables(c, rmax, hd.lcap);
         if (st != LB_OK) { free_colloids(c); c->ncol = 0; return st; }
     }

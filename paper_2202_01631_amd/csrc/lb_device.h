@@ -127,6 +127,10 @@ struct DColloid {
     int fixed, nlinks, nactive, changed;  // changed: owner map moved this step
     double capc;               // active cap m.n <= capc (0: the Janus half)
     double sF[3];              // soft-sphere force of this step (when the box has it)
+    double e[3];               // second body axis (orthogonal to m), turns with it
+    int pb, ps;                // surface pattern: bands (0: none), sectors
+    double pcos[LB_PATTERN_MAX_BANDS - 1];  // band cuts in m.n, increasing
+    double palpha[LB_PATTERN_MAX_CELLS], pmu[LB_PATTERN_MAX_CELLS], pH[LB_PATTERN_MAX_CELLS];
 };
 
 // -------------------------------------------------------- particle geometry
@@ -173,6 +177,70 @@ __host__ __device__ inline bool active_cap(const DColloid &q, const double r[3])
     double rr = r[0] * r[0] + r[1] * r[1];
     rr = rr + r[2] * r[2];
     return md <= q.capc * sqrt(rr);
+}
+
+// Surface cell of the point at displacement r from the centre: with a
+// pattern, band (cuts compared as m.r <= t |r|, as the cap test) times
+// sectors plus the azimuthal sector of r about m, counted from e towards
+// m x e in half-open intervals decided by signs and sizes of the two
+// projections; without one, 0 on the active cap and 1 elsewhere.  FP64, no
+// contraction: link tables are compared bit for bit.
+__host__ __device__ inline int azimuth_sector(double a, double b, int S)
+{
+    if (S <= 1) return 0;
+    int q;  // quadrant of the angle atan2(b, a) in [0, 2 pi); a = b = 0 is angle 0
+    if (a > 0.0 && b >= 0.0) q = 0;
+    else if (a <= 0.0 && b > 0.0) q = 1;
+    else if (a < 0.0 && b <= 0.0) q = (a == 0.0 && b == 0.0) ? 0 : 2;
+    else q = 3;
+    if (S == 2) return q < 2 ? 0 : 1;
+    if (S == 4) return q;
+    // eighths: the quadrant turned onto the first, whose lower half is y < x
+    double x = a, y = b;
+    if (q == 1) { x = b; y = -a; }
+    else if (q == 2) { x = -a; y = -b; }
+    else if (q == 3) { x = -b; y = a; }
+    return 2 * q + (y < x ? 0 : 1);
+}
+
+__host__ __device__ inline int surface_cell(const DColloid &q, const double r[3])
+{
+#pragma clang fp contract(off)
+    if (q.pb <= 0) return active_cap(q, r) ? 0 : 1;
+    double md = q.m[0] * r[0] + q.m[1] * r[1];
+    md = md + q.m[2] * r[2];
+    double rr = r[0] * r[0] + r[1] * r[1];
+    rr = rr + r[2] * r[2];
+    const double rn = sqrt(rr);
+    int band = 0;
+    for (int b = 0; b < q.pb - 1; b++)
+        if (!(md <= q.pcos[b] * rn)) band++;
+    const double w[3] = {q.m[1] * q.e[2] - q.m[2] * q.e[1], q.m[2] * q.e[0] - q.m[0] * q.e[2],
+                         q.m[0] * q.e[1] - q.m[1] * q.e[0]};
+    double a = q.e[0] * r[0] + q.e[1] * r[1];
+    a = a + q.e[2] * r[2];
+    double b = w[0] * r[0] + w[1] * r[1];
+    b = b + w[2] * r[2];
+    return band * q.ps + azimuth_sector(a, b, q.ps);
+}
+
+// production, phoretic mobility and wetting parameter of a surface cell
+__host__ __device__ inline double cell_alpha(const DColloid &q, int cell)
+{
+    return q.pb > 0 ? q.palpha[cell] : (cell == 0 ? q.am : q.ap);
+}
+__host__ __device__ inline double cell_mu(const DColloid &q, int cell)
+{
+    return q.pb > 0 ? q.pmu[cell] : (cell == 0 ? q.mum : q.mup);
+}
+__host__ __device__ inline double cell_H(const DColloid &q, int cell)
+{
+    return q.pb > 0 ? q.pH[cell] : q.H;
+}
+// active link: on the active cap, or in a pattern cell that produces
+__host__ __device__ inline bool cell_active(const DColloid &q, int cell)
+{
+    return q.pb > 0 ? q.palpha[cell] != 0.0 : cell == 0;
 }
 
 // Particle bounding box along one axis, with the node coordinates visited in

@@ -13,7 +13,7 @@ struct StepBuffers {
     void *fout;
     const void *psi, *cc;   // state at t
     void *psin, *ccn;       // state at t+1
-    void *mu, *u;           // derived fields of step t
+    void *mu, *chi, *u;     // derived fields of step t (chi stored in FP64 only)
     uint8_t *own;
     DColloid *col;
     int *lnode;
@@ -64,6 +64,8 @@ struct Batch {
     int nsub;         // psi/c sub-steps per step (all boxes of the batch)
     int soft;         // some box has soft-sphere repulsion (k_soft runs)
     int nopsi;        // every box single phase: no mu launches, single-phase kernels
+    int pattern;      // some particle carries a surface pattern: boundary nodes always
+                      // in the fix-up launches (the inline forms have no cell arithmetic)
     // with nsub > 1: descriptor tables of sub-step 0 (state at t -> its
     // target), next-state -> scratch and scratch -> next-state psi/c pairs
     const BoxDesc *dsub[3];

@@ -82,13 +82,18 @@ __device__ __forceinline__ void st_interior(S *base, unsigned on, const SVec<S, 
 // chi = c - c_b0 - E tanh psi (Eq. 2; 1/cosh^2 = 1 - tanh^2, cubic factored
 // as b psi (psi-1)(psi+1) + (a+b) psi to keep FP32 cancellation small).
 // At a solid face neighbour the Laplacian takes the ghost psi - (H/kappa)|e.n|
-// (Eq. 9, n through the face midpoint).
+// (Eq. 9, n through the face midpoint; H of the surface cell there when the
+// particle carries a pattern).
 // The node arithmetic lives in helpers with contraction off and explicit
 // fused forms, so every launch form of a kernel rounds identically.
 
 // psi value the Laplacian takes across face e (x+, x-, y+, y-, z+, z-) of
-// fluid node (x, y, z): the neighbour's, or the wetting ghost at a solid one
-template <class S>
+// fluid node (x, y, z): the neighbour's, or the wetting ghost at a solid one.
+// PAT = false: no particle of the box has a surface pattern (the forms that
+// treat boundary nodes inside the bulk launches; boxes with patterns take
+// the boundary fix-up launches, and these forms stay free of the cell
+// arithmetic and its registers).
+template <class S, bool PAT = true>
 __device__ __forceinline__ S face_psi(const KParams &p, const DColloid *__restrict__ col,
                                       uint8_t onb, int e, int x, int y, int z, S ps, S pv)
 {
@@ -102,7 +107,8 @@ __device__ __forceinline__ S face_psi(const KParams &p, const DColloid *__restri
                  p.nz, r);
     const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
     const double en = fabs(r[ax]) / rn;
-    const double gh = p.kappa > 0.0 ? (q.H / p.kappa) * en : 0.0;
+    const double H = (PAT && q.pb > 0) ? q.pH[surface_cell(q, r)] : q.H;
+    const double gh = p.kappa > 0.0 ? (H / p.kappa) * en : 0.0;
     return ps - (S)gh;
 }
 
@@ -116,8 +122,11 @@ template <class S> __device__ __forceinline__ S lap6(S ps, const S f[6])
 }
 
 // chi = c - c_b0 - E tanh psi, the solute's distance from its equilibrium
-// c0(psi) (Eq. 1); not stored: every kernel that needs it forms it from psi
-// and c with this one expression
+// c0(psi) (Eq. 1).  In FP32 arithmetic the kernels that need it form it from
+// psi and c with this one expression (cheaper than storing and reloading it);
+// in FP64, where tanh is dear, the mu pass stores it (chi_stored) and the
+// bulk psi/c updates read it back.  Either way the same value.
+template <class S> struct ChiStored { static constexpr bool value = sizeof(S) == 8; };
 template <class S> __device__ __forceinline__ S chi_of(const KParams &p, S ps, S cn)
 {
 #pragma clang fp contract(off)
@@ -139,7 +148,7 @@ __device__ __forceinline__ void mu_chi(const KParams &p, S ps, S lap, S cn, S &m
 
 // mu of fluid node n = (x, y, z) next to a particle: wetting ghost at every
 // solid face
-template <class S>
+template <class S, bool PAT = true>
 __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y,
                                             int z)
 {
@@ -153,10 +162,11 @@ __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, 
     S pv[6];
 #pragma unroll
     for (int e = 0; e < 6; e++)
-        pv[e] = face_psi<S>(p, D.b.col, own[nb[e]], e, x, y, z, ps, psi[nb[e]]);
+        pv[e] = face_psi<S, PAT>(p, D.b.col, own[nb[e]], e, x, y, z, ps, psi[nb[e]]);
     S m, c;
     mu_chi<S>(p, ps, lap6<S>(ps, pv), ((const S *)D.b.cc)[n], m, c);
     ((S *)D.b.mu)[n] = m;
+    if (ChiStored<S>::value) ((S *)D.b.chi)[n] = c;
 }
 
 // one node per thread
@@ -171,6 +181,7 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ mu = (S *)D.b.mu;
+    S *__restrict__ chi_out = (S *)D.b.chi;
     int x, y, z;
     if (!lattice_node(p, blk - A.bstart[j], x, y, z)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
@@ -185,14 +196,19 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     S pv[6];
 #pragma unroll
     for (int e = 0; e < 6; e++) pv[e] = ldb(psi, (unsigned)nb[e] * sizeof(S));
-    if (o & OWN_SOLID) { stb(mu, on, S(0)); return; }
+    if (o & OWN_SOLID) {
+        stb(mu, on, S(0));
+        if (ChiStored<S>::value) stb(chi_out, on, S(0));
+        return;
+    }
     if (o & OWN_BOUNDARY) {  // here (BND) or in the fix-up launch
-        if (BND) mu_bnd_node<S>(D, p, n, x, y, z);
+        if (BND) mu_bnd_node<S, false>(D, p, n, x, y, z);
         return;
     }
     S m, c;
     mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
     stb(mu, on, m);
+    if (ChiStored<S>::value) stb(chi_out, on, c);
 }
 
 // Row-vector form: V consecutive x nodes per lane, 8- or 16-byte loads and
@@ -212,6 +228,7 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
     const S *__restrict__ cc = (const S *)D.b.cc;
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ mu = (S *)D.b.mu;
+    S *__restrict__ chi_out = (S *)D.b.chi;
     int x0, y, z, li, gb;
     if (!vec_node<V>(p, blk - A.bstart[j], x0, y, z, li, gb)) return;
     const int sy = p.nx, sz = p.nx * p.ny;
@@ -234,7 +251,7 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
         if (li == 0) pl = ldb(psi, (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S));
         if (li == Ls - 1) pr = ldb(psi, (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S));
     }
-    Vec mv;
+    Vec mv, xv;
 #pragma unroll
     for (int k = 0; k < V; k++) {
         const uint8_t o = byte_of(ow, k);
@@ -245,11 +262,13 @@ __device__ __forceinline__ void mu_vec(const BatchArgs &A, const int blk)
         mu_chi<S>(p, ps, lap6<S>(ps, pv), cv.v[k], m, c);
         const bool solid = (o & OWN_SOLID) != 0;
         mv.v[k] = solid ? S(0) : m;
+        xv.v[k] = solid ? S(0) : c;
     }
     st_interior<S, V>(mu, on, mv, ow);
+    if (ChiStored<S>::value) st_interior<S, V>(chi_out, on, xv, ow);
     if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
         for (int k = 0; k < V; k++)
-            if (byte_of(ow, k) & OWN_BOUNDARY) mu_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
+            if (byte_of(ow, k) & OWN_BOUNDARY) mu_bnd_node<S, false>(D, p, n0 + k, x0 + k, y, z);
     }
 }
 
@@ -744,9 +763,10 @@ __device__ __forceinline__ void psi_c_update(const KParams &p, S ps, S cn, S chi
     cpart = fma((S)p.D, dchi, cn - adv_c);
 }
 
-// Janus emission of boundary node n = (x, y, z): alpha of the cap of every
-// link to a solid neighbour, directions in ascending order
-template <class S>
+// Emission of boundary node n = (x, y, z): alpha of the surface cell (the
+// cap of a Janus particle) of every link to a solid neighbour, directions in
+// ascending order
+template <class S, bool PAT = true>
 __device__ S emission(const KParams &p, const DColloid *__restrict__ col,
                       const uint8_t *__restrict__ own, int n, int x, int y, int z)
 {
@@ -767,14 +787,15 @@ __device__ S emission(const KParams &p, const DColloid *__restrict__ col,
         const DColloid &q = col[om[d] - 1];
         double r[3];
         displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-        src = src + (S)((active_cap(q, r) ? q.am : q.ap) * p.sub);
+        const double al = PAT ? cell_alpha(q, surface_cell(q, r)) : (active_cap(q, r) ? q.am : q.ap);
+        src = src + (S)(al * p.sub);
     }
     return src;
 }
 
 // psi and c of fluid node n = (x, y, z) next to a particle: no flux through
 // solid faces, emission of its links
-template <class S>
+template <class S, bool PAT = true>
 __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y, int z)
 {
     const S *__restrict__ psi = (const S *)D.b.psi;
@@ -804,7 +825,7 @@ __device__ void psic_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, 
     S psn, cpart;
     psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, solid, psn, cpart);
     ((S *)D.b.psin)[n] = psn;
-    ((S *)D.b.ccn)[n] = fma(-(S)p.kd, chi, cpart + emission<S>(p, D.b.col, own, n, x, y, z));
+    ((S *)D.b.ccn)[n] = fma(-(S)p.kd, chi, cpart + emission<S, PAT>(p, D.b.col, own, n, x, y, z));
 }
 
 // one node per thread.  SP (every box single phase: psi and mu zero, chi =
@@ -837,7 +858,11 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
     const uint8_t o = own[n];
     const unsigned on = (unsigned)n * sizeof(S);
     const S cn = ldb(cc, on);
+    constexpr bool CS = ChiStored<S>::value && !SP;
+    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S ps = SP ? S(0) : ldb(psi, on), m0 = SP ? S(0) : ldb(mu, on);
+    const S chi_l = CS ? ldb(chiv, on) : S(0);
+    S xm_l[6];
     const S u0[3] = {ldb(ua[0], on), ldb(ua[1], on), ldb(ua[2], on)};
     S um[6], pm[6], cm[6], mm[6], xm[6];
 #pragma unroll
@@ -847,6 +872,7 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
         cm[e] = ldb(cc, om);
         pm[e] = SP ? S(0) : ldb(psi, om);
         mm[e] = SP ? S(0) : ldb(mu, om);
+        xm_l[e] = CS ? ldb(chiv, om) : S(0);
     }
     if (o & OWN_SOLID) {
         if (!SP) stb(psin, on, ps);
@@ -854,13 +880,13 @@ __device__ __forceinline__ void psic_one(const BatchArgs &A, const int blk)
         return;
     }
     if (o & OWN_BOUNDARY) {  // here (BND) or in the fix-up launch
-        if (BND) psic_bnd_node<S>(D, p, n, x, y, z);
+        if (BND) psic_bnd_node<S, false>(D, p, n, x, y, z);
         return;
     }
-    // chi from psi and c (single phase: c itself)
-    const S chi = SP ? cn : chi_of<S>(p, ps, cn);
+    // chi read back (FP64) or formed from psi and c (single phase: c itself)
+    const S chi = SP ? cn : (CS ? chi_l : chi_of<S>(p, ps, cn));
 #pragma unroll
-    for (int e = 0; e < 6; e++) xm[e] = SP ? cm[e] : chi_of<S>(p, pm[e], cm[e]);
+    for (int e = 0; e < 6; e++) xm[e] = SP ? cm[e] : (CS ? xm_l[e] : chi_of<S>(p, pm[e], cm[e]));
     S psn, cpart;
     psi_c_update<S>(p, ps, cn, chi, m0, u0, um, pm, cm, mm, xm, 0u, psn, cpart);
     if (!SP) stb(psin, on, psn);
@@ -883,6 +909,8 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     const S *__restrict__ psi = (const S *)D.b.psi;
     const S *__restrict__ cc = (const S *)D.b.cc;
     const S *__restrict__ mu = (const S *)D.b.mu;
+    constexpr bool CS = ChiStored<S>::value && !SP;  // chi read back, not formed
+    const S *__restrict__ chiv = (const S *)D.b.chi;
     const S *__restrict__ ux = (const S *)D.b.u;
     const S *__restrict__ uy = ux + p.N;
     const S *__restrict__ uz = ux + 2 * (size_t)p.N;
@@ -928,6 +956,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
         if (!SP) c0[0] = ldb((const Vec *)psi, on);
         c0[1] = ldb((const Vec *)cc, on);
         if (!SP) c0[2] = ldb((const Vec *)mu, on);
+        if (CS) c0[3] = ldb((const Vec *)chiv, on);
         u0x = ldb((const Vec *)ux, on);
         u0y = ldb((const Vec *)uy, on);
         u0z = ldb((const Vec *)uz, on);
@@ -938,6 +967,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
             if (!SP) nbv[0][e] = ldb((const Vec *)psi, om);
             nbv[1][e] = ldb((const Vec *)cc, om);
             if (!SP) nbv[2][e] = ldb((const Vec *)mu, om);
+            if (CS) nbv[3][e] = ldb((const Vec *)chiv, om);
             if (e == 0) uyp = ldb((const Vec *)uy, om);
             else uym = ldb((const Vec *)uy, om);
         }
@@ -947,10 +977,11 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
             if (!SP) nbv[0][e] = ldb((const Vec *)psi, om);
             nbv[1][e] = ldb((const Vec *)cc, om);
             if (!SP) nbv[2][e] = ldb((const Vec *)mu, om);
+            if (CS) nbv[3][e] = ldb((const Vec *)chiv, om);
         }
         uzp = ldb((const Vec *)uz, (unsigned)nb[2] * sizeof(S));
         uzm = ldb((const Vec *)uz, (unsigned)nb[3] * sizeof(S));
-        if (!SP) {
+        if (!SP && !CS) {
             // chi of the centre vector and of the rows read from memory
 #pragma unroll
             for (int k = 0; k < V; k++) c0[3].v[k] = chi_of<S>(p, c0[0].v[k], c0[1].v[k]);
@@ -1009,7 +1040,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
             if (!SP) {
                 fl[0] = ldb(psi, ol);
                 fl[2] = ldb(mu, ol);
-                fl[3] = chi_of<S>(p, fl[0], fl[1]);
+                fl[3] = CS ? ldb(chiv, ol) : chi_of<S>(p, fl[0], fl[1]);
             }
             fl[4] = ldb(ux, ol);
         }
@@ -1019,7 +1050,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
             if (!SP) {
                 fr[0] = ldb(psi, orr);
                 fr[2] = ldb(mu, orr);
-                fr[3] = chi_of<S>(p, fr[0], fr[1]);
+                fr[3] = CS ? ldb(chiv, orr) : chi_of<S>(p, fr[0], fr[1]);
             }
             fr[4] = ldb(ux, orr);
         }
@@ -1055,7 +1086,7 @@ __device__ __forceinline__ void psic_vec(const BatchArgs &A, const int blk)
     st_interior<S, V>(ccn, on, cnv, ow);
     if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
         for (int k = 0; k < V; k++)
-            if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
+            if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S, false>(D, p, n0 + k, x0 + k, y, z);
     }
 }
 
@@ -1083,9 +1114,12 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
     const uint8_t *__restrict__ own = D.b.own;
     S *__restrict__ psin = (S *)D.b.psin;
     S *__restrict__ ccn = (S *)D.b.ccn;
-    // fields kept over z; chi (slot 3) is formed from psi and c, not loaded
-    const S *__restrict__ wf[5] = {psi, cc, mu, nullptr, uz};
+    // fields kept over z; chi (slot 3) read back in FP64, else formed from
+    // psi and c
+    constexpr bool CS = ChiStored<S>::value;
+    const S *__restrict__ wf[5] = {psi, cc, mu, CS ? (const S *)D.b.chi : nullptr, uz};
     auto chi_vec = [&](Vec &x, const Vec &ps, const Vec &cv) {
+        if (CS) return;
 #pragma unroll
         for (int k = 0; k < V; k++) x.v[k] = chi_of<S>(p, ps.v[k], cv.v[k]);
     };
@@ -1115,7 +1149,7 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
             const int n = c0 + sz * pl[s];
 #pragma unroll
             for (int f = 0; f < 5; f++)
-                if (f != 3) W[f][s] = ldb((const Vec *)wf[f], (unsigned)n * sizeof(S));
+                if (f != 3 || CS) W[f][s] = ldb((const Vec *)wf[f], (unsigned)n * sizeof(S));
             chi_vec(W[3][s], W[0][s], W[1][s]);
             WO[s] = ldb((const OW *)own, (unsigned)n);
         }
@@ -1135,7 +1169,7 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
             const int n2 = c0 + sz * z2;
 #pragma unroll
             for (int f = 0; f < 5; f++)
-                if (f != 3) nW[f] = ldb((const Vec *)wf[f], (unsigned)n2 * sizeof(S));
+                if (f != 3 || CS) nW[f] = ldb((const Vec *)wf[f], (unsigned)n2 * sizeof(S));
             chi_vec(nW[3], nW[0], nW[1]);
             nO = ldb((const OW *)own, (unsigned)n2);
             const unsigned o1 = (unsigned)(c0 + sz * wrap_p(z, p.nz)) * sizeof(S);
@@ -1146,7 +1180,8 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
         Vec Y[5][2];
         const unsigned oyp = (unsigned)(n0 + dyp) * sizeof(S), oym = (unsigned)(n0 + dym) * sizeof(S);
 #pragma unroll
-        for (int f = 0; f < 3; f++) {
+        for (int f = 0; f < 4; f++) {
+            if (f == 3 && !CS) continue;
             Y[f][0] = ldb((const Vec *)wf[f], oyp);
             Y[f][1] = ldb((const Vec *)wf[f], oym);
         }
@@ -1170,14 +1205,14 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
                 const unsigned ol = (unsigned)(rb + (x0 == 0 ? p.nx - 1 : x0 - 1)) * sizeof(S);
 #pragma unroll
                 for (int f = 0; f < 3; f++) fl[f] = ldb(wf[f], ol);
-                fl[3] = chi_of<S>(p, fl[0], fl[1]);
+                fl[3] = CS ? ldb(wf[3], ol) : chi_of<S>(p, fl[0], fl[1]);
                 fl[4] = ldb(ux, ol);
             }
             if (li == Ls - 1) {
                 const unsigned orr = (unsigned)(rb + (x0 + V == p.nx ? 0 : x0 + V)) * sizeof(S);
 #pragma unroll
                 for (int f = 0; f < 3; f++) fr[f] = ldb(wf[f], orr);
-                fr[3] = chi_of<S>(p, fr[0], fr[1]);
+                fr[3] = CS ? ldb(wf[3], orr) : chi_of<S>(p, fr[0], fr[1]);
                 fr[4] = ldb(ux, orr);
             }
         }
@@ -1209,7 +1244,7 @@ __device__ __forceinline__ void psic_zmarch(const BatchArgs &A, const int blk)
         st_interior<S, V>(ccn, on, cnv, ow);
         if (BND && (ow & ((V == 4) ? 0x80808080u : 0x8080u))) {
             for (int k = 0; k < V; k++)
-                if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S>(D, p, n0 + k, x0 + k, y, z);
+                if (byte_of(ow, k) & OWN_BOUNDARY) psic_bnd_node<S, false>(D, p, n0 + k, x0 + k, y, z);
         }
         // advance the window
 #pragma unroll
@@ -1402,8 +1437,9 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         const int ex = cx(d), ey = cy(d), ez = cz(d);
         double r[3];
         displacement(q, x, y, z, ex, ey, ez, 0.5, p.nx, p.ny, p.nz, r);
-        // cap from the current axis (the table is rebuilt only on owner changes)
-        const bool cap = active_cap(q, r);
+        // surface cell from the current axes (the table is rebuilt only on
+        // owner changes)
+        const int cell = surface_cell(q, r);
         const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         const double nh[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
         // grad c at the fluid node, c(x) substituted at solid neighbours
@@ -1415,7 +1451,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         double cv[6];
         for (int e = 0; e < 6; e++) cv[e] = (own[fn[e]] & OWN_SOLID) ? c0 : (double)cc[fn[e]];
         const double g[3] = {0.5 * (cv[0] - cv[1]), 0.5 * (cv[2] - cv[3]), 0.5 * (cv[4] - cv[5])};
-        const double mob = cap ? q.mum : q.mup;
+        const double mob = cell_mu(q, cell);
         const double ng = nh[0] * g[0] + nh[1] * g[1] + nh[2] * g[2];
         double slip[3], ub[3], wr[3];
         for (int a = 0; a < 3; a++) slip[a] = mob * (g[a] - nh[a] * ng);
@@ -1443,7 +1479,7 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         int j = 6;
         for (int i1 = 0; i1 < 6; i1++)
             for (int i2 = i1; i2 < 6; i2++) acc[j++] += coef * gv[i1] * gv[i2];
-        acc[27] += cap ? 1.0 : 0.0;
+        acc[27] += cell_active(q, cell) ? 1.0 : 0.0;
         }
     }
     const double tot = block_sum<28>(acc, lds);
@@ -1454,7 +1490,8 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
 // ------------------------------------------------------ k_colloid_update
 // One block per particle: link partials summed in chunk order (FP64), then
 // (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
-// R' = R + V', m' = m rotated by |Omega'| about Omega'.
+// R' = R + V', m' = m and e' = e rotated by |Omega'| about Omega' (e' then
+// made orthogonal to m' again and normalised).
 __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
 {
     __shared__ double sacc[28];
@@ -1561,6 +1598,15 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
         for (int a = 0; a < 3; a++) mn[a] = q.m[a] * cs + kxm[a] * sn + ax[a] * km * (1.0 - cs);
         const double nn = sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
         for (int a = 0; a < 3; a++) q.m[a] = mn[a] / nn;
+        double kxe[3];
+        cross3(ax, q.e, kxe);
+        const double ke = ax[0] * q.e[0] + ax[1] * q.e[1] + ax[2] * q.e[2];
+        double en[3];
+        for (int a = 0; a < 3; a++) en[a] = q.e[a] * cs + kxe[a] * sn + ax[a] * ke * (1.0 - cs);
+        const double em = en[0] * q.m[0] + en[1] * q.m[1] + en[2] * q.m[2];
+        for (int a = 0; a < 3; a++) en[a] = en[a] - em * q.m[a];
+        const double ne = sqrt(en[0] * en[0] + en[1] * en[1] + en[2] * en[2]);
+        for (int a = 0; a < 3; a++) q.e[a] = en[a] / ne;
     }
 }
 
@@ -1958,12 +2004,9 @@ __global__ __launch_bounds__(GCHUNK) void k_link_write(BatchArgs A)
     int l = sbase + off;
     for (int d = 1; d < 19; d++) {
         if (!(mask & (1u << d))) continue;
-        double r[3];
-        displacement(q, x, y, z, cx(d), cy(d), cz(d), 0.5, p.nx, p.ny, p.nz, r);
-        const bool cap = active_cap(q, r);
         if (l < lcap) {
             lnode[(size_t)k * lcap + l] = n;
-            ldc[(size_t)k * lcap + l] = (uint8_t)(d | (cap ? 0x80 : 0));
+            ldc[(size_t)k * lcap + l] = (uint8_t)d;
         }
         l++;
     }
@@ -2158,7 +2201,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     constexpr int V4 = sizeof(S) == 4 ? 4 : 2;  // FP64 scalars: 2 per 16-byte access
     // split: boundary nodes in fix-up launches (on the side stream if par);
     // psi/c sub-steps keep everything in order on s
-    const bool split = B.ncol > 0 && B.nodes >= SIDE_MIN_NODES;
+    const bool split = B.ncol > 0 && (B.nodes >= SIDE_MIN_NODES || B.pattern);
     const bool par = split && side && !tm && B.nsub <= 1;
     hipStream_t ss = par ? side->s : s;
     const dim3 gfix(B.args.nfix);

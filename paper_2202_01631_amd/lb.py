@@ -42,13 +42,21 @@ class Params(C.Structure):
                 ("soft_nu", C.c_double), ("soft_hc", C.c_double), ("lub_hc", C.c_double)]
 
 
+PATTERN_MAX_BANDS, PATTERN_MAX_CELLS = 8, 64
+
+
 class Colloid(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("m", C.c_double * 3),
                 ("vel", C.c_double * 3), ("omega", C.c_double * 3),
                 ("radius", C.c_double), ("alpha_minus", C.c_double),
                 ("alpha_plus", C.c_double), ("mu_minus", C.c_double),
                 ("mu_plus", C.c_double), ("H", C.c_double), ("rho_p", C.c_double),
-                ("fixed", C.c_int32), ("cap_cos", C.c_double)]
+                ("fixed", C.c_int32), ("cap_cos", C.c_double), ("e", C.c_double * 3),
+                ("pattern_bands", C.c_int32), ("pattern_sectors", C.c_int32),
+                ("pattern_cos", C.c_double * (PATTERN_MAX_BANDS - 1)),
+                ("pattern_alpha", C.c_double * PATTERN_MAX_CELLS),
+                ("pattern_mu", C.c_double * PATTERN_MAX_CELLS),
+                ("pattern_H", C.c_double * PATTERN_MAX_CELLS)]
 
 
 class Totals(C.Structure):
@@ -157,6 +165,24 @@ def make_colloid(d):
         setattr(q, key, float(d.get(key, 1.0 if key == "rho_p" else 0.0)))
     q.fixed = int(d.get("fixed", 0))
     q.cap_cos = float(d.get("cap_cos", 0.0))
+    e = d.get("e", (0.0, 0.0, 0.0))
+    for a in range(3):
+        q.e[a] = float(e[a])
+    pat = d.get("pattern")
+    if pat:
+        # {"bands": B, "sectors": S, "cos": B-1 cuts, "alpha"/"mu"/"H": B*S values}
+        q.pattern_bands, q.pattern_sectors = int(pat["bands"]), int(pat["sectors"])
+        cuts = list(pat.get("cos", ()))
+        if len(cuts) > PATTERN_MAX_BANDS - 1:
+            raise ValueError(f"at most {PATTERN_MAX_BANDS - 1} pattern cuts")
+        for i, v in enumerate(cuts):
+            q.pattern_cos[i] = float(v)
+        for key in ("alpha", "mu", "H"):
+            vals = list(pat.get(key, ()))
+            if len(vals) > PATTERN_MAX_CELLS:
+                raise ValueError(f"at most {PATTERN_MAX_CELLS} pattern cells")
+            for i, v in enumerate(vals):
+                getattr(q, "pattern_" + key)[i] = float(v)
     return q
 
 
@@ -166,6 +192,13 @@ def colloid_dict(q):
         d[k] = getattr(q, k)
     d["fixed"] = q.fixed
     d["cap_cos"] = q.cap_cos
+    d["e"] = np.array(q.e[:])
+    if q.pattern_bands > 0:
+        nc = q.pattern_bands * q.pattern_sectors
+        d["pattern"] = {"bands": q.pattern_bands, "sectors": q.pattern_sectors,
+                        "cos": list(q.pattern_cos[:q.pattern_bands - 1]),
+                        "alpha": list(q.pattern_alpha[:nc]), "mu": list(q.pattern_mu[:nc]),
+                        "H": list(q.pattern_H[:nc])}
     return d
 
 
