@@ -1,7 +1,8 @@
 """Drive the sanitizer build of the library (liblb_hostcheck.so) through the
 rest of the C ABI's call sequences (TEST INFRASTRUCTURE): every entry point,
 the error paths, save/load, timing, launch shapes, a batch of uneven boxes on
-a caller stream with an odd step count, contexts destroyed in any order.
+a caller stream with an odd step count, contexts destroyed in any order,
+particles with surface patterns.
 Exit status 0 and "abi ok" mean no sanitizer or runtime-misuse report.
 
     python abi_check.py LIB
@@ -57,6 +58,10 @@ def main():
             b.set_launch_shapes([(64, 4, 0), (32, 8, 1), (0, 0, 2 + 8 * 4)])
             b.launch_shapes()
             b.step(4)
+            # new shapes straight after a graph-replayed step: the captured
+            # step pairs are dropped only once their replay has finished
+            b.set_launch_shapes([(32, 8, 0), (64, 4, 0), (0, 0, 2 + 8 * 4)])
+            b.step(2)
             expect_error(b.set_launch_shapes, [(-1, 0, 0)] * 3)
             b.close()
     # error paths before and after init
@@ -77,6 +82,23 @@ def main():
         b.observables(check=False)
         b.links()
         b.close()
+    # surface patterns: a patterned box alone (boundary fix-up launches), in
+    # a batch beside a Janus box, saved and loaded; bad patterns refused
+    pw = dict(w, colloids=[dict(w["colloids"][0], e=(0.0, 0.0, 0.0),
+                                pattern=dict(bands=2, sectors=4, cos=[0.2], alpha=[1e-3] * 8,
+                                             mu=[0.1] * 8, H=[0.0] * 8))])
+    pb = lb.from_spec(pw, precision="fp32", stream=st.value)
+    pb.step(3)
+    pb.links()
+    s = pb.save_state()
+    pb.load_state(s)
+    other = lb.from_spec(w, precision="fp32", stream=st.value)
+    lb.batch_step([pb, other], 3)
+    for bad in (dict(bands=9, sectors=1), dict(bands=2, sectors=3, cos=[0.0]),
+                dict(bands=3, sectors=1, cos=[0.5, 0.1])):
+        expect_error(pb.add_colloids, [dict(pw["colloids"][0], pattern=bad)])
+    pb.close()
+    other.close()
     left = L.hostcheck_live_allocations()
     print("abi ok: %d device allocations left" % left, flush=True)
     if left:

@@ -4,7 +4,11 @@
 // that the ABI's call sequences (create, init, particles, batched steps with
 // graph capture, readback, destroy) can be checked for memory and lifetime
 // errors without a GPU.  Kernels are not executed: a launch only checks its
-// configuration and its stream.
+// configuration and its stream.  Asynchronous copies and fills are not done
+// when they are issued but at the next point where the caller may rely on
+// them (a stream, event or device synchronisation, a synchronous copy, a
+// free): a host buffer released before its asynchronous copy has run is then
+// read or written after its release, which AddressSanitizer reports.
 //
 // What is checked (a violation prints "hostcheck:" and aborts):
 //   * device memory: every copy and fill lies inside one live allocation;
@@ -17,7 +21,9 @@
 //     on after its last captured work (no unjoined fork), no synchronisation
 //     or copy may run on a capturing stream;
 //   * graphs: launched only while instantiated, on a live stream that is not
-//     capturing.
+//     capturing; an executable graph is destroyed only after its last launch
+//     is known complete (its stream, an event recorded after it or the device
+//     synchronised, or a free, which waits for the device).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -33,8 +39,21 @@ namespace {
 constexpr uint64_t STREAM_MAGIC = 0x53545245414d2121ull, EVENT_MAGIC = 0x4556454e54212121ull,
                    GRAPH_MAGIC = 0x4752415048212121ull, EXEC_MAGIC = 0x4558454321212121ull;
 
-std::recursive_mutex g_mu;
-std::map<uintptr_t, size_t> g_mem;  // live device allocations
+// Built on first use: the library's load-time registration of its
+// __device__ variables can run before this file's static constructors.
+// Never destroyed, so calls during process exit still find them.
+std::recursive_mutex &mutex_instance()
+{
+    static std::recursive_mutex *m = new std::recursive_mutex;
+    return *m;
+}
+std::map<uintptr_t, size_t> &memory_registry()  // live device allocations
+{
+    static std::map<uintptr_t, size_t> *m = new std::map<uintptr_t, size_t>;
+    return *m;
+}
+#define g_mu mutex_instance()
+#define g_mem memory_registry()
 hipError_t g_last = hipSuccess;
 size_t g_registered_vars = 0;  // entries of g_mem that are __device__ variables
 
@@ -47,6 +66,31 @@ size_t g_registered_vars = 0;  // entries of g_mem that are __device__ variables
 
 struct Capture;
 
+// asynchronous copies and fills not yet done, in issue order
+struct Pending {
+    void *dst;
+    const void *src;  // null: a fill with value v
+    size_t n;
+    int v;
+};
+std::vector<Pending> &pending_work()
+{
+    static std::vector<Pending> *q = new std::vector<Pending>;
+    return *q;
+}
+
+// do every pending copy and fill (issue order is one valid order of the
+// streams' work; doing other streams' work early only hides errors)
+void drain()
+{
+    std::vector<Pending> q;
+    q.swap(pending_work());
+    for (const Pending &w : q) {
+        if (w.src) memmove(w.dst, w.src, w.n);
+        else memset(w.dst, w.v, w.n);
+    }
+}
+
 }  // namespace
 
 struct ihipStream_t {
@@ -54,6 +98,7 @@ struct ihipStream_t {
     Capture *cap;        // capture this stream takes part in, or null
     long ops;            // work items enqueued (captured or not)
     long joined_at;      // ops count at the last join back into the origin
+    long synced;         // ops count known complete (synchronised)
 };
 
 struct ihipEvent_t {
@@ -71,6 +116,9 @@ struct ihipGraph {
 struct hipGraphExec {
     uint64_t magic;
     long nodes;
+    ihipStream_t *launch_stream;  // stream of the last launch not known complete, or null
+    long launch_ops;              // that stream's ops count after the launch
+    bool unknown;                 // launched on a stream destroyed before it was synchronised
 };
 
 namespace {
@@ -80,6 +128,25 @@ struct Capture {
     std::set<ihipStream_t *> members;
     long nodes;
 };
+
+std::set<ihipStream_t *> &live_streams()
+{
+    static std::set<ihipStream_t *> *s = new std::set<ihipStream_t *>;
+    return *s;
+}
+std::set<hipGraphExec *> &live_execs()
+{
+    static std::set<hipGraphExec *> *s = new std::set<hipGraphExec *>;
+    return *s;
+}
+
+// everything issued so far is complete
+void device_synced()
+{
+    for (ihipStream_t *q : live_streams()) q->synced = q->ops;
+    for (hipGraphExec *x : live_execs()) { x->launch_stream = nullptr; x->unknown = false; }
+}
+
 
 void check_stream(hipStream_t s, const char *what)
 {
@@ -142,13 +209,16 @@ hipError_t hipFree(void *p)
     if (!p) return hipSuccess;
     auto it = g_mem.find((uintptr_t)p);
     if (it == g_mem.end()) die("hipFree of memory that is not a live device allocation");
+    drain();  // hipFree waits for the device's work
+    device_synced();
+    it = g_mem.find((uintptr_t)p);
     g_mem.erase(it);
     free(p);
     return hipSuccess;
 }
 
 static hipError_t copy(void *dst, const void *src, size_t n, hipMemcpyKind k, hipStream_t s,
-                       const char *who)
+                       const char *who, bool sync)
 {
     std::lock_guard<std::recursive_mutex> l(g_mu);
     check_stream(s, "copy on a destroyed stream");
@@ -157,19 +227,24 @@ static hipError_t copy(void *dst, const void *src, size_t n, hipMemcpyKind k, hi
     if (k == hipMemcpyDeviceToHost || k == hipMemcpyDeviceToDevice) check_range(src, n, who);
     if (k == hipMemcpyHostToDevice && is_device(src)) die("host-to-device copy from device memory");
     if (k == hipMemcpyDeviceToHost && is_device(dst)) die("device-to-host copy into device memory");
-    if (n) memmove(dst, src, n);
+    if (!sync) {
+        if (n) pending_work().push_back(Pending{dst, src, n, 0});
+    } else {
+        drain();
+        if (n) memmove(dst, src, n);
+    }
     enqueue(s);
     return hipSuccess;
 }
 
 hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind k)
 {
-    return copy(dst, src, n, k, nullptr, "hipMemcpy outside a device allocation");
+    return copy(dst, src, n, k, nullptr, "hipMemcpy outside a device allocation", true);
 }
 
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind k, hipStream_t s)
 {
-    return copy(dst, src, n, k, s, "hipMemcpyAsync outside a device allocation");
+    return copy(dst, src, n, k, s, "hipMemcpyAsync outside a device allocation", false);
 }
 
 hipError_t hipMemsetAsync(void *dst, int v, size_t n, hipStream_t s)
@@ -178,18 +253,30 @@ hipError_t hipMemsetAsync(void *dst, int v, size_t n, hipStream_t s)
     check_stream(s, "hipMemsetAsync on a destroyed stream");
     if (s && s->cap) die("hipMemsetAsync on a capturing stream");
     check_range(dst, n, "hipMemsetAsync outside a device allocation");
-    memset(dst, v, n);
+    if (n) pending_work().push_back(Pending{dst, nullptr, n, v});
     enqueue(s);
     return hipSuccess;
 }
 
-hipError_t hipDeviceSynchronize(void) { return hipSuccess; }
+hipError_t hipDeviceSynchronize(void)
+{
+    std::lock_guard<std::recursive_mutex> l(g_mu);
+    drain();
+    device_synced();
+    return hipSuccess;
+}
 
 hipError_t hipStreamSynchronize(hipStream_t s)
 {
     std::lock_guard<std::recursive_mutex> l(g_mu);
     check_stream(s, "hipStreamSynchronize on a destroyed stream");
     if (s && s->cap) die("hipStreamSynchronize on a capturing stream");
+    drain();
+    if (s) {
+        s->synced = s->ops;
+        for (hipGraphExec *x : live_execs())
+            if (x->launch_stream == s) x->launch_stream = nullptr;
+    }
     return hipSuccess;
 }
 
@@ -198,6 +285,7 @@ hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned)
     std::lock_guard<std::recursive_mutex> l(g_mu);
     ihipStream_t *q = new ihipStream_t();
     q->magic = STREAM_MAGIC;
+    live_streams().insert(q);
     *s = q;
     return hipSuccess;
 }
@@ -208,6 +296,10 @@ hipError_t hipStreamDestroy(hipStream_t s)
     check_stream(s, "hipStreamDestroy of a destroyed stream");
     if (!s) die("hipStreamDestroy of the default stream");
     if (s->cap) die("hipStreamDestroy of a capturing stream");
+    // launches on it not known complete stay unknown (the device still runs them)
+    for (hipGraphExec *x : live_execs())
+        if (x->launch_stream == s) { x->launch_stream = nullptr; x->unknown = true; }
+    live_streams().erase(s);
     s->magic = 0;
     delete s;
     return hipSuccess;
@@ -238,6 +330,12 @@ hipError_t hipEventSynchronize(hipEvent_t e)
     std::lock_guard<std::recursive_mutex> l(g_mu);
     check_event(e, "hipEventSynchronize of a destroyed event");
     if (e->cap) die("hipEventSynchronize of an event recorded in a capture");
+    drain();
+    if (e->src && live_streams().count(e->src)) {
+        if (e->src->synced < e->seq) e->src->synced = e->seq;
+        for (hipGraphExec *x : live_execs())
+            if (x->launch_stream == e->src && x->launch_ops <= e->seq) x->launch_stream = nullptr;
+    }
     return hipSuccess;
 }
 
@@ -277,6 +375,15 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned)
         // join: the source stream's work up to the record is now ordered before s
         if (e->src && e->src != s && e->seq == e->src->ops) e->src->joined_at = e->src->ops;
     }
+    return hipSuccess;
+}
+
+hipError_t hipStreamIsCapturing(hipStream_t s, hipStreamCaptureStatus *st)
+{
+    std::lock_guard<std::recursive_mutex> l(g_mu);
+    check_stream(s, "hipStreamIsCapturing on a destroyed stream");
+    if (!st) die("hipStreamIsCapturing with a null argument");
+    *st = (s && s->cap) ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
     return hipSuccess;
 }
 
@@ -326,6 +433,7 @@ hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, hipGraphNode_t *
     hipGraphExec *q = new hipGraphExec();
     q->magic = EXEC_MAGIC;
     q->nodes = g->nodes;
+    live_execs().insert(q);
     *x = q;
     return hipSuccess;
 }
@@ -343,6 +451,9 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t x)
 {
     std::lock_guard<std::recursive_mutex> l(g_mu);
     if (!x || x->magic != EXEC_MAGIC) die("hipGraphExecDestroy of a destroyed graph");
+    if (x->launch_stream || x->unknown)
+        die("hipGraphExecDestroy of a graph whose last launch is not known complete");
+    live_execs().erase(x);
     x->magic = 0;
     delete x;
     return hipSuccess;
@@ -354,7 +465,10 @@ hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s)
     if (!x || x->magic != EXEC_MAGIC) die("hipGraphLaunch of a destroyed graph");
     check_stream(s, "hipGraphLaunch on a destroyed stream");
     if (s && s->cap) die("hipGraphLaunch on a capturing stream");
+    if (!s) die("hipGraphLaunch on the default stream");
     enqueue(s);
+    x->launch_stream = s;
+    x->launch_ops = s->ops;
     return hipSuccess;
 }
 

@@ -42,6 +42,8 @@ typedef enum {
 
 typedef enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1,
                hipStreamCaptureModeRelaxed = 2 } hipStreamCaptureMode;
+typedef enum { hipStreamCaptureStatusNone = 0, hipStreamCaptureStatusActive = 1,
+               hipStreamCaptureStatusInvalidated = 2 } hipStreamCaptureStatus;
 
 #define hipStreamDefault 0u
 #define hipStreamNonBlocking 1u
@@ -66,6 +68,7 @@ hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned flags);
 hipError_t hipStreamDestroy(hipStream_t s);
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
+hipError_t hipStreamIsCapturing(hipStream_t s, hipStreamCaptureStatus *st);
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g);
 hipError_t hipEventCreate(hipEvent_t *e);
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned flags);
