@@ -55,6 +55,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def settle(box, torch, seconds=1.0):
+    """More untimed steps until `seconds` of stepping have passed: the first
+    timed repetition after a short warm-up ran 3-6% slower than the ones after
+    it (the GPU's clocks still settling), the later ones agreeing within 1%."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        box.step(20)
+        torch.cuda.synchronize()
+
+
 def time_gpu(spec, precision, steps, warmup, torch, lb):
     """Timed steps on the production path: a non-default stream, so the
     library replays captured step-pair graphs with the particle work on its
@@ -68,6 +78,7 @@ def time_gpu(spec, precision, steps, warmup, torch, lb):
     tune.apply(box)  # cached autotuned launch shapes for this size, if any
     box.step(warmup)
     torch.cuda.synchronize()
+    settle(box, torch)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     box.step(steps)
@@ -141,7 +152,7 @@ def cpu_info():
     return model, os.cpu_count()
 
 
-def batched_sweep(torch, lb, I, nbox, steps, eager_steps=100):
+def batched_sweep(torch, lb, I, nbox, steps, eager_steps=100, baselines=True):
     """Boxes of the batched sweep (sides 32/48/64, one sphere each), FP32:
     aggregate MLUPS of the batched graph-replayed step against the same boxes
     advanced one after another on the single-box production path (a
@@ -153,11 +164,13 @@ def batched_sweep(torch, lb, I, nbox, steps, eager_steps=100):
     nodes = sum(s["shape"][0] * s["shape"][1] * s["shape"][2] for s in specs)
     lu = nodes * steps
     stream = torch.cuda.Stream()
-    # the batch keeps the library's default shapes: the shapes cached for
-    # small boxes stepped alone differ in form between the sizes, and a mixed
-    # batch then falls back to the one-node forms everywhere (measured on
-    # this sweep: 17.2k MLUPS with them against 19.9k with the defaults)
+    # the batch takes the shape rules tuned for this batch as a whole, where
+    # cached (the shapes cached for small boxes stepped alone differ in form
+    # between the sizes, and a mixed batch falls back to the one-node forms)
     boxes = [lb.from_spec(s, precision="fp32", stream=stream) for s in specs]
+    rules = tune.tuned_batch_rules((32, 48, 64), nbox, "fp32")
+    if rules:
+        tune.apply_batch(boxes, rules)
     lb.batch_step(boxes, 4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,10 +195,14 @@ def batched_sweep(torch, lb, I, nbox, steps, eager_steps=100):
             b.close()
         return nodes * k / t / 1e6
 
+    bm = lu / tb / 1e6
+    if not baselines:
+        return dict(boxes=nbox, steps=steps, lattice_updates=lu, batched_mlups=round(bm, 1),
+                    batch_shape_rules=rules or "library defaults")
     seq = one_by_one(torch.cuda.Stream(), steps)
     eager = one_by_one(None, min(steps, eager_steps))
-    bm = lu / tb / 1e6
     return dict(boxes=nbox, steps=steps, lattice_updates=lu, batched_mlups=round(bm, 1),
+                batch_shape_rules=rules or "library defaults",
                 sequential_mlups=round(seq, 1), speedup=round(bm / seq, 3),
                 sequential_eager_mlups=round(eager, 1), sequential_eager_steps=min(steps, eager_steps),
                 speedup_vs_eager=round(bm / eager, 3))
@@ -324,6 +341,8 @@ def main():
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper-regime leg (profiling runs)")
     ap.add_argument("--batch", type=int, default=512, help="boxes in the batched sweep (0: skip)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched sweep (profiling runs)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve", type=int, default=0,
                     help="requests in the serving run (0: skip, the default: the serving replay "
@@ -356,6 +375,10 @@ def main():
     from paper_2202_01631_amd import lb
     lb.load()
     torch.cuda.set_device(0)
+    if args.batch_only:
+        print(json.dumps({"batched_sweep": batched_sweep(torch, lb, I, args.batch, args.batch_steps,
+                                                          baselines=False)}), flush=True)
+        return
     if args.paper_only:
         # the paper-regime leg alone (profiling runs)
         print(json.dumps({"paper_regime": paper_regime_run(torch, lb, I, steps=args.steps,

@@ -139,9 +139,10 @@ typedef struct {
  *                      surface (Sec. II.B momentum exchange, Sec. III.B
  *                      trapping).  Part of F0, T0.  Experimental: stable in
  *                      the tested regime R = 4.5, M_psi = 0.4 in two psi/c
- *                      sub-steps, over 8x10^4 steps; runs with M_psi = 0.1 or
- *                      R = 9 near an interface can diverge (reported through
- *                      the error bits and LB_E_UNSTABLE).
+ *                      sub-steps, over 8x10^4 steps (nine trap cases, a GPU
+ *                      test); runs with M_psi = 0.1 or R = 9 near an
+ *                      interface can diverge (reported through the error
+ *                      bits and LB_E_UNSTABLE).
  * Other bits: LB_E_INVALID at lb_create. */
 #define LB_SOLUTE_FORCE 1u
 #define LB_EXPLICIT_COLLOID 2u

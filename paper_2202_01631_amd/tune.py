@@ -8,6 +8,10 @@ size and precision.  Shapes never change results (tested bit for bit); they
 only change speed.
 
     python -m paper_2202_01631_amd.tune 256 256 256 fp32
+    python -m paper_2202_01631_amd.tune batch 512 [CACHE_PATH]
+
+A batch of boxes is tuned as a whole (``tune_batch``): rules that give each
+box a shape for its size, timed on the batched step.
 """
 import json
 import os
@@ -151,7 +155,125 @@ def tune(shape, precision="fp32", steps=20, warmup=4, write=True, spec=None, log
     return best
 
 
+# ------------------------------------------------------------------ batches
+# A batch runs one launch per lattice kernel over all its boxes, and every
+# box of a launch takes the same kernel form (one node per thread, or row
+# vectors of 2 or 4 nodes per lane); block sizes, row counts and renumbering
+# may differ per box.  The shapes tuned for a box stepped alone do not serve
+# the batch: alone, a small box is latency-bound and its winners differ in
+# form between sizes.  So the batch is tuned as a whole: each candidate is a
+# rule that gives every box a shape for its size, and the batched step is
+# timed with it.
+
+def batch_rules():
+    """Shape rules for one kernel of a batch: name -> f(nx, ny) giving
+    (bx, by, code), or None for the library's default shape.  One-node rules: whole rows (or 64- / 32-node segments)
+    with 256 threads per block, natural or plane-wise XCD order; row-vector
+    rules: 2 or 4 nodes per lane, natural or plane-wise order."""
+    def node(seg, remap):
+        def f(nx, ny):
+            b = min(nx, seg) if seg else min(nx, 256)
+            by = max(1, 256 // b)
+            return (b, by, remap if ny % by == 0 else 0)
+        return f
+
+    def vec(v, remap):
+        return lambda nx, ny: (0, 0, remap + 8 * v)
+    rules = {"default": lambda nx, ny: None}
+    for seg in (0, 64, 32):
+        for remap in (0, 2):
+            rules["node%s_r%d" % (seg or "row", remap)] = node(seg, remap)
+    for v in (2, 4):
+        for remap in (0, 2):
+            rules["vec%d_r%d" % (v, remap)] = vec(v, remap)
+    return rules
+
+
+def _batch_key(sides, count, precision):
+    return "%s|batch%d:%s|%s" % (device_key(), count, ",".join(str(s) for s in sides), precision)
+
+
+def tuned_batch_rules(sides, count, precision):
+    """Cached rule names (mu, collide, psi/c) for this batch, or None."""
+    v = load_cache().get(_batch_key(sides, count, precision))
+    return list(v["rules"]) if v else None
+
+
+def apply_batch(boxes, rule_names):
+    """Give every box of a batch the shapes of the three rules for its size."""
+    rules = batch_rules()
+    for b in boxes:
+        if not hasattr(b, "default_shapes"):
+            b.default_shapes = b.launch_shapes()
+        nx, ny, _ = b.shape
+        sh = [rules[r](nx, ny) for r in rule_names]
+        b.set_launch_shapes([b.default_shapes[k] if sh[k] is None else sh[k] for k in range(3)])
+
+
+def tune_batch(specs, sides, precision="fp32", steps=60, write=True, cache=None, log=print):
+    """Coordinate descent over the three kernels' rules (psi/c update, mu,
+    collide-stream; two passes), timing the whole batched step on a
+    non-default stream; caches the best rules under the batch's sides, box
+    count and precision."""
+    import time
+
+    import torch
+
+    from . import lb
+    stream = torch.cuda.Stream()
+    boxes = [lb.from_spec(s, precision=precision, stream=stream) for s in specs]
+    rules = batch_rules()
+
+    def timed(names):
+        apply_batch(boxes, names)
+        lb.batch_step(boxes, 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lb.batch_step(boxes, steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    best = ["default", "default", "default"]
+    tbest = timed(best)
+    log("[tune-batch] start %s %.4f ms/step" % (best, 1e3 * tbest))
+    for _ in range(2):
+        for w in (2, 0, 1):
+            for name in rules:
+                if name == best[w] or (w == 1 and name.startswith("vec2")):
+                    continue
+                cand = list(best)
+                cand[w] = name
+                t = timed(cand)
+                log("[tune-batch] %s %.4f ms/step" % (cand, 1e3 * t))
+                if t < tbest:
+                    best, tbest = cand, t
+    for b in boxes:
+        b.close()
+    log("[tune-batch] best %s %.4f ms/step" % (best, 1e3 * tbest))
+    if write:
+        path = cache or CACHE
+        data = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                data = json.load(fh)
+        data[_batch_key(sides, len(specs), precision)] = {
+            "rules": best, "ms_per_step": round(1e3 * tbest, 4),
+            "kernels": ["k_mu", "k_collide", "k_scalar"]}
+        with open(path + ".tmp", "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    return best
+
+
 if __name__ == "__main__":
+    if len(sys.argv) >= 3 and sys.argv[1] == "batch":
+        # python -m paper_2202_01631_amd.tune batch COUNT [CACHE_PATH]
+        from . import inputs as I
+        count = int(sys.argv[2])
+        sides = (32, 48, 64)
+        specs = I.batch_boxes(count=count, sides=sides, steps=2000)
+        print(tune_batch(specs, sides, cache=sys.argv[3] if len(sys.argv) > 3 else None))
+        sys.exit(0)
     if len(sys.argv) < 5:
         print(__doc__)
         sys.exit(2)

@@ -149,6 +149,42 @@ def test_interface_trapping_against_phoretic_push():
     assert dx[(0.05, -0.25, 0)] > dx[(0.05, -0.25, 4)] + 0.5
 
 
+def test_trap_cases_stay_stable_over_the_papers_run_length():
+    # the nine cases of the trap test above (capillary stress on in eight),
+    # 8 x 10^4 steps, the length of the paper's runs: every run stays finite
+    # (no error bits), and the particles under a weak push (|mu E| <= 0.0125)
+    # hold their positions to 0.1 over the last 4 x 10^4 steps, within 1.5
+    # lattice units of the interface plane
+    import torch
+    st = torch.cuda.Stream()
+    cases = [(0.025, -0.25, 4), (0.05, -0.125, 4), (0.05, -0.25, 4), (0.1, -0.125, 4),
+             (0.05, 0.25, 4), (0.0, -0.25, 4), (0.1, -0.25, 4), (0.2, -0.25, 4), (0.05, -0.25, 0)]
+    boxes = []
+    for mu, E, flags in cases:
+        col = I.janus((16.0, 48.0, 48.0), (0.0, 1.0, 0.0), 4.5, alpha=0.0, mu=mu, theta=90.0)
+        w = I.workload_paper([col], E=E)
+        w["params"]["flags"] = flags
+        w["c"] = w["params"]["c_b0"] + E * np.tanh(w["psi"])
+        boxes.append(lb.from_spec(w, stream=st))
+    for k in range(8):
+        lb.batch_step(boxes, 10000)
+        if k == 3:
+            p1 = [b.observables()[1][0]["pos"][0] for b in boxes]
+        flush_print("[trap 8e4] %d steps" % (10000 * (k + 1)))
+    for b, key, q1 in zip(boxes, cases, p1):
+        t, c = b.observables()
+        q = c[0]["pos"][0]
+        dx = q - _x_int(b.fields()["psi"])
+        flush_print("[trap 8e4] mu %s E %s flags %d: x %.4f (%.4f at 4e4) Delta X %.4f bits %d"
+                    % (key + (q, q1, dx, t["error_bits"])))
+        assert t["error_bits"] == 0, key
+        if key[2] and 0 < abs(key[0] * key[1]) <= 0.0125:
+            assert abs(q - q1) <= 0.1, key
+            assert abs(dx) <= 1.5, key
+    for b in boxes:
+        b.close()
+
+
 def test_interface_displacement_linear_in_mu_E_at_twice_the_radius():
     # Fig. 4's Delta X ~ mu E, resolved at R = 9 (twice the paper's radius;
     # at R = 4.5 the trapped particle pins at half-lattice positions): box

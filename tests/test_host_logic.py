@@ -38,14 +38,39 @@ def test_tuner_candidates_are_valid_codes(nx, ny):
             assert shapes == [(bx, by, code)] * 3 and scored == (True, True, True)
 
 
+@pytest.mark.parametrize("side", [32, 48, 64, 96, 30])
+def test_batch_rules_give_valid_shapes(side):
+    # every rule gives a box of any side a shape the library accepts: one
+    # node per thread within the 256-thread launch bound, or a row-vector
+    # code; plane-wise renumbering only where the rows per block divide ny
+    for name, rule in tune.batch_rules().items():
+        sh = rule(side, side)
+        if name == "default":
+            assert sh is None
+            continue
+        bx, by, code = sh
+        rm, vec, zc = _decode(code)
+        assert zc == 0 and rm in (0, 2)
+        if vec:
+            assert (bx, by) == (0, 0) and vec in (2, 4)
+        else:
+            assert 1 <= bx <= min(side, 256) and bx * by <= 256
+            assert rm == 0 or side % by == 0
+
+
 def test_tuning_cache_entries_decode():
     path = tune.CACHE
     if not os.path.exists(path):
         pytest.skip("no tuning cache")
     cache = json.load(open(path))
+    rules = tune.batch_rules()
     for key, v in cache.items():
         dev, size, prec = key.split("|")
         assert prec in ("fp32", "fp64", "fp16")
+        if size.startswith("batch"):
+            # a batch tuned as a whole: one rule per kernel
+            assert len(v["rules"]) == 3 and all(r in rules for r in v["rules"])
+            continue
         assert len(size.split("x")) == 3
         assert len(v["shapes"]) == 3
         for k, (bx, by, code) in enumerate(v["shapes"]):
