@@ -155,14 +155,71 @@ static void disp(const or_ctx *c, const or_colloid *k, int x, int y, int z,
     r[2] = min_image(((double)z + s * (double)CZ[i]) - k->pos[2], c->nz);
 }
 
-/* a node is solid when it lies strictly inside the sphere (Sec. II.B) */
+/* option: a spheroid with semi-axis `axial` along m and `radius` across it
+ * (reading: the local surface rules of the model carry over to particles of
+ * other shapes, Sec. IV; the spheroid is the shape whose orientation is the
+ * axis m the particle already carries).  Spheres keep their own arithmetic. */
+static int spheroid(const or_colloid *k)
+{
+    return k->axial > 0.0 && k->axial != k->radius;
+}
+
+/* r split into its part s along m and the rest p across it */
+static void split_axis(const or_colloid *k, const double r[3], double *s, double p[3])
+{
+    double t = k->m[0] * r[0] + k->m[1] * r[1];
+    t = t + k->m[2] * r[2];
+    *s = t;
+    for (int a = 0; a < 3; a++) p[a] = r[a] - t * k->m[a];
+}
+
+/* a node is solid when it lies strictly inside the particle (Sec. II.B):
+ * |r|^2 < R^2, or for a spheroid s^2/a^2 + |p|^2/b^2 < 1, multiplied out */
 static int inside(const or_ctx *c, const or_colloid *k, int x, int y, int z)
 {
     double r[3], d2;
     disp(c, k, x, y, z, 0, 0.0, r);
+    if (spheroid(k)) {
+        double sa, p[3];
+        split_axis(k, r, &sa, p);
+        double pp = p[0] * p[0] + p[1] * p[1];
+        pp = pp + p[2] * p[2];
+        const double a2 = k->axial * k->axial, b2 = k->radius * k->radius;
+        return sa * sa * b2 + pp * a2 < a2 * b2;
+    }
     d2 = r[0] * r[0] + r[1] * r[1];
     d2 = d2 + r[2] * r[2];
     return d2 < k->radius * k->radius;
+}
+
+/* outward unit normal for the surface point seen at r from the centre
+ * (R9): r/|r| on a sphere; on a spheroid the gradient of
+ * s^2/a^2 + |p|^2/b^2, i.e. s m / a^2 + p / b^2, normalised */
+static void surface_normal(const or_colloid *k, const double r[3], double n[3])
+{
+    if (!spheroid(k)) {
+        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        for (int a = 0; a < 3; a++) n[a] = r[a] / rn;
+        return;
+    }
+    double sa, p[3], g[3];
+    split_axis(k, r, &sa, p);
+    const double a2 = k->axial * k->axial, b2 = k->radius * k->radius;
+    for (int a = 0; a < 3; a++) g[a] = (sa / a2) * k->m[a] + p[a] / b2;
+    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int a = 0; a < 3; a++) n[a] = g[a] / gn;
+}
+
+/* |e.n| for the lattice axis ax at the surface point seen at r */
+static double axis_cos(const or_colloid *k, const double r[3], int ax)
+{
+    if (!spheroid(k)) {
+        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        return fabs(r[ax]) / rn;
+    }
+    double n[3];
+    surface_normal(k, r, n);
+    return fabs(n[ax]);
 }
 
 /* active hemisphere of Eqs. 5-6: m.n <= 0, n taken at the link midpoint */
@@ -468,6 +525,10 @@ int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
             return fail(c, OR_E_INVALID, "cap_cos must lie in [-1, 1]");
         if (q.H != 0.0 && !(c->p.kappa > 0.0))
             return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
+        if (!(q.axial >= 0.0) || !isfinite(q.axial))
+            return fail(c, OR_E_INVALID, "axial semi-axis must be finite and >= 0");
+        if (spheroid(&q) && (c->p.soft_eps > 0.0 || c->p.lub_hc > 0.0))
+            return fail(c, OR_E_INVALID, "soft-sphere and lubrication forces need spheres");
         if (q.pat_bands < 0 || q.pat_bands > OR_PATTERN_MAX_BANDS)
             return fail(c, OR_E_INVALID, "pattern bands in [0, 8]");
         if (q.pat_bands > 0) {
@@ -482,8 +543,9 @@ int or_add_colloids(or_ctx *c, const or_colloid *cols, int32_t n)
                 if (q.pat_H[i] != 0.0 && !(c->p.kappa > 0.0))
                     return fail(c, OR_E_INVALID, "wetting needs kappa > 0");
         }
+        const double rb = q.axial > q.radius ? q.axial : q.radius;  /* bounding radius */
         for (int a = 0; a < 3; a++) {
-            if (2.0 * q.radius + 4.0 > (double)L[a])
+            if (2.0 * rb + 4.0 > (double)L[a])
                 return fail(c, OR_E_INVALID, "colloid does not fit in the box");
             q.m[a] /= mm;
             /* positions are kept in [0, L) */
@@ -560,8 +622,7 @@ static void chemical_potential(or_ctx *c)
             } else {
                 double r[3];
                 disp(c, &c->col[k], x, y, z, e, 0.5, r);
-                double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-                double en = fabs(r[(e - 1) / 2]) / rn;
+                double en = axis_cos(&c->col[k], r, (e - 1) / 2);
                 double ghost = c->psi[n];
                 if (p->kappa > 0.0)
                     ghost = c->psi[n] - (cell_H(&c->col[k], surface_cell(&c->col[k], r)) / p->kappa) * en;
@@ -602,8 +663,7 @@ static void stress(const or_ctx *c, long n, double P[3][3])
         } else {
             double r[3];
             disp(c, &c->col[k], x, y, z, e, 0.5, r);
-            double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-            double en = fabs(r[(e - 1) / 2]) / rn;
+            double en = axis_cos(&c->col[k], r, (e - 1) / 2);
             ph[e] = c->psi[n];
             if (p->kappa > 0.0)
                 ph[e] = c->psi[n] - (cell_H(&c->col[k], surface_cell(&c->col[k], r)) / p->kappa) * en;
@@ -706,8 +766,7 @@ static void collide_stream(or_ctx *c)
         coords(c, n, &x, &y, &z);
         double r[3], nh[3], g[3], slip[3], ur[3], ub[3];
         disp(c, q, x, y, z, d, 0.5, r);
-        double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-        for (int a = 0; a < 3; a++) nh[a] = r[a] / rn;
+        surface_normal(q, r, nh);
         /* phoretic slip (Eq. 4) with the Janus mobility of Eq. 6 */
         double mob = cell_mu(q, c->lcap[l]);
         for (int a = 0; a < 3; a++) {
@@ -866,6 +925,47 @@ static void solve6(double A[36], double b[6], double x[6])
     }
 }
 
+/* A spheroid's step: mass m = rho_p 4 pi a b^2 / 3, inertia tensor
+ * I = I_perp 1 + (I_par - I_perp) m m^T about the centre with I_par =
+ * 2 m b^2 / 5 about the axis and I_perp = m (a^2 + b^2) / 5 across it, taken
+ * at the axis of the start of the step (the gyroscopic term, second order
+ * in Omega, is left out); the same implicit (or explicit) update as a
+ * sphere's with M = diag(m, m, m, I). */
+static void spheroid_update(const or_colloid *q, const double Z[36], const double Fk[6],
+                            const double X[6], int expl, double Xn[6])
+{
+    const double a = q->axial, b = q->radius;
+    const double mass = q->rho_p * (4.0 * M_PI / 3.0) * a * b * b;
+    const double ipar = 0.4 * mass * b * b, iperp = 0.2 * mass * (a * a + b * b);
+    double M[36];
+    for (int i = 0; i < 36; i++) M[i] = 0.0;
+    for (int i = 0; i < 3; i++) M[6 * i + i] = mass;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            M[6 * (3 + i) + 3 + j] = (i == j ? iperp : 0.0) + (ipar - iperp) * q->m[i] * q->m[j];
+    if (expl) {
+        /* M X' = M X + F0 - zeta X: X' = X + M^-1 (F0 - zeta X), with
+         * I^-1 = 1/I_perp + (1/I_par - 1/I_perp) m m^T */
+        double s[6];
+        for (int i = 0; i < 6; i++) {
+            s[i] = Fk[i];
+            for (int j = 0; j < 6; j++) s[i] -= Z[6 * i + j] * X[j];
+        }
+        for (int i = 0; i < 3; i++) Xn[i] = X[i] + s[i] / mass;
+        const double ms = q->m[0] * s[3] + q->m[1] * s[4] + q->m[2] * s[5];
+        for (int i = 0; i < 3; i++)
+            Xn[3 + i] = X[3 + i] + s[3 + i] / iperp + (1.0 / ipar - 1.0 / iperp) * q->m[i] * ms;
+        return;
+    }
+    double A[36], bv[6];
+    for (int i = 0; i < 36; i++) A[i] = Z[i] + M[i];
+    for (int i = 0; i < 6; i++) {
+        bv[i] = Fk[i];
+        for (int j = 0; j < 6; j++) bv[i] += M[6 * i + j] * X[j];
+    }
+    solve6(A, bv, Xn);
+}
+
 /* step 4: rigid-body update, implicit in the link drag (Nguyen and Ladd):
  * (M + zeta) X' = M X + (F0, T0), X = (V, Omega); R' = R + V';
  * m' = m rotated by the angle |Omega'| about Omega' (Rodrigues). */
@@ -888,7 +988,9 @@ static void colloid_update(or_ctx *c)
             double mass = q->rho_p * (4.0 * M_PI / 3.0) * q->radius * q->radius * q->radius;
             double inertia = 0.4 * mass * q->radius * q->radius;
             double Mv[6] = {mass, mass, mass, inertia, inertia, inertia};
-            if (expl) {
+            if (spheroid(q)) {
+                spheroid_update(q, Z, Fk, X, expl, Xn);
+            } else if (expl) {
                 /* option: explicit update (Ladd), M X' = M X + F0 - zeta X */
                 for (int i = 0; i < 6; i++) {
                     double s = Fk[i];

@@ -90,6 +90,9 @@ typedef struct {
         pat_H[OR_PATTERN_MAX_CELLS];  /* per cell b * sectors + s: production per link
                                          (Eq. 5), phoretic mobility (Eq. 6) and wetting
                                          parameter (Eqs. 8-9) */
+    double axial;                /* shape: semi-axis along m of a spheroid whose other two
+                                    semi-axes are `radius` (0, or equal to radius: a
+                                    sphere) */
 } or_colloid;
 
 typedef struct {

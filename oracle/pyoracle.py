@@ -57,7 +57,7 @@ class Colloid(C.Structure):
                 ("pat_cos", C.c_double * (PATTERN_MAX_BANDS - 1)),
                 ("pat_alpha", C.c_double * PATTERN_MAX_CELLS),
                 ("pat_mu", C.c_double * PATTERN_MAX_CELLS),
-                ("pat_H", C.c_double * PATTERN_MAX_CELLS)]
+                ("pat_H", C.c_double * PATTERN_MAX_CELLS), ("axial", C.c_double)]
 
 
 class Totals(C.Structure):
@@ -149,6 +149,7 @@ def make_colloid(d):
         setattr(q, key, float(d.get(key, 1.0 if key == "rho_p" else 0.0)))
     q.fixed = int(d.get("fixed", 0))
     q.cap_cos = float(d.get("cap_cos", 0.0))
+    q.axial = float(d.get("axial", 0.0))
     for a in range(3):
         q.e[a] = float(d.get("e", (0.0, 0.0, 0.0))[a])
     pat = d.get("pattern")
@@ -169,6 +170,7 @@ def colloid_dict(q):
     d["fixed"] = q.fixed
     d["cap_cos"] = q.cap_cos
     d["e"] = np.array(q.e[:])
+    d["axial"] = q.axial
     return d
 
 
