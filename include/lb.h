@@ -183,6 +183,17 @@ typedef struct {                 /* FP64, caller-owned */
     double pattern_cos[LB_PATTERN_MAX_BANDS - 1];
     double pattern_alpha[LB_PATTERN_MAX_CELLS], pattern_mu[LB_PATTERN_MAX_CELLS],
         pattern_H[LB_PATTERN_MAX_CELLS];
+    double axial;                    /* shape (Sec. IV, particles of other shapes): semi-axis
+                                        along m of a spheroid whose other semi-axes are
+                                        `radius`; 0 or equal to radius: a sphere.  A spheroid
+                                        is solid where s^2 b^2 + |p|^2 a^2 < a^2 b^2 (s = m.r,
+                                        p = r - s m, a = axial, b = radius, FP64 without
+                                        contraction), its normal for the slip (Eq. 4) and the
+                                        wetting ghost (Eq. 9) is s m / a^2 + p / b^2
+                                        normalised, its mass rho_p 4 pi a b^2 / 3 and its
+                                        inertia tensor 2 m b^2 / 5 about m, m (a^2 + b^2) / 5
+                                        across it.  LB_E_INVALID if negative or not finite,
+                                        or together with soft-sphere or lubrication forces */
 } lb_colloid;
 
 typedef struct {

@@ -95,7 +95,7 @@ struct lb_ctx {
     // single phase: a = b = kappa = E = c_b0 = 0 and psi = 0 at init, so mu
     // is 0 and chi is c at every step (set by lb_init_fields)
     bool nopsi;
-    bool pattern;       // some particle carries a surface pattern
+    bool special;       // some particle carries a surface pattern or is not a sphere
     std::string err;
 };
 
@@ -220,8 +220,8 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
     // single-phase batch (every box): no mu launches, single-phase kernels
     B.nopsi = n > 0;
     for (int j = 0; j < n; j++) B.nopsi = B.nopsi && ctxs[j]->nopsi;
-    B.pattern = 0;
-    for (int j = 0; j < n; j++) B.pattern |= (ctxs[j]->pattern && ctxs[j]->ncol > 0) ? 1 : 0;
+    B.special = 0;
+    for (int j = 0; j < n; j++) B.special |= (ctxs[j]->special && ctxs[j]->ncol > 0) ? 1 : 0;
     if (B.nopsi) {
         // single-phase kernels exist in the one-node collide-stream and the
         // one-node and row-vector psi/c updates: other forms drop to those
@@ -558,9 +558,9 @@ struct StateHeader {
     int32_t nx, ny, nz, precision, ncol, lcap;
     int64_t step;
 };
-// (the last byte counts layouts of the particle record: "2" has the second
-// body axis and the surface pattern)
-static const uint64_t STATE_MAGIC = 0x4c42504852534132ull;
+// (the last byte counts layouts of the particle record: "3" has the second
+// body axis, the surface pattern and the spheroid's semi-axis)
+static const uint64_t STATE_MAGIC = 0x4c42504852534133ull;
 
 static size_t state_size(lb_ctx *c)
 {
@@ -778,7 +778,7 @@ static void free_colloids(lb_ctx *c)
     c->ccount = nullptr;
     c->ncol = 0;
     c->lcap = 0;
-    c->pattern = false;
+    c->special = false;
     c->dirty = true;  // descriptors hold the particle-table pointers
 }
 
@@ -911,6 +911,12 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
             return fail(c, LB_E_INVALID, "particle radius, density and axis must be positive");
         if (q.H != 0.0 && !(c->p.kappa > 0.0)) return fail(c, LB_E_INVALID, "wetting needs kappa > 0");
         if (!(q.cap_cos >= -1.0 && q.cap_cos <= 1.0)) return fail(c, LB_E_INVALID, "cap_cos must lie in [-1, 1]");
+        if (!(q.axial >= 0.0) || !std::isfinite(q.axial))
+            return fail(c, LB_E_INVALID, "axial semi-axis must be finite and >= 0");
+        const bool sph = q.axial > 0.0 && q.axial != q.radius;
+        if (sph && (c->p.soft_eps > 0.0 || c->p.lub_hc > 0.0))
+            return fail(c, LB_E_INVALID, "soft-sphere and lubrication forces need spheres");
+        const double rb = q.axial > q.radius ? q.axial : q.radius;
         if (q.pattern_bands < 0 || q.pattern_bands > LB_PATTERN_MAX_BANDS)
             return fail(c, LB_E_INVALID, "pattern bands must lie in [0, 8]");
         if (q.pattern_bands > 0) {
@@ -938,7 +944,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
             }
         }
         for (int a = 0; a < 3; a++) {
-            if (2.0 * q.radius + 8.0 > (double)Ls[a])
+            if (2.0 * rb + 8.0 > (double)Ls[a])
                 return fail(c, LB_E_INVALID, "particle too large for the box (2 R + 8 > side)");
             if (!std::isfinite(q.pos[a]) || !std::isfinite(q.vel[a]) || !std::isfinite(q.omega[a]))
                 return fail(c, LB_E_INVALID, "non-finite particle state");
@@ -958,6 +964,15 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
         d.rho_p = q.rho_p;
         d.mass = q.rho_p * (4.0 * M_PI / 3.0) * q.radius * q.radius * q.radius;
         d.inertia = 0.4 * d.mass * q.radius * q.radius;
+        if (sph) {
+            // spheroid: mass rho_p 4 pi a b^2 / 3, 2 m b^2 / 5 about the axis,
+            // m (a^2 + b^2) / 5 across it
+            const double a = q.axial, b = q.radius;
+            d.axial = a;
+            d.mass = q.rho_p * (4.0 * M_PI / 3.0) * a * b * b;
+            d.ipar = 0.4 * d.mass * b * b;
+            d.iperp = 0.2 * d.mass * (a * a + b * b);
+        }
         d.fixed = q.fixed ? 1 : 0;
         d.capc = q.cap_cos;
         {
@@ -986,7 +1001,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
             for (int a = 0; a < 3; a++) d.e[a] = ev[a] / ne;
         }
         d.changed = 1;  // build the owner map and link table on placement
-        rmax = std::max(rmax, q.radius);
+        rmax = std::max(rmax, rb);
     }
     // surfaces at least 2 lattice units apart (minimum image)
     for (int i = 0; i < n; i++)
@@ -996,7 +1011,8 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
                 double d = min_image(h[i].pos[a] - h[j].pos[a], Ls[a]);
                 s2 += d * d;
             }
-            if (sqrt(s2) < h[i].radius + h[j].radius + 2.0)
+            // (spheroids by their bounding spheres)
+            if (sqrt(s2) < bound_radius(h[i]) + bound_radius(h[j]) + 2.0)
                 return fail(c, LB_E_STATE, "particle surfaces closer than 2 lattice units");
         }
     free_colloids(c);
@@ -1013,7 +1029,7 @@ lb_status lb_add_colloids(lb_ctx *c, const lb_colloid *cols, int32_t n)
     }
     HIP_TRY(c, hipMemcpyAsync(c->dcol, h.data(), sizeof(DColloid) * n, hipMemcpyHostToDevice, c->stream));
     c->ncol = n;
-    for (int k = 0; k < n; k++) c->pattern = c->pattern || h[k].pb > 0;
+    for (int k = 0; k < n; k++) c->special = c->special || h[k].pb > 0 || is_spheroid(h[k]);
     c->dirty = true;
     {
         lb_status st = refresh_self(c);
@@ -1195,6 +1211,7 @@ lb_status lb_observables(lb_ctx *c, lb_totals *t, lb_colloid *out, int32_t n)
             q.rho_p = d.rho_p;
             q.fixed = d.fixed;
             q.cap_cos = d.capc;
+            q.axial = d.axial;
             for (int a = 0; a < 3; a++) q.e[a] = d.e[a];
             q.pattern_bands = d.pb;
             q.pattern_sectors = d.ps;
@@ -1367,8 +1384,8 @@ lb_status lb_load_state(lb_ctx *c, const void *buf, size_t n)
                     sizeof(DColloid) * hd.ncol)
             return fail(c, LB_E_INVALID, "state too short");
         double rmax = 0.0;
-        for (int k = 0; k < hd.ncol; k++) rmax = std::max(rmax, hc[k].radius);
-        for (int k = 0; k < hd.ncol; k++) c->pattern = c->pattern || hc[k].pb > 0;
+        for (int k = 0; k < hd.ncol; k++) rmax = std::max(rmax, bound_radius(hc[k]));
+        for (int k = 0; k < hd.ncol; k++) c->special = c->special || hc[k].pb > 0 || is_spheroid(hc[k]);
         lb_status st = alloc_colloid_tables(c, rmax, hd.lcap);
         if (st != LB_OK) { free_colloids(c); c->ncol = 0; return st; }
     }

@@ -131,6 +131,8 @@ struct DColloid {
     int pb, ps;                // surface pattern: bands (0: none), sectors
     double pcos[LB_PATTERN_MAX_BANDS - 1];  // band cuts in m.n, increasing
     double palpha[LB_PATTERN_MAX_CELLS], pmu[LB_PATTERN_MAX_CELLS], pH[LB_PATTERN_MAX_CELLS];
+    double axial;              // spheroid: semi-axis along m (0 or radius: a sphere)
+    double ipar, iperp;        // spheroid: moments of inertia about m and across it
 };
 
 // -------------------------------------------------------- particle geometry
@@ -155,15 +157,58 @@ __host__ __device__ inline void displacement(const DColloid &q, int x, int y, in
     r[2] = min_image(((double)z + s * (double)ez) - q.pos[2], nz);
 }
 
-// strictly inside the sphere
+// a spheroid (semi-axis axial along m, radius across it); spheres keep
+// their own arithmetic
+__host__ __device__ inline bool is_spheroid(const DColloid &q)
+{
+    return q.axial > 0.0 && q.axial != q.radius;
+}
+
+// half-width of the particle's bounding box
+__host__ __device__ inline double bound_radius(const DColloid &q)
+{
+    return q.axial > q.radius ? q.axial : q.radius;
+}
+
+// r split into its part s along m and the rest p across it
+__host__ __device__ inline double split_axis(const DColloid &q, const double r[3], double p[3])
+{
+#pragma clang fp contract(off)
+    double s = q.m[0] * r[0] + q.m[1] * r[1];
+    s = s + q.m[2] * r[2];
+    for (int a = 0; a < 3; a++) p[a] = r[a] - s * q.m[a];
+    return s;
+}
+
+// strictly inside the particle: |r|^2 < R^2, or s^2 b^2 + |p|^2 a^2 < a^2 b^2
 __host__ __device__ inline bool inside(const DColloid &q, int x, int y, int z, int nx, int ny, int nz)
 {
 #pragma clang fp contract(off)
     double r[3];
     displacement(q, x, y, z, 0, 0, 0, 0.0, nx, ny, nz, r);
+    if (is_spheroid(q)) {
+        double p[3];
+        const double s = split_axis(q, r, p);
+        double pp = p[0] * p[0] + p[1] * p[1];
+        pp = pp + p[2] * p[2];
+        const double a2 = q.axial * q.axial, b2 = q.radius * q.radius;
+        return s * s * b2 + pp * a2 < a2 * b2;
+    }
     double d2 = r[0] * r[0] + r[1] * r[1];
     d2 = d2 + r[2] * r[2];
     return d2 < q.radius * q.radius;
+}
+
+// outward unit normal of a spheroid for the surface point seen at r: the
+// gradient s m / a^2 + p / b^2 of its implicit function, normalised
+__host__ __device__ inline void spheroid_normal(const DColloid &q, const double r[3], double n[3])
+{
+    double p[3], g[3];
+    const double s = split_axis(q, r, p);
+    const double a2 = q.axial * q.axial, b2 = q.radius * q.radius;
+    for (int a = 0; a < 3; a++) g[a] = (s / a2) * q.m[a] + p[a] / b2;
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int a = 0; a < 3; a++) n[a] = g[a] / gn;
 }
 
 // active hemisphere m.n <= 0, n through the link midpoint (Eqs. 5-6)

@@ -64,8 +64,9 @@ struct Batch {
     int nsub;         // psi/c sub-steps per step (all boxes of the batch)
     int soft;         // some box has soft-sphere repulsion (k_soft runs)
     int nopsi;        // every box single phase: no mu launches, single-phase kernels
-    int pattern;      // some particle carries a surface pattern: boundary nodes always
-                      // in the fix-up launches (the inline forms have no cell arithmetic)
+    int special;      // some particle carries a surface pattern or is not a sphere:
+                      // boundary nodes always in the fix-up launches (the inline forms
+                      // have neither the cell arithmetic nor the spheroid normal)
     // with nsub > 1: descriptor tables of sub-step 0 (state at t -> its
     // target), next-state -> scratch and scratch -> next-state psi/c pairs
     const BoxDesc *dsub[3];

@@ -89,10 +89,10 @@ __device__ __forceinline__ void st_interior(S *base, unsigned on, const SVec<S, 
 
 // psi value the Laplacian takes across face e (x+, x-, y+, y-, z+, z-) of
 // fluid node (x, y, z): the neighbour's, or the wetting ghost at a solid one.
-// PAT = false: no particle of the box has a surface pattern (the forms that
-// treat boundary nodes inside the bulk launches; boxes with patterns take
-// the boundary fix-up launches, and these forms stay free of the cell
-// arithmetic and its registers).
+// PAT = false: no particle of the box has a surface pattern or another
+// shape than a sphere (the forms that treat boundary nodes inside the bulk
+// launches; boxes with such particles take the boundary fix-up launches, and
+// these forms stay free of that arithmetic and its registers).
 template <class S, bool PAT = true>
 __device__ __forceinline__ S face_psi(const KParams &p, const DColloid *__restrict__ col,
                                       uint8_t onb, int e, int x, int y, int z, S ps, S pv)
@@ -105,8 +105,15 @@ __device__ __forceinline__ S face_psi(const KParams &p, const DColloid *__restri
     const int ax = e >> 1, sg = (e & 1) ? -1 : 1;
     displacement(q, x, y, z, ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0, 0.5, p.nx, p.ny,
                  p.nz, r);
-    const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    const double en = fabs(r[ax]) / rn;
+    double en;
+    if (PAT && is_spheroid(q)) {
+        double n[3];
+        spheroid_normal(q, r, n);
+        en = fabs(n[ax]);
+    } else {
+        const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        en = fabs(r[ax]) / rn;
+    }
     const double H = (PAT && q.pb > 0) ? q.pH[surface_cell(q, r)] : q.H;
     const double gh = p.kappa > 0.0 ? (H / p.kappa) * en : 0.0;
     return ps - (S)gh;
@@ -1440,8 +1447,13 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
         // surface cell from the current axes (the table is rebuilt only on
         // owner changes)
         const int cell = surface_cell(q, r);
-        const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-        const double nh[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+        double nh[3];
+        if (is_spheroid(q)) {
+            spheroid_normal(q, r, nh);
+        } else {
+            const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            for (int a = 0; a < 3; a++) nh[a] = r[a] / rn;
+        }
         // grad c at the fluid node, c(x) substituted at solid neighbours
         const int sy = p.nx, sz = p.nx * p.ny;
         const int fn[6] = {n - x + wrap_p(x, p.nx), n - x + wrap_m(x, p.nx),
@@ -1488,6 +1500,57 @@ __global__ __launch_bounds__(LINK_THREADS) void k_link_partial(BatchArgs A)
 }
 
 // ------------------------------------------------------ k_colloid_update
+// A X = b by Gaussian elimination without pivoting (M + zeta is symmetric
+// positive definite)
+__device__ void solve6(double A[36], double bb[6], double Xn[6])
+{
+    for (int c = 0; c < 6; c++)
+        for (int i = c + 1; i < 6; i++) {
+            const double l = A[6 * i + c] / A[6 * c + c];
+            for (int j = c; j < 6; j++) A[6 * i + j] -= l * A[6 * c + j];
+            bb[i] -= l * bb[c];
+        }
+    for (int i = 5; i >= 0; i--) {
+        double s = bb[i];
+        for (int j = i + 1; j < 6; j++) s -= A[6 * i + j] * Xn[j];
+        Xn[i] = s / A[6 * i + i];
+    }
+}
+
+// A spheroid's step: M = diag(m, m, m, I), I = I_perp 1 + (I_par - I_perp)
+// m m^T at the axis of the start of the step (the gyroscopic term, second
+// order in Omega, left out); implicit (M + zeta) X' = M X + F, or explicit
+// X' = X + M^-1 (F - zeta X) with I^-1 = 1/I_perp + (1/I_par - 1/I_perp) m m^T
+__device__ void spheroid_step(const DColloid &q, const double Z[36], const double Fk[6],
+                              const double X[6], bool expl, double Xn[6])
+{
+    double M[36];
+    for (int i = 0; i < 36; i++) M[i] = 0.0;
+    for (int i = 0; i < 3; i++) M[6 * i + i] = q.mass;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            M[6 * (3 + i) + 3 + j] = (i == j ? q.iperp : 0.0) + (q.ipar - q.iperp) * q.m[i] * q.m[j];
+    if (expl) {
+        double s[6];
+        for (int i = 0; i < 6; i++) {
+            s[i] = Fk[i];
+            for (int j = 0; j < 6; j++) s[i] -= Z[6 * i + j] * X[j];
+        }
+        for (int i = 0; i < 3; i++) Xn[i] = X[i] + s[i] / q.mass;
+        const double ms = q.m[0] * s[3] + q.m[1] * s[4] + q.m[2] * s[5];
+        for (int i = 0; i < 3; i++)
+            Xn[3 + i] = X[3 + i] + s[3 + i] / q.iperp + (1.0 / q.ipar - 1.0 / q.iperp) * q.m[i] * ms;
+        return;
+    }
+    double A[36], bb[6];
+    for (int i = 0; i < 36; i++) A[i] = Z[i] + M[i];
+    for (int i = 0; i < 6; i++) {
+        bb[i] = Fk[i];
+        for (int j = 0; j < 6; j++) bb[i] += M[6 * i + j] * X[j];
+    }
+    solve6(A, bb, Xn);
+}
+
 // One block per particle: link partials summed in chunk order (FP64), then
 // (M + zeta) X' = M X + (F0, T0) + transfers (implicit update),
 // R' = R + V', m' = m and e' = e rotated by |Omega'| about Omega' (e' then
@@ -1543,6 +1606,8 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
     const bool expl = (p.flags & LB_EXPLICIT_COLLOID) != 0;
     if (q.fixed) {
         for (int i = 0; i < 6; i++) Xn[i] = X[i];
+    } else if (is_spheroid(q)) {
+        spheroid_step(q, Z, Fk, X, expl, Xn);
     } else if (expl) {
         // option: explicit update (Ladd), M X' = M X + F0 + transfers - zeta X
         const double Mv[6] = {q.mass, q.mass, q.mass, q.inertia, q.inertia, q.inertia};
@@ -1556,18 +1621,7 @@ __global__ __launch_bounds__(64) void k_colloid_update(BatchArgs A)
         double A[36], bb[6];
         for (int i = 0; i < 36; i++) A[i] = Z[i];
         for (int i = 0; i < 6; i++) { A[6 * i + i] += Mv[i]; bb[i] = Mv[i] * X[i] + Fk[i]; }
-        // Gaussian elimination without pivoting (M + zeta is symmetric positive definite)
-        for (int c = 0; c < 6; c++)
-            for (int i = c + 1; i < 6; i++) {
-                const double l = A[6 * i + c] / A[6 * c + c];
-                for (int j = c; j < 6; j++) A[6 * i + j] -= l * A[6 * c + j];
-                bb[i] -= l * bb[c];
-            }
-        for (int i = 5; i >= 0; i--) {
-            double s = bb[i];
-            for (int j = i + 1; j < 6; j++) s -= A[6 * i + j] * Xn[j];
-            Xn[i] = s / A[6 * i + i];
-        }
+        solve6(A, bb, Xn);
     }
     // force and torque acting: F0 - zeta X' (implicit), F0 - zeta X (explicit)
     for (int i = 0; i < 6; i++) {
@@ -1623,9 +1677,10 @@ struct BoxIter {
 __device__ __forceinline__ BoxIter box_of(const DColloid &q, const KParams &p)
 {
     BoxIter b;
-    b.bx = axis_box(q.pos[0], q.radius, p.nx);
-    b.by = axis_box(q.pos[1], q.radius, p.ny);
-    b.bz = axis_box(q.pos[2], q.radius, p.nz);
+    const double rb = bound_radius(q);
+    b.bx = axis_box(q.pos[0], rb, p.nx);
+    b.by = axis_box(q.pos[1], rb, p.ny);
+    b.bz = axis_box(q.pos[2], rb, p.nz);
     b.total = b.bx.count * b.by.count * b.bz.count;
     b.nchunk = (b.total + GCHUNK - 1) / GCHUNK;
     return b;
@@ -1670,7 +1725,7 @@ __device__ __forceinline__ int gather_boundary(const BoxIter &B, const KParams &
     __syncthreads();
     return cnt;
 }
-template <class S>
+template <class S, bool PAT>
 __device__ __forceinline__ void mu_fix(const BatchArgs &A, const int blk)
 {
     const int gk = blk / A.nsec, sec = blk - gk * A.nsec;
@@ -1685,11 +1740,11 @@ __device__ __forceinline__ void mu_fix(const BatchArgs &A, const int blk)
     for (int i = threadIdx.x; i < count; i += GCHUNK) {
         int x, y, z;
         const int n = box_node(B, list[i], p, x, y, z);
-        mu_bnd_node<S>(D, p, n, x, y, z);
+        mu_bnd_node<S, PAT>(D, p, n, x, y, z);
     }
 }
 
-template <class S>
+template <class S, bool PAT>
 __device__ __forceinline__ void psic_fix(const BatchArgs &A, const int blk)
 {
     const int gk = blk / A.nsec, sec = blk - gk * A.nsec;
@@ -1704,7 +1759,7 @@ __device__ __forceinline__ void psic_fix(const BatchArgs &A, const int blk)
     for (int i = threadIdx.x; i < count; i += GCHUNK) {
         int x, y, z;
         const int n = box_node(B, list[i], p, x, y, z);
-        psic_bnd_node<S>(D, p, n, x, y, z);
+        psic_bnd_node<S, PAT>(D, p, n, x, y, z);
     }
 }
 
@@ -1722,10 +1777,12 @@ __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
     else mu_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
 }
 
-template <class S>
+// PAT: some particle of the batch carries a surface pattern or is not a
+// sphere (the form without that arithmetic keeps a smaller register budget)
+template <class S, bool PAT>
 __global__ __launch_bounds__(GCHUNK) void k_mu_bnd(BatchArgs A)
 {
-    mu_fix<S>(A, blockIdx.x);
+    mu_fix<S, PAT>(A, blockIdx.x);
 }
 
 template <class S, int V, bool ZM, bool BND, bool SP = false>
@@ -1736,10 +1793,10 @@ __global__ __launch_bounds__(256) void k_scalar(BatchArgs A)
     else psic_vec<S, (V > 1 ? V : 2), BND, SP>(A, blockIdx.x + A.boff);
 }
 
-template <class S>
+template <class S, bool PAT>
 __global__ __launch_bounds__(GCHUNK) void k_scalar_bnd(BatchArgs A)
 {
-    psic_fix<S>(A, blockIdx.x);
+    psic_fix<S, PAT>(A, blockIdx.x);
 }
 
 // ------------------------------------------------------------- k_cover
@@ -2201,7 +2258,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     constexpr int V4 = sizeof(S) == 4 ? 4 : 2;  // FP64 scalars: 2 per 16-byte access
     // split: boundary nodes in fix-up launches (on the side stream if par);
     // psi/c sub-steps keep everything in order on s
-    const bool split = B.ncol > 0 && (B.nodes >= SIDE_MIN_NODES || B.pattern);
+    const bool split = B.ncol > 0 && (B.nodes >= SIDE_MIN_NODES || B.special);
     const bool par = split && side && !tm && B.nsub <= 1;
     hipStream_t ss = par ? side->s : s;
     const dim3 gfix(B.args.nfix);
@@ -2209,7 +2266,8 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     const bool bi = B.ncol > 0 && !split;  // boundary nodes inline
     auto mu = [&](const BatchArgs &a) {
         if (B.nopsi) return;  // single phase: mu stays 0
-        if (split) k_mu_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a);
+        if (split && B.special) k_mu_bnd<S, true><<<gfix, GCHUNK, 0, ss>>>(a);
+        else if (split) k_mu_bnd<S, false><<<gfix, GCHUNK, 0, ss>>>(a);
         if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 2 && bi) k_mu<S, 2, true><<<B.nblocks[0], 256, 0, s>>>(a);
@@ -2243,7 +2301,8 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     // sub-step 0 reads the state at t and writes the pair its table names
     BatchArgs a0 = B.args;
     if (B.nsub > 1) a0.d = B.dsub[0];
-    if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, ss>>>(a0);
+    if (split && B.special) k_scalar_bnd<S, true><<<gfix, GCHUNK, 0, ss>>>(a0);
+    else if (split) k_scalar_bnd<S, false><<<gfix, GCHUNK, 0, ss>>>(a0);
     const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
     auto scalar = [&](const dim3 gs, const BatchArgs &a) {
         if (B.nopsi && !B.zmarch) {
@@ -2300,7 +2359,8 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
         mu(a);
         if (tm) tm->end(0, s);
         if (tm) tm->begin(2, s);
-        if (split) k_scalar_bnd<S><<<gfix, GCHUNK, 0, s>>>(a);
+        if (split && B.special) k_scalar_bnd<S, true><<<gfix, GCHUNK, 0, s>>>(a);
+        else if (split) k_scalar_bnd<S, false><<<gfix, GCHUNK, 0, s>>>(a);
         scalar(dim3(B.nblocks[2]), a);
         if (tm) tm->end(2, s);
     }

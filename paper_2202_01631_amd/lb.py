@@ -56,7 +56,7 @@ class Colloid(C.Structure):
                 ("pattern_cos", C.c_double * (PATTERN_MAX_BANDS - 1)),
                 ("pattern_alpha", C.c_double * PATTERN_MAX_CELLS),
                 ("pattern_mu", C.c_double * PATTERN_MAX_CELLS),
-                ("pattern_H", C.c_double * PATTERN_MAX_CELLS)]
+                ("pattern_H", C.c_double * PATTERN_MAX_CELLS), ("axial", C.c_double)]
 
 
 class Totals(C.Structure):
@@ -165,6 +165,7 @@ def make_colloid(d):
         setattr(q, key, float(d.get(key, 1.0 if key == "rho_p" else 0.0)))
     q.fixed = int(d.get("fixed", 0))
     q.cap_cos = float(d.get("cap_cos", 0.0))
+    q.axial = float(d.get("axial", 0.0))  # spheroid semi-axis along m (0: sphere)
     e = d.get("e", (0.0, 0.0, 0.0))
     for a in range(3):
         q.e[a] = float(e[a])
@@ -193,6 +194,7 @@ def colloid_dict(q):
     d["fixed"] = q.fixed
     d["cap_cos"] = q.cap_cos
     d["e"] = np.array(q.e[:])
+    d["axial"] = q.axial
     if q.pattern_bands > 0:
         nc = q.pattern_bands * q.pattern_sectors
         d["pattern"] = {"bands": q.pattern_bands, "sectors": q.pattern_sectors,

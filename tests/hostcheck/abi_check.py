@@ -99,6 +99,20 @@ def main():
         expect_error(pb.add_colloids, [dict(pw["colloids"][0], pattern=bad)])
     pb.close()
     other.close()
+    # a spheroid (boundary fix-up launches), stepped and batched; refused
+    # with soft-sphere forces
+    sw = dict(w, colloids=[dict(w["colloids"][0], axial=6.0)])
+    sb = lb.from_spec(sw, precision="fp32", stream=st.value)
+    sb.step(3)
+    other = lb.from_spec(w, precision="fp32", stream=st.value)
+    lb.batch_step([other, sb], 2)
+    sb.close()
+    other.close()
+    soft = lb.Box((32, 32, 32), "fp32", **dict(lb.spec_params(w), soft_eps=0.05, soft_sigma=1.0,
+                                               soft_nu=1.0, soft_hc=1.0))
+    soft.init_fields(np.zeros(32 ** 3), np.zeros(32 ** 3))
+    expect_error(soft.add_colloids, sw["colloids"])
+    soft.close()
     left = L.hostcheck_live_allocations()
     print("abi ok: %d device allocations left" % left, flush=True)
     if left:

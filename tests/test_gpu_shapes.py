@@ -1,0 +1,137 @@
+"""GPU parity of spheroidal particles (a reading of Sec. IV: the model's
+local rules on particles of other shapes; semi-axis `axial` along the axis
+m, `radius` across it) against the FP64 oracle.
+
+Bars as for spheres: owner maps and link tables bit-exact, FP64 fields
+within 1e-12, particle states within 1e-11; FP32 within 2e-5; a box with a
+spheroid batched beside a box of spheres gives the bits it gives alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_01631_amd import inputs as I
+from paper_2202_01631_amd import lb
+from parity_util import U_FLOOR_FP32, field_errors, flush_print, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(shape, seed, colloids, precision="fp64", **kw):
+    N = int(np.prod(shape))
+    p = dict(I.FREE_ENERGY)
+    p["E"] = -0.2
+    p.update(kw)
+    return dict(name="spheroids%s" % (shape,), shape=shape, precision=precision, params=p,
+                psi=I.slab(shape, I.WIDTH, amp=0.05, seed=seed),
+                c=0.3 + I.noise(seed + 1, N, 0.05), colloids=list(colloids))
+
+
+def _spheroids():
+    """A moving prolate Janus spheroid with wetting, a turning oblate one with
+    a cap of another size, a prolate one with a surface pattern."""
+    a = I.janus((10.3, 11.2, 9.4), I.unit_vectors(21, 1)[0], 3.4, alpha=2e-3, mu_minus=0.2,
+                mu_plus=-0.1, theta=70.0)
+    a.update(axial=5.6, vel=np.array([0.012, -0.006, 0.004]), omega=np.array([0.001, 0.002, 0.0]))
+    b = I.janus((31.6, 12.1, 21.3), I.unit_vectors(22, 1)[0], 5.2, alpha=1e-3, mu=0.15,
+                theta=110.0)
+    b.update(axial=3.1, cap_cos=0.3, vel=np.array([-0.008, 0.004, 0.006]),
+             omega=np.array([0.003, -0.004, 0.002]))
+    c = I.janus((17.2, 27.4, 25.1), I.unit_vectors(23, 1)[0], 3.0, alpha=0.0, mu=0.0, theta=90.0)
+    c.update(axial=4.8, e=np.array([1.0, 0.0, 0.0]), vel=np.array([0.004, 0.01, -0.008]),
+             pattern=dict(bands=2, sectors=4, cos=[0.2], alpha=[1e-3, 0, 2e-3, 0, 0, 1e-3, 0, 0],
+                          mu=[0.2, -0.1, 0.1, 0.0, 0.05, 0.15, -0.2, 0.1],
+                          H=[0.003, 0.0, -0.002, 0.001, 0.0, 0.002, -0.003, 0.0]))
+    return [a, b, c]
+
+
+@pytest.mark.parametrize("flags", [0, lb.LB_EXPLICIT_COLLOID])
+def test_spheroids_match_oracle(flags):
+    # 30 steps of three moving, turning spheroids (prolate, oblate,
+    # patterned) with emission, slip and wetting: owner maps and link tables
+    # bit-exact every 10 steps, FP64 fields within 1e-12, particle states
+    # (position, axes, velocities) within 1e-11
+    shape = (44, 38, 34)
+    cols = _spheroids()
+    g, o = run_pair(_spec(shape, 51, cols, flags=flags), 0)
+    assert np.array_equal(g.owner(), o.owner())
+    assert np.array_equal(g.links(), o.links())
+    changed = 0
+    for _ in range(3):
+        own0 = o.owner()
+        g.step(10)
+        o.step(10)
+        changed += int((o.owner() != own0).sum())
+        assert np.array_equal(g.owner(), o.owner())
+        assert np.array_equal(g.links(), o.links())
+    assert changed > 0  # cover and uncover exercised
+    e = field_errors(g.fields(), o.fields(), o.owner() < 0)
+    flush_print("[spheroids] fp64 flags %d errors %s" % (flags, e))
+    assert max(e.values()) <= 1e-12
+    tg, cg = g.observables()
+    to, co = o.observables()
+    assert tg["n_active"] == to["n_active"]
+    for k in range(3):
+        assert cg[k]["axial"] == cols[k]["axial"]
+        for a in ("vel", "omega", "pos", "m", "e"):
+            assert np.abs(cg[k][a] - co[k][a]).max() <= 1e-11, (k, a)
+    g.close()
+    o.close()
+
+
+def test_spheroid_fp32_alone_batched_and_oracle():
+    # FP32: the spheroid box alone and batched beside a box of spheres (the
+    # batch then takes the boundary fix-up launches) give the same bits; the
+    # box of spheres gives its own bits too; 100 steps within 2e-5 of the
+    # oracle
+    import torch
+    shape = (44, 38, 34)
+    spec = _spec(shape, 53, _spheroids(), precision="fp32")
+    other = _spec((40, 36, 34), 54, [I.janus((18.2, 17.1, 16.9), (0.0, 0.6, 0.8), 4.4)],
+                  precision="fp32")
+    s = torch.cuda.Stream()
+    a = lb.from_spec(spec, stream=s)
+    a.step(100)
+    b = lb.from_spec(spec, stream=s)
+    c = lb.from_spec(other, stream=s)
+    lb.batch_step([b, c], 100)
+    d = lb.from_spec(other, stream=s)
+    d.step(100)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(c.populations(), d.populations())
+    o = oracle.from_spec(dict(spec, precision="fp64"))
+    o.step(100)
+    assert np.array_equal(a.owner(), o.owner())
+    assert np.array_equal(a.links(), o.links())
+    e = field_errors(a.fields(), o.fields(), o.owner() < 0, u_floor=U_FLOOR_FP32)
+    flush_print("[spheroids] fp32 100 steps errors %s" % e)
+    assert max(e.values()) <= 2e-5
+    for x in (a, b, c, d):
+        x.close()
+
+
+def test_axial_equal_to_radius_is_the_sphere():
+    # axial 0 or equal to the radius: the sphere's own kernels and bits
+    shape = (40, 36, 34)
+    base = I.janus((18.2, 17.1, 16.9), (0.0, 0.6, 0.8), 4.4)
+    base["vel"] = np.array([0.01, -0.004, 0.006])
+    out = []
+    for extra in ({}, dict(axial=4.4)):
+        g = lb.from_spec(_spec(shape, 55, [dict(base, **extra)], precision="fp32"))
+        g.step(20)
+        out.append((g.populations(), g.links()))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_spheroid_options_validated():
+    shape = (32, 32, 32)
+    N = 32 ** 3
+    q = dict(pos=(16.0, 16.0, 16.0), m=(0.0, 0.0, 1.0), radius=3.0, axial=5.0, rho_p=1.0)
+    for kw, col in ((dict(soft_eps=0.05, soft_sigma=1.0, soft_nu=1.0, soft_hc=1.0), q),
+                    (dict(lub_hc=2.0), q), ({}, dict(q, axial=-1.0)),
+                    ({}, dict(q, axial=12.5)), ({}, dict(q, axial=float("nan")))):
+        box = lb.Box(shape, "fp64", **dict(I.FREE_ENERGY, **kw))
+        box.init_fields(np.zeros(N), np.zeros(N))
+        with pytest.raises(lb.LBError):
+            box.add_colloids([col])
+        box.close()
