@@ -5,4 +5,4 @@ benchmark import this package; the solver never does.
 """
 from .pyoracle import (Oracle, OracleError, build, lattice, wetting_H, from_spec,  # noqa: F401
                        solubility_E, set_threads, SOLUTE_FORCE, EXPLICIT_COLLOID,
-                       CAPILLARY_FORCE)
+                       CAPILLARY_FORCE, STRESS_FORM)

@@ -86,6 +86,7 @@ struct or_ctx {
     double *f, *fs, *fn;          /* pre-collision state f(t), post-collision, f(t+1) */
     double *psi, *cc, *psin, *ccn;
     double *mu, *force, *uf, *src, *chi;
+    double *pst, *muc;            /* option OR_STRESS_FORM: stress (6 per node), mu_c */
     int *owner, *owner_new;
     or_colloid *col;
     int ncol;
@@ -349,7 +350,9 @@ int or_create(const or_params *p, or_ctx **out)
     if (dt * p->M_psi * (12.0 * fabs(p->a) + 36.0 * fabs(p->b) + 144.0 * p->kappa) >= 2.0)
         return OR_E_INVALID;
     if (dt * (12.0 * p->D_c + p->k_d) >= 2.0) return OR_E_INVALID;
-    if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID | OR_CAPILLARY_FORCE)) return OR_E_INVALID;
+    if (p->flags & ~(OR_SOLUTE_FORCE | OR_EXPLICIT_COLLOID | OR_CAPILLARY_FORCE | OR_STRESS_FORM))
+        return OR_E_INVALID;
+    if ((p->flags & OR_STRESS_FORM) && !(p->flags & OR_CAPILLARY_FORCE)) return OR_E_INVALID;
     if (!(p->soft_eps >= 0.0)) return OR_E_INVALID;
     if (p->soft_eps > 0.0 && !(p->soft_sigma > 0.0 && p->soft_nu > 0.0 && p->soft_hc > 0.0))
         return OR_E_INVALID;
@@ -377,6 +380,11 @@ int or_create(const or_params *p, or_ctx **out)
     c->chi = zalloc(sizeof(double) * N);
     c->owner = zalloc(sizeof(int) * N);
     c->owner_new = zalloc(sizeof(int) * N);
+    if (p->flags & OR_STRESS_FORM) {
+        c->pst = zalloc(sizeof(double) * 6 * N);
+        c->muc = zalloc(sizeof(double) * N);
+        if (!c->pst || !c->muc) { or_destroy(c); return OR_E_INVALID; }
+    }
     if (!c->f || !c->fs || !c->fn || !c->psi || !c->cc || !c->psin || !c->ccn || !c->mu ||
         !c->force || !c->uf || !c->src || !c->chi || !c->owner || !c->owner_new) {
         or_destroy(c);
@@ -402,6 +410,7 @@ int or_destroy(or_ctx *c)
     if (!c) return OR_OK;
     free(c->f); free(c->fs); free(c->fn); free(c->psi); free(c->cc); free(c->psin);
     free(c->ccn); free(c->mu); free(c->force); free(c->uf); free(c->src); free(c->chi);
+    free(c->pst); free(c->muc);
     free(c->owner); free(c->owner_new);
     free_colloids(c);
     free(c);
@@ -685,6 +694,24 @@ static void collide_stream(or_ctx *c)
     const or_params *p = &c->p;
     long N = c->N;
     double sumF[3] = {0.0, 0.0, 0.0};
+    const int divform = (p->flags & OR_STRESS_FORM) != 0;
+    if (divform) {
+        /* option: the stress P (xx, yy, zz, xy, xz, yz) and the coupling part
+         * mu_c = -C E chi sech^2(psi) of Eq. 2 at every fluid node */
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < N; n++) {
+            if (c->owner[n] >= 0) continue;
+            double P[3][3];
+            stress(c, n, P);
+            double *q = &c->pst[6 * n];
+            q[0] = P[0][0]; q[1] = P[1][1]; q[2] = P[2][2];
+            q[3] = P[0][1]; q[4] = P[0][2]; q[5] = P[1][2];
+            double ps = c->psi[n];
+            double chi = c->cc[n] - p->c_b0 - p->E * tanh(ps);
+            double ch = cosh(ps);
+            c->muc[n] = -p->C * p->E * chi / (ch * ch);
+        }
+    }
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         if (c->owner[n] >= 0) {
@@ -704,6 +731,25 @@ static void collide_stream(or_ctx *c)
             gm[2] += wt(i) * CZ[i] * mi;
         }
         for (int a = 0; a < 3; a++) F[a] = -c->psi[n] * 3.0 * gm[a] + p->ext_force[a];
+        if (divform) {
+            /* option: -div P by the same isotropic stencil, (div P)_b =
+             * 3 sum_i w_i c_ia P_ab(x + c_i), P(x) at solid neighbours, plus
+             * -psi grad(mu_c); replaces -psi grad(mu) */
+            double dP[3] = {0.0, 0.0, 0.0}, gc[3] = {0.0, 0.0, 0.0};
+            for (int i = 1; i < 19; i++) {
+                long m = nbr(c, n, i);
+                long y = c->owner[m] < 0 ? m : n;
+                const double *q = &c->pst[6 * y];
+                const double Pm[3][3] = {{q[0], q[3], q[4]}, {q[3], q[1], q[5]}, {q[4], q[5], q[2]}};
+                for (int b = 0; b < 3; b++)
+                    dP[b] += wt(i) * (CX[i] * Pm[0][b] + CY[i] * Pm[1][b] + CZ[i] * Pm[2][b]);
+                gc[0] += wt(i) * CX[i] * c->muc[y];
+                gc[1] += wt(i) * CY[i] * c->muc[y];
+                gc[2] += wt(i) * CZ[i] * c->muc[y];
+            }
+            for (int a = 0; a < 3; a++)
+                F[a] = -3.0 * dP[a] - c->psi[n] * 3.0 * gc[a] + p->ext_force[a];
+        }
         if (p->flags & OR_SOLUTE_FORCE) {
             /* option: the solvent also feels -c grad(mu_c) with mu_c = C chi,
              * the c-derivative of the coupling term of Eq. 1; same stencil,

@@ -38,7 +38,8 @@ typedef struct {
     double a, b, kappa, M_psi;   /* f = a/2 psi^2 + b/4 psi^4 + kappa/2 |grad psi|^2 (Eq. 1) */
     double C, E, c_b0, D_c, k_d; /* C/2 (c - c_b0 - E tanh psi)^2 (Eq. 1); Eq. 3a */
     double ext_force[3];         /* uniform body force on the fluid (tests) */
-    uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID, OR_CAPILLARY_FORCE */
+    uint32_t flags;              /* OR_SOLUTE_FORCE, OR_EXPLICIT_COLLOID, OR_CAPILLARY_FORCE,
+                                    OR_STRESS_FORM */
     int32_t ch_substeps;         /* psi/c updates per LB step, time step 1/n each
                                     (mu and chi recomputed between them, u held); 0 -> 1 */
     double soft_eps, soft_sigma, soft_nu, soft_hc;
@@ -63,10 +64,17 @@ typedef struct {
  * OR_CAPILLARY_FORCE   each particle also receives the thermodynamic stress of
  *                      the psi free energy at its boundary links, the share of
  *                      the interfacial force that the solvent force leaves out
- *                      at the particle surface (capillary and wetting forces) */
+ *                      at the particle surface (capillary and wetting forces)
+ * OR_STRESS_FORM       (with OR_CAPILLARY_FORCE) the solvent force of the psi
+ *                      free energy in divergence form, -div P, P the stress
+ *                      above taken at the fluid nodes and P(x) substituted at
+ *                      solid neighbours, plus the coupling part -psi grad(mu_c)
+ *                      of Eq. 2: the fluid then loses exactly what the particles
+ *                      gain at their links, and the pair conserves momentum */
 #define OR_SOLUTE_FORCE 1u
 #define OR_EXPLICIT_COLLOID 2u
 #define OR_CAPILLARY_FORCE 4u
+#define OR_STRESS_FORM 8u
 
 #define OR_PATTERN_MAX_BANDS 8
 #define OR_PATTERN_MAX_CELLS 64

@@ -116,7 +116,7 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-SOLUTE_FORCE, EXPLICIT_COLLOID, CAPILLARY_FORCE = 1, 2, 4   # option flags (oracle.h)
+SOLUTE_FORCE, EXPLICIT_COLLOID, CAPILLARY_FORCE, STRESS_FORM = 1, 2, 4, 8  # option flags (oracle.h)
 PARAM_KEYS = ("rho0", "tau", "a", "b", "kappa", "M_psi", "C", "E", "c_b0", "D_c", "k_d")
 COLLOID_SCALARS = ("radius", "alpha_minus", "alpha_plus", "mu_minus", "mu_plus", "H", "rho_p")
 

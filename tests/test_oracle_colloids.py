@@ -578,3 +578,86 @@ def test_lubrication_is_the_reynolds_force():
     assert G1[0] == pytest.approx(2.0 * F1[0], rel=1e-12)
     T1, T2 = lub((0, 0.01, 0), (0, -0.01, 0.005))
     assert np.abs(T1).max() == 0.0 and np.abs(T2).max() == 0.0
+
+
+def test_stress_form_conserves_momentum_with_the_particle():
+    # option OR_STRESS_FORM (with OR_CAPILLARY_FORCE and the explicit update,
+    # which hands the particle exactly its link momentum): the fluid feels
+    # -div P with P(x) at solid neighbours, and over the fluid nodes that
+    # sums to minus what the particle takes at its links, so fluid +
+    # particle + pending transfer momentum is conserved to round-off every
+    # step, with an interface, wetting and cover/uncover; without the
+    # divergence form the same run gains momentum (the potential-form force
+    # and the particle's stress differ near the contact line)
+    shape = (20, 18, 18)
+    N = int(np.prod(shape))
+    psi = I.slab(shape, I.WIDTH, amp=0.0, seed=1)
+    drift = {}
+    for flags in (oracle.CAPILLARY_FORCE | oracle.EXPLICIT_COLLOID,
+                  oracle.CAPILLARY_FORCE | oracle.EXPLICIT_COLLOID | oracle.STRESS_FORM):
+        o = oracle.Oracle(shape, flags=flags, **FE_CAP)
+        o.init_fields(psi, np.zeros(N))
+        o.add_colloids([dict(pos=(5.3, 9.1, 8.8), m=(0, 0, 1), radius=3.2,
+                             vel=(0.01, 0.004, -0.002), rho_p=1.5, H=0.002)])
+        mass = 1.5 * 4.0 / 3.0 * math.pi * 3.2 ** 3
+        worst, changed = 0.0, 0
+        for _ in range(10):
+            ob = o.owner()
+            pb, _ = _fluid_momentum(o)
+            _, cb = o.observables()
+            trb = o.colloid_diag(0)["trF"] if o.observables()[0]["step"] > 0 else np.zeros(3)
+            o.step(1)
+            pa, _ = _fluid_momentum(o)
+            _, ca = o.observables()
+            d = o.colloid_diag(0)
+            lhs = (pa + mass * ca[0]["vel"] + d["trF"]) - (pb + mass * cb[0]["vel"] + trb)
+            worst = max(worst, float(np.abs(lhs).max()))
+            changed += int((o.owner() != ob).sum())
+        drift[flags & oracle.STRESS_FORM] = worst
+        assert changed > 0
+        o.close()
+    assert drift[oracle.STRESS_FORM] <= 256 * N * EPS
+    assert drift[0] > 1e-3
+
+
+def test_stress_form_vanishes_in_uniform_fluid():
+    # psi uniform, neutral wetting: the stress is isotropic and uniform, so
+    # -div P (P(x) at solid neighbours) vanishes at every fluid node and the
+    # particle takes nothing; both to round-off
+    shape = (16, 16, 16)
+    N = 16 ** 3
+    o = oracle.Oracle(shape, flags=oracle.CAPILLARY_FORCE | oracle.STRESS_FORM, **FE_CAP)
+    o.init_fields(np.full(N, 0.7), np.zeros(N))
+    o.add_colloids([dict(pos=(7.6, 8.3, 7.9), m=(0, 0, 1), radius=3.5, fixed=1)])
+    o.step(1)
+    force = o.aux()["force"]
+    fl = o.owner() < 0
+    assert np.abs(force[:, fl]).max() <= 1e-15
+    assert np.abs(o.colloid_diag(0)["F0"]).max() <= 1e-13
+
+
+def test_stress_form_needs_the_capillary_option():
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle((16, 16, 16), flags=oracle.STRESS_FORM, **FE_CAP)
+
+
+def test_stress_form_keeps_the_coupling_force():
+    # psi uniform, c varying: the stress is uniform, so the divergence form
+    # reduces to its coupling part -psi grad(mu_c), which must equal the
+    # potential-form force -psi grad(mu) (mu = const + mu_c here), node by
+    # node; fixes the sign and factor of the mu_c term
+    shape = (16, 14, 12)
+    N = int(np.prod(shape))
+    x = np.stack(I.coords(shape)).astype(float)
+    c = 0.3 + 0.05 * np.sin(2 * np.pi * x[0] / 16) * np.cos(2 * np.pi * x[1] / 14)
+    fe = dict(FE_CAP, E=-0.2, c_b0=0.25)
+    F = {}
+    for flags in (oracle.CAPILLARY_FORCE, oracle.CAPILLARY_FORCE | oracle.STRESS_FORM):
+        o = oracle.Oracle(shape, flags=flags, **fe)
+        o.init_fields(np.full(N, 0.6), c)
+        o.step(1)
+        F[flags] = o.aux()["force"].copy()
+        o.close()
+    a, b = F[oracle.CAPILLARY_FORCE], F[oracle.CAPILLARY_FORCE | oracle.STRESS_FORM]
+    assert np.abs(a).max() > 1e-5
+    assert np.abs(a - b).max() <= 1e-15
