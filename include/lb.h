@@ -143,10 +143,22 @@ typedef struct {
  *                      test); runs with M_psi = 0.1 or R = 9 near an
  *                      interface can diverge (reported through the error
  *                      bits and LB_E_UNSTABLE).
+ * LB_STRESS_FORM       (with LB_CAPILLARY_FORCE) the solvent force of the psi
+ *                      free energy in divergence form: -div P by the same
+ *                      isotropic stencil, (div P)_b = 3 sum_i w_i c_ia
+ *                      P_ab(x + c_i) with P(x) at solid neighbours, plus the
+ *                      coupling part -psi grad(mu_c), mu_c = -C E chi
+ *                      sech^2(psi) of Eq. 2, instead of -psi grad(mu).  The
+ *                      fluid then loses exactly what the particles gain at
+ *                      their links, so fluid and particles together conserve
+ *                      momentum.  Selects the one-node forms of the mu update
+ *                      and collide-stream and the boundary fix-ups; the arena
+ *                      holds 7 more scalar fields.
  * Other bits: LB_E_INVALID at lb_create. */
 #define LB_SOLUTE_FORCE 1u
 #define LB_EXPLICIT_COLLOID 2u
 #define LB_CAPILLARY_FORCE 4u
+#define LB_STRESS_FORM 8u
 
 #define LB_PATTERN_MAX_BANDS 8
 #define LB_PATTERN_MAX_CELLS 64

@@ -26,7 +26,7 @@ size_t compute_bytes(int prec) { return prec == LB_FP64 ? 8 : 4; }
 // c[2], mu (N compute), in FP64 chi (N), u (3N compute), owner (N bytes),
 // and with psi/c sub-steps one more psi and c pair (N compute each).
 struct Layout {
-    size_t f[2], psi[2], cc[2], mu, chi, u, own, psis, ccs, total;
+    size_t f[2], psi[2], cc[2], mu, chi, u, own, psis, ccs, pst, muc, total;
 };
 
 int substeps_of(const lb_params &p) { return p.ch_substeps > 1 ? p.ch_substeps : 1; }
@@ -49,6 +49,12 @@ Layout layout_of(const lb_params &p)
     if (substeps_of(p) > 1) {
         L.psis = o; o = align256(o + N * cb);
         L.ccs = o; o = align256(o + N * cb);
+    }
+    L.pst = L.muc = 0;
+    if (p.flags & LB_STRESS_FORM) {
+        // the stress (6 planes) and mu_c of the divergence-form solvent force
+        L.pst = o; o = align256(o + 6 * N * cb);
+        L.muc = o; o = align256(o + N * cb);
     }
     L.total = o;
     return L;
@@ -139,6 +145,8 @@ static StepBuffers buffers(lb_ctx *c, int cu)
     b.mu = ptr(c, c->L.mu);
     b.chi = c->p.precision == LB_FP64 ? ptr(c, c->L.chi) : nullptr;
     b.u = ptr(c, c->L.u);
+    b.pst = (c->p.flags & LB_STRESS_FORM) ? ptr(c, c->L.pst) : nullptr;
+    b.muc = (c->p.flags & LB_STRESS_FORM) ? ptr(c, c->L.muc) : nullptr;
     b.own = (uint8_t *)ptr(c, c->L.own);
     b.col = c->dcol;
     b.lnode = c->lnode;
@@ -242,9 +250,15 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         }
     }
     B.solute_force = 0;
+    B.stress = 0;
     B.soft = 0;
     for (int j = 0; j < n; j++) {
         if (ctxs[j]->p.flags & LB_SOLUTE_FORCE) B.solute_force = 1;
+        if (ctxs[j]->p.flags & LB_STRESS_FORM) {
+            B.stress = 1;
+            // boundary nodes in the fix-up launches, which write the stress there
+            if (ctxs[j]->ncol > 0) B.special = 1;
+        }
         if (ctxs[j]->p.soft_eps > 0.0 || ctxs[j]->p.lub_hc > 0.0) B.soft = 1;
     }
     for (int w = 0; w < 3; w++) {
@@ -252,7 +266,10 @@ static void batch_fill(lb_ctx *const *ctxs, int n, const int *parity, std::vecto
         for (int j = 1; j < n; j++)
             same = same && d[j].ls[w].vec == d[0].ls[w].vec &&
                    (d[j].ls[w].zc > 1) == (d[0].ls[w].zc > 1);
-        if (w == 1 && B.solute_force) same = n > 0 && d[0].ls[1].vec <= 1 && same;
+        // the solute force and the divergence-form force live in the one-node
+        // collide-stream; the stress is written by the one-node mu update
+        if (w == 1 && (B.solute_force || B.stress)) same = n > 0 && d[0].ls[1].vec <= 1 && same;
+        if (w == 0 && B.stress) same = n > 0 && d[0].ls[0].vec <= 1 && same;
         if (!same) {
             for (int j = 0; j < n; j++) {
                 if (d[j].ls[w].vec > 1) {
@@ -454,7 +471,11 @@ static lb_status check_params(const lb_params *p, std::string &why)
         why = "kappa, M_psi, C, D_c, k_d must be >= 0";
         return LB_E_INVALID;
     }
-    if (p->flags & ~(LB_SOLUTE_FORCE | LB_EXPLICIT_COLLOID | LB_CAPILLARY_FORCE)) {
+    if ((p->flags & LB_STRESS_FORM) && !(p->flags & LB_CAPILLARY_FORCE)) {
+        why = "LB_STRESS_FORM needs LB_CAPILLARY_FORCE";
+        return LB_E_INVALID;
+    }
+    if (p->flags & ~(LB_SOLUTE_FORCE | LB_EXPLICIT_COLLOID | LB_CAPILLARY_FORCE | LB_STRESS_FORM)) {
         why = "unknown option flags";
         return LB_E_INVALID;
     }
@@ -873,7 +894,9 @@ lb_status lb_init_fields(lb_ctx *c, const double *psi, const double *cc, const d
     // single phase (A = kappa = E = 0, c_b0 = 0, psi = 0): mu stays 0 and chi
     // equals c, and psi stays 0 through the psi/c update and cover/uncover;
     // batches of such boxes skip the mu pass and read chi from c
-    bool np = c->p.a == 0.0 && c->p.b == 0.0 && c->p.kappa == 0.0 && c->p.E == 0.0 && c->p.c_b0 == 0.0;
+    // (not with LB_STRESS_FORM, whose force reads the stress the mu pass writes)
+    bool np = c->p.a == 0.0 && c->p.b == 0.0 && c->p.kappa == 0.0 && c->p.E == 0.0 &&
+              c->p.c_b0 == 0.0 && !(c->p.flags & LB_STRESS_FORM);
     for (size_t n = 0; np && n < N; n++) np = psi[n] == 0.0;
     c->nopsi = np;
     if (np) {

@@ -14,6 +14,7 @@ struct StepBuffers {
     const void *psi, *cc;   // state at t
     void *psin, *ccn;       // state at t+1
     void *mu, *chi, *u;     // derived fields of step t (chi stored in FP64 only)
+    void *pst, *muc;        // LB_STRESS_FORM: stress (6 planes xx yy zz xy xz yz) and mu_c
     uint8_t *own;
     DColloid *col;
     int *lnode;
@@ -61,6 +62,7 @@ struct Batch {
     int zmarch;       // z-marching form of the psi/c update (all boxes of the batch)
     long long nodes;  // lattice nodes over all boxes
     int solute_force; // some box has LB_SOLUTE_FORCE (one-node collide-stream with the term)
+    int stress;       // some box has LB_STRESS_FORM (one-node mu and collide-stream, fix-ups)
     int nsub;         // psi/c sub-steps per step (all boxes of the batch)
     int soft;         // some box has soft-sphere repulsion (k_soft runs)
     int nopsi;        // every box single phase: no mu launches, single-phase kernels

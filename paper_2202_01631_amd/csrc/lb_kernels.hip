@@ -153,8 +153,37 @@ __device__ __forceinline__ void mu_chi(const KParams &p, S ps, S lap, S cn, S &m
     mu = fma(-(S)(p.C * p.E) * chi, fma(-t, t, S(1)), m);
 }
 
+// option LB_STRESS_FORM: the stress of the psi free energy at fluid node n,
+// P = (a/2 psi^2 + 3b/4 psi^4 - kappa psi lap - kappa/2 |g|^2) 1 + kappa g g^T,
+// g the central difference over the faces (pv: x+, x-, y+, y-, z+, z-, with
+// the wetting ghosts at solid faces), and mu_c = -C E chi sech^2(psi), the
+// coupling part of mu; stored for the divergence-form force of collide-stream
+template <class S>
+__device__ __forceinline__ void store_stress(const BoxDesc &D, const KParams &p, int n, S ps,
+                                             const S pv[6], S cn)
+{
+    const S lap = lap6<S>(ps, pv);
+    const S g[3] = {S(0.5) * (pv[0] - pv[1]), S(0.5) * (pv[2] - pv[3]), S(0.5) * (pv[4] - pv[5])};
+    const S kap = (S)p.kappa;
+    const S ps2 = ps * ps;
+    const S g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const S sd = S(0.5) * (S)p.a * ps2 + S(0.75) * (S)p.b * ps2 * ps2 - kap * ps * lap -
+                 S(0.5) * kap * g2;
+    S *__restrict__ P = (S *)D.b.pst;
+    const size_t N = (size_t)p.N;
+    P[n] = sd + kap * g[0] * g[0];
+    P[N + n] = sd + kap * g[1] * g[1];
+    P[2 * N + n] = sd + kap * g[2] * g[2];
+    P[3 * N + n] = kap * g[0] * g[1];
+    P[4 * N + n] = kap * g[0] * g[2];
+    P[5 * N + n] = kap * g[1] * g[2];
+    const S t = s_tanh<S>(ps);
+    const S chi = fma(-(S)p.E, t, cn - (S)p.cb0);
+    ((S *)D.b.muc)[n] = -(S)(p.C * p.E) * chi * fma(-t, t, S(1));
+}
+
 // mu of fluid node n = (x, y, z) next to a particle: wetting ghost at every
-// solid face
+// solid face (and, in the fix-up launches, the stress of LB_STRESS_FORM)
 template <class S, bool PAT = true>
 __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, int n, int x, int y,
                                             int z)
@@ -171,13 +200,16 @@ __device__ __forceinline__ void mu_bnd_node(const BoxDesc &D, const KParams &p, 
     for (int e = 0; e < 6; e++)
         pv[e] = face_psi<S, PAT>(p, D.b.col, own[nb[e]], e, x, y, z, ps, psi[nb[e]]);
     S m, c;
-    mu_chi<S>(p, ps, lap6<S>(ps, pv), ((const S *)D.b.cc)[n], m, c);
+    const S cn = ((const S *)D.b.cc)[n];
+    mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
     ((S *)D.b.mu)[n] = m;
     if (ChiStored<S>::value) ((S *)D.b.chi)[n] = c;
+    if (PAT && (p.flags & LB_STRESS_FORM)) store_stress<S>(D, p, n, ps, pv, cn);
 }
 
-// one node per thread
-template <class S, bool BND>
+// one node per thread; ST: some box of the batch has LB_STRESS_FORM (the
+// stress is written for those boxes)
+template <class S, bool BND, bool ST = false>
 __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
 {
     const int j = find_box(A.bstart, A.nbox, blk);
@@ -216,6 +248,7 @@ __device__ __forceinline__ void mu_one(const BatchArgs &A, const int blk)
     mu_chi<S>(p, ps, lap6<S>(ps, pv), cn, m, c);
     stb(mu, on, m);
     if (ChiStored<S>::value) stb(chi_out, on, c);
+    if (ST && (p.flags & LB_STRESS_FORM)) store_stress<S>(D, p, n, ps, pv, cn);
 }
 
 // Row-vector form: V consecutive x nodes per lane, 8- or 16-byte loads and
@@ -304,7 +337,8 @@ template <class S, bool SF = false, bool SP = false>
 __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, const S g[19],
                                                           const S mv[19], S m0, unsigned solid,
                                                           S ps, const S *xv = nullptr,
-                                                          S x0 = S(0), S cn = S(0))
+                                                          S x0 = S(0), S cn = S(0),
+                                                          const S *fdiv = nullptr)
 {
 #pragma clang fp contract(off)
     NodeMoments<S> m;
@@ -321,6 +355,11 @@ __device__ __forceinline__ NodeMoments<S> collide_moments(const KParams &p, cons
         m.Fx = (S)p.fx;
         m.Fy = (S)p.fy;
         m.Fz = (S)p.fz;
+    } else if (SF && fdiv) {
+        // option LB_STRESS_FORM: the divergence-form force, formed by the caller
+        m.Fx = fdiv[0] + (S)p.fx;
+        m.Fy = fdiv[1] + (S)p.fy;
+        m.Fz = fdiv[2] + (S)p.fz;
     } else {
     // grad(mu) = 3 sum_i w_i c_i mu(x + c_i)
     S mi[19];
@@ -476,7 +515,48 @@ __global__ __launch_bounds__(256) void k_collide(BatchArgs A)
             }
         }
     }
-    const NodeMoments<S> M = collide_moments<S, SF, SP>(p, g, mv, m0, solid, ps, xv, x0, cn);
+    // option LB_STRESS_FORM (one-node form only): -div P - psi grad(mu_c),
+    // (div P)_b = 3 sum_i w_i c_ia P_ab(x + c_i), P and mu_c of this node at
+    // solid neighbours
+    S fdiv[3] = {S(0), S(0), S(0)};
+    const bool divform = SF && (p.flags & LB_STRESS_FORM);
+    if (divform) {
+        const S *__restrict__ Pst = (const S *)D.b.pst;
+        const S *__restrict__ muc = (const S *)D.b.muc;
+        S dx = S(0), dy = S(0), dz = S(0), hx = S(0), hy = S(0), hz = S(0);
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+            const int m = (solid & (1u << i)) ? n : n + xo[cx(i) + 1] + yo[cy(i) + 1] + zo[cz(i) + 1];
+            const S wi = (S)(3.0 * wgt(i));
+            const S mc = muc[m];
+            if (cx(i)) {
+                const S w = cx(i) > 0 ? wi : -wi;
+                dx = fma(w, Pst[m], dx);
+                dy = fma(w, Pst[3 * N + m], dy);
+                dz = fma(w, Pst[4 * N + m], dz);
+                hx = fma(w, mc, hx);
+            }
+            if (cy(i)) {
+                const S w = cy(i) > 0 ? wi : -wi;
+                dx = fma(w, Pst[3 * N + m], dx);
+                dy = fma(w, Pst[N + m], dy);
+                dz = fma(w, Pst[5 * N + m], dz);
+                hy = fma(w, mc, hy);
+            }
+            if (cz(i)) {
+                const S w = cz(i) > 0 ? wi : -wi;
+                dx = fma(w, Pst[4 * N + m], dx);
+                dy = fma(w, Pst[5 * N + m], dy);
+                dz = fma(w, Pst[2 * N + m], dz);
+                hz = fma(w, mc, hz);
+            }
+        }
+        fdiv[0] = fma(-ps, hx, -dx);
+        fdiv[1] = fma(-ps, hy, -dy);
+        fdiv[2] = fma(-ps, hz, -dz);
+    }
+    const NodeMoments<S> M = collide_moments<S, SF, SP>(p, g, mv, m0, solid, ps, xv, x0, cn,
+                                                        divform ? fdiv : nullptr);
     const S om = (S)p.om;
     const S pref = (S)p.pref;
     // nodes without solid neighbours store along a straight line (FP64
@@ -1770,10 +1850,10 @@ __device__ __forceinline__ void psic_fix(const BatchArgs &A, const int blk)
 // two launches of an update may run side by side on two streams.  With BND
 // the bulk launch does the boundary nodes itself (small steps, where a
 // separate fix-up launch would cost more than it saves).
-template <class S, int V, bool BND>
+template <class S, int V, bool BND, bool ST = false>
 __global__ __launch_bounds__(256) void k_mu(BatchArgs A)
 {
-    if (V == 1) mu_one<S, BND>(A, blockIdx.x);
+    if (V == 1) mu_one<S, BND, ST>(A, blockIdx.x);
     else mu_vec<S, (V > 1 ? V : 2), BND>(A, blockIdx.x);
 }
 
@@ -2268,7 +2348,8 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
         if (B.nopsi) return;  // single phase: mu stays 0
         if (split && B.special) k_mu_bnd<S, true><<<gfix, GCHUNK, 0, ss>>>(a);
         else if (split) k_mu_bnd<S, false><<<gfix, GCHUNK, 0, ss>>>(a);
-        if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
+        if (B.stress) k_mu<S, 1, false, true><<<B.nblocks[0], 256, 0, s>>>(a);
+        else if (vm == 4 && bi) k_mu<S, V4, true><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 4) k_mu<S, V4, false><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 2 && bi) k_mu<S, 2, true><<<B.nblocks[0], 256, 0, s>>>(a);
         else if (vm == 2) k_mu<S, 2, false><<<B.nblocks[0], 256, 0, s>>>(a);
@@ -2287,7 +2368,7 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (tm) tm->end(0, s);
     if (tm) tm->begin(1, s);
-    if (B.solute_force) k_collide<P, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
+    if (B.solute_force || B.stress) k_collide<P, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.nopsi && B.vec[1] <= 1) k_collide<P, false, true><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.vec[1] == 4) k_collide_v<P, V4><<<B.nblocks[1], 256, 0, s>>>(B.args);
     else if (B.vec[1] == 2) k_collide_v<P, 2><<<B.nblocks[1], 256, 0, s>>>(B.args);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "csrc", "liblbphoretic.so")
 
 LB_FP64, LB_FP32, LB_FP16_STORAGE = 0, 1, 2
-LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID, LB_CAPILLARY_FORCE = 1, 2, 4   # lb_params.flags options
+LB_SOLUTE_FORCE, LB_EXPLICIT_COLLOID, LB_CAPILLARY_FORCE, LB_STRESS_FORM = 1, 2, 4, 8  # lb_params.flags
 PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp16": LB_FP16_STORAGE}
 STATUS = {0: "LB_OK", -1: "LB_E_INVALID", -2: "LB_E_OOM", -3: "LB_E_DEVICE",
           -4: "LB_E_UNSTABLE", -5: "LB_E_STATE"}

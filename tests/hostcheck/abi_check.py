@@ -108,6 +108,17 @@ def main():
     lb.batch_step([other, sb], 2)
     sb.close()
     other.close()
+    # the divergence-form solvent force (one-node forms, fix-ups, 7 more
+    # arena fields), alone and batched beside a box without it
+    dw = dict(w, params=dict(w["params"], flags=lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM))
+    db = lb.from_spec(dw, precision="fp32", stream=st.value)
+    db.step(3)
+    other = lb.from_spec(w, precision="fp32", stream=st.value)
+    lb.batch_step([other, db], 2)
+    db.close()
+    other.close()
+    expect_error(lambda: lb.Box((32, 32, 32), "fp32",
+                                **dict(lb.spec_params(w), flags=lb.LB_STRESS_FORM)))
     soft = lb.Box((32, 32, 32), "fp32", **dict(lb.spec_params(w), soft_eps=0.05, soft_sigma=1.0,
                                                soft_nu=1.0, soft_hc=1.0))
     soft.init_fields(np.zeros(32 ** 3), np.zeros(32 ** 3))

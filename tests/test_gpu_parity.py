@@ -137,10 +137,14 @@ def test_fp64_several_moving_colloids(seed):
 @pytest.mark.parametrize("flags", [lb.LB_SOLUTE_FORCE, lb.LB_EXPLICIT_COLLOID,
                                    lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID,
                                    lb.LB_CAPILLARY_FORCE,
-                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID | lb.LB_CAPILLARY_FORCE])
+                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID | lb.LB_CAPILLARY_FORCE,
+                                   lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM,
+                                   lb.LB_SOLUTE_FORCE | lb.LB_EXPLICIT_COLLOID | lb.LB_CAPILLARY_FORCE
+                                   | lb.LB_STRESS_FORM])
 def test_fp64_options_match_oracle(flags):
     # the options (solvent force -c grad(mu_c); explicit rigid-body update;
-    # capillary stress on the particles) against the oracle's: moving
+    # capillary stress on the particles; the divergence-form solvent force)
+    # against the oracle's: moving
     # particles with cover/uncover, 60 and 90 degree wetting, solute emitted
     # and a nonzero E so that chi varies, 40 steps
     shape = (40, 36, 34)
