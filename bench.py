@@ -229,13 +229,15 @@ def paper_regime_run(torch, lb, I, steps=2000, warmup=200):
     an active Janus sphere on the interface and an inactive one in the bulk,
     FP32, graph-replayed on a non-default stream.  Beside it the same box in
     the default form (M_psi = 0.1, one psi/c update per step, no capillary
-    stress), to show what the sub-steps and the stress cost.  Tuned launch
+    stress), to show what the sub-steps and the stress cost, and the paper's
+    form with the divergence-form solvent force (LB_STRESS_FORM).  Tuned launch
     shapes where the cache has them."""
     from paper_2202_01631_amd import tune
     cols = [I.janus((16.3, 47.6, 48.2), (0.29, 0.94, 0.19), 4.5, alpha=1e-3, mu=0.3, theta=60.0),
             I.janus((33.0, 20.4, 70.7), (0.0, 0.0, 1.0), 4.5, alpha=0.0, mu=0.2, theta=90.0)]
     out = {}
-    for name, over in (("paper", {}), ("default_form", dict(M_psi=0.1, ch_substeps=1, flags=0))):
+    for name, over in (("paper", {}), ("default_form", dict(M_psi=0.1, ch_substeps=1, flags=0)),
+                       ("paper_stress_form", dict(flags=lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM))):
         w = I.workload_paper(cols, E=-0.25)
         w["params"].update(over)
         st = torch.cuda.Stream()

@@ -142,7 +142,9 @@ typedef struct {
  *                      sub-steps, over 8x10^4 steps (nine trap cases, a GPU
  *                      test); runs with M_psi = 0.1 or R = 9 near an
  *                      interface can diverge (reported through the error
- *                      bits and LB_E_UNSTABLE).
+ *                      bits and LB_E_UNSTABLE): the fluid keeps the
+ *                      potential-form force, and the pair does not conserve
+ *                      momentum.  LB_STRESS_FORM removes that defect.
  * LB_STRESS_FORM       (with LB_CAPILLARY_FORCE) the solvent force of the psi
  *                      free energy in divergence form: -div P by the same
  *                      isotropic stencil, (div P)_b = 3 sum_i w_i c_ia
