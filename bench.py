@@ -439,7 +439,13 @@ def main():
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4),
                      "traffic_frac_of_copy": (round(traffic / (kc * 1e-3) / 1e9 / copy_gbs, 4)
-                                              if traffic else None)},
+                                              if traffic else None),
+                     # the whole step beside the kernel: its algorithmic bytes
+                     # (state read and written once) at the measured rate
+                     "step_bytes_per_lu": STEP_BYTES[main_prec],
+                     "step_achieved": round(r["mlups"] * 1e6 * STEP_BYTES[main_prec] / 1e9, 1),
+                     "step_frac": round(r["mlups"] * 1e6 * STEP_BYTES[main_prec] / 1e9
+                                        / HBM_PEAK_GBS, 4)},
         "reps_ms_per_step": r["reps_ms_per_step"],
         "median_ms_per_step": r["median_ms_per_step"],
         "step_roofline": {p: {"mlups": round(v["mlups"], 1),
