@@ -135,3 +135,33 @@ def test_spheroid_options_validated():
         with pytest.raises(lb.LBError):
             box.add_colloids([col])
         box.close()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "fp32"])
+def test_every_option_together_batched_equals_alone(precision):
+    # spheroids (one with a pattern), the capillary stress with the
+    # divergence-form force, the explicit update and two psi/c sub-steps in
+    # one box, batched beside a box of plain spheres: both boxes give the bits
+    # they give alone, and the run stays finite
+    import torch
+    shape = (44, 38, 34)
+    flags = (lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM | lb.LB_EXPLICIT_COLLOID)
+    spec = _spec(shape, 57, _spheroids(), precision=precision, flags=flags, ch_substeps=2)
+    other = _spec((40, 36, 34), 58, [I.janus((18.2, 17.1, 16.9), (0.0, 0.6, 0.8), 4.4)],
+                  precision=precision, ch_substeps=2)
+    s = torch.cuda.Stream()
+    a = lb.from_spec(spec, stream=s)
+    b = lb.from_spec(other, stream=s)
+    lb.batch_step([a, b], 30)
+    a1 = lb.from_spec(spec, stream=s)
+    b1 = lb.from_spec(other, stream=s)
+    a1.step(30)
+    b1.step(30)
+    assert np.array_equal(a.populations(), a1.populations())
+    assert np.array_equal(b.populations(), b1.populations())
+    assert np.array_equal(a.links(), a1.links())
+    for x in (a, b):
+        t, _ = x.observables()
+        assert t["error_bits"] == 0
+    for x in (a, b, a1, b1):
+        x.close()
