@@ -223,6 +223,96 @@ def serving_run(torch, I, nreq, rate, step_scale):
     return summ
 
 
+def _field_errors(a, b, fluid):
+    """Per field max|a - b| over the fluid nodes relative to max|b| (floors:
+    rho, psi 1; c 1e-6; u 1e-8), the measure the precision forms are stated in."""
+    out = {}
+    for key, floor in (("rho", 1.0), ("psi", 1.0), ("c", 1e-6), ("u", 1e-8)):
+        x, y = a[key][..., fluid], b[key][..., fluid]
+        out[key] = float(abs(x - y).max() / max(float(abs(y).max()), floor))
+    # the velocity also absolutely: in a nearly quiescent box max|u| is small
+    out["u_abs"] = float(abs(a["u"][..., fluid] - b["u"][..., fluid]).max())
+    out["u_max"] = float(abs(b["u"][..., fluid]).max())
+    return out
+
+
+def _far_from_solid(solid, shape, reach):
+    """Nodes more than `reach` face steps from every node of `solid` (periodic)."""
+    import numpy as np
+    nx, ny, nz = shape
+    grown = solid.reshape(nz, ny, nx).copy()
+    for _ in range(reach):
+        g = grown.copy()
+        for ax in range(3):
+            g |= np.roll(grown, 1, axis=ax) | np.roll(grown, -1, axis=ax)
+        grown = g
+    return ~grown.reshape(-1)
+
+
+def precision_runs(torch, lb, I, steps1=10000, steps2=5000, every=1000):
+    """The precision forms against the FP64 GPU path (itself held to the oracle
+    by the parity tests): 128^3 FP32 and one sphere of radius 8 on the
+    interface for 10^4 steps, the particle's trajectory sampled every 1000
+    steps; 256^3 with 64 spheres in FP16 storage for 5000 steps, per-field
+    errors and the particles' velocities at the end.  Each run is timed."""
+    import numpy as np
+    out = {}
+    for name, spec, prec, steps in (("box128_fp32_vs_fp64", I.workload_single(n=128), "fp32", steps1),
+                                    ("box256_fp16_vs_fp64",
+                                     I.workload_many(n=256, count=64, radius=6.0), "fp16", steps2)):
+        runs = {}
+        for p in (prec, "fp64"):
+            st = torch.cuda.Stream()
+            b = lb.from_spec(spec, precision=p, stream=st)
+            from paper_2202_01631_amd import tune
+            tune.apply(b)
+            traj, t = [], 0.0
+            for k in range(steps // every):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.step(every)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+                _, cols = b.observables(check=False)
+                traj.append([c["pos"].copy() for c in cols])
+            tot, cols = b.observables(check=False)
+            runs[p] = dict(traj=traj, cols=cols, fields=b.fields(), fluid=b.owner() < 0,
+                           bits=tot["error_bits"], mlups=b.N * steps / t / 1e6)
+            b.close()
+        lo, hi = runs[prec], runs["fp64"]
+        L = np.array(spec["shape"], dtype=float)
+
+        def dpos(p, q):
+            d = (p - q + L / 2) % L - L / 2
+            return float(np.abs(d).max())
+        traj_dev = [max(dpos(p, q) for p, q in zip(a, b)) for a, b in zip(lo["traj"], hi["traj"])]
+        vmax = max(float(np.abs(c["vel"]).max()) for c in hi["cols"])
+        vdev = max(float(np.abs(a["vel"] - b["vel"]).max()) for a, b in zip(lo["cols"], hi["cols"]))
+        out[name] = dict(
+            steps=steps, precision=prec,
+            mlups={prec: round(lo["mlups"], 1), "fp64": round(hi["mlups"], 1)},
+            # nodes whose solid/fluid state differs (the particles' paths
+            # differ slightly); the field errors are over the nodes fluid in both
+            owner_differences=int((lo["fluid"] != hi["fluid"]).sum()),
+            field_errors={k: float("%.3g" % v) for k, v in
+                          _field_errors(lo["fields"], hi["fields"],
+                                        lo["fluid"] & hi["fluid"]).items()},
+            # the same away from the particles (more than 3 face steps from a
+            # solid node of either run), where cover/uncover at slightly
+            # different times leaves local transients
+            field_errors_away_from_particles={
+                k: float("%.3g" % v) for k, v in
+                _field_errors(lo["fields"], hi["fields"],
+                              _far_from_solid(~(lo["fluid"] & hi["fluid"]), spec["shape"],
+                                              3)).items()},
+            # largest particle position difference at every sample (every `every` steps)
+            position_deviation=[float("%.3g" % v) for v in traj_dev], sample_every=every,
+            velocity_deviation_of_max_v=float("%.3g" % (vdev / max(vmax, 1e-30))),
+            velocity_deviation=float("%.3g" % vdev), max_v=float("%.3g" % vmax),
+            error_bits=[lo["bits"], hi["bits"]])
+    return out
+
+
 def paper_regime_run(torch, lb, I, steps=2000, warmup=200):
     """The paper's own regime (Sec. II.C): 64 x 96 x 96, M_psi = 0.4 in two
     psi/c sub-steps, D_c = 0.05, R = 4.5, capillary stress on the particles;
@@ -466,6 +556,12 @@ def main():
             out["batched_sweep"] = {"error": str(e)}
         log("[bench] batched sweep %s" % out["batched_sweep"])
     if not args.only:
+        log("[bench] precision forms against the FP64 GPU path (128^3 x 10^4, 256^3 x 5000)")
+        try:
+            out["precision_forms"] = precision_runs(torch, lb, I)
+        except lb.LBError as e:
+            out["precision_forms"] = {"error": str(e)}
+        log("[bench] precision forms %s" % out["precision_forms"])
         log("[bench] paper regime 64x96x96")
         try:
             out["paper_regime"] = paper_regime_run(torch, lb, I)
