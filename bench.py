@@ -253,15 +253,20 @@ def precision_runs(torch, lb, I, steps1=10000, steps2=5000, every=1000):
     """The precision forms against the FP64 GPU path (itself held to the oracle
     by the parity tests): 128^3 FP32 and one sphere of radius 8 on the
     interface for 10^4 steps, the particle's trajectory sampled every 1000
-    steps; 256^3 with 64 spheres in FP16 storage for 5000 steps, per-field
-    errors and the particles' velocities at the end.  Each run is timed."""
+    steps; 256^3 with 64 spheres in FP16 storage for 5000 steps, with FP32
+    beside it as the reference for how far round-off alone carries that
+    many-particle run, per-field errors and the particles' velocities at the
+    end.  Each run is timed."""
     import numpy as np
     out = {}
-    for name, spec, prec, steps in (("box128_fp32_vs_fp64", I.workload_single(n=128), "fp32", steps1),
-                                    ("box256_fp16_vs_fp64",
-                                     I.workload_many(n=256, count=64, radius=6.0), "fp16", steps2)):
+    many = I.workload_many(n=256, count=64, radius=6.0)
+    cases = (("box128_fp32_vs_fp64", I.workload_single(n=128), ("fp32",), steps1),
+             # FP32 beside FP16 storage: how far round-off alone carries the
+             # many-particle run in the same number of steps
+             ("box256_fp16_vs_fp64", many, ("fp16", "fp32"), steps2))
+    for name, spec, precs, steps in cases:
         runs = {}
-        for p in (prec, "fp64"):
+        for p in precs + ("fp64",):
             st = torch.cuda.Stream()
             b = lb.from_spec(spec, precision=p, stream=st)
             from paper_2202_01631_amd import tune
@@ -279,37 +284,42 @@ def precision_runs(torch, lb, I, steps1=10000, steps2=5000, every=1000):
             runs[p] = dict(traj=traj, cols=cols, fields=b.fields(), fluid=b.owner() < 0,
                            bits=tot["error_bits"], mlups=b.N * steps / t / 1e6)
             b.close()
-        lo, hi = runs[prec], runs["fp64"]
+        hi = runs["fp64"]
         L = np.array(spec["shape"], dtype=float)
 
         def dpos(p, q):
             d = (p - q + L / 2) % L - L / 2
             return float(np.abs(d).max())
-        traj_dev = [max(dpos(p, q) for p, q in zip(a, b)) for a, b in zip(lo["traj"], hi["traj"])]
-        vmax = max(float(np.abs(c["vel"]).max()) for c in hi["cols"])
-        vdev = max(float(np.abs(a["vel"] - b["vel"]).max()) for a, b in zip(lo["cols"], hi["cols"]))
-        out[name] = dict(
-            steps=steps, precision=prec,
-            mlups={prec: round(lo["mlups"], 1), "fp64": round(hi["mlups"], 1)},
-            # nodes whose solid/fluid state differs (the particles' paths
-            # differ slightly); the field errors are over the nodes fluid in both
-            owner_differences=int((lo["fluid"] != hi["fluid"]).sum()),
-            field_errors={k: float("%.3g" % v) for k, v in
-                          _field_errors(lo["fields"], hi["fields"],
-                                        lo["fluid"] & hi["fluid"]).items()},
-            # the same away from the particles (more than 3 face steps from a
-            # solid node of either run), where cover/uncover at slightly
-            # different times leaves local transients
-            field_errors_away_from_particles={
-                k: float("%.3g" % v) for k, v in
-                _field_errors(lo["fields"], hi["fields"],
-                              _far_from_solid(~(lo["fluid"] & hi["fluid"]), spec["shape"],
-                                              3)).items()},
-            # largest particle position difference at every sample (every `every` steps)
-            position_deviation=[float("%.3g" % v) for v in traj_dev], sample_every=every,
-            velocity_deviation_of_max_v=float("%.3g" % (vdev / max(vmax, 1e-30))),
-            velocity_deviation=float("%.3g" % vdev), max_v=float("%.3g" % vmax),
-            error_bits=[lo["bits"], hi["bits"]])
+        for prec in precs:
+            lo = runs[prec]
+            traj_dev = [max(dpos(p, q) for p, q in zip(a, b))
+                        for a, b in zip(lo["traj"], hi["traj"])]
+            vmax = max(float(np.abs(c["vel"]).max()) for c in hi["cols"])
+            vdev = max(float(np.abs(a["vel"] - b["vel"]).max())
+                       for a, b in zip(lo["cols"], hi["cols"]))
+            key = name if prec == precs[0] else name.replace(precs[0], prec)
+            out[key] = dict(
+                steps=steps, precision=prec,
+                mlups={prec: round(lo["mlups"], 1), "fp64": round(hi["mlups"], 1)},
+                # nodes whose solid/fluid state differs (the particles' paths
+                # differ slightly); the field errors are over the nodes fluid in both
+                owner_differences=int((lo["fluid"] != hi["fluid"]).sum()),
+                field_errors={k: float("%.3g" % v) for k, v in
+                              _field_errors(lo["fields"], hi["fields"],
+                                            lo["fluid"] & hi["fluid"]).items()},
+                # the same away from the particles (more than 3 face steps from a
+                # solid node of either run), where cover/uncover at slightly
+                # different times leaves local transients
+                field_errors_away_from_particles={
+                    k: float("%.3g" % v) for k, v in
+                    _field_errors(lo["fields"], hi["fields"],
+                                  _far_from_solid(~(lo["fluid"] & hi["fluid"]), spec["shape"],
+                                                  3)).items()},
+                # largest particle position difference at every sample (every `every` steps)
+                position_deviation=[float("%.3g" % v) for v in traj_dev], sample_every=every,
+                velocity_deviation_of_max_v=float("%.3g" % (vdev / max(vmax, 1e-30))),
+                velocity_deviation=float("%.3g" % vdev), max_v=float("%.3g" % vmax),
+                error_bits=[lo["bits"], hi["bits"]])
     return out
 
 
