@@ -166,3 +166,27 @@ def test_oversized_request_is_refused():
     srv.submit(0, spec, 0.0)
     res = srv.run()
     assert "error" in res[0]
+
+
+def test_bench_error_helpers():
+    # the precision leg's measures: the relative error per field with its
+    # floor, and the mask of nodes beyond a reach from solid nodes
+    import sys
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    shape = (8, 7, 6)
+    N = 336
+    solid = np.zeros(N, bool)
+    solid[0] = True
+    far1 = bench._far_from_solid(solid, shape, 1)
+    assert far1.sum() == N - 7                   # the node and its 6 face neighbours
+    far2 = bench._far_from_solid(solid, shape, 2)
+    assert far2.sum() == N - 25                  # Manhattan distance <= 2: 1 + 6 + 18
+    a = dict(rho=np.ones(N), psi=np.zeros(N), c=np.full(N, 1e-7), u=np.zeros((3, N)))
+    b = dict(rho=np.ones(N) + 1e-3, psi=np.full(N, 0.5), c=np.zeros(N), u=np.zeros((3, N)))
+    b["u"][0, 3] = 2e-3
+    e = bench._field_errors(a, b, np.ones(N, bool))
+    assert abs(e["rho"] - 1e-3 / (1 + 1e-3)) < 1e-12
+    assert e["psi"] == 0.5 and abs(e["c"] - 1e-7 / 1e-6) < 1e-12  # floors 1 and 1e-6
+    assert e["u"] == 1.0 and e["u_abs"] == 2e-3 and e["u_max"] == 2e-3
