@@ -93,6 +93,8 @@ struct or_ctx {
     double *F0, *T0, *zeta, *trF, *trT, *Flast, *Tlast;
     int *lk, *ln, *ld, *lcap;
     long nl, lcapacity;
+    double *lslip;                /* slip of each link in the last link loop */
+    long nslip;                   /* links that loop covered (0: none) */
     long step;
     int stage;
     int err;
@@ -399,10 +401,11 @@ static void free_colloids(or_ctx *c)
 {
     free(c->col); free(c->F0); free(c->T0); free(c->zeta); free(c->trF); free(c->trT);
     free(c->Flast); free(c->Tlast);
-    free(c->lk); free(c->ln); free(c->ld); free(c->lcap);
+    free(c->lk); free(c->ln); free(c->ld); free(c->lcap); free(c->lslip);
     c->col = NULL; c->F0 = c->T0 = c->zeta = c->trF = c->trT = c->Flast = c->Tlast = NULL;
     c->lk = c->ln = c->ld = c->lcap = NULL;
-    c->ncol = 0; c->nl = 0; c->lcapacity = 0;
+    c->lslip = NULL;
+    c->ncol = 0; c->nl = 0; c->lcapacity = 0; c->nslip = 0;
 }
 
 int or_destroy(or_ctx *c)
@@ -479,13 +482,16 @@ static void build_links(or_ctx *c)
         }
     }
     if (total > c->lcapacity) {
-        free(c->lk); free(c->ln); free(c->ld); free(c->lcap);
+        free(c->lk); free(c->ln); free(c->ld); free(c->lcap); free(c->lslip);
         c->lcapacity = total;
         c->lk = zalloc(sizeof(int) * total);
         c->ln = zalloc(sizeof(int) * total);
         c->ld = zalloc(sizeof(int) * total);
         c->lcap = zalloc(sizeof(int) * total);
+        c->lslip = zalloc(sizeof(double) * 3 * total);
+        c->nslip = 0;
     }
+    int same = c->nslip > 0 && total == c->nl; /* table unchanged so far */
     long *off = zalloc(sizeof(long) * (c->ncol + 1));
     for (int k = 1; k <= c->ncol; k++) off[k] = off[k - 1] + count[k - 1];
     for (long n = 0; n < c->N; n++) {
@@ -498,12 +504,14 @@ static void build_links(or_ctx *c)
             double r[3];
             disp(c, &c->col[k], x, y, z, d, 0.5, r);
             long l = off[k]++;
+            if (same && (c->lk[l] != k || c->ln[l] != (int)n || c->ld[l] != d)) same = 0;
             c->lk[l] = k;
             c->ln[l] = (int)n;
             c->ld[l] = d;
             c->lcap[l] = surface_cell(&c->col[k], r);
         }
     }
+    if (!same) c->nslip = 0; /* the slip record belongs to the old table */
     c->nl = total;
     free(count);
     free(off);
@@ -821,6 +829,7 @@ static void collide_stream(or_ctx *c)
         }
         double ng = nh[0] * g[0] + nh[1] * g[1] + nh[2] * g[2];
         for (int a = 0; a < 3; a++) slip[a] = mob * (g[a] - nh[a] * ng);
+        for (int a = 0; a < 3; a++) c->lslip[3 * l + a] = slip[a];
         rigid_velocity(q, r, ur);
         for (int a = 0; a < 3; a++) ub[a] = ur[a] + slip[a];
         double cd[3] = {(double)CX[d], (double)CY[d], (double)CZ[d]};
@@ -863,6 +872,7 @@ static void collide_stream(or_ctx *c)
         c->diag[OR_DIAG_SUM_DP + a] = sumdp[a];
     }
     c->diag[OR_DIAG_SUM_DMASS] = dmass;
+    c->nslip = c->nl;
 }
 
 /* step 2b (options, soft_eps > 0 or lub_hc > 0): soft-sphere repulsion and
@@ -1253,6 +1263,16 @@ int or_get_links(or_ctx *c, int32_t *rec4, int64_t cap, int64_t *n)
         rec4[4 * l + 2] = c->ld[l];
         rec4[4 * l + 3] = link_tag(&c->col[c->lk[l]], c->lcap[l]);
     }
+    return OR_OK;
+}
+
+int or_get_link_slip(or_ctx *c, double *slip3, int64_t cap)
+{
+    if (!c || !slip3) return OR_E_INVALID;
+    if (c->nslip == 0 || c->nslip != c->nl)
+        return fail(c, OR_E_STATE, "no slip record for the current link table");
+    if (cap < c->nl) return fail(c, OR_E_INVALID, "slip buffer too small");
+    for (long i = 0; i < 3 * c->nl; i++) slip3[i] = c->lslip[i];
     return OR_OK;
 }
 

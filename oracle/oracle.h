@@ -139,6 +139,10 @@ int or_set_populations(or_ctx *c, const double *f);
 int or_get_aux(or_ctx *c, double *mu, double *force, double *uforced);
 int or_get_owner(or_ctx *c, int32_t *owner);           /* -1 fluid, k solid */
 int or_get_links(or_ctx *c, int32_t *rec4, int64_t cap, int64_t *n);
+/* slip velocity (Eq. 4) of each link as the last step's link loop used it,
+ * 3 per link in link-table order; OR_E_STATE when the table has changed
+ * size since (a moving particle), OR_E_INVALID when cap < links */
+int or_get_link_slip(or_ctx *c, double *slip3, int64_t cap);
 int or_observables(or_ctx *c, or_totals *t, or_colloid *out, int32_t n);
 int or_colloid_diag(or_ctx *c, int32_t k, double *out40); /* F0[3] T0[3] zeta[36] -> see .c */
 int or_step_diag(or_ctx *c, double *out);              /* OR_DIAG_N doubles */

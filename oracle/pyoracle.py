@@ -94,6 +94,7 @@ def lib():
         L.or_get_aux.argtypes = [vp, dp, dp, dp]
         L.or_get_owner.argtypes = [vp, C.POINTER(C.c_int32)]
         L.or_get_links.argtypes = [vp, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]
+        L.or_get_link_slip.argtypes = [vp, dp, C.c_int64]
         L.or_observables.argtypes = [vp, C.POINTER(Totals), C.POINTER(Colloid), C.c_int32]
         L.or_colloid_diag.argtypes = [vp, C.c_int32, dp]
         L.or_step_diag.argtypes = [vp, dp]
@@ -254,6 +255,15 @@ class Oracle:
         self._check(lib().or_get_links(self._ctx, rec.ctypes.data_as(C.POINTER(C.c_int32)),
                                        n.value, C.byref(n)), "get_links")
         return rec[:n.value]
+
+    def link_slip(self):
+        """Slip velocity of every link in the last step's link loop, (links, 3),
+        in link-table order (fixed particles: the table is rebuilt each step)."""
+        n = len(self.links())
+        out = np.empty(3 * max(1, n))
+        self._check(lib().or_get_link_slip(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)), n),
+                    "get_link_slip")
+        return out[:3 * n].reshape(n, 3)
 
     def observables(self):
         t = Totals()

@@ -4,7 +4,8 @@ capillary stress.  Parity with the oracle over a few steps, then two
 regression checks of the physics the paper reports, without its data:
 
 * Fig. 3B / Eq. (Vp): in a single phase fluid the swimming speed is linear in
-  the two cap mobilities mu_- and mu_+;
+  the two cap mobilities mu_- and mu_+, and its size is Eq. (Vp)'s once the
+  per-link activity, the sink and the slip's sampling are accounted for;
 * Sec. III.B: an inactive particle with uniform mobility at a
   neutral-wetting interface is held by the capillary trap against a weak
   phoretic push, displaced away from the solute-rich phase for mu > 0, and
@@ -69,6 +70,65 @@ def test_paper_regime_parity():
         g.close()
 
 
+D3Q19 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+                  [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def _eq7_lattice_factors(R, ell):
+    """What Eq. 7 becomes on the lattice for a sphere of radius R centred on
+    a node, axis m = +x, emitting alpha per active link, with the sink's
+    screening length ell = sqrt(D/k_d).  Returns (n_active, screening,
+    stencil):
+    * n_active: links with m.n <= 0 at the midpoint, by enumeration; the
+      per-link activity alpha is the surface flux alpha n_active / (2 pi R^2);
+    * screening: the sink's reduction of the surface concentration's l = 1
+      mode for a given flux, from the screened solution c ~ cos(theta)
+      e^(-r/ell)(1 + r/ell)/r^2 against the unscreened cos(theta)/r^2:
+      2 / (2 + x^2/(1 + x)), x = R/ell;
+    * stencil: the fraction of the surface's tangential gradient that the
+      slip sees, sampling that screened field at the links' fluid nodes
+      with central differences, c(x) put in for a solid neighbour, weighted
+      as the links weigh the slip, sum 6 w_d c_d (c_d.s)."""
+    h = int(np.ceil(R)) + 3
+    ax = np.arange(-h, h + 1, dtype=np.float64)
+    X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    solid = r * r < R * R
+    prof = lambda q: np.exp(-q / ell) * (1.0 + q / ell) / (q / ell) ** 2
+    rr = np.where(solid, R, r)
+    c = np.where(solid, 0.0, X / rr * prof(rr))
+    fl = np.argwhere(~solid & (r < R + 2.0))
+    F_lat = F_ex = 0.0
+    n_act = 0
+    m = np.array([1.0, 0.0, 0.0])
+    for i, j, k in fl:
+        for d in range(1, 19):
+            a = np.array([i, j, k]) + D3Q19[d]
+            if not solid[tuple(a)]:
+                continue
+            p = np.array([ax[i], ax[j], ax[k]]) + 0.5 * D3Q19[d]
+            n = p / np.linalg.norm(p)
+            n_act += int(m @ p <= 0.0)
+            g = np.zeros(3)
+            for e in range(3):
+                up, dn = np.array([i, j, k]), np.array([i, j, k])
+                up[e] += 1
+                dn[e] -= 1
+                su, sd = solid[tuple(up)], solid[tuple(dn)]
+                cu = c[i, j, k] if su else c[tuple(up)]
+                cd = c[i, j, k] if sd else c[tuple(dn)]
+                g[e] = 0.5 * (cu - cd)
+            s_lat = g - n * (n @ g)
+            s_ex = prof(R) / R * (m - n * (n @ m))
+            cw = 6.0 * W19[d] * D3Q19[d][0]
+            F_lat += cw * (D3Q19[d] @ s_lat)
+            F_ex += cw * (D3Q19[d] @ s_ex)
+    x = R / ell
+    return n_act, 2.0 / (2.0 + x * x / (1.0 + x)), F_lat / F_ex
+
+
 def test_swim_speed_linear_in_the_cap_mobilities():
     # Fig. 3B: single phase (A = E = kappa = 0, psi = 0), alpha = 1e-3 on the
     # m.n <= 0 cap, axis +x.  Mean speed over steps 2500..7500 (averaging
@@ -100,6 +160,20 @@ def test_swim_speed_linear_in_the_cap_mobilities():
     assert 1.8 <= v[(0.2, 0.0)] / v[(0.1, 0.0)] <= 2.4
     mid = 0.5 * (v[(0.2, 0.0)] + v[(0.0, 0.2)])
     assert abs(v[(0.1, 0.1)] - mid) <= 0.1 * mid
+    # the magnitude: Eq. 7 with the per-link activity as a surface flux,
+    # times the two lattice factors of _eq7_lattice_factors (the sink's
+    # screening and the slip stencil's sampling of the surface gradient).
+    # The speeds lie within -20% .. +35% of that: close to it when the
+    # mobility sits on the emitting cap, higher when it sits on the inert
+    # cap
+    R, D, kd = 4.5, 0.05, 1e-3
+    n_act, screen, stencil = _eq7_lattice_factors(R, np.sqrt(D / kd))
+    flux = 1e-3 * n_act / (2.0 * np.pi * R * R)
+    for mu, speed in v.items():
+        pred = abs(mu[0] + mu[1]) * flux / (8.0 * D) * screen * stencil
+        flush_print("[swim] mu %s speed / lattice Eq. 7 %.3f (links %d, screening %.3f, "
+                    "stencil %.3f)" % (mu, speed / pred, n_act, screen, stencil))
+        assert 0.8 <= speed / pred <= 1.35, mu
 
 
 def test_interface_trapping_against_phoretic_push():
