@@ -4,6 +4,7 @@ bounce-back on links and of the implicit rigid-body update, the rotation of
 the particle axis, Eq. 10, and the direction and linearity of
 self-diffusiophoretic swimming (Sec. III.A, Fig. 3B)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -352,6 +353,66 @@ def test_slip_of_a_uniform_gradient_is_exact():
     F = np.array([math.fsum(v) for v in np.array(F).T])
     assert np.abs(o.colloid_diag(0)["F0"] - F).max() <= 1e-13
     o.close()
+
+
+def _cubic_array_drag_inverse(c):
+    """1/K for Stokes flow through a simple cubic array of spheres at solid
+    fraction c: the drag per sphere is 6 pi eta a U K, U the mean velocity
+    over the unit cell.  Hasimoto (1959) gave the terms to c^2, Sangani and
+    Acrivos (1982) the next two; the published coefficients."""
+    return (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c ** 2 + 3.9799 * c ** (8.0 / 3.0)
+            - 3.0734 * c ** (10.0 / 3.0))
+
+
+def test_fixed_sphere_drag_follows_the_periodic_array_law():
+    # bounce-back hydrodynamics (Sec. II.B) against Stokes flow through a
+    # periodic array: one fixed sphere (radius 2.7) in boxes of side 10 ... 16
+    # (solid fraction 0.07 ... 0.02), single phase, tau = 1 (nu = 1/6), fluid
+    # driven by a uniform body force g.  In the steady state the drag equals
+    # g times the fluid node count; the mean velocity U over the box (solid
+    # nodes at rest) is extrapolated from the slowest mode's exponential
+    # approach (three samples one relaxation time apart, Aitken).  The
+    # hydrodynamic radius a_h that makes 6 pi eta a_h U / K^-1(c(a_h)) the
+    # drag is then the same in every box to 2.5% -- the box-size dependence,
+    # a 30% change of the drag at fixed U, is the periodic array's -- and
+    # within a quarter lattice unit of the input radius.  A wrong viscosity
+    # or wall placement moves a_h by more; a missing periodic interaction
+    # spreads it.
+    g, nu, R = 1e-6, 1.0 / 6.0, 2.7
+    a_h = []
+    oracle.set_threads(min(8, os.cpu_count() or 1))  # results do not depend on it
+    for L in (10, 12, 14, 16):
+        N = L ** 3
+        o = oracle.Oracle((L, L, L), a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0, E=0.0, c_b0=0.0,
+                          D_c=0.1, k_d=0.0, tau=1.0, ext_force=(g, 0.0, 0.0))
+        o.init_fields(np.zeros(N), np.zeros(N))
+        o.add_colloids([dict(pos=(L / 2 + 0.23, L / 2 - 0.17, L / 2 + 0.11), m=(0, 0, 1),
+                             radius=R, fixed=1)])
+        drag = g * int((o.owner() < 0).sum())
+        # relaxation time of the mean flow: box mass over the drag coefficient
+        tr = int(N * _cubic_array_drag_inverse(4.0 / 3.0 * math.pi * R ** 3 / N)
+                 / (6.0 * math.pi * nu * R))
+        o.step(5 * tr)
+        u = []
+        for _ in range(3):
+            o.step(tr)
+            u.append(o.fields()["u"][0].sum() / N)
+        U = u[2] - (u[2] - u[1]) ** 2 / ((u[2] - u[1]) - (u[1] - u[0]))
+        assert abs(U - u[2]) <= 5e-3 * U   # nearly steady already
+        lo, hi = 0.5 * R, 1.5 * R
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            c = 4.0 / 3.0 * math.pi * mid ** 3 / N
+            if 6.0 * math.pi * nu * U * mid / _cubic_array_drag_inverse(c) > drag:
+                hi = mid
+            else:
+                lo = mid
+        a_h.append(lo)
+        o.close()
+    oracle.set_threads(1)
+    m = float(np.mean(a_h))
+    assert max(a_h) - min(a_h) <= 0.025 * m, a_h
+    assert abs(m - R) <= 0.25, a_h
 
 
 def test_explicit_update_conserves_momentum():
