@@ -359,9 +359,21 @@ const char *lb_last_error(const lb_ctx *ctx);
  * lb_wetting_H: H of Eqs. 9-10 for a contact angle in degrees,
  *   cos(theta) = ((1+h)^(3/2) - (1-h)^(3/2))/2, h = H / sqrt(kappa b),
  *   solved for h in [-1, 1] by bisection; NaN if kappa b <= 0.
+ * lb_wetting_H_lattice: H for which the lattice itself realises the contact
+ *   angle theta on a flat wall (Eqs. 8-9 discretised as the library does: the
+ *   wall energy H psi at the fluid nodes next to the solid, the discrete
+ *   gradient energy of the face differences).  Young's cosine is
+ *   (gamma(+psi_b) - gamma(-psi_b)) / sigma of the discrete one-dimensional
+ *   minimisers (psi_b = sqrt(-a/b); sigma the lower of the kinks centred
+ *   between and on nodes); H found by bisection in [-sqrt(kappa b),
+ *   sqrt(kappa b)].  For interfaces a few nodes wide Eq. 10 over-states the
+ *   wetting this discretisation gives (the paper's a, b, kappa: Eq. 10's H
+ *   for 60 degrees realises about 43); for wide interfaces the two agree.
+ *   NaN unless a < 0 < b and kappa > 0, or when theta is beyond that range.
  * lb_solubility_E: E of Eq. 1 giving an oil/water ratio of the equilibrium
  *   solute c0(psi) = c_b0 + E tanh psi at psi = -1 and +1. */
 double lb_wetting_H(double theta_deg, double kappa, double b);
+double lb_wetting_H_lattice(double theta_deg, double a, double b, double kappa);
 double lb_solubility_E(double ratio, double c_b0);
 
 #ifdef __cplusplus

@@ -1373,6 +1373,108 @@ double or_wetting_H(double theta_deg, double kappa, double b)
     return 0.5 * (lo + hi) * sqrt(kappa * b);
 }
 
+/* The contact angle the lattice realises (test infrastructure: the reading
+ * of Eqs. 8-10 on this lattice).  The wetting ghost of mu_psi is the
+ * derivative of
+ *   E = sum_nodes [f(psi) - f(psi_b)] + kappa/2 sum_faces (difference)^2
+ *       + H * (psi at the fluid nodes next to the wall),
+ * so on a flat wall the state is a one-dimensional chain psi_1, psi_2, ...
+ * held at a bulk value far away.  Young: cos(theta) = (gamma_+ - gamma_-) /
+ * sigma, gamma_s the least E of the chain against bulk s psi_b and sigma the
+ * least E of a free interface between -psi_b and +psi_b.  Each minimum by
+ * Newton steps on the exact gradient and tridiagonal Hessian, halved until
+ * E does not increase. */
+static double chain_E(const double *q, int n, double a, double b, double kappa,
+                      double H, int wall, double lo, double hi)
+{
+    double pb2 = -a / b, fb = a / 2.0 * pb2 + b / 4.0 * pb2 * pb2, E = 0.0;
+    for (int i = 0; i < n; i++) {
+        E += a / 2.0 * q[i] * q[i] + b / 4.0 * q[i] * q[i] * q[i] * q[i] - fb;
+        double right = (i + 1 < n) ? q[i + 1] : hi;
+        E += kappa / 2.0 * (right - q[i]) * (right - q[i]);
+    }
+    if (wall) E += H * q[0];
+    else E += kappa / 2.0 * (q[0] - lo) * (q[0] - lo);
+    return E;
+}
+
+static double chain_min(double *q, int n, double a, double b, double kappa, double H,
+                        int wall, double lo, double hi)
+{
+    double *g = malloc(sizeof(double) * n), *dg = malloc(sizeof(double) * n);
+    double *step = malloc(sizeof(double) * n), *t = malloc(sizeof(double) * n);
+    double *cc = malloc(sizeof(double) * n);
+    double E = chain_E(q, n, a, b, kappa, H, wall, lo, hi);
+    for (int it = 0; it < 200; it++) {
+        double worst = 0.0;
+        for (int i = 0; i < n; i++) {
+            double left = (i > 0) ? q[i - 1] : lo, right = (i + 1 < n) ? q[i + 1] : hi;
+            g[i] = a * q[i] + b * q[i] * q[i] * q[i] + kappa * (q[i] - right);
+            dg[i] = a + 3.0 * b * q[i] * q[i] + kappa;
+            if (i > 0 || !wall) { g[i] += kappa * (q[i] - left); dg[i] += kappa; }
+            if (i == 0 && wall) g[i] += H;
+            if (fabs(g[i]) > worst) worst = fabs(g[i]);
+        }
+        if (worst < 1e-15) break;
+        /* solve (tridiag: dg on the diagonal, -kappa beside it) step = -g */
+        cc[0] = -kappa / dg[0];
+        step[0] = -g[0] / dg[0];
+        for (int i = 1; i < n; i++) {
+            double den = dg[i] + kappa * cc[i - 1];
+            cc[i] = -kappa / den;
+            step[i] = (-g[i] + kappa * step[i - 1]) / den;
+        }
+        for (int i = n - 2; i >= 0; i--) step[i] -= cc[i] * step[i + 1];
+        double s = 1.0, Et = E;
+        while (s > 1e-12) {
+            for (int i = 0; i < n; i++) t[i] = q[i] + s * step[i];
+            Et = chain_E(t, n, a, b, kappa, H, wall, lo, hi);
+            if (Et <= E) break;
+            s /= 2.0;
+        }
+        if (s <= 1e-12) break;
+        for (int i = 0; i < n; i++) q[i] = t[i];
+        E = Et;
+    }
+    free(g); free(dg); free(step); free(t); free(cc);
+    return E;
+}
+
+double or_lattice_cos(double a, double b, double kappa, double H)
+{
+    double pb = sqrt(-a / b), w = sqrt(2.0 * kappa / -a);
+    int n = (int)(16.0 * w) + 1;
+    if (n < 64) n = 64;
+    double *q = malloc(sizeof(double) * 2 * n);
+    double gp, gm, sigma = 0.0;
+    for (int i = 0; i < n; i++) q[i] = pb;
+    gp = chain_min(q, n, a, b, kappa, H, 1, 0.0, pb);
+    for (int i = 0; i < n; i++) q[i] = -pb;
+    gm = chain_min(q, n, a, b, kappa, H, 1, 0.0, -pb);
+    for (int centre = 0; centre < 2; centre++) {
+        /* kink started between two nodes, then on a node; keep the lower */
+        for (int i = 0; i < 2 * n; i++) q[i] = pb * tanh((i - n + 0.5 * centre) / w);
+        double s = chain_min(q, 2 * n, a, b, kappa, 0.0, 0, -pb, pb);
+        if (centre == 0 || s < sigma) sigma = s;
+    }
+    free(q);
+    return (gp - gm) / sigma;
+}
+
+double or_wetting_H_lattice(double theta_deg, double a, double b, double kappa)
+{
+    if (!(a < 0.0 && b > 0.0 && kappa > 0.0)) return NAN;
+    double target = cos(theta_deg * M_PI / 180.0), Hmax = sqrt(kappa * b);
+    double lo = -Hmax, hi = Hmax;
+    if (target < or_lattice_cos(a, b, kappa, lo) || target > or_lattice_cos(a, b, kappa, hi))
+        return NAN;
+    for (int it = 0; it < 60; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (or_lattice_cos(a, b, kappa, mid) < target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* solubility ratio r = <c>_oil / <c>_water of the equilibrium c0(psi) =
  * c_b0 + E tanh(psi) (Eq. 1) at psi = -1 (oil) and +1 (water):
  * r = (c_b0 - E tanh 1) / (c_b0 + E tanh 1). */

@@ -149,6 +149,10 @@ int or_step_diag(or_ctx *c, double *out);              /* OR_DIAG_N doubles */
 int or_lattice(int32_t *cvec57, double *w19);
 int or_set_threads(int32_t n);                         /* per-node loops; results unchanged */
 double or_wetting_H(double theta_deg, double kappa, double b);
+/* the flat-wall contact angle this lattice realises: Young's cosine for H,
+ * and the H giving theta (NaN unless a < 0 < b, kappa > 0 and theta in range) */
+double or_lattice_cos(double a, double b, double kappa, double H);
+double or_wetting_H_lattice(double theta_deg, double a, double b, double kappa);
 double or_solubility_E(double ratio, double c_b0);
 const char *or_last_error(const or_ctx *c);
 

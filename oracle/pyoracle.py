@@ -105,6 +105,10 @@ def lib():
         L.or_set_threads(int(os.environ.get("ORACLE_THREADS", "1")))
         L.or_wetting_H.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_wetting_H.restype = C.c_double
+        L.or_lattice_cos.argtypes = [C.c_double] * 4
+        L.or_lattice_cos.restype = C.c_double
+        L.or_wetting_H_lattice.argtypes = [C.c_double] * 4
+        L.or_wetting_H_lattice.restype = C.c_double
         L.or_solubility_E.argtypes = [C.c_double, C.c_double]
         L.or_solubility_E.restype = C.c_double
         L.or_last_error.argtypes = [vp]
@@ -304,6 +308,14 @@ def wetting_H(theta_deg, kappa, b):
     return lib().or_wetting_H(float(theta_deg), float(kappa), float(b))
 
 
+def lattice_cos(a, b, kappa, H):
+    return lib().or_lattice_cos(float(a), float(b), float(kappa), float(H))
+
+
+def wetting_H_lattice(theta_deg, a, b, kappa):
+    return lib().or_wetting_H_lattice(float(theta_deg), float(a), float(b), float(kappa))
+
+
 def solubility_E(ratio, c_b0):
     return lib().or_solubility_E(float(ratio), float(c_b0))
 
@@ -321,7 +333,10 @@ def from_spec(spec, steps=None):
     for d in spec.get("colloids", []):
         q = dict(d)
         if "H" not in q:
-            q["H"] = wetting_H(q.get("contact_angle", 90.0), p["kappa"], p["b"])
+            th = q.get("contact_angle", 90.0)
+            # Eq. 10 by default; "lattice": the angle this lattice realises
+            q["H"] = (wetting_H_lattice(th, p["a"], p["b"], p["kappa"])
+                      if spec.get("wetting_map") == "lattice" else wetting_H(th, p["kappa"], p["b"]))
         cols.append(q)
     if cols:
         o.add_colloids(cols)

@@ -1475,6 +1475,125 @@ double lb_wetting_H(double theta_deg, double kappa, double b)
     return 0.5 * (lo + hi) * sqrt(kappa * b);
 }
 
+}  // extern "C"
+
+// ------------------------------------------- wetting map of the lattice
+// The wetting ghost of the chemical potential (psi - (H/kappa)|e.n| at a
+// solid face neighbour) is the derivative of the discrete free energy
+//   sum_x [f(psi) - f_b] + kappa/2 sum_faces (psi' - psi)^2 + H sum_wall psi,
+// the wall sum over the fluid nodes next to the solid, weighted by |e.n| per
+// solid face neighbour (H per unit area for any wall orientation).  On a flat
+// wall this is a one-dimensional chain; the contact angle it realises follows
+// from Young's balance of the discrete tensions.  Minimisers by Newton's method
+// on the tridiagonal Hessian with a backtracking line search.
+namespace {
+
+struct Chain {
+    double a, b, kappa, H;
+    bool wall;                 // node 0 next to the wall (else pinned at `left`)
+    double left, right;        // pinned values beyond the ends
+    std::vector<double> p;
+};
+
+double chain_energy(const Chain &c, const std::vector<double> &p)
+{
+    const double pb2 = -c.a / c.b, fb = 0.5 * c.a * pb2 + 0.25 * c.b * pb2 * pb2;
+    const size_t M = p.size();
+    double e = 0.0;
+    for (size_t i = 0; i < M; i++) {
+        const double q = p[i];
+        e += 0.5 * c.a * q * q + 0.25 * c.b * q * q * q * q - fb;
+        const double nxt = i + 1 < M ? p[i + 1] : c.right;
+        e += 0.5 * c.kappa * (nxt - q) * (nxt - q);
+    }
+    if (c.wall) e += c.H * p[0];
+    else e += 0.5 * c.kappa * (p[0] - c.left) * (p[0] - c.left);
+    return e;
+}
+
+double chain_minimum(Chain &c)
+{
+    const size_t M = c.p.size();
+    std::vector<double> g(M), d(M), cp(M), dp(M), x(M), trial(M);
+    double e = chain_energy(c, c.p);
+    for (int it = 0; it < 100; it++) {
+        double gmax = 0.0;
+        for (size_t i = 0; i < M; i++) {
+            const double q = c.p[i];
+            const double prv = i > 0 ? c.p[i - 1] : (c.wall ? q : c.left);
+            const double nxt = i + 1 < M ? c.p[i + 1] : c.right;
+            g[i] = c.a * q + c.b * q * q * q + c.kappa * ((q - prv) + (q - nxt));
+            d[i] = c.a + 3.0 * c.b * q * q + ((i == 0 && c.wall) ? 1.0 : 2.0) * c.kappa;
+            gmax = std::max(gmax, std::fabs(g[i]));
+        }
+        if (c.wall) g[0] += c.H;
+        gmax = std::max(gmax, std::fabs(g[0]));
+        if (gmax < 1e-15) break;
+        // Thomas algorithm for (diag d, off-diagonals -kappa) x = -g
+        cp[0] = -c.kappa / d[0];
+        dp[0] = -g[0] / d[0];
+        for (size_t i = 1; i < M; i++) {
+            const double den = d[i] + c.kappa * cp[i - 1];
+            cp[i] = -c.kappa / den;
+            dp[i] = (-g[i] + c.kappa * dp[i - 1]) / den;
+        }
+        x[M - 1] = dp[M - 1];
+        for (size_t i = M - 1; i-- > 0;) x[i] = dp[i] - cp[i] * x[i + 1];
+        double t = 1.0, et = e;
+        for (; t > 1e-12; t *= 0.5) {
+            for (size_t i = 0; i < M; i++) trial[i] = c.p[i] + t * x[i];
+            et = chain_energy(c, trial);
+            if (et <= e) break;
+        }
+        if (!(t > 1e-12)) break;
+        c.p.swap(trial);
+        e = et;
+    }
+    return e;
+}
+
+// Young's cosine of the discrete flat wall with wetting parameter H:
+// (gamma(+psi_b) - gamma(-psi_b)) / sigma, the wall tensions against each
+// bulk phase over the tension of the discrete flat interface (the lower of
+// the kink centred between nodes and on a node)
+double lattice_cos(double a, double b, double kappa, double H)
+{
+    const double pb = std::sqrt(-a / b), w = std::sqrt(2.0 * kappa / -a);
+    const int M = std::max(64, (int)(16.0 * w) + 1);
+    double gam[2];
+    for (int k = 0; k < 2; k++) {
+        const double s = k == 0 ? pb : -pb;
+        Chain c{a, b, kappa, H, true, 0.0, s, std::vector<double>(M, s)};
+        gam[k] = chain_minimum(c);
+    }
+    double sigma = INFINITY;
+    for (int k = 0; k < 2; k++) {
+        Chain c{a, b, kappa, 0.0, false, -pb, pb, std::vector<double>(2 * M)};
+        for (int i = 0; i < 2 * M; i++) c.p[i] = pb * std::tanh((i - M + 0.5 * k) / w);
+        sigma = std::min(sigma, chain_minimum(c));
+    }
+    return (gam[0] - gam[1]) / sigma;
+}
+
+}  // namespace
+
+extern "C" {
+
+double lb_wetting_H_lattice(double theta_deg, double a, double b, double kappa)
+{
+    if (!(a < 0.0 && b > 0.0 && kappa > 0.0) || !std::isfinite(theta_deg)) return NAN;
+    const double target = std::cos(theta_deg * M_PI / 180.0), scale = std::sqrt(kappa * b);
+    double lo = -scale, hi = scale;
+    const double clo = lattice_cos(a, b, kappa, lo), chi = lattice_cos(a, b, kappa, hi);
+    if (!(target >= clo && target <= chi)) return NAN;
+    for (int it = 0; it < 60; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (lattice_cos(a, b, kappa, mid) < target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 double lb_solubility_E(double ratio, double c_b0)
 {
     return -c_b0 * (ratio - 1.0) / ((ratio + 1.0) * tanh(1.0));

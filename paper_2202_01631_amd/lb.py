@@ -25,7 +25,7 @@ EXPORTS = ("lb_footprint_bytes", "lb_create", "lb_destroy", "lb_init_fields",
            "lb_save_state", "lb_load_state", "lb_batch_step", "lb_batch_step_noalloc",
            "lb_set_launch_shapes",
            "lb_get_launch_shapes", "lb_timing_enable", "lb_timing_read",
-           "lb_last_error", "lb_wetting_H", "lb_solubility_E")
+           "lb_last_error", "lb_wetting_H", "lb_wetting_H_lattice", "lb_solubility_E")
 
 
 class Params(C.Structure):
@@ -117,10 +117,12 @@ def load():
     L.lb_last_error.restype = C.c_char_p
     L.lb_wetting_H.argtypes = [C.c_double, C.c_double, C.c_double]
     L.lb_wetting_H.restype = C.c_double
+    L.lb_wetting_H_lattice.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+    L.lb_wetting_H_lattice.restype = C.c_double
     L.lb_solubility_E.argtypes = [C.c_double, C.c_double]
     L.lb_solubility_E.restype = C.c_double
     for name in EXPORTS:
-        if name not in ("lb_last_error", "lb_wetting_H", "lb_solubility_E"):
+        if name not in ("lb_last_error", "lb_wetting_H", "lb_wetting_H_lattice", "lb_solubility_E"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -215,6 +217,10 @@ def footprint_bytes(shape, precision="fp32", **params):
 
 def wetting_H(theta_deg, kappa, b):
     return load().lb_wetting_H(float(theta_deg), float(kappa), float(b))
+
+
+def wetting_H_lattice(theta_deg, a, b, kappa):
+    return load().lb_wetting_H_lattice(float(theta_deg), float(a), float(b), float(kappa))
 
 
 def solubility_E(ratio, c_b0):
@@ -393,7 +399,10 @@ def from_spec(spec, precision=None, arena=None, stream=None, **override):
     for d in spec.get("colloids", []):
         q = dict(d)
         if "H" not in q:
-            q["H"] = wetting_H(q.get("contact_angle", 90.0), p["kappa"], p["b"])
+            th = q.get("contact_angle", 90.0)
+            # Eq. 10 by default; "lattice": the angle this lattice realises
+            q["H"] = (wetting_H_lattice(th, p["a"], p["b"], p["kappa"])
+                      if spec.get("wetting_map") == "lattice" else wetting_H(th, p["kappa"], p["b"]))
         cols.append(q)
     if cols:
         b.add_colloids(cols)

@@ -37,6 +37,12 @@ def test_host_parameter_maps_match_oracle():
     for th in (0.0, 30.0, 45.0, 60.0, 90.0, 120.0, 135.0, 180.0):
         assert lb.wetting_H(th, 0.04, 0.0625) == pytest.approx(oracle.wetting_H(th, 0.04, 0.0625), abs=1e-15)
     assert math.isnan(lb.wetting_H(60.0, 0.0, 0.0625))
+    for th in (45.0, 60.0, 90.0, 120.0, 135.0):
+        for kap in (0.04, 0.5):
+            assert lb.wetting_H_lattice(th, -0.0625, 0.0625, kap) == pytest.approx(
+                oracle.wetting_H_lattice(th, -0.0625, 0.0625, kap), abs=1e-14)
+    assert math.isnan(lb.wetting_H_lattice(60.0, 0.0625, 0.0625, 0.04))
+    assert math.isnan(lb.wetting_H_lattice(60.0, -0.0625, 0.0625, 0.0))
     for r in (1.0, 2.0, 3.5, 5.0):
         assert lb.solubility_E(r, 0.5) == pytest.approx(oracle.solubility_E(r, 0.5), rel=1e-15)
 

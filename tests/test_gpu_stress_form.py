@@ -1,8 +1,8 @@
 """GPU checks of the divergence-form solvent force (LB_STRESS_FORM, with
 LB_CAPILLARY_FORCE; the momentum exchange of Sec. II.B made exact for the
 capillary coupling): FP32 and FP64 against the oracle on the paper's
-regime box, and batched beside a box without the option bit for bit as
-alone."""
+regime box, batched beside a box without the option bit for bit as alone,
+long runs that stay finite, and a particle settling at its contact angle."""
 import numpy as np
 import pytest
 
@@ -132,4 +132,45 @@ def test_trap_runs_at_one_psi_update_stay_stable():
         t, _ = b.observables()
         assert t["error_bits"] == 0
         assert np.abs(b.fields()["u"]).max() < 0.03
+        b.close()
+
+
+def test_particle_settles_at_its_contact_angle():
+    # Young's position (Sec. III.B; the wetting of Eqs. 8-10): a sphere of
+    # radius 8 released on a flat interface (64^3, interfaces at x = 16 and
+    # 48, the paper's free energy, no solute) settles with its centre R cos
+    # theta into the phase it prefers -- oil (psi < 0, x < 16) for theta < 90
+    # degrees.  With H from the lattice's own map (the angle a flat wall of
+    # this lattice realises) and the capillary stress in divergence form,
+    # after 8000 steps the offset is within 0.5 of -R cos theta (measured
+    # -3.88 / +3.84 / 0.00 for 60 / 120 / 90 degrees).  With H from the
+    # printed Eq. 10, the same 60 degrees realises about 43 on this lattice
+    # and the particle sits beyond 4.8 (measured 5.53).
+    import torch
+    shape = (64, 64, 64)
+    R = 8.0
+    st = torch.cuda.Stream()
+    cases = [("lattice", 60.0), ("lattice", 90.0), ("lattice", 120.0), ("eq10", 60.0)]
+    boxes = []
+    for wmap, th in cases:
+        col = I.janus((16.0, 32.0, 32.0), (0.0, 1.0, 0.0), R, alpha=0.0, mu=0.0, theta=th)
+        w = I.workload_paper([col], E=0.0, shape=shape)
+        w["params"]["flags"] = lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM
+        w["wetting_map"] = wmap
+        boxes.append(lb.from_spec(w, stream=st))
+    lb.batch_step(boxes, 8000)
+    for b, (wmap, th) in zip(boxes, cases):
+        t, c = b.observables()
+        assert t["error_bits"] == 0
+        f = b.fields()["psi"].reshape(shape[2], shape[1], shape[0])
+        far = np.concatenate([f[:, :12, :].reshape(-1, shape[0]), f[:, 52:, :].reshape(-1, shape[0])])
+        col = far.mean(axis=0)
+        i = 4 + int(np.argmax((col[4:28] < 0) & (col[5:29] >= 0)))
+        dx = c[0]["pos"][0] - (i + col[i] / (col[i] - col[i + 1]))
+        want = -R * np.cos(np.radians(th))
+        flush_print("[young] %s theta %.0f: offset %.3f (R cos theta %.3f)" % (wmap, th, dx, want))
+        if wmap == "lattice":
+            assert abs(dx - want) <= 0.5, (wmap, th, dx)
+        else:
+            assert dx < want - 0.8, (wmap, th, dx)
         b.close()
