@@ -263,11 +263,15 @@ def test_interface_displacement_linear_in_mu_E_at_twice_the_radius():
     # Fig. 4's Delta X ~ mu E, resolved at R = 9 (twice the paper's radius;
     # at R = 4.5 the trapped particle pins at half-lattice positions): box
     # 128 x 160 x 160, interfaces at x = 32 and 96, E = -0.25, mu = 0.025,
-    # 0.05, 0.1, 0.2, capillary stress on, solute at equilibrium.  After 7500
-    # steps (before the slow instability this option shows at this radius
-    # after ~8000 steps) Delta X / (-mu E) agrees to 15% of its mean across
-    # the eightfold range of mu.  The path is deterministic, so the run
-    # reproduces bit for bit.
+    # 0.05, 0.1, 0.2, capillary stress on, solute at equilibrium.  The
+    # particles overshoot and hop between lattice-pinned positions until
+    # about step 4000; Delta X is averaged over steps 4500 ... 7500 (seven
+    # samples; before the slow instability this option shows at this radius
+    # after ~8000 steps), and Delta X / (-mu E) agrees to 15% of its mean
+    # across the eightfold range of mu.  Which pinned position a particle
+    # ends in hangs on rounding (the mu = 0.2 one sat 0.6 further out with
+    # another FP32 tanh, still within the bar), so one sample at a fixed
+    # step would not do.
     import torch
     shape = (128, 160, 160)
     st = torch.cuda.Stream()
@@ -277,18 +281,26 @@ def test_interface_displacement_linear_in_mu_E_at_twice_the_radius():
         w = I.workload_paper([col], E=-0.25, shape=shape)
         w["c"] = w["params"]["c_b0"] - 0.25 * np.tanh(w["psi"])
         boxes.append(lb.from_spec(w, stream=st))
-    lb.batch_step(boxes, 7500)
-    ratio = []
-    for b, mu in zip(boxes, mus):
+
+    def delta_x(b):
         t, c = b.observables()
         assert t["error_bits"] == 0
         f = b.fields()["psi"].reshape(shape[2], shape[1], shape[0])
         col = f[:, :40, :].reshape(-1, shape[0]).mean(axis=0)
         i = 24 + int(np.argmax((col[24:40] < 0) & (col[25:41] >= 0)))
-        xint = i + col[i] / (col[i] - col[i + 1])
-        dx = c[0]["pos"][0] - xint
-        ratio.append(dx / (0.25 * mu))
-        flush_print("[trap R=9] mu %s Delta X %.4f ratio %.1f" % (mu, dx, ratio[-1]))
+        return c[0]["pos"][0] - (i + col[i] / (col[i] - col[i + 1]))
+
+    lb.batch_step(boxes, 4500)
+    dx = [[delta_x(b)] for b in boxes]
+    for _ in range(6):
+        lb.batch_step(boxes, 500)
+        for k, b in enumerate(boxes):
+            dx[k].append(delta_x(b))
+    ratio = []
+    for b, mu, d in zip(boxes, mus, dx):
+        ratio.append(np.mean(d) / (0.25 * mu))
+        flush_print("[trap R=9] mu %s Delta X %.4f (steps 4500..7500: %s) ratio %.1f"
+                    % (mu, np.mean(d), np.round(d, 3), ratio[-1]))
         b.close()
     m = np.mean(ratio)
     assert m > 0 and all(abs(r - m) <= 0.15 * m for r in ratio)
