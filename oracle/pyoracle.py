@@ -322,7 +322,8 @@ def solubility_E(ratio, c_b0):
 
 def from_spec(spec, steps=None):
     """Oracle box built from a workload spec of paper_2202_01631_amd.inputs.
-    The contact angle maps to H through Eq. 10 and the solubility ratio to E
+    The contact angle maps to H through Eq. 10 (or the lattice's own map when
+    the spec says ``wetting_map: "lattice"``) and the solubility ratio to E
     with this module's own functions."""
     p = dict(spec["params"])
     p["E"] = solubility_E(spec.get("solubility_ratio", 1.0), p.get("c_b0", 0.0)) \

@@ -389,8 +389,9 @@ def spec_params(spec, **override):
 
 def from_spec(spec, precision=None, arena=None, stream=None, **override):
     """Box built from a workload spec of paper_2202_01631_amd.inputs; the
-    contact angle maps to H (Eq. 10) and the solubility ratio to E through the
-    library's own host helpers."""
+    contact angle maps to H (Eq. 10, or with ``wetting_map: "lattice"`` the H
+    whose flat wall this lattice wets at that angle) and the solubility ratio
+    to E through the library's own host helpers."""
     p = spec_params(spec, **override)
     prec = precision or spec.get("precision", "fp64")
     b = Box(spec["shape"], prec, arena=arena, stream=stream, **p)
