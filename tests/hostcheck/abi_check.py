@@ -124,6 +124,19 @@ def main():
     soft.init_fields(np.zeros(32 ** 3), np.zeros(32 ** 3))
     expect_error(soft.add_colloids, sw["colloids"])
     soft.close()
+    # host parameter maps: Eq. 10, the lattice's own wetting map (its
+    # one-dimensional minimisers, with a wide interface too) and Eq. 1's E
+    for th in (0.0, 60.0, 90.0, 135.0):
+        assert np.isfinite(lb.wetting_H(th, 0.04, 0.0625))
+        assert np.isfinite(lb.wetting_H_lattice(th, -0.0625, 0.0625, 0.04))
+    assert np.isfinite(lb.wetting_H_lattice(60.0, -0.0625, 0.0625, 4.0))
+    assert np.isnan(lb.wetting_H_lattice(60.0, 0.0625, 0.0625, 0.04))
+    assert np.isnan(lb.wetting_H_lattice(float("nan"), -0.0625, 0.0625, 0.04))
+    assert np.isfinite(lb.solubility_E(3.0, 0.5))
+    lw = dict(w, wetting_map="lattice")
+    lbox = lb.from_spec(lw, precision="fp32", stream=st.value)
+    lbox.step(2)
+    lbox.close()
     left = L.hostcheck_live_allocations()
     print("abi ok: %d device allocations left" % left, flush=True)
     if left:
