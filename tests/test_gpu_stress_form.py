@@ -215,3 +215,44 @@ def test_active_particle_swims_along_the_interface():
     assert y2 - y1 > 3.0 and abs(z2 - 48.0) < 0.5
     assert th2 < th1 < 30.0 and th2 < 20.0
     b.close()
+
+
+def test_passive_offsets_grow_away_from_neutral_wetting():
+    # Fig. 5A's passive points at the paper's radius: inactive particles
+    # (R = 4.5, mu = 0) released on the interface of the paper box settle
+    # further from the plane the more the contact angle departs from 90
+    # degrees, into the phase they prefer, mirror-symmetric about 90 degrees.
+    # Lattice map for H, capillary stress in divergence form, 12000 steps:
+    # the offsets are ordered like -cos(theta), odd about 90 degrees to 0.02,
+    # and between 0.55 and 1 of R cos(theta) (measured 0.63 at 75 and 105
+    # degrees, 0.86 at 60 and 120, 0.76 at 45 and 135: a sphere of radius
+    # 4.5 on this lattice sits short of the continuum Young position)
+    import torch
+    shape = (64, 96, 96)
+    st = torch.cuda.Stream()
+    ths = (45.0, 60.0, 75.0, 90.0, 105.0, 120.0, 135.0)
+    boxes = []
+    for th in ths:
+        col = I.janus((16.0, 48.0, 48.0), (0.0, 1.0, 0.0), 4.5, alpha=0.0, mu=0.0, theta=th)
+        w = I.workload_paper([col], E=0.0)
+        w["params"]["flags"] = lb.LB_CAPILLARY_FORCE | lb.LB_STRESS_FORM
+        w["wetting_map"] = "lattice"
+        boxes.append(lb.from_spec(w, stream=st))
+    lb.batch_step(boxes, 12000)
+    dx = []
+    for b in boxes:
+        t, c = b.observables()
+        assert t["error_bits"] == 0
+        f = b.fields()["psi"].reshape(shape[2], shape[1], shape[0])
+        far = np.concatenate([f[:24].reshape(-1, shape[0]), f[72:].reshape(-1, shape[0])])
+        col = far.mean(axis=0)
+        i = 8 + int(np.argmax((col[8:24] < 0) & (col[9:25] >= 0)))
+        dx.append(c[0]["pos"][0] - (i + col[i] / (col[i] - col[i + 1])))
+        b.close()
+    flush_print("[fig5A] offsets %s" % np.round(dx, 3))
+    assert all(dx[k] < dx[k + 1] for k in range(len(ths) - 1))
+    for k in range(3):
+        assert abs(dx[k] + dx[6 - k]) <= 0.02
+        want = -4.5 * np.cos(np.radians(ths[k]))
+        assert 0.55 <= dx[k] / want <= 1.0, (ths[k], dx[k])
+    assert abs(dx[3]) <= 0.05
