@@ -314,6 +314,11 @@ def test_contact_angle_the_lattice_realises():
     for th in (60.0, 75.0, 120.0):
         Hl = oracle.wetting_H_lattice(th, a, b, 4.0)
         assert Hl / oracle.wetting_H(th, 4.0, b) == pytest.approx(1.0 / math.sqrt(2.0), rel=1e-3)
+    # and for a != -b (bulk psi_b^2 = -a/b): the same integral scales H by
+    # psi_b^2 sqrt(kappa b/2), so H = h sqrt(kappa b) psi_b^2 / sqrt 2
+    for th in (60.0, 120.0):
+        Hl = oracle.wetting_H_lattice(th, -0.1, 0.05, 4.0)
+        assert Hl == pytest.approx(oracle.wetting_H(th, 4.0, 0.05) * 2.0 / math.sqrt(2.0), rel=1e-3)
     # (4) at the paper's kappa the printed Eq. 10 over-states the wetting:
     # its H for 60 degrees realises 42.7 degrees
     th = math.degrees(math.acos(oracle.lattice_cos(a, b, kappa, oracle.wetting_H(60.0, kappa, b))))
