@@ -171,7 +171,8 @@ typedef struct {                 /* FP64, caller-owned */
     double alpha_minus, alpha_plus;  /* production per link on the active cap m.n <= cap_cos /
                                         on the rest (Eq. 5) */
     double mu_minus, mu_plus;        /* phoretic mobility on the two caps (Eq. 6) */
-    double H;                        /* wetting parameter of Eqs. 8-9 (lb_wetting_H) */
+    double H;                        /* wetting parameter of Eqs. 8-9 (from a contact angle:
+                                        lb_wetting_H, Eq. 10, or lb_wetting_H_lattice) */
     double rho_p;                    /* particle density: mass rho_p 4/3 pi R^3 */
     int32_t fixed;                   /* 1: position, axis and velocities held */
     double cap_cos;                  /* the active cap is m.n <= cap_cos, in [-1, 1]; 0 (the
