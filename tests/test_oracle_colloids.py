@@ -226,6 +226,50 @@ def test_moving_colloid_momentum_balance():
     assert n_changed > 0  # cover/uncover exercised
 
 
+def test_first_implicit_update_is_the_closed_form():
+    # the implicit rigid-body update (Sec. II.B, in the manner of Nguyen and
+    # Ladd) on the first step of a sphere launched through a fluid at rest:
+    # the post-collision populations are w_d rho0, the link sum of 2 f*_d c_d
+    # over a closed surface vanishes, so F0 = T0 = 0 and the update reduces
+    # to X' = (M + zeta)^-1 M X, X = (V, Omega), M = diag(m, m, m, I, I, I)
+    # with m = rho_p 4/3 pi R^3 and I = 2/5 m R^2, and the drag tensor zeta =
+    # sum over links of 6 w_d rho0 g g^T, g = (c_d, r x c_d), r from the
+    # centre to the link midpoint -- here from links enumerated by brute
+    # force.  The position then moves by V'.  A wrong wall coefficient, a
+    # dropped torque block or the explicit update instead miss by far.
+    shape = (18, 16, 16)
+    N = int(np.prod(shape))
+    col = dict(pos=(8.7, 7.4, 8.2), m=(0.0, 0.6, 0.8), radius=3.3, vel=(1e-3, -2e-3, 5e-4),
+               omega=(2e-4, -1e-4, 3e-4), rho_p=1.3)
+    o = oracle.Oracle(shape, a=0.0, b=0.0, kappa=0.0, M_psi=0.0, C=0.0, E=0.0, c_b0=0.0,
+                      D_c=0.1, k_d=0.0, tau=1.0)
+    o.init_fields(np.zeros(N), np.zeros(N))
+    o.add_colloids([col])
+    recs, _ = brute_links(shape, [col])
+    X = np.stack(I.coords(shape))
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    zeta = np.zeros((6, 6))
+    for _, n, dd, _ in recs:
+        cd = CVEC[dd].astype(np.float64)
+        r = X[:, n] + 0.5 * cd - np.array(col["pos"])
+        g = np.concatenate([cd, np.cross(r, cd)])
+        zeta += 6.0 * w[dd] * np.outer(g, g)
+    m = col["rho_p"] * 4.0 / 3.0 * math.pi * col["radius"] ** 3
+    Mm = np.diag([m, m, m] + [0.4 * m * col["radius"] ** 2] * 3)
+    Xv = np.concatenate([col["vel"], col["omega"]])
+    want = np.linalg.solve(Mm + zeta, Mm @ Xv)
+    o.step(1)
+    _, c = o.observables()
+    got = np.concatenate([c[0]["vel"], c[0]["omega"]])
+    d = o.colloid_diag(0)
+    assert np.abs(d["F0"]).max() <= 1e-15 and np.abs(d["T0"]).max() <= 1e-14
+    assert np.abs(zeta - d["zeta"]).max() <= 1e-12
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(Xv).max() * 10
+    assert np.abs(c[0]["pos"] - (np.array(col["pos"]) + c[0]["vel"])).max() <= 1e-14
+    assert np.abs(got - Xv).max() > 1e-5   # the drag did act
+    o.close()
+
+
 def test_axis_rotation_and_translation():
     # after one step the axis is the old one rotated by |Omega'| about Omega'
     # (rotation vector Omega' dt, dt = 1), and the centre moved by V'
