@@ -270,6 +270,63 @@ def test_first_implicit_update_is_the_closed_form():
     o.close()
 
 
+def test_cover_and_uncover_follow_their_rule():
+    # the repair of the nodes a moving particle crosses (implied by moving
+    # particles, Sec. II.B): a node that turns fluid takes f^eq(rho0, u_w),
+    # u_w = V' + Omega' x r the particle's rigid velocity there after the
+    # update (r from the new centre), and psi, c the mean over its face
+    # neighbours fluid before and after; the particle gives up rho0 u_w for
+    # it and takes the momentum sum f_i c_i of every node it covers.  A sphere
+    # driven through a quiescent binary fluid, stepped until both kinds of
+    # node appear; every repaired node checked against the rule written out
+    # here (textbook equilibrium, minimum image), the transfer to the particle
+    # summed here from the covered nodes' populations
+    shape = (20, 14, 14)
+    N = int(np.prod(shape))
+    p = dict(a=-0.0625, b=0.0625, kappa=0.04, M_psi=0.1, C=0.0625, E=-0.1, c_b0=0.5,
+             D_c=0.1, k_d=1e-3, tau=1.0)
+    o = oracle.Oracle(shape, **p)
+    psi0 = np.tanh((I.coords(shape)[2] - 7.0) / I.WIDTH) + I.noise(5, N, 0.01)
+    o.init_fields(psi0, 0.5 + I.noise(6, N, 0.05))
+    o.add_colloids([dict(pos=(6.3, 7.1, 6.8), m=(0.0, 0.6, 0.8), radius=3.4, vel=(0.3, 0.05, 0.0),
+                         omega=(0.0, 0.0, 0.04), rho_p=1.0)])
+    X = np.stack(I.coords(shape))
+    Ls = np.array(shape, dtype=np.float64)
+    seen_cover = seen_uncover = 0
+    for _ in range(12):
+        own0 = o.owner()
+        o.step(1)
+        own1 = o.owner()
+        f = o.populations()
+        fl = o.fields()
+        _, c = o.observables()
+        q = c[0]
+        up = np.nonzero((own0 >= 0) & (own1 < 0))[0]
+        dn = np.nonzero((own0 < 0) & (own1 >= 0))[0]
+        tr = np.zeros(3)
+        for n in dn:
+            tr += f[:, n] @ CVEC
+        for n in up:
+            r = _min_image(X[:, n] - q["pos"], Ls)
+            uw = q["vel"] + np.cross(q["omega"], r)
+            assert np.abs(f[:, n] - _feq(1.0, uw)).max() <= 1e-16
+            tr -= uw
+            nb = []
+            for e in range(1, 7):
+                m = int(((X[:, n] + CVEC[e]) % Ls) @ np.array([1, shape[0], shape[0] * shape[1]]))
+                if own0[m] < 0 and own1[m] < 0:
+                    nb.append(m)
+            if nb:
+                assert fl["psi"][n] == pytest.approx(np.mean(fl["psi"][nb]), abs=1e-15)
+                assert fl["c"][n] == pytest.approx(np.mean(fl["c"][nb]), abs=1e-15)
+        if len(up) or len(dn):
+            assert np.abs(o.colloid_diag(0)["trF"] - tr).max() <= 1e-14
+        seen_cover += len(dn)
+        seen_uncover += len(up)
+    assert seen_cover > 0 and seen_uncover > 0
+    o.close()
+
+
 def test_axis_rotation_and_translation():
     # after one step the axis is the old one rotated by |Omega'| about Omega'
     # (rotation vector Omega' dt, dt = 1), and the centre moved by V'
