@@ -2382,6 +2382,14 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     // sub-step 0 reads the state at t and writes the pair its table names
     BatchArgs a0 = B.args;
     if (B.nsub > 1) a0.d = B.dsub[0];
+    // the link pass first on the side stream: its few blocks take CUs before
+    // the bulk psi/c update fills them (it reads the state at t, like the
+    // boundary psi/c fix-up after it, and writes neither's inputs)
+    const bool early_links = par && B.ncol > 0;
+    if (early_links) {
+        if (B.soft) k_soft<<<(B.ncol + 63) / 64, 64, 0, ss>>>(B.args, B.ncol);
+        k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);
+    }
     if (split && B.special) k_scalar_bnd<S, true><<<gfix, GCHUNK, 0, ss>>>(a0);
     else if (split) k_scalar_bnd<S, false><<<gfix, GCHUNK, 0, ss>>>(a0);
     const int vs = B.vec[2] == 4 ? 4 : (B.vec[2] == 2 ? 2 : 1);
@@ -2447,8 +2455,10 @@ void launch_step(const Batch &B, hipStream_t s, const SideStream *side, TimingHo
     }
     if (B.ncol <= 0) return;
     if (tm) tm->begin(3, s);
-    if (B.soft) k_soft<<<(B.ncol + 63) / 64, 64, 0, ss>>>(B.args, B.ncol);
-    k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);
+    if (!early_links) {
+        if (B.soft) k_soft<<<(B.ncol + 63) / 64, 64, 0, ss>>>(B.args, B.ncol);
+        k_link_partial<P><<<dim3(B.nlchunk_max, B.ncol), LINK_THREADS, 0, ss>>>(B.args);
+    }
     k_colloid_update<<<B.ncol, 64, 0, ss>>>(B.args);
     if (par) {
         hipEventRecord(side->ev[3], ss);
