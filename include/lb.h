@@ -155,7 +155,12 @@ typedef struct {
  *                      their links, so fluid and particles together conserve
  *                      momentum.  Selects the one-node forms of the mu update
  *                      and collide-stream and the boundary fix-ups; the arena
- *                      holds 7 more scalar fields.
+ *                      holds 7 more scalar fields.  Either form wants the
+ *                      interface to relax faster than a particle disturbs it:
+ *                      at M_psi = 0.1 in one psi/c update a strongly pushed or
+ *                      emitting particle on an interface can still diverge
+ *                      (LB_E_UNSTABLE); the paper's M_psi = 0.4 in two
+ *                      sub-steps held in every tested case.
  * Other bits: LB_E_INVALID at lb_create. */
 #define LB_SOLUTE_FORCE 1u
 #define LB_EXPLICIT_COLLOID 2u
